@@ -1,0 +1,204 @@
+"""Synthetic rigid-water systems with random multipoles and polarizabilities.
+
+Each water has five sites in the order O, H1, H2, B1, B2, where B1 and B2 are
+the O-H bond barycentres.  Charges are O -0.8, H +0.4, B 0.  Every site gets a
+random dipole (uniform in the ball |d| <= 0.1 e*A) and a random traceless
+quadrupole (xx, yy, xy, xz, yz uniform in [-0.1, 0.1] e*A^2, zz = -(xx+yy)).
+O, B1 and B2 get a random SPD polarizability R diag(l1,l2,l3) R^T with
+eigenvalues uniform in [0.3, 1.0] A^3 and a Haar-random rotation R; the H
+sites are not polarizable (zero tensor).
+
+Layouts (all float64, caller order):
+  pos   [n, 3]  A
+  mol   [n]     int32 molecule id
+  q     [n]     e
+  dip   [n, 3]  e*A
+  quad  [n, 6]  e*A^2, (xx, xy, xz, yy, yz, zz), traceless
+  alpha [n, 6]  A^3,   (xx, xy, xz, yy, yz, zz), zero row = not polarizable
+  box   [3] or None (cluster)
+
+Periodic boxes: waters sit on a jittered simple-cubic lattice
+(n_side = ceil(N^(1/3)), a random subset of lattice points, spacing L/n_side,
+jitter U[-0.1, 0.1] A per axis) with Haar-random orientations; an
+orientation is redrawn while any site of the water lies within 1.0 A of a
+site of another water.  Clusters: oxygens placed one after the other,
+uniformly in a sphere of radius 1.15 (3n / (4 pi 0.0334))^(1/3) A, keeping
+O-O >= 2.5 A, then oriented the same way.
+
+The random stream is numpy's PCG64 seeded with 22010804 + seed index; the
+draw order is fixed (lattice subset, jitter, orientations, orientation
+redraws, dipoles, quadrupoles, polarizabilities).
+"""
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+SITE_NAMES = ("O", "H1", "H2", "B1", "B2")
+WATER_SITES = 5
+_OH = 0.9572
+_HOH = math.radians(104.52)
+_SEED_BASE = 22010804
+
+# Named workloads: sizes and discretisation parameters of the water boxes.
+CONFIGS = {
+    "box216": dict(index=1, n_waters=216, box=18.643, cutoff=8.0, beta=0.45,
+                   grid=20, order=5, tol=1e-8),
+    "box4096": dict(index=2, n_waters=4096, box=49.66, cutoff=9.0, beta=0.40,
+                    grid=48, order=5, tol=1e-8),
+    "box32000": dict(index=3, n_waters=32000, box=98.55, cutoff=9.0,
+                     beta=0.40, grid=96, order=5, tol=1e-8),
+    "box96000": dict(index=5, n_waters=96000, box=142.2, cutoff=9.0,
+                     beta=0.40, grid=144, order=5, tol=1e-8),
+    "box1024": dict(index=4, n_waters=1024, box=31.318, cutoff=9.0,
+                    beta=0.40, grid=32, order=5, tol=1e-8),
+}
+
+
+def _water_frame():
+    """Body-frame coordinates of O, H1, H2, B1, B2 (O at origin)."""
+    h = 0.5 * _HOH
+    h1 = np.array([_OH * math.sin(h), 0.0, _OH * math.cos(h)])
+    h2 = np.array([-_OH * math.sin(h), 0.0, _OH * math.cos(h)])
+    o = np.zeros(3)
+    return np.stack([o, h1, h2, 0.5 * (o + h1), 0.5 * (o + h2)])
+
+
+def _haar_rotations(rng, n):
+    """n Haar-random rotation matrices from normalised Gaussian quaternions."""
+    qv = rng.standard_normal((n, 4))
+    qv /= np.linalg.norm(qv, axis=1, keepdims=True)
+    w, x, y, z = qv.T
+    rot = np.empty((n, 3, 3))
+    rot[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    rot[:, 0, 1] = 2 * (x * y - z * w)
+    rot[:, 0, 2] = 2 * (x * z + y * w)
+    rot[:, 1, 0] = 2 * (x * y + z * w)
+    rot[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    rot[:, 1, 2] = 2 * (y * z - x * w)
+    rot[:, 2, 0] = 2 * (x * z - y * w)
+    rot[:, 2, 1] = 2 * (y * z + x * w)
+    rot[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return rot
+
+
+def _place_sites(centres, rot):
+    frame = _water_frame()
+    return centres[:, None, :] + np.einsum("nab,sb->nsa", rot, frame)
+
+
+def _clash_molecules(sites, box, min_sep=1.0):
+    """Molecule indices (later of each clashing pair) with an intermolecular
+    site pair closer than min_sep."""
+    n = sites.shape[0]
+    flat = sites.reshape(-1, 3)
+    if box is not None:
+        flat = np.mod(flat, box)
+        tree = cKDTree(flat, boxsize=box)
+    else:
+        tree = cKDTree(flat)
+    pairs = tree.query_pairs(min_sep, output_type="ndarray")
+    if len(pairs) == 0:
+        return np.zeros(0, dtype=np.int64)
+    mi = pairs[:, 0] // WATER_SITES
+    mj = pairs[:, 1] // WATER_SITES
+    inter = mi != mj
+    later = np.maximum(mi[inter], mj[inter])
+    del n
+    return np.unique(later)
+
+
+def _orient(rng, centres, box):
+    rot = _haar_rotations(rng, len(centres))
+    for _ in range(1000):
+        sites = _place_sites(centres, rot)
+        bad = _clash_molecules(sites, box)
+        if len(bad) == 0:
+            return sites
+        rot[bad] = _haar_rotations(rng, len(bad))
+    raise RuntimeError("could not orient waters without clashes")
+
+
+def _multipoles(rng, n_waters):
+    n = n_waters * WATER_SITES
+    q = np.tile(np.array([-0.8, 0.4, 0.4, 0.0, 0.0]), n_waters)
+    # dipoles uniform in the ball of radius 0.1
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    rad = 0.1 * rng.random(n) ** (1.0 / 3.0)
+    dip = v * rad[:, None]
+    u = rng.uniform(-0.1, 0.1, size=(n, 5))  # xx, yy, xy, xz, yz
+    quad = np.empty((n, 6))
+    quad[:, 0] = u[:, 0]
+    quad[:, 3] = u[:, 1]
+    quad[:, 1] = u[:, 2]
+    quad[:, 2] = u[:, 3]
+    quad[:, 4] = u[:, 4]
+    quad[:, 5] = -(u[:, 0] + u[:, 1])
+    # polarizabilities at O, B1, B2
+    pol_mask = np.tile(np.array([True, False, False, True, True]), n_waters)
+    npol = int(pol_mask.sum())
+    eig = rng.uniform(0.3, 1.0, size=(npol, 3))
+    rot = _haar_rotations(rng, npol)
+    a3 = np.einsum("nab,nb,ncb->nac", rot, eig, rot)
+    alpha = np.zeros((n, 6))
+    alpha[pol_mask] = np.stack([a3[:, 0, 0], a3[:, 0, 1], a3[:, 0, 2],
+                                a3[:, 1, 1], a3[:, 1, 2], a3[:, 2, 2]], axis=1)
+    return q, dip, quad, alpha
+
+
+def _pack(sites, n_waters, box, rng):
+    q, dip, quad, alpha = _multipoles(rng, n_waters)
+    pos = sites.reshape(-1, 3).copy()
+    mol = np.repeat(np.arange(n_waters, dtype=np.int32), WATER_SITES)
+    return dict(pos=pos, mol=mol, q=q, dip=dip, quad=quad, alpha=alpha,
+                box=None if box is None else np.array([box, box, box], float))
+
+
+def water_box(n_waters, box_len, seed_index=0):
+    """Jittered-lattice periodic water box (positions wrapped into [0, L))."""
+    rng = np.random.Generator(np.random.PCG64(_SEED_BASE + seed_index))
+    n_side = int(math.ceil(n_waters ** (1.0 / 3.0) - 1e-9))
+    if n_side ** 3 < n_waters:
+        n_side += 1
+    spacing = box_len / n_side
+    chosen = np.sort(rng.choice(n_side ** 3, size=n_waters, replace=False))
+    ix = chosen % n_side
+    iy = (chosen // n_side) % n_side
+    iz = chosen // (n_side * n_side)
+    centres = (np.stack([ix, iy, iz], axis=1) + 0.5) * spacing
+    centres = centres + rng.uniform(-0.1, 0.1, size=centres.shape)
+    sites = _orient(rng, centres, np.array([box_len] * 3))
+    sites = np.mod(sites, box_len)
+    return _pack(sites, n_waters, box_len, rng)
+
+
+def water_cluster(n_waters, seed_index=0):
+    """Random compact gas-phase water cluster (O-O >= 2.5 A)."""
+    rng = np.random.Generator(np.random.PCG64(_SEED_BASE + 1000 + seed_index))
+    radius = 1.15 * (3.0 * n_waters / (4.0 * math.pi * 0.0334)) ** (1.0 / 3.0)
+    centres = []
+    tries = 0
+    while len(centres) < n_waters:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("cluster placement failed")
+        p = rng.uniform(-radius, radius, size=3)
+        if p @ p > radius * radius:
+            continue
+        if centres:
+            d = np.linalg.norm(np.asarray(centres) - p, axis=1)
+            if d.min() < 2.5:
+                continue
+        centres.append(p)
+    sites = _orient(rng, np.asarray(centres), None)
+    return _pack(sites, n_waters, None, rng)
+
+
+def config_system(name):
+    """System dict plus its discretisation parameters for a named workload."""
+    c = CONFIGS[name]
+    sysd = water_box(c["n_waters"], c["box"], seed_index=c["index"])
+    params = dict(beta=c["beta"], cutoff=c["cutoff"], grid=c["grid"],
+                  order=c["order"], tol=c["tol"])
+    return sysd, params

@@ -1,0 +1,347 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+P1  T symmetric positive definite; two independent assemblies agree; PCG
+    equals the dense solve (paper: T is SPD thanks to Thole damping, Eq. 18).
+P2  Ewald beta-invariance of E0, T p, E_pol, E_elec (self terms, exclusion
+    corrections and Thole composition).
+P3  NaCl / CsCl Madelung constants (charge Ewald).
+P4  Cluster in a growing box: Ewald plus the surface term -> direct sum.
+P5  SPME -> brute-force Ewald as the grid is refined / order raised.
+P6  Zero net force (direct, Ewald).
+P7  Finite-difference forces (direct, Ewald, SPME).
+P8  E_pol of Eq. 19 equals the variational Eq. 17 at convergence.
+P9  Closed forms: charge + polarizable site; two sites on an axis
+    (Applequist 2x2); alpha -> 0 limit.
+P10 PCG, plain CG and block-Jacobi reach the same mu.
+P11 Rotation invariance (cluster); translation invariance (Ewald).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import System, Params, Context, permanent_field, apply_T
+from oracle.units import COULOMB
+from synth import water_cluster, water_box
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _ions(pos, q, box):
+    n = len(pos)
+    return System(pos=np.asarray(pos, float), mol=np.arange(n), q=np.asarray(q, float),
+                  dip=np.zeros((n, 3)), quad=np.zeros((n, 6)), alpha=np.zeros((n, 6)),
+                  box=np.asarray(box, float))
+
+
+def _cluster(n, seed):
+    return System.from_dict(water_cluster(n, seed))
+
+
+def _small_box(n=8, L=7.0, seed=7):
+    return System.from_dict(water_box(n, L, seed))
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("nw,seed", [(2, 0), (5, 1), (8, 2)])
+def test_p1_dense_T_cluster(nw, seed):
+    s = _cluster(nw, seed)
+    p = Params(method="direct", tol=1e-12)
+    c = Context(s, p)
+    T1 = oracle.dense_T_columns(s, p, ctx=c)
+    T2 = oracle.dense_T_blocks(s, p, ctx=c)
+    assert np.abs(T1 - T1.T).max() <= 1e-13 * np.abs(T1).max()
+    assert np.abs(T1 - T2).max() <= 1e-12 * np.abs(T1).max()
+    np.linalg.cholesky(T1)                       # raises if not SPD
+    E0 = permanent_field(s, p, ctx=c)
+    mu_dense = np.linalg.solve(T1, E0.ravel()).reshape(-1, 3)
+    mu, it, rho = oracle.model.solve(s, p, E0, ctx=c)
+    assert rho <= 1e-12
+    assert np.abs(mu - mu_dense).max() <= 1e-10 * np.abs(mu_dense).max()
+
+
+def test_p1_dense_T_periodic_ewald():
+    s = _small_box()
+    p = Params(method="ewald", beta=0.5, realspace="images", rmax=13.0, tol=1e-12)
+    c = Context(s, p)
+    T1 = oracle.dense_T_columns(s, p, ctx=c)
+    T2 = oracle.dense_T_blocks(s, p, ctx=c)
+    assert np.abs(T1 - T1.T).max() <= 1e-12 * np.abs(T1).max()
+    assert np.abs(T1 - T2).max() <= 1e-11 * np.abs(T1).max()
+    np.linalg.cholesky(T1)
+
+
+def test_p1_undamped_intramolecular_not_spd():
+    """Without damping the same-molecule couplings break positivity
+    (the reason the paper damps the field)."""
+    s = _cluster(1, 3)
+    p = Params(method="direct", thole_a=1e9)   # lambda -> 1: undamped
+    T = oracle.dense_T_columns(s, p)
+    assert np.linalg.eigvalsh(T).min() < 0
+    T28 = oracle.dense_T_columns(s, Params(method="direct", thole_a=0.28))
+    assert np.linalg.eigvalsh(T28).min() > 0
+
+
+# ---------------------------------------------------------------- P2
+def test_p2_beta_invariance():
+    s = _small_box(8, 7.0, 7)
+    res = []
+    rng = np.random.default_rng(0)
+    pvec = rng.normal(size=(len(s.pol), 3)) * 0.1
+    for beta in (0.45, 0.6, 0.75):
+        p = Params(method="ewald", beta=beta, realspace="images",
+                   rmax=6.2 / beta, tol=1e-11)
+        c = Context(s, p)
+        E0 = permanent_field(s, p, ctx=c)
+        Tp = apply_T(s, p, pvec, ctx=c)
+        out = oracle.evaluate(s, p, forces=False)
+        res.append((E0, Tp, out["E_pol"], out["E_elec"]))
+    for r in res[1:]:
+        assert np.abs(r[0] - res[0][0]).max() <= 1e-10 * np.abs(res[0][0]).max()
+        assert np.abs(r[1] - res[0][1]).max() <= 1e-10 * np.abs(res[0][1]).max()
+        assert r[2] == pytest.approx(res[0][2], rel=1e-10)
+        assert r[3] == pytest.approx(res[0][3], rel=1e-10)
+
+
+# ---------------------------------------------------------------- P3
+def _madelung():
+    out = {}
+    with open(os.path.join(HERE, "golden", "madelung.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                out[k] = float(v)
+    return out
+
+
+def test_p3_madelung():
+    ref = _madelung()
+    a = 4.0
+    fcc = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    pos = np.vstack([fcc, fcc + [.5, 0, 0]]) * a
+    q = np.r_[np.ones(4), -np.ones(4)]
+    s = _ions(pos, q, [a, a, a])
+    p = Params(method="ewald", beta=1.0, realspace="images", rmax=7.0)
+    e = oracle.electrostatic_energy(s, p) / COULOMB
+    assert -e * (a / 2) / 4 == pytest.approx(ref["NaCl"], abs=2e-6)
+    s2 = _ions(np.array([[0, 0, 0], [.5, .5, .5]]) * a, [1.0, -1.0], [a, a, a])
+    e2 = oracle.electrostatic_energy(s2, p) / COULOMB
+    assert -e2 * (a * math.sqrt(3) / 2) == pytest.approx(ref["CsCl"], abs=2e-6)
+
+
+# ---------------------------------------------------------------- P4
+def test_p4_cluster_in_large_box():
+    d = water_cluster(3, 4)
+    direct = System.from_dict(d)
+    pd = Params(method="direct")
+    e_dir = oracle.electrostatic_energy(direct, pd)
+    E_dir = permanent_field(direct, pd)
+    errs = []
+    for L in (30.0, 45.0):
+        box = np.array([L, L, L])
+        s = System.from_dict(dict(d, pos=d["pos"] + L / 2, box=box))
+        p = Params(method="ewald", beta=0.35, cutoff=L / 2 - 0.5,
+                   realspace="minimage")
+        M = (s.q[:, None] * s.pos).sum(0) + s.dip.sum(0)
+        V = L ** 3
+        e = oracle.electrostatic_energy(s, p) + COULOMB * 2 * math.pi / (3 * V) * M @ M
+        E = permanent_field(s, p) - 4 * math.pi / (3 * V) * M
+        errs.append((abs(e - e_dir), np.abs(E - E_dir).max()))
+    assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1]
+    assert errs[1][0] < 1e-3 * abs(e_dir)
+    assert errs[1][1] < 1e-3 * np.abs(E_dir).max()
+
+
+# ---------------------------------------------------------------- P5
+def test_p5_spme_converges_to_ewald():
+    s = System.from_dict(water_box(27, 9.5, 3))
+    base = dict(beta=0.45, cutoff=4.5, tol=1e-11)
+    ref = oracle.evaluate(s, Params(method="ewald", realspace="minimage", **base))
+    errs = []
+    for K in (12, 18, 27):
+        o = oracle.evaluate(s, Params(method="spme", grid=(K, K, K), order=5, **base))
+        errs.append((abs(o["E_pol"] - ref["E_pol"]), abs(o["E_elec"] - ref["E_elec"]),
+                     np.abs(o["forces"] - ref["forces"]).max()))
+    for k in range(3):
+        assert errs[0][k] > errs[1][k] > errs[2][k]
+    assert errs[2][0] < 1e-3 * abs(ref["E_pol"])
+    # order at fixed grid
+    eo = []
+    for order in (4, 6, 8):
+        o = oracle.evaluate(s, Params(method="spme", grid=(18, 18, 18), order=order,
+                                      **base), forces=False)
+        eo.append(abs(o["E_elec"] - ref["E_elec"]))
+    assert eo[0] > eo[1] > eo[2]
+
+
+# ---------------------------------------------------------------- P6 / P7
+def test_p6_zero_net_force():
+    s = _cluster(4, 5)
+    o = oracle.evaluate(s, Params(method="direct", tol=1e-10))
+    assert np.abs(o["forces"].sum(0)).max() < 1e-11 * np.abs(o["forces"]).max()
+    sb = _small_box(8, 7.0, 9)
+    ob = oracle.evaluate(sb, Params(method="ewald", beta=0.5, realspace="images",
+                                    rmax=12.0, tol=1e-10))
+    assert np.abs(ob["forces"].sum(0)).max() < 1e-10 * np.abs(ob["forces"]).max()
+
+
+def _fd_check(d, p, sites, h=1e-4, rtol=1e-6):
+    s = System.from_dict(d)
+    o = oracle.evaluate(s, p)
+
+    def etot(pos):
+        oo = oracle.evaluate(System.from_dict(dict(d, pos=pos)), p, forces=False)
+        return oo["E_pol"] + oo["E_elec"]
+
+    scale = np.abs(o["forces"]).max()
+    for (i, a) in sites:
+        pp = d["pos"].copy()
+        pp[i, a] += h
+        ep = etot(pp)
+        pp[i, a] -= 2 * h
+        em = etot(pp)
+        fd = -(ep - em) / (2 * h)
+        assert abs(fd - o["forces"][i, a]) <= rtol * scale, (i, a, fd, o["forces"][i, a])
+
+
+def test_p7_fd_direct():
+    _fd_check(water_cluster(3, 2), Params(method="direct", tol=1e-12),
+              [(0, 0), (4, 1), (7, 2), (13, 0)])
+
+
+def test_p7_fd_ewald():
+    _fd_check(water_box(4, 6.5, 11), Params(method="ewald", beta=0.55,
+                                            realspace="images", rmax=11.0, tol=1e-12),
+              [(0, 2), (3, 0), (11, 1)])
+
+
+def _clear_of_cutoff(d, cutoff, L, margin=1e-2):
+    """Sites with no minimum-image pair distance within margin of the
+    cutoff (a pair crossing the cutoff makes the energy jump)."""
+    out = []
+    for i in range(len(d["pos"])):
+        dd = d["pos"] - d["pos"][i]
+        dd -= L * np.round(dd / L)
+        if np.all(np.abs(np.linalg.norm(dd, axis=1) - cutoff) > margin):
+            out.append(i)
+    return out
+
+
+def test_p7_fd_spme():
+    d = water_box(8, 8.0, 12)
+    ok = _clear_of_cutoff(d, 3.9, 8.0)
+    assert len(ok) >= 3
+    _fd_check(d, Params(method="spme", beta=0.5, cutoff=3.9,
+                        grid=(12, 12, 12), order=5, tol=1e-12),
+              [(ok[0], 0), (ok[len(ok) // 2], 2), (ok[-1], 1)])
+
+
+# ---------------------------------------------------------------- P8
+def test_p8_variational_form():
+    s = _cluster(6, 6)
+    o = oracle.evaluate(s, Params(method="direct", tol=1e-8))
+    assert abs(o["E_pol"] - o["E_pol_var"]) <= 1e-9 * abs(o["E_pol"])
+    assert o["E_pol"] < 0
+
+
+# ---------------------------------------------------------------- P9
+def _two_site(pos, q, alpha_iso, mol):
+    n = len(pos)
+    al = np.zeros((n, 6))
+    for k, a in enumerate(alpha_iso):
+        al[k, [0, 3, 5]] = a
+    return System(pos=np.asarray(pos, float), mol=np.asarray(mol), q=np.asarray(q, float),
+                  dip=np.zeros((n, 3)), quad=np.zeros((n, 6)), alpha=al)
+
+
+def test_p9a_charge_and_polarizable_site():
+    r, qv, a = 3.1, 0.7, 1.4
+    s = _two_site([[0, 0, 0], [0, 0, r]], [qv, 0.0], [0.0, a], [0, 1])
+    o = oracle.evaluate(s, Params(method="direct", tol=1e-13))
+    assert np.allclose(o["mu"][0], [0, 0, a * qv / r ** 2], rtol=1e-12)
+    assert o["E_pol"] == pytest.approx(-0.5 * COULOMB * a * qv ** 2 / r ** 4, rel=1e-12)
+
+
+def test_p9b_applequist_axis():
+    Q, D, dd, aA, aB, ath = 0.9, 2.7, 1.6, 1.1, 0.7, 0.28
+    s = _two_site([[0, 0, -D], [0, 0, 0], [0, 0, dd]], [Q, 0, 0], [0, aA, aB], [0, 1, 1])
+    o = oracle.evaluate(s, Params(method="direct", thole_a=ath, tol=1e-13))
+    EA, EB = Q / D ** 2, Q / (D + dd) ** 2
+    x = ath * dd ** 3 / math.sqrt(aA * aB)
+    l3 = 1 - math.exp(-x)
+    l5 = 1 - (1 + x) * math.exp(-x)
+    t = (3 * l5 - l3) / dd ** 3          # zz field of a unit z dipole on axis
+    det = 1 / (aA * aB) - t * t
+    muA = (EA / aB + t * EB) / det
+    muB = (EB / aA + t * EA) / det
+    assert np.allclose(o["mu"], [[0, 0, muA], [0, 0, muB]], rtol=1e-11, atol=1e-14)
+    assert o["E_pol"] == pytest.approx(-0.5 * COULOMB * (muA * EA + muB * EB), rel=1e-11)
+
+
+def test_p9c_small_alpha_limit():
+    d = water_cluster(3, 8)
+    eps = 1e-5
+    d2 = dict(d, alpha=d["alpha"] * eps)
+    s = System.from_dict(d2)
+    p = Params(method="direct", tol=1e-14)
+    o = oracle.evaluate(s, p, forces=False)
+    E0 = o["E0"]
+    a3 = s.alpha3[s.pol]
+    first = -0.5 * COULOMB * np.einsum("na,nab,nb->", E0, a3, E0)
+    assert o["E_pol"] == pytest.approx(first, rel=1e-3)
+
+
+# ---------------------------------------------------------------- P10
+def test_p10_solvers_agree():
+    s = _cluster(5, 9)
+    p = Params(method="direct", tol=1e-12)
+    c = Context(s, p)
+    E0 = permanent_field(s, p, ctx=c)
+    mv = lambda v: apply_T(s, p, v, ctx=c)
+    pc = lambda r: oracle.model.precond(s, r)
+    mu, it, _ = oracle.pcg(mv, pc, E0, pc(E0), 1e-12)
+    assert it <= 3 * len(s.pol)
+    mu_cg, _ = oracle.plain_cg(mv, E0, np.zeros_like(E0), 1e-12)
+    mu_j, _ = oracle.jacobi(mv, pc, E0, np.zeros_like(E0), 1e-12)
+    scale = np.abs(mu).max()
+    assert np.abs(mu - mu_cg).max() < 1e-9 * scale
+    assert np.abs(mu - mu_j).max() < 1e-9 * scale
+
+
+# ---------------------------------------------------------------- P11
+def _rot(rng):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q * np.sign(np.linalg.det(q))
+
+
+def _rot6(t6, R):
+    from oracle.model import _quad_tensor
+    T = _quad_tensor(t6)
+    Tr = np.einsum("ab,nbc,dc->nad", R, T, R)
+    return np.stack([Tr[:, 0, 0], Tr[:, 0, 1], Tr[:, 0, 2], Tr[:, 1, 1],
+                     Tr[:, 1, 2], Tr[:, 2, 2]], 1)
+
+
+def test_p11_rotation_invariance():
+    d = water_cluster(4, 10)
+    R = _rot(np.random.default_rng(3))
+    dr = dict(d, pos=d["pos"] @ R.T, dip=d["dip"] @ R.T, quad=_rot6(d["quad"], R),
+              alpha=_rot6(d["alpha"], R))
+    p = Params(method="direct", tol=1e-12)
+    o1 = oracle.evaluate(System.from_dict(d), p)
+    o2 = oracle.evaluate(System.from_dict(dr), p)
+    assert o2["E_pol"] == pytest.approx(o1["E_pol"], rel=1e-10)
+    assert o2["E_elec"] == pytest.approx(o1["E_elec"], rel=1e-10)
+    assert np.allclose(o2["forces"], o1["forces"] @ R.T, atol=1e-9)
+
+
+def test_p11_translation_invariance_ewald():
+    d = water_box(8, 7.0, 13)
+    p = Params(method="ewald", beta=0.5, realspace="images", rmax=12.0, tol=1e-12)
+    o1 = oracle.evaluate(System.from_dict(d), p, forces=False)
+    o2 = oracle.evaluate(System.from_dict(dict(d, pos=d["pos"] + [1.3, -0.4, 2.2])),
+                         p, forces=False)
+    assert o2["E_pol"] == pytest.approx(o1["E_pol"], rel=1e-10)
+    assert o2["E_elec"] == pytest.approx(o1["E_elec"], rel=1e-10)
