@@ -1,0 +1,179 @@
+/*
+ * sibfa_pol.h -- C-ABI of the MI355X (gfx950) library for the SIBFA
+ * many-body polarization path under periodic boundaries (Smooth PME) and
+ * for gas-phase clusters.
+ *
+ * What it computes (Naseem-Khan et al., "Development of the Quantum Inspired
+ * SIBFA Many-Body Polarizable Force Field", technical appendix,
+ * Polarization, Eq. 17-19): given sites carrying permanent multipoles
+ * (charge q, dipole d, traceless Buckingham quadrupole Theta) and 3x3
+ * polarizability tensors alpha_i,
+ *   E      = field of the permanent multipoles at the polarizable sites,
+ *   T      = polarization matrix: alpha_i^-1 on the diagonal blocks and minus
+ *            the Thole-damped dipole field tensors off the diagonal,
+ *   mu     = solution of T mu = E (Eq. 18), by preconditioned conjugate
+ *            gradient (Computational Details),
+ *   E_pol  = -1/2 mu . E (Eq. 19),
+ *   E_elec = plain multipole-multipole electrostatic energy (Eq. 2 without
+ *            the penetration correction),
+ *   forces = -d(E_elec + E_pol)/dr at the converged mu.
+ * Periodic boxes use Ewald splitting with Smooth PME for the reciprocal
+ * part (the paper's SPME treatment of multipoles and polarization), tin-foil
+ * boundary, minimum image in real space.
+ *
+ * Conventions shared by every call:
+ *  - Units: A, e, e*A, e*A^2, A^3; energies kcal/mol (332.0637133 e^2/A);
+ *    forces kcal/mol/A; tolerances in Debye (4.803204 D per e*A).
+ *  - Array arguments are DEVICE pointers on the context's device, in the
+ *    caller's site order, row-major AoS: xyz [n][3], dipoles [n][3],
+ *    quadrupoles [n][6] ordered xx,xy,xz,yy,yz,zz, polarizabilities [n][6]
+ *    in the same order.  They are read (or written) during the call on the
+ *    context's stream and never retained: the library copies what it needs
+ *    into its own cell-sorted device buffers.  Scalars (energies, iteration
+ *    counts, residuals) are HOST pointers.
+ *  - Calls that return host scalars synchronize the context's stream;
+ *    the others only enqueue work on it.
+ *  - Exclusions: a molecule's own sites do not interact through E or
+ *    E_elec; induced dipoles of one molecule do couple (Thole-damped).
+ *  - Thole damping: lambda_3 = 1 - exp(-a u^3), u = r/(abar_i abar_j)^(1/6),
+ *    abar = trace(alpha)/3, a_ij = min(a_i, a_j); higher tensors are the
+ *    exact derivatives of the damped field.  No damping when a site is not
+ *    polarizable.
+ *  - Errors: every call returns a sibfa_status; on a negative status the
+ *    message is available from sibfa_last_error and the context stays
+ *    usable (state set by earlier successful calls is kept).
+ *  - Thread safety: one host thread per context at a time; different
+ *    contexts may be used concurrently.
+ */
+#ifndef SIBFA_POL_H
+#define SIBFA_POL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sibfa_ctx_s* sibfa_ctx;
+
+typedef enum {
+  SIBFA_OK = 0,
+  SIBFA_E_ARG = -1,           /* invalid argument (NULL, size, NaN, cutoff) */
+  SIBFA_E_STATE = -2,         /* call order violated                        */
+  SIBFA_E_NOMEM = -3,         /* device allocation failed                   */
+  SIBFA_E_NOT_SPD = -4,       /* p.Tp <= 0 met in the solver                */
+  SIBFA_E_NOT_CONVERGED = -5, /* max_iter reached above the tolerance       */
+  SIBFA_E_DEVICE = -6         /* HIP runtime error                          */
+} sibfa_status;
+
+typedef enum { SIBFA_FP64 = 0, SIBFA_MIXED = 1 } sibfa_precision;
+
+typedef struct {
+  double ewald_beta;    /* A^-1, Ewald splitting parameter (periodic only)   */
+  double cutoff;        /* A, real-space cutoff; must be < min(box)/2        */
+  int grid[3];          /* PME points per axis: even, factors 2,3,5 only     */
+  int order;            /* B-spline order: 4, 5 or 6                         */
+  double thole_a;       /* default Thole factor (0.28 in the paper's model)  */
+  double tol_debye;     /* solver tolerance: RMS of alpha*(E - T mu), Debye  */
+  int max_iter;         /* PCG iteration limit (including restarts)          */
+  sibfa_precision precision; /* FP64, or FP32 pair/PME math with FP64
+                                accumulation, reductions and residuals      */
+} sibfa_params;
+
+typedef struct {
+  int iterations;          /* PCG iterations of the last solve              */
+  int restarts;            /* true-residual restarts of the last solve      */
+  double true_rms_debye;   /* RMS of alpha*(E - T mu), recomputed in FP64    */
+  double e_pol;            /* kcal/mol, Eq. 19                               */
+  double e_pol_variational;/* kcal/mol, Eq. 17 at the returned mu            */
+  double e_elec;           /* kcal/mol                                       */
+  double e_elec_real;      /* kcal/mol, real-space pairs                     */
+  double e_elec_recip;     /* kcal/mol, reciprocal (0 for clusters)          */
+  double e_elec_self;      /* kcal/mol, Ewald self term (0 for clusters)     */
+  int n_sites, n_polarizable;
+  int max_neighbors;       /* largest real-space neighbour count of a site   */
+} sibfa_stats;
+
+typedef void* (*sibfa_alloc_fn)(size_t bytes, void* user);
+typedef void (*sibfa_free_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  alloc/free (both or neither)
+ * provide device memory, e.g. from a caching allocator; NULL = hipMalloc. */
+sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream,
+                          sibfa_alloc_fn alloc_fn, sibfa_free_fn free_fn,
+                          void* user);
+void sibfa_destroy(sibfa_ctx ctx);
+const char* sibfa_last_error(sibfa_ctx ctx);
+
+/* Fill *p with the defaults (beta 0.4, cutoff 9, grid 32^3, order 5,
+ * thole 0.28, tol 1e-8 D, 200 iterations, FP64). */
+void sibfa_default_params(sibfa_params* p);
+
+/* Device bytes a context will hold for a system of n_sites sites of which
+ * n_polarizable are polarizable (box NULL = cluster); for admission
+ * control.  Returns 0 on invalid arguments. */
+size_t sibfa_footprint_bytes(int n_sites, int n_polarizable,
+                             const double* box, const sibfa_params* p);
+
+/* Define the system: n_sites sites at xyz [n][3] (device), molecule ids
+ * mol [n] (device int32, each in [0, n)), box [3] (HOST, orthorhombic edge
+ * lengths) or NULL for a non-periodic cluster, and the parameters (HOST).
+ * Periodic systems need every molecule's sites within the cutoff of each
+ * other (checked when lists are built: SIBFA_E_ARG). */
+sibfa_status sibfa_set_system(sibfa_ctx ctx, int n_sites, const double* xyz,
+                              const int32_t* mol, const double* box,
+                              const sibfa_params* params);
+
+/* New positions for the same sites; keeps mu for a warm start. */
+sibfa_status sibfa_update_positions(sibfa_ctx ctx, const double* xyz);
+
+/* Permanent multipoles (device): q [n], dip [n][3], quad [n][6] traceless.
+ * dip or quad may be NULL (zero). */
+sibfa_status sibfa_set_multipoles(sibfa_ctx ctx, const double* q,
+                                  const double* dip, const double* quad);
+
+/* Polarizabilities alpha [n][6] (device; symmetric positive definite, or an
+ * all-zero row for a non-polarizable site) and optional per-site Thole
+ * factors thole [n] (device; NULL = params.thole_a). */
+sibfa_status sibfa_set_polarizabilities(sibfa_ctx ctx, const double* alpha,
+                                        const double* thole);
+
+/* Permanent field E (Eq. 18's right-hand side, e/A^2) at every site, [n][3]
+ * (device), zero rows at non-polarizable sites. */
+sibfa_status sibfa_permanent_field(sibfa_ctx ctx, double* field_out);
+
+/* tp_out = T p for p given on every site [n][3] (device; rows of
+ * non-polarizable sites are ignored, their output rows are zero). */
+sibfa_status sibfa_apply_T(sibfa_ctx ctx, const double* p, double* tp_out);
+
+/* Solve T mu = E by PCG (block-diagonal preconditioner alpha).
+ * warm_start: start from the dipoles kept from the previous solve (or set
+ * by sibfa_set_dipoles) instead of alpha E.  mu_out [n][3] (device) or
+ * NULL; iters and true_rms_debye (HOST) may be NULL.  Returns
+ * SIBFA_E_NOT_CONVERGED (mu still returned) or SIBFA_E_NOT_SPD. */
+sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
+                                 int* iters, double* true_rms_debye);
+
+/* Energies (HOST, kcal/mol) and forces [n][3] (device, kcal/mol/A, or
+ * NULL) at the current dipoles; solves first if they are stale.  virial
+ * must be NULL (not provided). */
+sibfa_status sibfa_energy_forces(sibfa_ctx ctx, double* e_pol, double* e_elec,
+                                 double* forces, double* virial);
+
+/* Copy out / restore the induced dipoles [n][3] (device). */
+sibfa_status sibfa_get_dipoles(sibfa_ctx ctx, double* mu);
+sibfa_status sibfa_set_dipoles(sibfa_ctx ctx, const double* mu);
+
+/* Real-space neighbour counts per site [n] (device int32): intermolecular
+ * sites within the cutoff (all sites within reach for clusters). */
+sibfa_status sibfa_neighbor_counts(sibfa_ctx ctx, int32_t* counts_out);
+
+/* Statistics of the last solve / energy evaluation (HOST). */
+sibfa_status sibfa_get_stats(sibfa_ctx ctx, sibfa_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIBFA_POL_H */

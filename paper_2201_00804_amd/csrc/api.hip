@@ -1,0 +1,986 @@
+// Host side of the C-ABI: context, device memory, preparation of the sorted
+// system and lists, PME tables, and the solver driver.
+//
+// Solver (paper: Tinker-HP's preconditioned conjugate gradient, Eq. 18):
+// block-Jacobi PCG with z = alpha r.  One iteration enqueues
+//   spread(p = z + beta p) -> 5 FFT passes (z pass fused with the
+//   influence function) -> real-space + PME-gather matvec (with p.Tp)
+//   -> update (x, r, z, r.z, z.z)
+// and reads z.z back to test  DEBYE * sqrt(z.z / N_pol) <= tol.  On exit the
+// residual is recomputed from scratch in FP64 and the iteration restarts
+// from x while that true residual is above the tolerance; in mixed mode
+// (FP32 pair and PME arithmetic inside the iteration) this is iterative
+// refinement against the FP64 operator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sibfa_pol.h"
+#include "common.h"
+#include "kernels.h"
+#include "nlist.h"
+
+using namespace sibfa;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sibfa_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  sibfa_alloc_fn af = nullptr;
+  sibfa_free_fn ff = nullptr;
+  void* user = nullptr;
+  std::string err;
+
+  sibfa_params prm{};
+  int n = 0, npol = 0, periodic = 0;
+  double box[3] = {0, 0, 0};
+  bool have_sys = false, have_mult = false, have_pol = false, has_thole = false;
+  bool dirty_sort = true, dirty_mult = true, dirty_pol = true, dirty_lists = true;
+  bool e0_valid = false, mu_valid = false, mu_have = false;
+  double e_real = 0, e_rec = 0, e_self = 0;
+  sibfa_stats stats{};
+
+  std::vector<DevBuf> bufs;   // every allocation, freed on destroy / resize
+
+  // caller-order copies
+  double *xyz_c = nullptr, *q_c = nullptr, *dip_c = nullptr, *quad_c = nullptr;
+  double *alpha_c = nullptr, *thole_c = nullptr, *mu_c = nullptr;
+  int* mol_c = nullptr;
+  // cells
+  int nc[3] = {1, 1, 1}, ncell = 1;
+  int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cursor = nullptr;
+  int *perm = nullptr, *inv_perm = nullptr, *mol_count = nullptr, *mol_s = nullptr;
+  int* scan_tmp = nullptr;
+  // records
+  double4 *sp = nullptr, *sd = nullptr, *sth = nullptr;
+  double2* sth2 = nullptr;
+  float4 *sp32 = nullptr, *sd32 = nullptr, *sth32 = nullptr;
+  float2* sth232 = nullptr;
+  double* sa = nullptr;
+  int *is_pol = nullptr, *pol_scan = nullptr, *polidx = nullptr, *polsite = nullptr;
+  // polarizable-site arrays (sized n: npol <= n)
+  double4* pp = nullptr;
+  float4* pp32 = nullptr;
+  double *pa = nullptr, *alpha_s = nullptr, *ainv_s = nullptr;
+  // lists
+  int cap[4] = {0, 0, 0, 0};
+  int* nb[4] = {nullptr, nullptr, nullptr, nullptr};
+  int* ncnt[4] = {nullptr, nullptr, nullptr, nullptr};
+  DevBuf nbbuf[4];
+  int* dints = nullptr;   // [0..3] max counts, [4] error bits, [5] npol, [6..] spare
+  // solver vectors (pol order)
+  double4 *E0 = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+          *t = nullptr;
+  float4 *p32 = nullptr, *x32 = nullptr;
+  // site vectors
+  double4 *mu_s = nullptr, *Freal = nullptr;
+  float4* mu_s32 = nullptr;
+  // PME
+  PmeView pm{};
+  std::vector<DevBuf> pmebufs;
+  // reductions
+  Reduce red{};
+  double* h_pinned = nullptr;   // host copies of the reduction scalars
+  int* h_ints = nullptr;
+};
+
+namespace {
+
+sibfa_status fail(sibfa_ctx c, sibfa_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+sibfa_status hip_fail(sibfa_ctx c, hipError_t e, const char* where) {
+  return fail(c, SIBFA_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return hip_fail(c, _e, #call); \
+  } while (0)
+
+void* dev_alloc(sibfa_ctx c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* ptr = nullptr;
+  if (c->af) ptr = c->af(bytes, c->user);
+  else if (hipMalloc(&ptr, bytes) != hipSuccess) ptr = nullptr;
+  return ptr;
+}
+
+void dev_free(sibfa_ctx c, void* ptr) {
+  if (!ptr) return;
+  if (c->ff) c->ff(ptr, c->user);
+  else (void)hipFree(ptr);
+}
+
+template <typename T>
+bool alloc_into(sibfa_ctx c, std::vector<DevBuf>& list, T*& out, size_t count) {
+  void* ptr = dev_alloc(c, count * sizeof(T));
+  if (!ptr) return false;
+  list.push_back({ptr, count * sizeof(T)});
+  out = static_cast<T*>(ptr);
+  return true;
+}
+
+void free_list(sibfa_ctx c, std::vector<DevBuf>& list) {
+  for (auto& b : list) dev_free(c, b.p);
+  list.clear();
+}
+
+bool factor_radices(int K, int* rad, int* nrad) {
+  int m = K, k = 0;
+  while (m % 4 == 0 && k < 16) { rad[k++] = 4; m /= 4; }
+  while (m % 2 == 0 && k < 16) { rad[k++] = 2; m /= 2; }
+  while (m % 3 == 0 && k < 16) { rad[k++] = 3; m /= 3; }
+  while (m % 5 == 0 && k < 16) { rad[k++] = 5; m /= 5; }
+  *nrad = k;
+  return m == 1;
+}
+
+// Cardinal B-spline values M_p(t) at the integers t = 0..p-1 (recursion
+// M_n(u) = (u M_{n-1}(u) + (n-u) M_{n-1}(u-1))/(n-1), M_1 = 1 on [0,1)).
+std::vector<long double> bspline_at_integers(int p) {
+  std::vector<long double> lev(p, 0.0L), nxt(p, 0.0L);
+  lev[0] = 1.0L;
+  for (int n = 2; n <= p; ++n) {
+    for (int t = 0; t < p; ++t) {
+      const long double u = t;
+      const long double a = (t <= n - 2) ? lev[t] : 0.0L;
+      const long double b = (t >= 1 && t - 1 <= n - 2) ? lev[t - 1] : 0.0L;
+      nxt[t] = (u * a + (n - u) * b) / (n - 1);
+    }
+    lev = nxt;
+  }
+  return lev;
+}
+
+// |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2, a vanishing value (odd
+// order, Nyquist index of an even grid) replaced by the mean of its
+// neighbours.
+std::vector<double> bspline_moduli(int K, int p) {
+  const std::vector<long double> M = bspline_at_integers(p);
+  std::vector<double> mod(K);
+  const long double twopi = 6.283185307179586476925286766559L;
+  for (int m = 0; m < K; ++m) {
+    long double re = 0, im = 0;
+    for (int k = 0; k <= p - 2; ++k) {
+      const long double ang = twopi * m * k / K;
+      re += M[k + 1] * cosl(ang);
+      im += M[k + 1] * sinl(ang);
+    }
+    mod[m] = (double)(re * re + im * im);
+  }
+  for (int m = 0; m < K; ++m)
+    if (mod[m] < 1e-7) mod[m] = 0.5 * (mod[(m - 1 + K) % K] + mod[(m + 1) % K]);
+  return mod;
+}
+
+SysView make_view(sibfa_ctx c) {
+  SysView s{};
+  s.n = c->n;
+  s.npol = c->npol;
+  s.periodic = c->periodic;
+  for (int a = 0; a < 3; ++a) {
+    s.box[a] = c->periodic ? c->box[a] : 1.0;
+    s.ibox[a] = c->periodic ? 1.0 / c->box[a] : 1.0;
+  }
+  s.cutoff2 = c->prm.cutoff * c->prm.cutoff;
+  s.beta = c->prm.ewald_beta;
+  s.uniform_thole = c->has_thole ? 0 : 1;
+  s.thole_a = c->prm.thole_a;
+  s.sp = c->sp; s.sd = c->sd; s.sth = c->sth; s.sth2 = c->sth2; s.sa = c->sa;
+  s.polidx = c->polidx;
+  s.sp32 = c->sp32; s.sd32 = c->sd32; s.sth32 = c->sth32; s.sth232 = c->sth232;
+  s.polsite = c->polsite; s.pp = c->pp; s.pp32 = c->pp32; s.pa = c->pa;
+  s.alpha = c->alpha_s; s.ainv = c->ainv_s;
+  s.nb_all = c->nb[0]; s.nc_all = c->ncnt[0]; s.cap_all = c->cap[0];
+  s.nb_in = c->nb[1]; s.nc_in = c->ncnt[1]; s.cap_in = c->cap[1];
+  s.nb_pol = c->nb[2]; s.nc_pol = c->ncnt[2]; s.cap_pol = c->cap[2];
+  s.nb_ipol = c->nb[3]; s.nc_ipol = c->ncnt[3]; s.cap_ipol = c->cap[3];
+  return s;
+}
+
+bool mixed(sibfa_ctx c) { return c->prm.precision == SIBFA_MIXED; }
+
+sibfa_status check_params(sibfa_ctx c, const sibfa_params* p, const double* box) {
+  if (!p) return fail(c, SIBFA_E_ARG, "params is NULL");
+  if (!(p->tol_debye > 0) || p->max_iter < 1)
+    return fail(c, SIBFA_E_ARG, "tol_debye must be > 0 and max_iter >= 1");
+  if (!(p->thole_a > 0) || !std::isfinite(p->thole_a))
+    return fail(c, SIBFA_E_ARG, "thole_a must be positive");
+  if (p->precision != SIBFA_FP64 && p->precision != SIBFA_MIXED)
+    return fail(c, SIBFA_E_ARG, "unknown precision");
+  if (box) {
+    for (int a = 0; a < 3; ++a)
+      if (!(box[a] > 0) || !std::isfinite(box[a])) return fail(c, SIBFA_E_ARG, "box edges must be positive");
+    if (!(p->cutoff > 0)) return fail(c, SIBFA_E_ARG, "cutoff must be positive");
+    if (!(p->cutoff < 0.5 * std::min(box[0], std::min(box[1], box[2]))))
+      return fail(c, SIBFA_E_ARG, "cutoff must be below half the smallest box edge");
+    if (!(p->ewald_beta > 0)) return fail(c, SIBFA_E_ARG, "ewald_beta must be positive");
+    if (p->order < 4 || p->order > 6) return fail(c, SIBFA_E_ARG, "order must be 4, 5 or 6");
+    for (int a = 0; a < 3; ++a) {
+      int rad[16], nr;
+      if (p->grid[a] < 2 * p->order || p->grid[a] % 2 != 0 || !factor_radices(p->grid[a], rad, &nr))
+        return fail(c, SIBFA_E_ARG, "grid sizes must be even, >= 2*order, with factors 2, 3, 5 only");
+      if (p->grid[a] > 1024) return fail(c, SIBFA_E_ARG, "grid sizes above 1024 are not supported");
+    }
+  }
+  return SIBFA_OK;
+}
+
+void release_system(sibfa_ctx c) {
+  free_list(c, c->bufs);
+  free_list(c, c->pmebufs);
+  for (int k = 0; k < 4; ++k) {
+    dev_free(c, c->nbbuf[k].p);
+    c->nbbuf[k] = DevBuf{};
+    c->nb[k] = nullptr;
+    c->cap[k] = 0;
+  }
+  c->have_sys = c->have_mult = c->have_pol = false;
+  c->e0_valid = c->mu_valid = c->mu_have = false;
+}
+
+sibfa_status sync_read(sibfa_ctx c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return SIBFA_OK;
+}
+
+sibfa_status read_scalars(sibfa_ctx c, int first, int count) {
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + first, c->red.scalars + first, count * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  return sync_read(c);
+}
+
+// ------------------------------------------------------------ preparation
+sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
+  for (int k = 0; k < 4; ++k) {
+    const int rows = (k < 2) ? c->n : std::max(c->npol, 1);
+    if (c->nb[k] && c->cap[k] >= want[k]) continue;
+    dev_free(c, c->nbbuf[k].p);
+    const size_t bytes = (size_t)rows * want[k] * sizeof(int);
+    void* ptr = dev_alloc(c, bytes);
+    if (!ptr) { c->nbbuf[k] = DevBuf{}; c->nb[k] = nullptr; c->cap[k] = 0;
+                return fail(c, SIBFA_E_NOMEM, "neighbour list allocation failed"); }
+    c->nbbuf[k] = {ptr, bytes};
+    c->nb[k] = static_cast<int*>(ptr);
+    c->cap[k] = want[k];
+  }
+  return SIBFA_OK;
+}
+
+sibfa_status build_lists(sibfa_ctx c) {
+  int want[4];
+  if (c->periodic) {
+    const double V = c->box[0] * c->box[1] * c->box[2];
+    const double sph = 4.0 / 3.0 * kPi * std::pow(c->prm.cutoff, 3);
+    const double e_all = c->n / V * sph, e_pol = c->npol / V * sph;
+    want[0] = std::min(c->n, (int)(1.3 * e_all) + 64);
+    want[2] = std::min(std::max(c->npol, 1), (int)(1.3 * e_pol) + 64);
+  } else {
+    want[0] = std::max(c->n, 1);
+    want[2] = std::max(c->npol, 1);
+  }
+  want[1] = std::max(c->cap[1], 8);
+  want[3] = std::max(c->cap[3], 8);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    for (int k = 0; k < 4; ++k) want[k] = std::max(want[k], c->cap[k]);
+    sibfa_status st = alloc_lists(c, want);
+    if (st != SIBFA_OK) return st;
+    launch_fill_int(c->dints, 0, 8, c->stream);
+    NlistArgs a{};
+    a.periodic = c->periodic;
+    for (int d = 0; d < 3; ++d) {
+      a.nc[d] = c->nc[d];
+      a.box[d] = c->periodic ? c->box[d] : 1.0;
+      a.ibox[d] = c->periodic ? 1.0 / c->box[d] : 1.0;
+    }
+    a.cutoff2 = c->periodic ? c->prm.cutoff * c->prm.cutoff : INFINITY;
+    a.cell_start = c->cell_start;
+    a.sp = c->sp;
+    a.mol_s = c->mol_s;
+    a.polidx = c->polidx;
+    a.mol_count = c->mol_count;
+    a.nb_all = c->nb[0]; a.nc_all = c->ncnt[0]; a.cap_all = c->cap[0];
+    a.nb_in = c->nb[1]; a.nc_in = c->ncnt[1]; a.cap_in = c->cap[1];
+    a.nb_pol = c->nb[2]; a.nc_pol = c->ncnt[2]; a.cap_pol = c->cap[2];
+    a.nb_ipol = c->nb[3]; a.nc_ipol = c->ncnt[3]; a.cap_ipol = c->cap[3];
+    a.maxcnt = c->dints;
+    a.err = c->dints + 4;
+    launch_nlist(a, c->ncell, c->stream);
+    HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    sibfa_status s2 = sync_read(c);
+    if (s2 != SIBFA_OK) return s2;
+    if (c->h_ints[4] & 1)
+      return fail(c, SIBFA_E_ARG,
+                  "the sites of a molecule must lie within the cutoff of each other");
+    bool over = false;
+    for (int k = 0; k < 4; ++k)
+      if (c->h_ints[k] > c->cap[k]) { over = true; want[k] = c->h_ints[k] + 16; }
+    c->stats.max_neighbors = c->h_ints[0];
+    if (!over) return SIBFA_OK;
+  }
+  return fail(c, SIBFA_E_NOMEM, "neighbour lists kept overflowing");
+}
+
+sibfa_status prepare(sibfa_ctx c) {
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!c->have_mult) return fail(c, SIBFA_E_STATE, "sibfa_set_multipoles has not been called");
+  if (!c->have_pol) return fail(c, SIBFA_E_STATE, "sibfa_set_polarizabilities has not been called");
+  hipStream_t s = c->stream;
+  RecArgs ra{};
+  ra.n = c->n;
+  ra.periodic = c->periodic;
+  for (int a = 0; a < 3; ++a) {
+    ra.box[a] = c->periodic ? c->box[a] : 1.0;
+    ra.ibox[a] = c->periodic ? 1.0 / c->box[a] : 1.0;
+  }
+  ra.perm = c->perm;
+  ra.xyz = c->xyz_c; ra.mol = c->mol_c; ra.q = c->q_c; ra.dip = c->dip_c; ra.quad = c->quad_c;
+  ra.alpha = c->alpha_c; ra.thole = c->has_thole ? c->thole_c : nullptr;
+  ra.thole_default = c->prm.thole_a;
+  ra.sp = c->sp; ra.sd = c->sd; ra.sth = c->sth; ra.sth2 = c->sth2;
+  ra.sp32 = c->sp32; ra.sd32 = c->sd32; ra.sth32 = c->sth32; ra.sth232 = c->sth232;
+  ra.sa = c->sa; ra.mol_s = c->mol_s; ra.inv_perm = c->inv_perm; ra.is_pol = c->is_pol;
+  ra.pol_scan = c->pol_scan; ra.polidx = c->polidx; ra.polsite = c->polsite;
+  ra.pp = c->pp; ra.pp32 = c->pp32; ra.pa = c->pa; ra.alpha_s = c->alpha_s; ra.ainv_s = c->ainv_s;
+  ra.err = c->dints + 4;
+
+  if (c->dirty_sort) {
+    launch_fill_int(c->cell_count, 0, c->ncell + 1, s);
+    launch_fill_int(c->cursor, 0, c->ncell, s);
+    launch_fill_int(c->mol_count, 0, c->n, s);
+    launch_fill_int(c->dints, 0, 8, s);
+    BinArgs b{};
+    b.n = c->n;
+    b.periodic = c->periodic;
+    for (int a = 0; a < 3; ++a) {
+      b.nc[a] = c->nc[a];
+      b.box[a] = ra.box[a];
+      b.ibox[a] = ra.ibox[a];
+    }
+    b.xyz = c->xyz_c; b.mol = c->mol_c; b.cell_of = c->cell_of; b.cell_count = c->cell_count;
+    b.mol_count = c->mol_count; b.err = c->dints + 4;
+    launch_bin(b, s);
+    launch_exclusive_scan(c->cell_count, c->cell_start, c->ncell + 1, c->scan_tmp, s);
+    launch_scatter(c->cell_of, c->cell_start, c->cursor, c->perm, c->n, s);
+    launch_sort_cells(c->cell_start, c->ncell, c->perm, s);
+    launch_rec_pos(ra, s);
+    HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    sibfa_status st = sync_read(c);
+    if (st != SIBFA_OK) return st;
+    if (c->h_ints[4] & 2) return fail(c, SIBFA_E_ARG, "molecule ids must lie in [0, n_sites)");
+    c->dirty_sort = false;
+    c->dirty_mult = c->dirty_pol = c->dirty_lists = true;
+    c->e0_valid = false;
+  }
+  if (c->dirty_mult) {
+    launch_rec_mult(ra, s);
+    c->dirty_mult = false;
+    c->e0_valid = false;
+  }
+  if (c->dirty_pol) {
+    launch_fill_int(c->dints, 0, 8, s);
+    launch_rec_pol(ra, s);
+    launch_exclusive_scan(c->is_pol, c->pol_scan, c->n + 1, c->scan_tmp, s);
+    launch_rec_polsites(ra, s);
+    HIP_TRY(hipMemcpyAsync(c->h_ints, c->pol_scan + c->n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->h_ints + 4, c->dints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+    sibfa_status st = sync_read(c);
+    if (st != SIBFA_OK) return st;
+    if (c->h_ints[4] & 4)
+      return fail(c, SIBFA_E_ARG, "every nonzero polarizability must be positive definite");
+    c->npol = c->h_ints[0];
+    c->stats.n_polarizable = c->npol;
+    c->dirty_pol = false;
+    c->dirty_lists = true;
+    c->e0_valid = false;
+  }
+  if (c->dirty_lists) {
+    sibfa_status st = build_lists(c);
+    if (st != SIBFA_OK) return st;
+    c->dirty_lists = false;
+    c->e0_valid = false;
+  }
+  return SIBFA_OK;
+}
+
+// ------------------------------------------------------------ compute steps
+void conv(sibfa_ctx c, bool mix) { launch_convolution(c->pm, c->red, mix, c->stream); }
+
+// t = T v (v in pol order, double + float copy)
+void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
+  SysView s = make_view(c);
+  if (c->periodic) {
+    DirUpdate du{};
+    du.upd = 0;
+    du.p = v;
+    du.p32 = v32;
+    launch_spread_dip(s, c->pm, c->red, du, mix, c->stream);
+    conv(c, mix);
+  }
+  launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, c->stream);
+}
+
+sibfa_status compute_E0(sibfa_ctx c) {
+  SysView s = make_view(c);
+  const bool mix = mixed(c);
+  launch_perm(s, c->red, c->E0, mix, c->stream);
+  if (c->periodic) {
+    launch_spread_mult(s, c->pm, nullptr, mix, c->stream);
+    conv(c, mix);
+    launch_gather_field(s, c->pm, c->E0, mix, c->stream);
+  }
+  sibfa_status st = read_scalars(c, 0, S_COUNT);
+  if (st != SIBFA_OK) return st;
+  c->e_real = c->h_pinned[S_EREAL];
+  c->e_self = c->periodic ? c->h_pinned[S_ESELF] : 0.0;
+  c->e_rec = c->periodic ? c->h_pinned[S_EREC] : 0.0;
+  c->e0_valid = true;
+  return SIBFA_OK;
+}
+
+double rms_debye(sibfa_ctx c, double zz) {
+  return c->npol > 0 ? kDebye * std::sqrt(zz / c->npol) : 0.0;
+}
+
+sibfa_status solve(sibfa_ctx c, bool warm) {
+  SysView s = make_view(c);
+  hipStream_t st = c->stream;
+  const bool mix = mixed(c);
+  if (c->npol == 0) {
+    c->stats.iterations = 0;
+    c->stats.restarts = 0;
+    c->stats.true_rms_debye = 0.0;
+    c->mu_valid = c->mu_have = true;
+    launch_fill_double(c->mu_c, 0.0, 3 * (size_t)c->n, st);
+    return SIBFA_OK;
+  }
+  if (warm && c->mu_have) launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
+  else launch_precond(s, c->E0, c->x, st);
+  launch_copy4(c->x, c->x, c->x32, c->npol, st);
+  const double tol = c->prm.tol_debye;
+  int it = 0, restarts = 0;
+  double rho_true = 0.0;
+  sibfa_status result = SIBFA_OK;
+  for (;;) {
+    // residual from scratch (FP64 operator)
+    matvec(c, c->x, c->x32, c->t, -1, false);
+    launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
+    sibfa_status e = read_scalars(c, S_ZZ, 1);
+    if (e != SIBFA_OK) return e;
+    rho_true = rms_debye(c, c->h_pinned[S_ZZ]);
+    if (rho_true <= tol) break;
+    if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
+    if (it > 0) ++restarts;
+    int k = 0;
+    for (;;) {
+      if (k > 0) {
+        DirUpdate du{};
+        du.upd = 1;
+        du.num = S_RZ0 + (k & 1);
+        du.den = S_RZ0 + ((k - 1) & 1);
+        du.z = c->z;
+        du.p = c->p;
+        du.p32 = c->p32;
+        if (c->periodic) {
+          launch_spread_dip(s, c->pm, c->red, du, mix, st);
+          conv(c, mix);
+        } else {
+          launch_direction(s, c->red, du.num, du.den, c->z, c->p, c->p32, st);
+        }
+      } else if (c->periodic) {
+        DirUpdate du{};
+        du.upd = 0;
+        du.p = c->p;
+        du.p32 = c->p32;
+        launch_spread_dip(s, c->pm, c->red, du, mix, st);
+        conv(c, mix);
+      }
+      launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
+      launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
+                    c->q, st);
+      ++k;
+      ++it;
+      HIP_TRY(hipMemcpyAsync(c->h_pinned + S_PQ, c->red.scalars + S_PQ, 7 * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+      e = sync_read(c);
+      if (e != SIBFA_OK) return e;
+      if (!(c->h_pinned[S_PQ] > 0.0)) {
+        result = SIBFA_E_NOT_SPD;
+        break;
+      }
+      const double rho = rms_debye(c, c->h_pinned[S_ZZ]);
+      if (rho <= tol || it >= c->prm.max_iter) break;
+    }
+    if (result == SIBFA_E_NOT_SPD) break;
+    launch_copy4(c->x, c->x, c->x32, c->npol, st);
+  }
+  c->stats.iterations = it;
+  c->stats.restarts = restarts;
+  c->stats.true_rms_debye = rho_true;
+  launch_pol_to_caller(s, c->perm, c->x, c->mu_c, st);
+  c->mu_have = true;
+  c->mu_valid = (result == SIBFA_OK);
+  if (result == SIBFA_E_NOT_SPD)
+    return fail(c, result, "p.Tp <= 0: the polarization matrix is not positive definite");
+  if (result == SIBFA_E_NOT_CONVERGED)
+    return fail(c, result, "solver did not reach the tolerance within max_iter");
+  return SIBFA_OK;
+}
+
+sibfa_status setup_pme(sibfa_ctx c) {
+  free_list(c, c->pmebufs);
+  PmeView& pm = c->pm;
+  pm = PmeView{};
+  if (!c->periodic) {
+    pm.order = 5;
+    return SIBFA_OK;
+  }
+  const int order = c->prm.order;
+  pm.order = order;
+  for (int a = 0; a < 3; ++a) {
+    pm.K[a] = c->prm.grid[a];
+    pm.scale[a] = pm.K[a] / c->box[a];
+    factor_radices(pm.K[a], pm.rad[a], &pm.nrad[a]);
+  }
+  pm.kxh = pm.K[0] / 2 + 1;
+  const size_t nr = (size_t)pm.K[0] * pm.K[1] * pm.K[2];
+  const size_t nh = (size_t)pm.kxh * pm.K[1] * pm.K[2];
+  double *Q, *phi, *G;
+  double2* C;
+  float *Q32, *phi32, *G32;
+  float2* C32;
+  if (!alloc_into(c, c->pmebufs, Q, nr) || !alloc_into(c, c->pmebufs, phi, nr) ||
+      !alloc_into(c, c->pmebufs, C, nh) || !alloc_into(c, c->pmebufs, G, nh) ||
+      !alloc_into(c, c->pmebufs, Q32, nr) || !alloc_into(c, c->pmebufs, phi32, nr) ||
+      !alloc_into(c, c->pmebufs, C32, nh) || !alloc_into(c, c->pmebufs, G32, nh))
+    return fail(c, SIBFA_E_NOMEM, "PME grid allocation failed");
+  pm.Q = Q; pm.phi = phi; pm.C = C; pm.G = G;
+  pm.Q32 = Q32; pm.phi32 = phi32; pm.C32 = C32; pm.G32 = G32;
+  launch_fill_double(Q, 0.0, nr, c->stream);
+  launch_fill_float(Q32, 0.f, nr, c->stream);
+  // twiddles
+  const long double twopi = 6.283185307179586476925286766559L;
+  for (int a = 0; a < 3; ++a) {
+    const int K = pm.K[a];
+    std::vector<double2> tw(K);
+    std::vector<float2> tw32(K);
+    for (int k = 0; k < K; ++k) {
+      const long double ang = -twopi * k / K;
+      tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+      tw32[k] = make_float2((float)cosl(ang), (float)sinl(ang));
+    }
+    double2* d;
+    float2* f;
+    if (!alloc_into(c, c->pmebufs, d, K) || !alloc_into(c, c->pmebufs, f, K))
+      return fail(c, SIBFA_E_NOMEM, "PME table allocation failed");
+    HIP_TRY(hipMemcpy(d, tw.data(), K * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f, tw32.data(), K * sizeof(float2), hipMemcpyHostToDevice));
+    pm.tw[a] = d;
+    pm.tw32[a] = f;
+  }
+  // influence function G(m) = B(m) C(m) on the half spectrum
+  std::vector<double> mod[3];
+  for (int a = 0; a < 3; ++a) mod[a] = bspline_moduli(pm.K[a], order);
+  const double V = c->box[0] * c->box[1] * c->box[2];
+  const double beta = c->prm.ewald_beta;
+  std::vector<double> g(nh);
+  std::vector<float> g32(nh);
+  for (int kz = 0; kz < pm.K[2]; ++kz) {
+    const int mz = kz <= pm.K[2] / 2 ? kz : kz - pm.K[2];
+    for (int ky = 0; ky < pm.K[1]; ++ky) {
+      const int my = ky <= pm.K[1] / 2 ? ky : ky - pm.K[1];
+      for (int kx = 0; kx < pm.kxh; ++kx) {
+        const double fx = kx / c->box[0], fy = my / c->box[1], fz = mz / c->box[2];
+        const double m2 = fx * fx + fy * fy + fz * fz;
+        double val = 0.0;
+        if (kx != 0 || my != 0 || mz != 0) {
+          val = std::exp(-kPi * kPi * m2 / (beta * beta)) / (kPi * V * m2);
+          val /= mod[0][kx] * mod[1][ky] * mod[2][kz];
+        }
+        const size_t idx = ((size_t)kz * pm.K[1] + ky) * pm.kxh + kx;
+        g[idx] = val;
+        g32[idx] = (float)val;
+      }
+    }
+  }
+  HIP_TRY(hipMemcpy(G, g.data(), nh * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(G32, g32.data(), nh * sizeof(float), hipMemcpyHostToDevice));
+  return SIBFA_OK;
+}
+
+sibfa_status finite_check(sibfa_ctx c, const double* dev, size_t count, const char* what) {
+  // a NaN/Inf anywhere makes the sum non-finite; checked on a host copy
+  std::vector<double> h(count);
+  HIP_TRY(hipMemcpyAsync(h.data(), dev, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sibfa_status st = sync_read(c);
+  if (st != SIBFA_OK) return st;
+  for (double v : h)
+    if (!std::isfinite(v)) return fail(c, SIBFA_E_ARG, std::string(what) + " contains NaN or Inf");
+  return SIBFA_OK;
+}
+
+}  // namespace
+
+// ============================================================ C-ABI
+extern "C" {
+
+void sibfa_default_params(sibfa_params* p) {
+  if (!p) return;
+  p->ewald_beta = 0.4;
+  p->cutoff = 9.0;
+  p->grid[0] = p->grid[1] = p->grid[2] = 32;
+  p->order = 5;
+  p->thole_a = 0.28;
+  p->tol_debye = 1e-8;
+  p->max_iter = 200;
+  p->precision = SIBFA_FP64;
+}
+
+sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream, sibfa_alloc_fn alloc_fn,
+                          sibfa_free_fn free_fn, void* user) {
+  if (!out) return SIBFA_E_ARG;
+  *out = nullptr;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return SIBFA_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIBFA_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return SIBFA_E_DEVICE;
+  sibfa_ctx c = new sibfa_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->af = alloc_fn;
+  c->ff = free_fn;
+  c->user = user;
+  sibfa_default_params(&c->prm);
+  if (hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ints, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return SIBFA_E_NOMEM;
+  }
+  *out = c;
+  return SIBFA_OK;
+}
+
+void sibfa_destroy(sibfa_ctx c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  release_system(c);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->h_ints) (void)hipHostFree(c->h_ints);
+  delete c;
+}
+
+const char* sibfa_last_error(sibfa_ctx c) { return c ? c->err.c_str() : "NULL context"; }
+
+size_t sibfa_footprint_bytes(int n_sites, int n_polarizable, const double* box,
+                             const sibfa_params* p) {
+  if (n_sites <= 0 || n_polarizable < 0 || n_polarizable > n_sites || !p) return 0;
+  const size_t n = n_sites, np = std::max(n_polarizable, 1);
+  size_t bytes = 0;
+  bytes += n * (3 + 1 + 3 + 6 + 6 + 1 + 3) * sizeof(double);        // caller copies
+  bytes += n * (4 + 4 + 4 + 2) * sizeof(double) + n * (4 + 4 + 4 + 2) * sizeof(float);
+  bytes += n * 12 * sizeof(int) + n * (1 + 6 + 6) * sizeof(double) + n * 24;  // pol arrays
+  bytes += n * (2 * 32 + 16);                                         // mu_s, Freal
+  bytes += np * (7 * 32 + 2 * 16);                                    // solver vectors
+  size_t cap_all, cap_pol;
+  if (box) {
+    const double V = box[0] * box[1] * box[2];
+    const double sph = 4.0 / 3.0 * kPi * std::pow(p->cutoff, 3);
+    cap_all = std::min(n, (size_t)(1.3 * n / V * sph) + 64);
+    cap_pol = std::min(np, (size_t)(1.3 * np / V * sph) + 64);
+    const size_t nr = (size_t)p->grid[0] * p->grid[1] * p->grid[2];
+    const size_t nh = (size_t)(p->grid[0] / 2 + 1) * p->grid[1] * p->grid[2];
+    bytes += nr * 2 * (8 + 4) + nh * (16 + 8 + 8 + 4);
+  } else {
+    cap_all = n;
+    cap_pol = np;
+  }
+  bytes += (n * (cap_all + 8) + np * (cap_pol + 8)) * sizeof(int);
+  bytes += 4 * n * sizeof(int);
+  return bytes + (1 << 20);
+}
+
+sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const int32_t* mol,
+                              const double* box, const sibfa_params* params) {
+  if (!c) return SIBFA_E_ARG;
+  if (n_sites <= 0 || !xyz || !mol) return fail(c, SIBFA_E_ARG, "n_sites > 0, xyz and mol required");
+  sibfa_status st = check_params(c, params, box);
+  if (st != SIBFA_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  release_system(c);
+  c->prm = *params;
+  c->n = n_sites;
+  c->npol = 0;
+  c->periodic = box ? 1 : 0;
+  for (int a = 0; a < 3; ++a) c->box[a] = box ? box[a] : 0.0;
+  c->stats = sibfa_stats{};
+  c->stats.n_sites = n_sites;
+  // cell grid: edge >= cutoff/2 (periodic); one cell for clusters
+  if (c->periodic) {
+    for (int a = 0; a < 3; ++a)
+      c->nc[a] = std::max(1, std::min(1024, (int)std::floor(c->box[a] / (0.5 * c->prm.cutoff))));
+  } else {
+    c->nc[0] = c->nc[1] = c->nc[2] = 1;
+  }
+  c->ncell = c->nc[0] * c->nc[1] * c->nc[2];
+  const size_t n = n_sites;
+  auto& L = c->bufs;
+  bool ok = alloc_into(c, L, c->xyz_c, 3 * n) && alloc_into(c, L, c->q_c, n) &&
+            alloc_into(c, L, c->dip_c, 3 * n) && alloc_into(c, L, c->quad_c, 6 * n) &&
+            alloc_into(c, L, c->alpha_c, 6 * n) && alloc_into(c, L, c->thole_c, n) &&
+            alloc_into(c, L, c->mu_c, 3 * n) && alloc_into(c, L, c->mol_c, n) &&
+            alloc_into(c, L, c->cell_of, n) && alloc_into(c, L, c->cell_count, c->ncell + 1) &&
+            alloc_into(c, L, c->cell_start, c->ncell + 1) && alloc_into(c, L, c->cursor, c->ncell) &&
+            alloc_into(c, L, c->perm, n) && alloc_into(c, L, c->inv_perm, n) &&
+            alloc_into(c, L, c->mol_count, n) && alloc_into(c, L, c->mol_s, n) &&
+            alloc_into(c, L, c->scan_tmp, scan_temp_ints((int)std::max<size_t>(n + 1, c->ncell + 1)) + 16) &&
+            alloc_into(c, L, c->sp, n) && alloc_into(c, L, c->sd, n) && alloc_into(c, L, c->sth, n) &&
+            alloc_into(c, L, c->sth2, n) && alloc_into(c, L, c->sp32, n) &&
+            alloc_into(c, L, c->sd32, n) && alloc_into(c, L, c->sth32, n) &&
+            alloc_into(c, L, c->sth232, n) && alloc_into(c, L, c->sa, n) &&
+            alloc_into(c, L, c->is_pol, n + 1) && alloc_into(c, L, c->pol_scan, n + 1) &&
+            alloc_into(c, L, c->polidx, n) && alloc_into(c, L, c->polsite, n) &&
+            alloc_into(c, L, c->pp, n) && alloc_into(c, L, c->pp32, n) && alloc_into(c, L, c->pa, n) &&
+            alloc_into(c, L, c->alpha_s, 6 * n) && alloc_into(c, L, c->ainv_s, 6 * n) &&
+            alloc_into(c, L, c->dints, 16) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
+            alloc_into(c, L, c->r, n) && alloc_into(c, L, c->z, n) && alloc_into(c, L, c->p, n) &&
+            alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
+            alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->mu_s, n) &&
+            alloc_into(c, L, c->mu_s32, n) && alloc_into(c, L, c->Freal, n);
+  for (int k = 0; k < 4 && ok; ++k) ok = alloc_into(c, L, c->ncnt[k], n);
+  const int max_blocks = (int)(n / 4 + 8192);
+  double* partials;
+  unsigned* counters;
+  double* scalars;
+  ok = ok && alloc_into(c, L, partials, (size_t)S_COUNT * max_blocks) &&
+       alloc_into(c, L, counters, S_COUNT) && alloc_into(c, L, scalars, 64);
+  if (!ok) {
+    release_system(c);
+    return fail(c, SIBFA_E_NOMEM, "device allocation failed");
+  }
+  c->red.partials = partials;
+  c->red.counters = counters;
+  c->red.scalars = scalars;
+  c->red.max_blocks = max_blocks;
+  launch_fill_int(reinterpret_cast<int*>(counters), 0, S_COUNT, c->stream);
+  launch_fill_double(scalars, 0.0, 64, c->stream);
+  launch_fill_int(c->is_pol + n, 0, 1, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->xyz_c, xyz, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->mol_c, mol, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+  st = finite_check(c, c->xyz_c, 3 * n, "xyz");
+  if (st != SIBFA_OK) { release_system(c); return st; }
+  st = setup_pme(c);
+  if (st != SIBFA_OK) { release_system(c); return st; }
+  c->have_sys = true;
+  c->dirty_sort = true;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_update_positions(sibfa_ctx c, const double* xyz) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!xyz) return fail(c, SIBFA_E_ARG, "xyz is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(c->xyz_c, xyz, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                         c->stream));
+  sibfa_status st = finite_check(c, c->xyz_c, 3 * (size_t)c->n, "xyz");
+  if (st != SIBFA_OK) return st;
+  c->dirty_sort = true;
+  c->e0_valid = false;
+  c->mu_valid = false;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_set_multipoles(sibfa_ctx c, const double* q, const double* dip, const double* quad) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!q) return fail(c, SIBFA_E_ARG, "q is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t n = c->n;
+  hipStream_t s = c->stream;
+  HIP_TRY(hipMemcpyAsync(c->q_c, q, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (dip) HIP_TRY(hipMemcpyAsync(c->dip_c, dip, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else launch_fill_double(c->dip_c, 0.0, 3 * n, s);
+  if (quad) HIP_TRY(hipMemcpyAsync(c->quad_c, quad, 6 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else launch_fill_double(c->quad_c, 0.0, 6 * n, s);
+  sibfa_status st = finite_check(c, c->q_c, n, "q");
+  if (st == SIBFA_OK) st = finite_check(c, c->dip_c, 3 * n, "dip");
+  if (st == SIBFA_OK) st = finite_check(c, c->quad_c, 6 * n, "quad");
+  if (st != SIBFA_OK) return st;
+  c->have_mult = true;
+  c->dirty_mult = true;
+  c->e0_valid = false;
+  c->mu_valid = false;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_set_polarizabilities(sibfa_ctx c, const double* alpha, const double* thole) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!alpha) return fail(c, SIBFA_E_ARG, "alpha is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t n = c->n;
+  HIP_TRY(hipMemcpyAsync(c->alpha_c, alpha, 6 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->has_thole = thole != nullptr;
+  if (thole) HIP_TRY(hipMemcpyAsync(c->thole_c, thole, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  sibfa_status st = finite_check(c, c->alpha_c, 6 * n, "alpha");
+  if (st == SIBFA_OK && thole) st = finite_check(c, c->thole_c, n, "thole");
+  if (st != SIBFA_OK) return st;
+  c->have_pol = true;
+  c->dirty_pol = true;
+  c->e0_valid = false;
+  c->mu_valid = false;
+  c->mu_have = false;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_permanent_field(sibfa_ctx c, double* field_out) {
+  if (!c) return SIBFA_E_ARG;
+  if (!field_out) return fail(c, SIBFA_E_ARG, "field_out is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
+  launch_pol_to_caller(make_view(c), c->perm, c->E0, field_out, c->stream);
+  return sync_read(c);
+}
+
+sibfa_status sibfa_apply_T(sibfa_ctx c, const double* pin, double* tp_out) {
+  if (!c) return SIBFA_E_ARG;
+  if (!pin || !tp_out) return fail(c, SIBFA_E_ARG, "p and tp_out are required");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  SysView s = make_view(c);
+  launch_caller_to_pol(s, c->perm, pin, c->q, c->p32, c->stream);
+  matvec(c, c->q, c->p32, c->t, -1, mixed(c));
+  launch_pol_to_caller(s, c->perm, c->t, tp_out, c->stream);
+  return sync_read(c);
+}
+
+sibfa_status sibfa_solve_induced(sibfa_ctx c, int warm_start, double* mu_out, int* iters,
+                                 double* true_rms_debye) {
+  if (!c) return SIBFA_E_ARG;
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
+  st = solve(c, warm_start != 0);
+  if (mu_out && c->mu_have)
+    (void)hipMemcpyAsync(mu_out, c->mu_c, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                         c->stream);
+  if (iters) *iters = c->stats.iterations;
+  if (true_rms_debye) *true_rms_debye = c->stats.true_rms_debye;
+  sibfa_status s2 = sync_read(c);
+  return st != SIBFA_OK ? st : s2;
+}
+
+sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, double* forces,
+                                 double* virial) {
+  if (!c) return SIBFA_E_ARG;
+  if (virial) return fail(c, SIBFA_E_ARG, "the virial is not provided; pass NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
+  if (!c->mu_valid && (st = solve(c, c->mu_have)) != SIBFA_OK) return st;
+  SysView s = make_view(c);
+  hipStream_t sm = c->stream;
+  const bool mix = mixed(c);
+  if (c->npol > 0) {
+    launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, sm);
+    launch_dot(s, c->red, c->x, c->E0, S_MUE, sm);
+    matvec(c, c->x, c->x32, c->t, -1, false);
+    launch_dot(s, c->red, c->x, c->t, S_MUTMU, sm);
+  } else {
+    launch_fill_double(c->red.scalars + S_MUE, 0.0, 2, sm);
+    launch_fill_double(reinterpret_cast<double*>(c->x), 0.0, 4, sm);
+  }
+  if (forces) {
+    launch_mu_sites(s, c->x, c->mu_s, c->mu_s32, sm);
+    launch_force(s, c->mu_s, c->mu_s32, c->Freal, mix, sm);
+    if (c->periodic) {
+      launch_spread_mult(s, c->pm, c->mu_s, mix, sm);
+      conv(c, mix);
+      launch_gather_force(s, c->pm, c->mu_s, c->Freal, c->perm, forces, mix, sm);
+    } else {
+      launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
+    }
+  }
+  st = read_scalars(c, 0, S_COUNT);
+  if (st != SIBFA_OK) return st;
+  const double mue = c->h_pinned[S_MUE], mutmu = c->h_pinned[S_MUTMU];
+  c->stats.e_pol = -0.5 * kCoulomb * mue;
+  c->stats.e_pol_variational = kCoulomb * (0.5 * mutmu - mue);
+  c->stats.e_elec_real = kCoulomb * c->e_real;
+  c->stats.e_elec_recip = kCoulomb * c->e_rec;
+  c->stats.e_elec_self = kCoulomb * c->e_self;
+  c->stats.e_elec = c->stats.e_elec_real + c->stats.e_elec_recip + c->stats.e_elec_self;
+  if (e_pol) *e_pol = c->stats.e_pol;
+  if (e_elec) *e_elec = c->stats.e_elec;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_get_dipoles(sibfa_ctx c, double* mu) {
+  if (!c) return SIBFA_E_ARG;
+  if (!mu) return fail(c, SIBFA_E_ARG, "mu is NULL");
+  if (!c->mu_have) return fail(c, SIBFA_E_STATE, "no induced dipoles yet");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(mu, c->mu_c, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                         c->stream));
+  return sync_read(c);
+}
+
+sibfa_status sibfa_set_dipoles(sibfa_ctx c, const double* mu) {
+  if (!c) return SIBFA_E_ARG;
+  if (!mu) return fail(c, SIBFA_E_ARG, "mu is NULL");
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(c->mu_c, mu, 3 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                         c->stream));
+  sibfa_status st = finite_check(c, c->mu_c, 3 * (size_t)c->n, "mu");
+  if (st != SIBFA_OK) return st;
+  c->mu_have = true;
+  c->mu_valid = false;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_neighbor_counts(sibfa_ctx c, int32_t* counts_out) {
+  if (!c) return SIBFA_E_ARG;
+  if (!counts_out) return fail(c, SIBFA_E_ARG, "counts_out is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  launch_counts_out(c->n, c->perm, c->ncnt[0], counts_out, c->stream);
+  return sync_read(c);
+}
+
+sibfa_status sibfa_get_stats(sibfa_ctx c, sibfa_stats* out) {
+  if (!c || !out) return SIBFA_E_ARG;
+  *out = c->stats;
+  return SIBFA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+// Internal declarations shared by the library's translation units: device
+// views of the cell-sorted system, small device helpers (wave and block
+// reductions, minimum image, B-spline weights) and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sibfa {
+
+constexpr double kCoulomb = 332.0637133;   // kcal*A/(mol*e^2)
+constexpr double kDebye = 4.803204;        // D per e*A
+constexpr double kSqrtPi = 1.7724538509055160273;
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kBlock = 256;      // threads per block for site-parallel kernels
+constexpr int kMaxOrder = 6;     // largest B-spline order supported
+
+// Reduction slots (each has partials, a completion counter and a scalar).
+enum Slot {
+  S_EREAL = 0,   // real-space MM energy (e^2/A, times 1/2 applied)
+  S_ESELF,       // Ewald self energy
+  S_EREC,        // reciprocal energy of the last convolution
+  S_PQ,          // p.Tp
+  S_RZ0,         // r.z, ping
+  S_RZ1,         // r.z, pong
+  S_ZZ,          // z.z
+  S_MUE,         // mu.E0
+  S_MUTMU,       // mu.T mu
+  S_AUX,         // scratch
+  S_COUNT
+};
+
+// Device view of the system in cell-sorted order.  Site records are AoS so
+// that a neighbour gather touches one or two cache lines.
+template <typename R>
+struct Vec4 { using type = double4; };
+template <>
+struct Vec4<float> { using type = float4; };
+
+struct SysView {
+  int n, npol;
+  int periodic;
+  double box[3], ibox[3];
+  double cutoff2;
+  double beta;
+  int uniform_thole;
+  double thole_a;
+  // sorted site records, FP64
+  const double4* sp;    // x, y, z, q       (positions wrapped into the box)
+  const double4* sd;    // dx, dy, dz, s    (s = abar^-1/2, 0 if not polarizable)
+  const double4* sth;   // Theta xx, xy, xz, yy
+  const double2* sth2;  // Theta yz, zz
+  const double* sa;     // Thole factor per site
+  const int* polidx;    // sorted site -> polarizable index, or -1
+  // FP32 copies (mixed precision)
+  const float4* sp32;
+  const float4* sd32;
+  const float4* sth32;
+  const float2* sth232;
+  // polarizable-site records (polarizable order = sorted order restricted)
+  const int* polsite;   // polarizable index -> sorted site
+  const double4* pp;    // x, y, z, s
+  const float4* pp32;
+  const double* pa;     // Thole factor
+  const double* alpha;  // [npol][6] xx,xy,xz,yy,yz,zz
+  const double* ainv;   // [npol][6]
+  // neighbour lists (ELL: row i holds count[i] entries starting at i*cap)
+  const int* nb_all;  const int* nc_all;  int cap_all;    // intermolecular, r < rc
+  const int* nb_in;   const int* nc_in;   int cap_in;     // same molecule
+  const int* nb_pol;  const int* nc_pol;  int cap_pol;    // pol-pol, inter, r < rc
+  const int* nb_ipol; const int* nc_ipol; int cap_ipol;   // pol-pol, same molecule
+};
+
+struct PmeView {
+  int K[3];
+  int order;
+  int kxh;             // K[0]/2 + 1
+  double scale[3];     // K_a / L_a
+  double* Q;           // real spread grid [K2][K1][K0] (x fastest)
+  double* phi;         // real potential grid, same layout
+  double2* C;          // complex half grid [K2][K1][kxh]
+  float* Q32;
+  float* phi32;
+  float2* C32;
+  const double* G;     // influence function [K2][K1][kxh]
+  const float* G32;
+  const double2* tw[3];   // twiddles exp(-2 pi i k / K_a), k < K_a
+  const float2* tw32[3];
+  int nrad[3];
+  int rad[3][16];
+};
+
+struct Reduce {
+  double* partials;      // [S_COUNT][max_blocks]
+  unsigned* counters;    // [S_COUNT]
+  double* scalars;       // [S_COUNT]
+  int max_blocks;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over groups of G consecutive lanes (G a power of two <= 64).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// Deterministic block reduction followed by a grid-level finalisation: the
+// last block to finish sums the per-block partials in index order and stores
+// the scalar.  Every thread of the block must call it.
+__device__ __forceinline__ void block_reduce_to_slot(double v, Reduce red, int slot) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ bool last;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    red.partials[slot * red.max_blocks + blockIdx.x] = s;
+    __threadfence();
+    unsigned prev = atomicAdd(&red.counters[slot], 1u);
+    last = (prev == (unsigned)(nb - 1));
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+      s += red.partials[slot * red.max_blocks + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+      red.scalars[slot] = t;
+      red.counters[slot] = 0u;
+    }
+  }
+  __syncthreads();   // the shared staging is reused by the next call
+}
+
+template <typename R>
+__device__ __forceinline__ R min_image(R d, R L, R iL) {
+  return d - L * rint(d * iL);
+}
+
+// Cardinal B-spline weights of order P at fractional offset w in [0,1):
+// th[D][t] is the D-th derivative of M_P(w + t) for t = 0..P-1, grid point
+// index floor(u) - t.  Built with the two-term recursion
+//   M_n(u) = (u M_{n-1}(u) + (n - u) M_{n-1}(u - 1)) / (n - 1)
+// and derivatives from differences of lower orders.
+template <typename R, int P, int ND>
+__device__ __forceinline__ void bspline_weights(R w, R th[ND + 1][P]) {
+  R lev[P][P];   // lev[k][t] = M_{k+1}(w + t)
+  lev[0][0] = R(1);
+#pragma unroll
+  for (int t = 1; t < P; ++t) lev[0][t] = R(0);
+#pragma unroll
+  for (int k = 1; k < P; ++k) {
+    const int n = k + 1;
+    const R inv = R(1) / R(n - 1);
+#pragma unroll
+    for (int t = P - 1; t >= 0; --t) {
+      const R u = w + R(t);
+      const R a = (t <= k - 1) ? lev[k - 1][t] : R(0);
+      const R b = (t >= 1 && t - 1 <= k - 1) ? lev[k - 1][t - 1] : R(0);
+      lev[k][t] = (u * a + (R(n) - u) * b) * inv;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) th[0][t] = lev[P - 1][t];
+  if (ND >= 1) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const R a = lev[P - 2][t];
+      const R b = (t >= 1) ? lev[P - 2][t - 1] : R(0);
+      th[ND >= 1 ? 1 : 0][t] = a - b;
+    }
+  }
+  if (ND >= 2) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const R a = lev[P - 3][t];
+      const R b = (t >= 1) ? lev[P - 3][t - 1] : R(0);
+      const R c = (t >= 2) ? lev[P - 3][t - 2] : R(0);
+      th[ND >= 2 ? 2 : 0][t] = a - R(2) * b + c;
+    }
+  }
+  if (ND >= 3) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const R a = lev[P - 4][t];
+      const R b = (t >= 1) ? lev[P - 4][t - 1] : R(0);
+      const R c = (t >= 2) ? lev[P - 4][t - 2] : R(0);
+      const R d = (t >= 3) ? lev[P - 4][t - 3] : R(0);
+      th[ND >= 3 ? 3 : 0][t] = a - R(3) * b + R(3) * c - d;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+// nlist.hip
+void launch_fill_int(int* p, int v, size_t n, hipStream_t s);
+void launch_fill_double(double* p, double v, size_t n, hipStream_t s);
+void launch_fill_float(float* p, float v, size_t n, hipStream_t s);
+size_t scan_temp_ints(int n);
+void launch_exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);
+
+}  // namespace sibfa

@@ -1,0 +1,448 @@
+// Cell binning, deterministic cell sort, per-site records and real-space
+// neighbour lists.
+//
+// Sites are binned into cells of edge >= cutoff/2 (a 5x5x5 cell stencil
+// then covers the cutoff sphere), counting-sorted by cell, and each cell's
+// segment is sorted by caller index so that the order -- and with it every
+// summation order downstream -- is reproducible.  The neighbour-list kernel
+// runs one wavefront per cell: 64 candidate sites are loaded per step and
+// tested against every site of the cell; hits are compacted with ballots so
+// list order is deterministic too.  Four ELL lists are produced:
+//   all   intermolecular site pairs within the cutoff (E, E_elec, forces)
+//   in    same-molecule site pairs (excluded or damped, always present)
+//   pol   intermolecular polarizable pairs within the cutoff (T)
+//   ipol  same-molecule polarizable pairs (T, Thole-damped)
+#include "common.h"
+#include "nlist.h"
+
+namespace sibfa {
+
+// ------------------------------------------------------------ fill / scan
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+static int fill_blocks(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void launch_fill_int(int* p, int v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill<int>, dim3(fill_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+}
+void launch_fill_double(double* p, double v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+}
+void launch_fill_float(float* p, float v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill<float>, dim3(fill_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+}
+
+constexpr int kScanTile = 4 * kBlock;   // elements per block
+
+__device__ int block_exclusive_scan(int v, int* total) {
+  __shared__ int wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wid) base += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ void k_scan_tiles(const int* in, int* out, int n, int* tile_sums) {
+  const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  int v[4], s = 0;
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, &total);
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int* out, int n, const int* tile_offsets) {
+  const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  const int add = tile_offsets[blockIdx.x];
+  for (int k = 0; k < 4; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+size_t scan_temp_ints(int n) {
+  const size_t tiles = (size_t)(n + kScanTile - 1) / kScanTile;
+  if (tiles <= 1) return 1;
+  return 2 * tiles + scan_temp_ints((int)tiles);
+}
+
+void launch_exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s) {
+  if (n <= 0) return;
+  const int tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, in, out, n, tmp);
+  if (tiles == 1) return;
+  launch_exclusive_scan(tmp, tmp + tiles, tiles, tmp + 2 * tiles, s);
+  hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(kBlock), 0, s, out, n,
+                     (const int*)(tmp + tiles));
+}
+
+// ------------------------------------------------------------ binning
+__device__ __forceinline__ double wrap(double x, double L, double iL) {
+  double w = x - L * floor(x * iL);
+  return (w >= L) ? w - L : w;
+}
+
+__global__ void k_bin(BinArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  int cell = 0;
+  if (a.periodic) {
+    int ci[3];
+    for (int d = 0; d < 3; ++d) {
+      double w = wrap(a.xyz[3 * c + d], a.box[d], a.ibox[d]);
+      int k = (int)(w * a.nc[d] * a.ibox[d]);
+      ci[d] = k >= a.nc[d] ? a.nc[d] - 1 : (k < 0 ? 0 : k);
+    }
+    cell = ci[0] + a.nc[0] * (ci[1] + a.nc[1] * ci[2]);
+  }
+  a.cell_of[c] = cell;
+  atomicAdd(&a.cell_count[cell], 1);
+  const int m = a.mol[c];
+  if (m >= 0 && m < a.n) atomicAdd(&a.mol_count[m], 1);
+  else atomicOr(a.err, 2);
+}
+
+__global__ void k_scatter(const int* cell_of, const int* cell_start, int* cursor,
+                          int* perm, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int cell = cell_of[c];
+  const int slot = atomicAdd(&cursor[cell], 1);
+  perm[cell_start[cell] + slot] = c;
+}
+
+// One thread per cell: insertion sort of the cell's segment by caller index.
+__global__ void k_sort_cells(const int* cell_start, int ncell, int* perm) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  const int s = cell_start[cell], e = cell_start[cell + 1];
+  for (int i = s + 1; i < e; ++i) {
+    const int v = perm[i];
+    int j = i - 1;
+    while (j >= s && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+__global__ void k_max_int(const int* v, int n, int* out) {
+  int m = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    m = max(m, v[i]);
+  for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+void launch_bin(const BinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+}
+void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int* perm,
+                    int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     cell_of, cell_start, cursor, perm, n);
+}
+void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_cells, dim3((ncell + 63) / 64), dim3(64), 0, s, cell_start,
+                     ncell, perm);
+}
+void launch_max_int(const int* v, int n, int* out, hipStream_t s) {
+  int blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_max_int, dim3(blocks), dim3(kBlock), 0, s, v, n, out);
+}
+
+// ------------------------------------------------------------ records
+// Positions (wrapped when periodic) and molecule ids in sorted order; the
+// inverse permutation.
+__global__ void k_rec_pos(RecArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int c = a.perm[i];
+  double x = a.xyz[3 * c], y = a.xyz[3 * c + 1], z = a.xyz[3 * c + 2];
+  if (a.periodic) {
+    x = wrap(x, a.box[0], a.ibox[0]);
+    y = wrap(y, a.box[1], a.ibox[1]);
+    z = wrap(z, a.box[2], a.ibox[2]);
+  }
+  double4 p = a.sp[i];
+  p.x = x; p.y = y; p.z = z;
+  a.sp[i] = p;
+  float4 p32 = a.sp32[i];
+  p32.x = (float)x; p32.y = (float)y; p32.z = (float)z;
+  a.sp32[i] = p32;
+  a.mol_s[i] = a.mol[c];
+  a.inv_perm[c] = i;
+}
+
+__global__ void k_rec_mult(RecArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int c = a.perm[i];
+  const double q = a.q ? a.q[c] : 0.0;
+  double d[3] = {0, 0, 0}, t[6] = {0, 0, 0, 0, 0, 0};
+  if (a.dip) for (int k = 0; k < 3; ++k) d[k] = a.dip[3 * c + k];
+  if (a.quad) for (int k = 0; k < 6; ++k) t[k] = a.quad[6 * c + k];
+  double4 p = a.sp[i];
+  p.w = q;
+  a.sp[i] = p;
+  float4 p32 = a.sp32[i];
+  p32.w = (float)q;
+  a.sp32[i] = p32;
+  double4 dd = a.sd[i];
+  dd.x = d[0]; dd.y = d[1]; dd.z = d[2];
+  a.sd[i] = dd;
+  float4 dd32 = a.sd32[i];
+  dd32.x = (float)d[0]; dd32.y = (float)d[1]; dd32.z = (float)d[2];
+  a.sd32[i] = dd32;
+  a.sth[i] = make_double4(t[0], t[1], t[2], t[3]);
+  a.sth2[i] = make_double2(t[4], t[5]);
+  a.sth32[i] = make_float4((float)t[0], (float)t[1], (float)t[2], (float)t[3]);
+  a.sth232[i] = make_float2((float)t[4], (float)t[5]);
+}
+
+// Polarizability records: s = abar^-1/2 (0 when not polarizable), Thole
+// factor, polarizable flag.
+__global__ void k_rec_pol(RecArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int c = a.perm[i];
+  const double* al = a.alpha + 6 * c;
+  bool pol = false;
+  for (int k = 0; k < 6; ++k) pol = pol || (al[k] != 0.0);
+  const double abar = (al[0] + al[3] + al[5]) / 3.0;
+  const double s = pol && abar > 0.0 ? 1.0 / sqrt(abar) : 0.0;
+  double4 dd = a.sd[i];
+  dd.w = s;
+  a.sd[i] = dd;
+  float4 dd32 = a.sd32[i];
+  dd32.w = (float)s;
+  a.sd32[i] = dd32;
+  a.sa[i] = a.thole ? a.thole[c] : a.thole_default;
+  a.is_pol[i] = pol ? 1 : 0;
+}
+
+// After the scan of is_pol: polarizable index maps and polarizable records,
+// including alpha^-1 (checked symmetric positive definite).
+__global__ void k_rec_polsites(RecArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const bool pol = a.is_pol[i] != 0;
+  const int pi = a.pol_scan[i];
+  a.polidx[i] = pol ? pi : -1;
+  if (!pol) return;
+  a.polsite[pi] = i;
+  const int c = a.perm[i];
+  const double4 p = a.sp[i];
+  const double s = a.sd[i].w;
+  a.pp[pi] = make_double4(p.x, p.y, p.z, s);
+  a.pp32[pi] = make_float4((float)p.x, (float)p.y, (float)p.z, (float)s);
+  a.pa[pi] = a.sa[i];
+  const double* al = a.alpha + 6 * c;
+  const double xx = al[0], xy = al[1], xz = al[2], yy = al[3], yz = al[4], zz = al[5];
+  for (int k = 0; k < 6; ++k) a.alpha_s[6 * pi + k] = al[k];
+  // Cholesky-type positivity test: leading principal minors > 0
+  const double m1 = xx, m2 = xx * yy - xy * xy;
+  const double det = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+  if (!(m1 > 0.0 && m2 > 0.0 && det > 0.0)) atomicOr(a.err, 4);
+  const double id = 1.0 / det;
+  a.ainv_s[6 * pi + 0] = (yy * zz - yz * yz) * id;
+  a.ainv_s[6 * pi + 1] = (xz * yz - xy * zz) * id;
+  a.ainv_s[6 * pi + 2] = (xy * yz - xz * yy) * id;
+  a.ainv_s[6 * pi + 3] = (xx * zz - xz * xz) * id;
+  a.ainv_s[6 * pi + 4] = (xy * xz - xx * yz) * id;
+  a.ainv_s[6 * pi + 5] = (xx * yy - xy * xy) * id;
+}
+
+void launch_rec_pos(const RecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_pos, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+}
+void launch_rec_mult(const RecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_mult, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+}
+void launch_rec_pol(const RecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_pol, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+}
+void launch_rec_polsites(const RecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_polsites, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+}
+
+// ------------------------------------------------------------ neighbour lists
+constexpr int kNlIB = 128;   // i-sites of a cell handled per pass
+
+__global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
+  __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
+  __shared__ int moli[kNlIB], poli[kNlIB];
+  __shared__ int cnt[4][kNlIB];
+  const int lane = threadIdx.x;
+  const int cell = blockIdx.x;
+  const int cx = cell % a.nc[0];
+  const int cy = (cell / a.nc[0]) % a.nc[1];
+  const int cz = cell / (a.nc[0] * a.nc[1]);
+  const int i0 = a.cell_start[cell], i1 = a.cell_start[cell + 1];
+  const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+  const double iL0 = a.ibox[0], iL1 = a.ibox[1], iL2 = a.ibox[2];
+  // stencil extents per axis: all cells when the axis has fewer than 5
+  int span[3], lo[3];
+  const int c3[3] = {cx, cy, cz};
+  for (int d = 0; d < 3; ++d) {
+    if (a.nc[d] < 5) { span[d] = a.nc[d]; lo[d] = 0; }
+    else { span[d] = 5; lo[d] = c3[d] - 2; }
+  }
+  for (int ib = i0; ib < i1; ib += kNlIB) {
+    const int ni = min(kNlIB, i1 - ib);
+    for (int t = lane; t < ni; t += 64) {
+      const double4 p = a.sp[ib + t];
+      xi[t] = p.x; yi[t] = p.y; zi[t] = p.z;
+      moli[t] = a.mol_s[ib + t];
+      poli[t] = a.polidx[ib + t];
+      cnt[0][t] = cnt[1][t] = cnt[2][t] = cnt[3][t] = 0;
+    }
+    __syncthreads();
+    for (int sz = 0; sz < span[2]; ++sz) {
+      int zz = lo[2] + sz;
+      zz = (zz + a.nc[2]) % a.nc[2];
+      for (int sy = 0; sy < span[1]; ++sy) {
+        int yy = lo[1] + sy;
+        yy = (yy + a.nc[1]) % a.nc[1];
+        const int rowcell = a.nc[0] * (yy + a.nc[1] * zz);
+        // x cells of this row as at most two contiguous runs
+        int rs[2], re[2], nrun;
+        if (span[0] == a.nc[0]) {
+          rs[0] = rowcell; re[0] = rowcell + a.nc[0]; nrun = 1;
+        } else {
+          const int x0 = lo[0], x1 = lo[0] + 4;
+          if (x0 >= 0 && x1 < a.nc[0]) { rs[0] = rowcell + x0; re[0] = rowcell + x1 + 1; nrun = 1; }
+          else if (x0 < 0) {
+            rs[0] = rowcell; re[0] = rowcell + x1 + 1;
+            rs[1] = rowcell + a.nc[0] + x0; re[1] = rowcell + a.nc[0]; nrun = 2;
+          } else {
+            rs[0] = rowcell + x0; re[0] = rowcell + a.nc[0];
+            rs[1] = rowcell; re[1] = rowcell + (x1 - a.nc[0]) + 1; nrun = 2;
+          }
+        }
+        for (int r = 0; r < nrun; ++r) {
+          const int j0 = a.cell_start[rs[r]], j1 = a.cell_start[re[r]];
+          for (int jc = j0; jc < j1; jc += 64) {
+            const int j = jc + lane;
+            const bool valid = j < j1;
+            double xj = 0, yj = 0, zj = 0;
+            int molj = -1, polj = -1;
+            if (valid) {
+              const double4 p = a.sp[j];
+              xj = p.x; yj = p.y; zj = p.z;
+              molj = a.mol_s[j];
+              polj = a.polidx[j];
+            }
+            for (int t = 0; t < ni; ++t) {
+              double dx = xi[t] - xj, dy = yi[t] - yj, dz = zi[t] - zj;
+              if (a.periodic) {
+                dx -= L0 * rint(dx * iL0);
+                dy -= L1 * rint(dy * iL1);
+                dz -= L2 * rint(dz * iL2);
+              }
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              const int i = ib + t;
+              const bool same = valid && (molj == moli[t]) && (j != i);
+              const bool inter = valid && (molj != moli[t]) && (r2 < a.cutoff2);
+              const bool pi = poli[t] >= 0;
+              const bool pj = polj >= 0;
+              const unsigned long long b0 = __ballot(inter);
+              const unsigned long long b1 = __ballot(same);
+              const unsigned long long b2 = __ballot(inter && pi && pj);
+              const unsigned long long b3 = __ballot(same && pi && pj);
+              const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+              if (b0) {
+                const int base = cnt[0][t];
+                if (inter) {
+                  const int k = base + __popcll(b0 & below);
+                  if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
+                }
+              }
+              if (b1) {
+                const int base = cnt[1][t];
+                if (same) {
+                  const int k = base + __popcll(b1 & below);
+                  if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
+                }
+              }
+              if (b2) {
+                const int base = cnt[2][t];
+                if (inter && pi && pj) {
+                  const int k = base + __popcll(b2 & below);
+                  if (k < a.cap_pol) a.nb_pol[(size_t)poli[t] * a.cap_pol + k] = polj;
+                }
+              }
+              if (b3) {
+                const int base = cnt[3][t];
+                if (same && pi && pj) {
+                  const int k = base + __popcll(b3 & below);
+                  if (k < a.cap_ipol) a.nb_ipol[(size_t)poli[t] * a.cap_ipol + k] = polj;
+                }
+              }
+              __syncthreads();   // every lane has read cnt[*][t]
+              if (lane == 0) {
+                cnt[0][t] += __popcll(b0);
+                cnt[1][t] += __popcll(b1);
+                cnt[2][t] += __popcll(b2);
+                cnt[3][t] += __popcll(b3);
+              }
+              __syncthreads();
+            }
+          }
+        }
+      }
+    }
+    // counts, overflow maxima and the same-molecule completeness check
+    for (int t = lane; t < ni; t += 64) {
+      const int i = ib + t;
+      a.nc_all[i] = cnt[0][t];
+      a.nc_in[i] = cnt[1][t];
+      atomicMax(&a.maxcnt[0], cnt[0][t]);
+      atomicMax(&a.maxcnt[1], cnt[1][t]);
+      if (poli[t] >= 0) {
+        a.nc_pol[poli[t]] = cnt[2][t];
+        a.nc_ipol[poli[t]] = cnt[3][t];
+        atomicMax(&a.maxcnt[2], cnt[2][t]);
+        atomicMax(&a.maxcnt[3], cnt[3][t]);
+      }
+      if (cnt[1][t] != a.mol_count[moli[t]] - 1) atomicOr(a.err, 1);
+    }
+    __syncthreads();
+  }
+}
+
+void launch_nlist(const NlistArgs& a, int ncell, hipStream_t s) {
+  hipLaunchKernelGGL(k_nlist, dim3(ncell), dim3(64), 0, s, a);
+}
+
+}  // namespace sibfa

@@ -1,0 +1,492 @@
+// Real-space pair kernels over the ELL neighbour lists.
+//
+// Mapping: G consecutive lanes own one site and stride through its list;
+// the G partial sums are folded with cross-lane shuffles.  Same-molecule
+// pairs (few per site, short distances where the excluded Ewald part
+// E_n - c0_n cancels strongly) are always evaluated in FP64; the
+// intermolecular pairs run in the kernel's precision R (double, or float in
+// mixed mode) with FP64 accumulation.
+//
+//  k_perm    : permanent field E at polarizable sites (Thole-damped Mmu
+//              class, excluded within a molecule) and the MM real-space
+//              energy, plus Ewald self terms.
+//  k_matvec  : (T p)_i = alpha_i^-1 p_i - [damped dipole field of p + PME
+//              field of p (gathered from the potential grid, fused) + self],
+//              with p.Tp for the solver.
+//  k_force   : real-space forces of MM, Mmu and mumu classes at fixed mu.
+#include "common.h"
+#include "pairmath.h"
+#include "kernels.h"
+
+namespace sibfa {
+
+template <typename R>
+__device__ __forceinline__ void load_mp(const SysView& s, int j, MP<R>& M, R x[3]);
+
+template <>
+__device__ __forceinline__ void load_mp<double>(const SysView& s, int j, MP<double>& M,
+                                                double x[3]) {
+  const double4 p = s.sp[j], d = s.sd[j], t = s.sth[j];
+  const double2 t2 = s.sth2[j];
+  x[0] = p.x; x[1] = p.y; x[2] = p.z;
+  M.q = p.w;
+  M.d[0] = d.x; M.d[1] = d.y; M.d[2] = d.z;
+  M.t[0] = t.x; M.t[1] = t.y; M.t[2] = t.z; M.t[3] = t.w; M.t[4] = t2.x; M.t[5] = t2.y;
+}
+
+template <>
+__device__ __forceinline__ void load_mp<float>(const SysView& s, int j, MP<float>& M, float x[3]) {
+  const float4 p = s.sp32[j], d = s.sd32[j], t = s.sth32[j];
+  const float2 t2 = s.sth232[j];
+  x[0] = p.x; x[1] = p.y; x[2] = p.z;
+  M.q = p.w;
+  M.d[0] = d.x; M.d[1] = d.y; M.d[2] = d.z;
+  M.t[0] = t.x; M.t[1] = t.y; M.t[2] = t.z; M.t[3] = t.w; M.t[4] = t2.x; M.t[5] = t2.y;
+}
+
+template <typename R>
+__device__ __forceinline__ R site_s(const SysView& s, int j);
+template <>
+__device__ __forceinline__ double site_s<double>(const SysView& s, int j) { return s.sd[j].w; }
+template <>
+__device__ __forceinline__ float site_s<float>(const SysView& s, int j) { return s.sd32[j].w; }
+
+template <typename R>
+__device__ __forceinline__ void displacement(const SysView& s, const R xi[3], const R xj[3],
+                                             R Rv[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R d = xi[a] - xj[a];
+    if (s.periodic) d = min_image<R>(d, R(s.box[a]), R(s.ibox[a]));
+    Rv[a] = d;
+  }
+}
+
+// base kernel E_0..E_N: Ewald B_n when periodic, bare c0_n for clusters
+template <typename R, int N>
+__device__ __forceinline__ void base_coeffs(const SysView& s, R r, R rinv, R rinv2, R E[N + 1]) {
+  if (s.periodic) ewald_coeffs<R, N>(r, rinv, rinv2, R(s.beta), E);
+  else bare_coeffs<R, N>(rinv, rinv2, E);
+}
+
+__device__ __forceinline__ double thole_a_pair(const SysView& s, int i, int j) {
+  return s.uniform_thole ? s.thole_a : fmin(s.sa[i], s.sa[j]);
+}
+__device__ __forceinline__ double thole_a_polpair(const SysView& s, int i, int j) {
+  return s.uniform_thole ? s.thole_a : fmin(s.pa[i], s.pa[j]);
+}
+
+// ------------------------------------------------------------------ E0 + E_elec
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4* E0) {
+  const int sub = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double acc[3] = {0.0, 0.0, 0.0};
+  double U = 0.0, Uself = 0.0;
+  int pi = -1;
+  if (i < s.n) {
+    pi = s.polidx[i];
+    // same-molecule pairs: excluded (E_n - c0_n), FP64; nothing for clusters
+    if (s.periodic) {
+      MP<double> Mi;
+      double xi[3];
+      load_mp<double>(s, i, Mi, xi);
+      const int cnt = s.nc_in[i];
+      for (int k = sub; k < cnt; k += G) {
+        const int j = s.nb_in[(size_t)i * s.cap_in + k];
+        MP<double> Mj;
+        double xj[3], Rv[3];
+        load_mp<double>(s, j, Mj, xj);
+        displacement<double>(s, xi, xj, Rv);
+        const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+        const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+        double B[5], c0[5], c[6];
+        ewald_coeffs<double, 4>(r, rinv, rinv2, s.beta, B);
+        bare_coeffs<double, 4>(rinv, rinv2, c0);
+#pragma unroll
+        for (int n = 0; n < 5; ++n) c[n] = B[n] - c0[n];
+        c[5] = 0.0;
+        double u, fdum[3];
+        mp_pair<double, true, false>(c, Mi, Mj, Rv, u, fdum);
+        U += 0.5 * u;
+        if (pi >= 0) {
+          double E[3];
+          mp_field<double>(c, Mj, Rv, E);
+          acc[0] += E[0]; acc[1] += E[1]; acc[2] += E[2];
+        }
+      }
+    }
+    // intermolecular pairs within the cutoff, precision R
+    MP<R> Mi;
+    R xi[3];
+    load_mp<R>(s, i, Mi, xi);
+    const R si = site_s<R>(s, i);
+    const int cnt = s.nc_all[i];
+    for (int k = sub; k < cnt; k += G) {
+      const int j = s.nb_all[(size_t)i * s.cap_all + k];
+      MP<R> Mj;
+      R xj[3], Rv[3];
+      load_mp<R>(s, j, Mj, xj);
+      displacement<R>(s, xi, xj, Rv);
+      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      R c[6];
+      base_coeffs<R, 4>(s, r, rinv, rinv2, c);
+      c[5] = R(0);
+      R u, fdum[3];
+      mp_pair<R, true, false>(c, Mi, Mj, Rv, u, fdum);
+      U += 0.5 * (double)u;
+      if (pi >= 0) {
+        const R sj = site_s<R>(s, j);
+        if (sj > R(0)) {
+          const R x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj;
+          R tp[5], c0[4];
+          thole_tp<R>(x, tp);
+          bare_coeffs<R, 3>(rinv, rinv2, c0);
+#pragma unroll
+          for (int n = 1; n <= 3; ++n) c[n] -= tp[n] * c0[n];
+        }
+        R E[3];
+        mp_field<R>(c, Mj, Rv, E);
+        acc[0] += (double)E[0]; acc[1] += (double)E[1]; acc[2] += (double)E[2];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) acc[a] = group_sum<G>(acc[a]);
+  if (sub == 0 && i < s.n && s.periodic) {
+    const double4 p = s.sp[i], d = s.sd[i], t = s.sth[i];
+    const double2 t2 = s.sth2[i];
+    const double b = s.beta, b3 = b * b * b, b5 = b3 * b * b;
+    const double tt = t.x * t.x + t.w * t.w + t2.y * t2.y +
+                      2.0 * (t.y * t.y + t.z * t.z + t2.x * t2.x);
+    Uself = -(b / kSqrtPi * p.w * p.w + 2.0 * b3 / (3.0 * kSqrtPi) * (d.x * d.x + d.y * d.y + d.z * d.z) +
+              8.0 * b5 / (45.0 * kSqrtPi) * tt);
+    const double sf = 4.0 * b3 / (3.0 * kSqrtPi);
+    acc[0] += sf * d.x; acc[1] += sf * d.y; acc[2] += sf * d.z;
+  }
+  if (sub == 0 && pi >= 0) E0[pi] = make_double4(acc[0], acc[1], acc[2], 0.0);
+  block_reduce_to_slot(U, red, S_EREAL);
+  block_reduce_to_slot(Uself, red, S_ESELF);
+}
+
+// ------------------------------------------------------------------ matvec
+template <typename R>
+__device__ __forceinline__ void load_p(const double4* p, const float4* p32, int j, R v[3]);
+template <>
+__device__ __forceinline__ void load_p<double>(const double4* p, const float4*, int j, double v[3]) {
+  const double4 a = p[j];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z;
+}
+template <>
+__device__ __forceinline__ void load_p<float>(const double4*, const float4* p32, int j, float v[3]) {
+  const float4 a = p32[j];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_pp(const SysView& s, int j, R x[3], R& sj);
+template <>
+__device__ __forceinline__ void load_pp<double>(const SysView& s, int j, double x[3], double& sj) {
+  const double4 a = s.pp[j];
+  x[0] = a.x; x[1] = a.y; x[2] = a.z; sj = a.w;
+}
+template <>
+__device__ __forceinline__ void load_pp<float>(const SysView& s, int j, float x[3], float& sj) {
+  const float4 a = s.pp32[j];
+  x[0] = a.x; x[1] = a.y; x[2] = a.z; sj = a.w;
+}
+
+template <typename R>
+__device__ __forceinline__ R grid_at(const PmeView& pm, size_t idx);
+template <>
+__device__ __forceinline__ double grid_at<double>(const PmeView& pm, size_t idx) { return pm.phi[idx]; }
+template <>
+__device__ __forceinline__ float grid_at<float>(const PmeView& pm, size_t idx) { return pm.phi32[idx]; }
+
+// Minus the gradient of the interpolated potential at x (this lane's share
+// of the P*P (y, z) columns), added to f.
+template <typename R, int P, int G>
+__device__ __forceinline__ void gather_field_share(const PmeView& pm, const double x[3], int sub,
+                                                   double f[3]) {
+  int base[3];
+  R th[3][2][P];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = x[a] * pm.scale[a];
+    double fl = floor(u);
+    const R w = (R)(u - fl);
+    int k = (int)fl;
+    if (k >= pm.K[a]) k -= pm.K[a];
+    base[a] = k;
+    bspline_weights<R, P, 1>(w, th[a]);
+  }
+  const R s0 = (R)pm.scale[0], s1 = (R)pm.scale[1], s2 = (R)pm.scale[2];
+  for (int c = sub; c < P * P; c += G) {
+    const int ty = c % P, tz = c / P;
+    int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
+    int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
+    const size_t row = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
+    R gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int tx = 0; tx < P; ++tx) {
+      int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
+      const R g = grid_at<R>(pm, row + ix);
+      gx += g * th[0][1][tx];
+      gy += g * th[0][0][tx];
+    }
+    gz = gy;
+    // gx: sum g th'x ; gy: sum g thx (shared for y and z derivatives)
+    f[0] -= (double)(gx * th[1][0][ty] * th[2][0][tz] * s0);
+    f[1] -= (double)(gy * th[1][1][ty] * th[2][0][tz] * s1);
+    f[2] -= (double)(gz * th[1][0][ty] * th[2][1][tz] * s2);
+  }
+}
+
+template <typename R, int G, int P, bool PME>
+__global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce red,
+                                                   const double4* p, const float4* p32,
+                                                   double4* out, int dot_slot) {
+  const int sub = threadIdx.x % G;
+  const int pi = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double f[3] = {0.0, 0.0, 0.0};
+  if (pi < s.npol) {
+    double xi[3], si;
+    load_pp<double>(s, pi, xi, si);
+    // same-molecule polarizable pairs (damped, FP64)
+    const int cin = s.nc_ipol[pi];
+    for (int k = sub; k < cin; k += G) {
+      const int j = s.nb_ipol[(size_t)pi * s.cap_ipol + k];
+      double xj[3], sj, Rv[3], pj[3];
+      load_pp<double>(s, j, xj, sj);
+      load_p<double>(p, p32, j, pj);
+      displacement<double>(s, xi, xj, Rv);
+      const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double Eb[3], c0[3], tp[5];
+      base_coeffs<double, 2>(s, r, rinv, rinv2, Eb);
+      bare_coeffs<double, 2>(rinv, rinv2, c0);
+      thole_tp<double>(thole_a_polpair(s, pi, j) * r2 * r * si * sj, tp);
+      double E[3];
+      dip_field<double>(Eb[1] - tp[1] * c0[1], Eb[2] - tp[2] * c0[2], pj, Rv, E);
+      f[0] += E[0]; f[1] += E[1]; f[2] += E[2];
+    }
+    // intermolecular polarizable pairs within the cutoff, precision R
+    R xr[3], sr;
+    load_pp<R>(s, pi, xr, sr);
+    const int cnt = s.nc_pol[pi];
+    for (int k = sub; k < cnt; k += G) {
+      const int j = s.nb_pol[(size_t)pi * s.cap_pol + k];
+      R xj[3], sj, Rv[3], pj[3];
+      load_pp<R>(s, j, xj, sj);
+      load_p<R>(p, p32, j, pj);
+      displacement<R>(s, xr, xj, Rv);
+      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      R Eb[3], c0[3], tp[5];
+      base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
+      bare_coeffs<R, 2>(rinv, rinv2, c0);
+      thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+      R E[3];
+      dip_field<R>(Eb[1] - tp[1] * c0[1], Eb[2] - tp[2] * c0[2], pj, Rv, E);
+      f[0] += (double)E[0]; f[1] += (double)E[1]; f[2] += (double)E[2];
+    }
+    if (PME) gather_field_share<R, P, G>(pm, xi, sub, f);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
+  double dot = 0.0;
+  if (sub == 0 && pi < s.npol) {
+    const double4 pv = p[pi];
+    if (s.periodic) {
+      const double b = s.beta, sf = 4.0 * b * b * b / (3.0 * kSqrtPi);
+      f[0] += sf * pv.x; f[1] += sf * pv.y; f[2] += sf * pv.z;
+    }
+    const double* ai = s.ainv + 6 * (size_t)pi;
+    double q[3];
+    q[0] = ai[0] * pv.x + ai[1] * pv.y + ai[2] * pv.z - f[0];
+    q[1] = ai[1] * pv.x + ai[3] * pv.y + ai[4] * pv.z - f[1];
+    q[2] = ai[2] * pv.x + ai[4] * pv.y + ai[5] * pv.z - f[2];
+    out[pi] = make_double4(q[0], q[1], q[2], 0.0);
+    dot = pv.x * q[0] + pv.y * q[1] + pv.z * q[2];
+  }
+  if (dot_slot >= 0) block_reduce_to_slot(dot, red, dot_slot);
+}
+
+// ------------------------------------------------------------------ forces
+template <typename R>
+__device__ __forceinline__ void load_mu(const double4* mu, const float4* mu32, int j, R v[3]);
+template <>
+__device__ __forceinline__ void load_mu<double>(const double4* mu, const float4*, int j, double v[3]) {
+  const double4 a = mu[j];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z;
+}
+template <>
+__device__ __forceinline__ void load_mu<float>(const double4*, const float4* mu32, int j, float v[3]) {
+  const float4 a = mu32[j];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z;
+}
+
+template <typename R>
+__device__ __forceinline__ MP<R> dipole_only(const R d[3]) {
+  MP<R> m;
+  m.q = R(0);
+  m.d[0] = d[0]; m.d[1] = d[1]; m.d[2] = d[2];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m.t[k] = R(0);
+  return m;
+}
+
+template <typename R>
+__device__ __forceinline__ void accumulate_classes(const R cMM[6], const R cT[6], bool mm,
+                                                   const MP<R>& Mi, const MP<R>& Mj,
+                                                   const R mui[3], const R muj[3],
+                                                   const R Rv[3], double F[3]) {
+  R u, f[3];
+  if (mm) {
+    mp_pair<R, false, true>(cMM, Mi, Mj, Rv, u, f);
+    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+  }
+  const MP<R> Ui = dipole_only<R>(mui), Uj = dipole_only<R>(muj);
+  if (mm) {
+    mp_pair<R, false, true>(cT, Ui, Mj, Rv, u, f);
+    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+    mp_pair<R, false, true>(cT, Mi, Uj, Rv, u, f);
+    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+  }
+}
+
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, const float4* mu32,
+                                                  double4* Fout) {
+  const int sub = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double F[3] = {0.0, 0.0, 0.0};
+  if (i < s.n) {
+    {
+      // same-molecule pairs, FP64: MM and Mmu excluded (E_n - c0_n, periodic
+      // only), mumu damped
+      MP<double> Mi;
+      double xi[3], mui[3];
+      load_mp<double>(s, i, Mi, xi);
+      load_mu<double>(mu, mu32, i, mui);
+      const double si = s.sd[i].w;
+      const int cnt = s.nc_in[i];
+      for (int k = sub; k < cnt; k += G) {
+        const int j = s.nb_in[(size_t)i * s.cap_in + k];
+        MP<double> Mj;
+        double xj[3], Rv[3], muj[3];
+        load_mp<double>(s, j, Mj, xj);
+        load_mu<double>(mu, mu32, j, muj);
+        displacement<double>(s, xi, xj, Rv);
+        const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+        const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+        double Eb[6], c0[6], cx[6], cd[6];
+        base_coeffs<double, 5>(s, r, rinv, rinv2, Eb);
+        bare_coeffs<double, 5>(rinv, rinv2, c0);
+        double u, f[3];
+        if (s.periodic) {
+#pragma unroll
+          for (int n = 0; n < 6; ++n) cx[n] = Eb[n] - c0[n];
+          accumulate_classes<double>(cx, cx, true, Mi, Mj, mui, muj, Rv, F);
+        }
+        const double sj = s.sd[j].w;
+        if (si > 0.0 && sj > 0.0) {
+          double tp[5];
+          thole_tp<double>(thole_a_pair(s, i, j) * r2 * r * si * sj, tp);
+#pragma unroll
+          for (int n = 0; n < 6; ++n) cd[n] = Eb[n] - (n >= 1 && n <= 4 ? tp[n] : 0.0) * c0[n];
+          const MP<double> Ui = dipole_only<double>(mui), Uj = dipole_only<double>(muj);
+          mp_pair<double, false, true>(cd, Ui, Uj, Rv, u, f);
+          F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+        }
+      }
+    }
+    MP<R> Mi;
+    R xi[3], mui[3];
+    load_mp<R>(s, i, Mi, xi);
+    load_mu<R>(mu, mu32, i, mui);
+    const R si = site_s<R>(s, i);
+    const int cnt = s.nc_all[i];
+    for (int k = sub; k < cnt; k += G) {
+      const int j = s.nb_all[(size_t)i * s.cap_all + k];
+      MP<R> Mj;
+      R xj[3], Rv[3], muj[3];
+      load_mp<R>(s, j, Mj, xj);
+      load_mu<R>(mu, mu32, j, muj);
+      displacement<R>(s, xi, xj, Rv);
+      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      R Eb[6], cT[6];
+      base_coeffs<R, 5>(s, r, rinv, rinv2, Eb);
+#pragma unroll
+      for (int n = 0; n < 6; ++n) cT[n] = Eb[n];
+      const R sj = site_s<R>(s, j);
+      if (si > R(0) && sj > R(0)) {
+        R tp[5], c0[5];
+        thole_tp<R>(R(thole_a_pair(s, i, j)) * r2 * r * si * sj, tp);
+        bare_coeffs<R, 4>(rinv, rinv2, c0);
+#pragma unroll
+        for (int n = 1; n <= 4; ++n) cT[n] -= tp[n] * c0[n];
+      }
+      accumulate_classes<R>(Eb, cT, true, Mi, Mj, mui, muj, Rv, F);
+      R u, f[3];
+      const MP<R> Ui = dipole_only<R>(mui), Uj = dipole_only<R>(muj);
+      mp_pair<R, false, true>(cT, Ui, Uj, Rv, u, f);
+      F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
+  if (sub == 0 && i < s.n) Fout[i] = make_double4(F[0], F[1], F[2], 0.0);
+}
+
+// ------------------------------------------------------------------ launchers
+constexpr int kG = 16;
+
+static int blocks_for(int items, int G) {
+  const int per = kBlock / G;
+  int b = (items + per - 1) / per;
+  return b < 1 ? 1 : b;
+}
+
+void launch_perm(const SysView& s, const Reduce& red, double4* E0, bool mixed, hipStream_t st) {
+  const dim3 g(blocks_for(s.n, kG)), b(kBlock);
+  if (mixed) hipLaunchKernelGGL((k_perm<float, kG>), g, b, 0, st, s, red, E0);
+  else hipLaunchKernelGGL((k_perm<double, kG>), g, b, 0, st, s, red, E0);
+}
+
+template <int P>
+static void matvec_p(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
+                     const float4* p32, double4* out, int dot_slot, bool mixed, hipStream_t st) {
+  const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
+  if (s.periodic) {
+    if (mixed)
+      hipLaunchKernelGGL((k_matvec<float, kG, P, true>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+    else
+      hipLaunchKernelGGL((k_matvec<double, kG, P, true>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+  } else {
+    if (mixed)
+      hipLaunchKernelGGL((k_matvec<float, kG, P, false>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+    else
+      hipLaunchKernelGGL((k_matvec<double, kG, P, false>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+  }
+}
+
+void launch_matvec(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
+                   const float4* p32, double4* out, int dot_slot, bool mixed, hipStream_t st) {
+  switch (pm.order) {
+    case 4: matvec_p<4>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
+    case 6: matvec_p<6>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
+    default: matvec_p<5>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
+  }
+}
+
+void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
+                  hipStream_t st) {
+  const dim3 g(blocks_for(s.n, kG)), b(kBlock);
+  if (mixed) hipLaunchKernelGGL((k_force<float, kG>), g, b, 0, st, s, mu, mu32, F);
+  else hipLaunchKernelGGL((k_force<double, kG>), g, b, 0, st, s, mu, mu32, F);
+}
+
+}  // namespace sibfa

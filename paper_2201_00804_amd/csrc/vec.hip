@@ -1,0 +1,209 @@
+// Vector kernels of the PCG driver and the reorderings between the caller's
+// site order and the library's polarizable-site order.
+//
+// Vectors over polarizable sites are double4 (w unused).  The block
+// preconditioner is z = alpha r with the 3x3 site polarizability
+// (the inverse of T's diagonal blocks).  Dot products are reduced per block
+// and finalised deterministically by the last block (block_reduce_to_slot).
+#include "common.h"
+#include "kernels.h"
+
+namespace sibfa {
+
+__device__ __forceinline__ double3 amul(const double* a, double4 v) {
+  return make_double3(a[0] * v.x + a[1] * v.y + a[2] * v.z,
+                      a[1] * v.x + a[3] * v.y + a[4] * v.z,
+                      a[2] * v.x + a[4] * v.y + a[5] * v.z);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_residual(SysView s, Reduce red, const double4* E0,
+                                                          const double4* t, double4* r, double4* z,
+                                                          double4* p, float4* p32, int rz_slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0, zz = 0.0;
+  if (i < s.npol) {
+    const double4 e = E0[i], tv = t[i];
+    const double4 rv = make_double4(e.x - tv.x, e.y - tv.y, e.z - tv.z, 0.0);
+    const double3 zv = amul(s.alpha + 6 * (size_t)i, rv);
+    r[i] = rv;
+    const double4 z4 = make_double4(zv.x, zv.y, zv.z, 0.0);
+    z[i] = z4;
+    p[i] = z4;
+    p32[i] = make_float4((float)zv.x, (float)zv.y, (float)zv.z, 0.f);
+    rz = rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
+    zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
+  }
+  block_reduce_to_slot(rz, red, rz_slot);
+  block_reduce_to_slot(zz, red, S_ZZ);
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz_slot,
+                                                   int rz_next_slot, double4* x, double4* r,
+                                                   double4* z, const double4* p, const double4* q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0, zz = 0.0;
+  if (i < s.npol) {
+    const double gamma = red.scalars[rz_slot] / red.scalars[S_PQ];
+    const double4 pv = p[i], qv = q[i];
+    double4 xv = x[i], rv = r[i];
+    xv.x += gamma * pv.x; xv.y += gamma * pv.y; xv.z += gamma * pv.z;
+    rv.x -= gamma * qv.x; rv.y -= gamma * qv.y; rv.z -= gamma * qv.z;
+    const double3 zv = amul(s.alpha + 6 * (size_t)i, rv);
+    x[i] = xv;
+    r[i] = rv;
+    z[i] = make_double4(zv.x, zv.y, zv.z, 0.0);
+    rz = rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
+    zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
+  }
+  block_reduce_to_slot(rz, red, rz_next_slot);
+  block_reduce_to_slot(zz, red, S_ZZ);
+}
+
+// p = z + beta p with beta = scalars[num] / scalars[den] (no grid to spread)
+__global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int num, int den,
+                                                      const double4* z, double4* p, float4* p32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.npol) return;
+  const double beta = red.scalars[num] / red.scalars[den];
+  const double4 zv = z[i], pv = p[i];
+  const double4 o = make_double4(zv.x + beta * pv.x, zv.y + beta * pv.y, zv.z + beta * pv.z, 0.0);
+  p[i] = o;
+  p32[i] = make_float4((float)o.x, (float)o.y, (float)o.z, 0.f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_precond(SysView s, const double4* in, double4* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.npol) return;
+  const double3 v = amul(s.alpha + 6 * (size_t)i, in[i]);
+  out[i] = make_double4(v.x, v.y, v.z, 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(SysView s, Reduce red, const double4* a,
+                                                const double4* b, int slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (i < s.npol) {
+    const double4 u = a[i], v = b[i];
+    d = u.x * v.x + u.y * v.y + u.z * v.z;
+  }
+  block_reduce_to_slot(d, red, slot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red, const double4* E0,
+                                                          const double4* t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double zz = 0.0;
+  if (i < s.npol) {
+    const double4 e = E0[i], tv = t[i];
+    const double4 rv = make_double4(e.x - tv.x, e.y - tv.y, e.z - tv.z, 0.0);
+    const double3 zv = amul(s.alpha + 6 * (size_t)i, rv);
+    zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
+  }
+  block_reduce_to_slot(zz, red, S_ZZ);
+}
+
+__global__ void k_copy4(const double4* in, double4* out, float4* out32, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 v = in[i];
+  out[i] = v;
+  if (out32) out32[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
+}
+
+__global__ void k_mu_sites(SysView s, const double4* x, double4* mu, float4* mu32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const int pi = s.polidx[i];
+  const double4 v = pi >= 0 ? x[pi] : make_double4(0.0, 0.0, 0.0, 0.0);
+  mu[i] = v;
+  mu32[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
+}
+
+__global__ void k_pol_to_caller(SysView s, const int* perm, const double4* v, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const int pi = s.polidx[i];
+  const double4 a = pi >= 0 ? v[pi] : make_double4(0.0, 0.0, 0.0, 0.0);
+  const size_t c = perm[i];
+  out[3 * c] = a.x;
+  out[3 * c + 1] = a.y;
+  out[3 * c + 2] = a.z;
+}
+
+__global__ void k_caller_to_pol(SysView s, const int* perm, const double* in, double4* v,
+                                float4* v32) {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= s.npol) return;
+  const size_t c = perm[s.polsite[pi]];
+  const double4 a = make_double4(in[3 * c], in[3 * c + 1], in[3 * c + 2], 0.0);
+  v[pi] = a;
+  if (v32) v32[pi] = make_float4((float)a.x, (float)a.y, (float)a.z, 0.f);
+}
+
+__global__ void k_forces_out(int n, const int* perm, const double4* F, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 f = F[i];
+  const size_t c = perm[i];
+  out[3 * c] = kCoulomb * f.x;
+  out[3 * c + 1] = kCoulomb * f.y;
+  out[3 * c + 2] = kCoulomb * f.z;
+}
+
+__global__ void k_counts_out(int n, const int* perm, const int* counts, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[perm[i]] = counts[i];
+}
+
+static dim3 grid_for(int n) { return dim3(n > 0 ? (n + kBlock - 1) / kBlock : 1); }
+
+void launch_init_residual(const SysView& s, const Reduce& red, const double4* E0, const double4* t,
+                          double4* r, double4* z, double4* p, float4* p32, int rz_slot,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_init_residual, grid_for(s.npol), dim3(kBlock), 0, st, s, red, E0, t, r, z,
+                     p, p32, rz_slot);
+}
+void launch_update(const SysView& s, const Reduce& red, int rz_slot, int rz_next_slot, double4* x,
+                   double4* r, double4* z, const double4* p, const double4* q, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, grid_for(s.npol), dim3(kBlock), 0, st, s, red, rz_slot,
+                     rz_next_slot, x, r, z, p, q);
+}
+void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
+                      double4* p, float4* p32, hipStream_t st) {
+  hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32);
+}
+void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
+}
+void launch_dot(const SysView& s, const Reduce& red, const double4* a, const double4* b, int slot,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, grid_for(s.npol), dim3(kBlock), 0, st, s, red, a, b, slot);
+}
+void launch_residual_norm(const SysView& s, const Reduce& red, const double4* E0, const double4* t,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_norm, grid_for(s.npol), dim3(kBlock), 0, st, s, red, E0, t);
+}
+void launch_copy4(const double4* in, double4* out, float4* out32, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_copy4, grid_for(n), dim3(kBlock), 0, st, in, out, out32, n);
+}
+void launch_mu_sites(const SysView& s, const double4* x, double4* mu, float4* mu32, hipStream_t st) {
+  hipLaunchKernelGGL(k_mu_sites, grid_for(s.n), dim3(kBlock), 0, st, s, x, mu, mu32);
+}
+void launch_pol_to_caller(const SysView& s, const int* perm, const double4* v, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_pol_to_caller, grid_for(s.n), dim3(kBlock), 0, st, s, perm, v, out);
+}
+void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, double4* v,
+                          float4* v32, hipStream_t st) {
+  if (s.npol > 0)
+    hipLaunchKernelGGL(k_caller_to_pol, grid_for(s.npol), dim3(kBlock), 0, st, s, perm, in, v, v32);
+}
+void launch_forces_out(int n, const int* perm, const double4* F, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_forces_out, grid_for(n), dim3(kBlock), 0, st, n, perm, F, out);
+}
+
+void launch_counts_out(int n, const int* perm, const int* counts, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_counts_out, grid_for(n), dim3(kBlock), 0, st, n, perm, counts, out);
+}
+
+}  // namespace sibfa

@@ -1,0 +1,173 @@
+"""Python binding of the C-ABI with torch tensors for device memory and the
+current torch stream.  Every computation runs in the HIP library; this
+module only checks shapes/dtypes and passes pointers.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+class SibfaError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+
+
+def default_params(**kw):
+    lib = _lib.load()
+    p = _lib.Params()
+    lib.sibfa_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "grid":
+            g = (v, v, v) if isinstance(v, int) else tuple(v)
+            p.grid[0], p.grid[1], p.grid[2] = g
+        elif k == "precision":
+            p.precision = {"fp64": _lib.FP64, "mixed": _lib.MIXED}.get(v, v)
+        elif k == "beta":
+            p.ewald_beta = v
+        elif k == "tol":
+            p.tol_debye = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def footprint_bytes(n_sites, n_polarizable, box, params):
+    lib = _lib.load()
+    b = None if box is None else (ctypes.c_double * 3)(*[float(x) for x in box])
+    return int(lib.sibfa_footprint_bytes(int(n_sites), int(n_polarizable), b, ctypes.byref(params)))
+
+
+def _dev(t, dtype, shape, device, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Engine:
+    """One system (box or cluster) resident on one device."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.sibfa_create(ctypes.byref(h), int(device),
+                                   ctypes.c_void_p(self.stream.cuda_stream), None, None, None)
+        if st != 0:
+            raise SibfaError(st, "sibfa_create failed")
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sibfa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SibfaError(st, self.lib.sibfa_last_error(self.h).decode())
+
+    # -- setup ------------------------------------------------------------
+    def set_system(self, pos, mol, box, params):
+        n = pos.shape[0]
+        _dev(pos, torch.float64, (n, 3), self.device, "pos")
+        _dev(mol, torch.int32, (n,), self.device, "mol")
+        b = None if box is None else (ctypes.c_double * 3)(*[float(x) for x in box])
+        self.params = params
+        self._check(self.lib.sibfa_set_system(self.h, n, _ptr(pos), _ptr(mol), b,
+                                              ctypes.byref(params)))
+        self.n = n
+
+    def update_positions(self, pos):
+        _dev(pos, torch.float64, (self.n, 3), self.device, "pos")
+        self._check(self.lib.sibfa_update_positions(self.h, _ptr(pos)))
+
+    def set_multipoles(self, q, dip=None, quad=None):
+        _dev(q, torch.float64, (self.n,), self.device, "q")
+        _dev(dip, torch.float64, (self.n, 3), self.device, "dip")
+        _dev(quad, torch.float64, (self.n, 6), self.device, "quad")
+        self._check(self.lib.sibfa_set_multipoles(self.h, _ptr(q), _ptr(dip), _ptr(quad)))
+
+    def set_polarizabilities(self, alpha, thole=None):
+        _dev(alpha, torch.float64, (self.n, 6), self.device, "alpha")
+        _dev(thole, torch.float64, (self.n,), self.device, "thole")
+        self._check(self.lib.sibfa_set_polarizabilities(self.h, _ptr(alpha), _ptr(thole)))
+
+    def load(self, sysd, params):
+        """Convenience: system dict (numpy arrays as produced by synth)."""
+        dev = self.device
+        t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+        self.set_system(t(sysd["pos"]), t(sysd["mol"], torch.int32), sysd.get("box"), params)
+        self.set_multipoles(t(sysd["q"]), t(sysd["dip"]), t(sysd["quad"]))
+        self.set_polarizabilities(t(sysd["alpha"]),
+                                  None if sysd.get("thole") is None else t(sysd["thole"]))
+
+    # -- compute ----------------------------------------------------------
+    def permanent_field(self):
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        self._check(self.lib.sibfa_permanent_field(self.h, _ptr(out)))
+        return out
+
+    def apply_T(self, p):
+        _dev(p, torch.float64, (self.n, 3), self.device, "p")
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        self._check(self.lib.sibfa_apply_T(self.h, _ptr(p), _ptr(out)))
+        return out
+
+    def solve(self, warm_start=False):
+        mu = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int(0)
+        rms = ctypes.c_double(0.0)
+        self._check(self.lib.sibfa_solve_induced(self.h, int(bool(warm_start)), _ptr(mu),
+                                                 ctypes.byref(it), ctypes.byref(rms)))
+        return mu, it.value, rms.value
+
+    def energy_forces(self, forces=True, out=None):
+        e_pol = ctypes.c_double(0.0)
+        e_elec = ctypes.c_double(0.0)
+        f = None
+        if forces:
+            f = out if out is not None else torch.empty((self.n, 3), dtype=torch.float64,
+                                                        device=self.device)
+            _dev(f, torch.float64, (self.n, 3), self.device, "forces")
+        self._check(self.lib.sibfa_energy_forces(self.h, ctypes.byref(e_pol), ctypes.byref(e_elec),
+                                                 _ptr(f), None))
+        return e_pol.value, e_elec.value, f
+
+    def get_dipoles(self):
+        mu = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        self._check(self.lib.sibfa_get_dipoles(self.h, _ptr(mu)))
+        return mu
+
+    def set_dipoles(self, mu):
+        _dev(mu, torch.float64, (self.n, 3), self.device, "mu")
+        self._check(self.lib.sibfa_set_dipoles(self.h, _ptr(mu)))
+
+    def neighbor_counts(self):
+        out = torch.empty((self.n,), dtype=torch.int32, device=self.device)
+        self._check(self.lib.sibfa_neighbor_counts(self.h, _ptr(out)))
+        return out
+
+    def stats(self):
+        s = _lib.Stats()
+        self._check(self.lib.sibfa_get_stats(self.h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_}

@@ -1,0 +1,115 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bars (FP64 path): energies within 1e-6 relative, forces within 1e-5
+relative RMS; fields, T p and mu elementwise within 1e-8 of their largest
+entry (both sides are FP64; only summation order and library erfc/exp
+differ).  Integer work (neighbour counts) bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import cKDTree
+
+import oracle
+from oracle.model import System, Context, permanent_field, apply_T
+from synth import water_box, water_cluster, config_system
+from tests.gpu_util import (say, oracle_params, gpu_params, engine_for, rel_err, rms_rel,
+                            pol_rows)
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-6
+F_TOL = 1e-5
+V_TOL = 1e-8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _compare_full(sysd, kw, label, iters_slack=1):
+    say(f"[parity] {label}: n_sites={len(sysd['pos'])}")
+    s = System.from_dict(sysd)
+    op = oracle_params(sysd, **kw)
+    ctx = Context(s, op)
+    rows = pol_rows(sysd)
+    E0_o = permanent_field(s, op, ctx=ctx)
+    rng = np.random.default_rng(17)
+    pvec = rng.normal(size=(len(rows), 3)) * 0.1
+    Tp_o = apply_T(s, op, pvec, ctx=ctx)
+    ref = oracle.evaluate(s, op)
+
+    eng = engine_for(sysd, gpu_params(sysd, **kw))
+    E0_g = eng.permanent_field().cpu().numpy()
+    assert rel_err(E0_g[rows], E0_o) < V_TOL, rel_err(E0_g[rows], E0_o)
+    nonpol = np.setdiff1d(np.arange(len(sysd["pos"])), rows)
+    assert np.all(E0_g[nonpol] == 0.0)
+    pfull = np.zeros((len(sysd["pos"]), 3))
+    pfull[rows] = pvec
+    Tp_g = eng.apply_T(torch.as_tensor(pfull, device="cuda")).cpu().numpy()
+    assert rel_err(Tp_g[rows], Tp_o) < V_TOL, rel_err(Tp_g[rows], Tp_o)
+    mu_g, it, rms = eng.solve()
+    mu_g = mu_g.cpu().numpy()
+    assert rms <= kw.get("tol", 1e-10)
+    assert rel_err(mu_g[rows], ref["mu"]) < 1e-7, rel_err(mu_g[rows], ref["mu"])
+    assert abs(it - ref["iters"]) <= iters_slack, (it, ref["iters"])
+    e_pol, e_elec, F = eng.energy_forces()
+    F = F.cpu().numpy()
+    st = eng.stats()
+    say(f"  E_pol gpu {e_pol:.12g} oracle {ref['E_pol']:.12g}; E_elec gpu {e_elec:.12g} "
+        f"oracle {ref['E_elec']:.12g}; F rms rel {rms_rel(F, ref['forces']):.3e}; "
+        f"iters {it}/{ref['iters']}")
+    assert abs(e_pol - ref["E_pol"]) <= E_TOL * abs(ref["E_pol"]) + 1e-12
+    assert abs(e_elec - ref["E_elec"]) <= E_TOL * abs(ref["E_elec"]) + 1e-12
+    assert abs(st["e_pol_variational"] - ref["E_pol_var"]) <= E_TOL * abs(ref["E_pol"]) + 1e-12
+    assert rms_rel(F, ref["forces"]) <= F_TOL
+    eng.close()
+
+
+@pytest.mark.parametrize("nw,seed", [(1, 0), (2, 1), (9, 2), (33, 3), (64, 4)])
+def test_cluster_parity(nw, seed):
+    _compare_full(water_cluster(nw, seed), dict(tol=1e-10), f"cluster{nw}")
+
+
+def test_small_box_parity():
+    # 27 waters, 9.5 A box: every site sees most of the box; ragged PME grid 24
+    _compare_full(water_box(27, 9.5, 3), dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-10),
+                  "box27")
+
+
+def test_small_box_other_orders():
+    for order, grid in ((4, 20), (6, 30)):
+        _compare_full(water_box(27, 9.5, 5), dict(beta=0.45, cutoff=4.5, grid=grid, order=order,
+                                                  tol=1e-10), f"box27-order{order}")
+
+
+@pytest.mark.slow
+def test_box216_parity():
+    d, prm = config_system("box216")
+    _compare_full(d, dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"], tol=1e-10),
+                  "box216")
+
+
+def _kdtree_counts(sysd, cutoff):
+    pos = np.mod(sysd["pos"], sysd["box"])
+    tree = cKDTree(pos, boxsize=sysd["box"])
+    pairs = tree.query_pairs(cutoff, output_type="ndarray")
+    mol = sysd["mol"]
+    inter = pairs[mol[pairs[:, 0]] != mol[pairs[:, 1]]]
+    cnt = np.zeros(len(pos), np.int64)
+    np.add.at(cnt, inter[:, 0], 1)
+    np.add.at(cnt, inter[:, 1], 1)
+    return cnt
+
+
+@pytest.mark.parametrize("name", ["box216", "box4096"])
+def test_neighbor_counts_exact(name):
+    say(f"[nlist] {name}")
+    d, prm = config_system(name)
+    eng = engine_for(d, gpu_params(d, beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"]))
+    got = eng.neighbor_counts().cpu().numpy()
+    ref = _kdtree_counts(d, prm["cutoff"])
+    assert np.array_equal(got, ref)
+    eng.close()
