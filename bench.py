@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Benchmark of the polarization path on one MI355X.
+
+One step = one full pol+elec energy/force evaluation of the 32,000-water
+periodic box (98.55 A, cutoff 9 A, beta 0.40/A, SPME 96^3 order 5, PCG to a
+true-residual RMS of 1e-8 D, cold start): cell sort and neighbour lists,
+permanent field (real space + SPME), PCG solve, E_pol, E_elec and all site
+forces.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is evaluations per second of the precision
+named in `dtype`; both precisions are reported under "fp64" and "mixed".
+The roofline object covers the kernel with the largest share of the timed
+region (per-launch durations from HIP events recorded by the library on its
+own stream).  The CPU baseline times the FP64 oracle on a bounded sample of
+the same workload and scales it to one evaluation.
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pol+elec energy/force evals/s @32k waters, FP32-mixed vs FP64; p50/p99 latency"
+WORKLOAD = "box32000"
+
+# MI355X published peaks.  The pair kernels run on the vector ALUs without
+# packed FP32 (disabled at compile time), so FP32 and FP64 share the
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s rate.
+PEAK_ALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic flop counts (FMA = 2, each erfc/exp/rsqrt = 1), see the design doc:
+# one damped dipole-dipole pair of the matvec, and the per-site share of the
+# fused PME gather (order 5: 25 columns x 5 points x 4 + 25 x 9 + splines
+# + alpha^-1 p and the residual bookkeeping).
+FLOPS_MATVEC_PAIR = 69
+FLOPS_MATVEC_SITE = 855
+FLOPS_FORCE_PAIR = 560
+FLOPS_FIELD_PAIR = 190
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_gpu(sysd, prm, precision, steps, warmup):
+    import torch
+    from paper_2201_00804_amd import Engine, default_params
+
+    params = default_params(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"],
+                            order=prm["order"], tol=prm["tol"], precision=precision,
+                            max_iter=400)
+    eng = Engine(0)
+    eng.load(sysd, params)
+    dev = eng.device
+    pos = torch.as_tensor(sysd["pos"], dtype=torch.float64, device=dev).contiguous()
+    F = torch.empty_like(pos)
+
+    def step():
+        eng.update_positions(pos)
+        _, it, rms = eng.solve(warm_start=False)
+        e_pol, e_elec, _ = eng.energy_forces(out=F)
+        return it, rms, e_pol, e_elec
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    eng.set_profiling(True)
+    times = []
+    info = None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    prof = eng.profile()
+    eng.set_profiling(False)
+    st = eng.stats()
+    out = dict(total_s=total, step_s=times, iters=info[0], true_rms_debye=info[1],
+               e_pol=info[2], e_elec=info[3], profile=prof, stats=st,
+               forces=F.detach().cpu().numpy(), mu=eng.get_dipoles().cpu().numpy())
+    eng.close()
+    return out
+
+
+def roofline(res, steps):
+    prof = res["profile"]
+    ms = prof["ms"]
+    calls = prof["calls"]
+    pairs = prof["pairs"]
+    npol = res["stats"]["n_polarizable"]
+    n = res["stats"]["n_sites"]
+    dom = max(ms, key=lambda k: ms[k])
+    share = {k: round(v / max(sum(ms.values()), 1e-30), 4) for k, v in ms.items()}
+    avg_ms = ms[dom] / max(calls[dom], 1)
+    if dom == "matvec":
+        flops = (pairs["pol"] + pairs["pol_same_molecule"]) * FLOPS_MATVEC_PAIR + \
+            npol * FLOPS_MATVEC_SITE
+    elif dom == "force_real":
+        flops = (pairs["all"] + pairs["same_molecule"]) * FLOPS_FORCE_PAIR
+    elif dom == "field_real":
+        flops = (pairs["all"] + pairs["same_molecule"]) * FLOPS_FIELD_PAIR
+    else:
+        flops = None
+    if flops is None:
+        return dict(kernel=dom, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=None, traffic=None, avg_launch_ms=avg_ms, phase_share=share)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    return dict(kernel={"matvec": "k_matvec", "force_real": "k_force",
+                        "field_real": "k_perm"}[dom],
+                bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS,
+                unit="TFLOP/s", frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=None,
+                avg_launch_ms=round(avg_ms, 4), flops_per_launch=int(flops),
+                launches=calls[dom], phase_share=share)
+
+
+def cpu_baseline(sysd, prm, iters, sample=24):
+    """The FP64 oracle on a bounded sample of the same box, scaled to one
+    evaluation: the oracle's real-space pair sums for `sample` sites
+    (polarizable ones for E and T p, arbitrary ones for forces and the MM
+    energy) and its neighbour search for them, each scaled by N/sample, plus
+    one full-size SPME pass of each kind (permanent field; dipoles, once per
+    matvec; combined density for forces)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import realspace as rs
+    from oracle.model import System, Params, Context
+
+    with threadpool_limits(limits=1):
+        s = System.from_dict(sysd)
+        p = Params(method="spme", beta=prm["beta"], cutoff=prm["cutoff"],
+                   grid=(prm["grid"],) * 3, order=prm["order"], tol=prm["tol"])
+        pol = s.pol
+        rng = np.random.default_rng(7)
+        samp_pol = np.sort(rng.choice(pol, sample, replace=False))
+        samp_all = np.sort(rng.choice(s.n, sample, replace=False))
+        both = np.union1d(samp_pol, samp_all)
+        t, wall = {}, 0.0
+
+        def timed(fn):
+            nonlocal wall
+            t0 = time.perf_counter()
+            out = fn()
+            dt = time.perf_counter() - t0
+            wall += dt
+            return out, dt
+
+        _, t_fixed = timed(lambda: Context(s, p, subset=both[:1]))
+        ctx, t_ctx = timed(lambda: Context(s, p, subset=both))
+        t["pairs"] = t_fixed + max(t_ctx - t_fixed, 0.0) * s.n / len(both)
+        mult = (s.q, s.dip, s.th)
+        none3 = (None, None, None)
+        I = ctx.pairs.i
+        m_pol = np.isin(I, samp_pol)
+        m_all = np.isin(I, samp_all)
+        _, dt = timed(lambda: rs.pair_sum(ctx.pairs, "Mmu", ctx.kernel, p.beta, ctx.thole, none3,
+                                          mult, "field", s.n, pair_mask=m_pol))
+        t["real_field"] = dt * len(pol) / sample
+        _, t["spme_field"] = timed(lambda: ctx.recip_derivs(mult, s.pos[samp_pol], 1))
+        pv = rng.normal(size=(len(pol), 3)) * 0.05
+        pf = ctx.full(pv)
+        mask_t = m_pol & ctx.is_pol[ctx.pairs.j]
+        _, dt = timed(lambda: rs.pair_sum(ctx.pairs, ctx.mumu_cls, ctx.kernel, p.beta, ctx.thole,
+                                          none3, (None, pf, None), "field", s.n, pair_mask=mask_t))
+        _, t_spme_t = timed(lambda: ctx.recip_derivs((None, pf, None), s.pos[samp_pol], 1))
+        t["matvec_per_iter"] = dt * len(pol) / sample + t_spme_t
+        mud = (None, pf, None)
+
+        def forces():
+            for cls, a, b in (("MM", mult, mult), ("Mmu", mud, mult), ("Mmu", mult, mud),
+                              (ctx.mumu_cls, mud, mud)):
+                rs.pair_sum(ctx.pairs, cls, ctx.kernel, p.beta, ctx.thole, a, b, "force", s.n,
+                            pair_mask=m_all)
+
+        _, dt = timed(forces)
+        t["real_force"] = dt * s.n / sample
+        comb = (s.q, s.dip + pf, s.th)
+        _, t["spme_force"] = timed(lambda: ctx.recip_derivs(comb, s.pos[samp_all], 3))
+        _, dt = timed(lambda: rs.pair_sum(ctx.pairs, "MM", ctx.kernel, p.beta, ctx.thole, mult,
+                                          mult, "energy", s.n, pair_mask=m_all))
+        t["real_energy"] = dt * s.n / sample
+        t_eval = (t["pairs"] + t["real_field"] + t["spme_field"] + (iters + 1) *
+                  t["matvec_per_iter"] + t["real_force"] + t["spme_force"] + t["real_energy"])
+    return dict(value=1.0 / t_eval, unit="evals/s", cores=1, kind="oracle",
+                sample=(f"{sample} polarizable + {sample} arbitrary sites of the 32,000-water "
+                        f"box (real-space rows and neighbour search scaled by N/sample) plus "
+                        f"full-size SPME passes (permanent; dipole, once per matvec; combined "
+                        f"for forces); {iters + 1} matvecs per solve; {wall:.1f} s of "
+                        f"measured single-thread CPU work"),
+                seconds_per_eval=round(t_eval, 1),
+                parts_s={k: round(v, 2) for k, v in t.items()})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path is built for a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from synth import config_system
+    sysd, prm = config_system(WORKLOAD)
+    import numpy as np
+
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precisions:
+        print(f"[bench] {prec}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+              flush=True)
+        results[prec] = run_gpu(sysd, prm, prec, args.steps, args.warmup)
+        r = results[prec]
+        print(f"[bench] {prec}: {1e3 * r['total_s'] / args.steps:.2f} ms/step, iters "
+              f"{r['iters']}, rms {r['true_rms_debye']:.2e} D", file=sys.stderr, flush=True)
+
+    def summary(r):
+        return dict(value=round(args.steps / r["total_s"], 3),
+                    ms_per_step=round(1e3 * r["total_s"] / args.steps, 3),
+                    p50_ms=round(1e3 * _percentile(r["step_s"], 0.5), 3),
+                    p99_ms=round(1e3 * _percentile(r["step_s"], 0.99), 3),
+                    iterations=r["iters"], restarts=r["stats"]["restarts"],
+                    true_rms_debye=r["true_rms_debye"], e_pol=r["e_pol"], e_elec=r["e_elec"],
+                    phase_ms_per_step={k: round(v / args.steps, 4)
+                                       for k, v in r["profile"]["ms"].items()})
+
+    head = "mixed" if "mixed" in results else precisions[0]
+    main_r = results[head]
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / main_r["total_s"], 3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * main_r["total_s"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "32,000 rigid waters, 98.55 A periodic box, cutoff 9 A, "
+                               "beta 0.40/A, SPME 96^3 order 5, PCG to 1e-8 D RMS (cold start)",
+                   "n_waters": 32000, "n_sites": len(sysd["pos"]), "precision": head},
+        "latency_ms": {"p50": round(1e3 * _percentile(main_r["step_s"], 0.5), 3),
+                       "p99": round(1e3 * _percentile(main_r["step_s"], 0.99), 3)},
+        "roofline": roofline(main_r, args.steps),
+    }
+    for k, r in results.items():
+        out[k] = summary(r)
+    if "fp64" in results and "mixed" in results:
+        a, b = results["fp64"], results["mixed"]
+        rel = lambda x, y: abs(x - y) / max(abs(y), 1e-300)
+        out["mixed_vs_fp64"] = {
+            "speedup": round(a["total_s"] / b["total_s"], 3),
+            "e_pol_rel": rel(b["e_pol"], a["e_pol"]),
+            "e_elec_rel": rel(b["e_elec"], a["e_elec"]),
+            "force_rms_rel": float(np.sqrt(np.mean((b["forces"] - a["forces"]) ** 2) /
+                                           np.mean(a["forces"] ** 2))),
+            "mu_rms_debye": float(4.803204 * np.sqrt(np.mean(np.sum((b["mu"] - a["mu"]) ** 2, 1)))),
+        }
+    if not args.no_cpu_baseline:
+        iters = results.get("fp64", main_r)["iters"]
+        print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sysd, prm, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

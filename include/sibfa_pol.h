@@ -173,6 +173,32 @@ sibfa_status sibfa_neighbor_counts(sibfa_ctx ctx, int32_t* counts_out);
 /* Statistics of the last solve / energy evaluation (HOST). */
 sibfa_status sibfa_get_stats(sibfa_ctx ctx, sibfa_stats* out);
 
+/* Per-phase kernel timing with HIP events recorded on the context's stream
+ * around the launches of each phase (enable = 1 starts and clears the
+ * accumulators, 0 stops).  Phases: */
+typedef enum {
+  SIBFA_PH_LISTS = 0,     /* binning, cell sort, records, neighbour lists   */
+  SIBFA_PH_FIELD_REAL,    /* real-space permanent field + E_elec pairs      */
+  SIBFA_PH_FIELD_RECIP,   /* permanent PME: spread, convolution, gather     */
+  SIBFA_PH_SPREAD,        /* solver: direction update + dipole spreading    */
+  SIBFA_PH_FFT,           /* solver: 3D FFT convolution (5 passes)          */
+  SIBFA_PH_MATVEC,        /* solver: real-space T p with fused PME gather   */
+  SIBFA_PH_UPDATE,        /* solver: x, r, z updates and dot products       */
+  SIBFA_PH_FORCE_REAL,    /* real-space forces                              */
+  SIBFA_PH_FORCE_RECIP,   /* combined-density PME forces                    */
+  SIBFA_PH_COUNT
+} sibfa_phase;
+
+typedef struct {
+  double ms[16];          /* accumulated event time per phase, milliseconds */
+  int calls[16];          /* number of timed launches (groups) per phase    */
+  long long pairs[4];     /* list entries: all, same-molecule, pol, pol-same */
+} sibfa_profile;
+
+sibfa_status sibfa_set_profiling(sibfa_ctx ctx, int enable);
+/* Synchronizes the stream and returns the accumulated times. */
+sibfa_status sibfa_get_profile(sibfa_ctx ctx, sibfa_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

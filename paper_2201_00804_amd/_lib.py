@@ -31,6 +31,14 @@ class Stats(ctypes.Structure):
                 ("n_polarizable", ctypes.c_int), ("max_neighbors", ctypes.c_int)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("calls", ctypes.c_int * 16),
+                ("pairs", ctypes.c_longlong * 4)]
+
+
+PHASES = ["lists", "field_real", "field_recip", "spread", "fft", "matvec", "update",
+          "force_real", "force_recip"]
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -56,6 +64,8 @@ SIGNATURES = [
     ("sibfa_set_dipoles", ctypes.c_int, [_P, _P]),
     ("sibfa_neighbor_counts", ctypes.c_int, [_P, _P]),
     ("sibfa_get_stats", ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    ("sibfa_set_profiling", ctypes.c_int, [_P, ctypes.c_int]),
+    ("sibfa_get_profile", ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
 ]
 
 _lib = None

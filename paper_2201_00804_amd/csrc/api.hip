@@ -95,6 +95,16 @@ struct sibfa_ctx_s {
   Reduce red{};
   double* h_pinned = nullptr;   // host copies of the reduction scalars
   int* h_ints = nullptr;
+  unsigned long long* dsums = nullptr;   // list entry totals
+  long long pair_totals[4] = {0, 0, 0, 0};
+  // profiling: HIP events on the context stream around each phase
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  struct Mark { int phase; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  double prof_ms[16] = {0};
+  int prof_calls[16] = {0};
 };
 
 namespace {
@@ -271,6 +281,53 @@ sibfa_status read_scalars(sibfa_ctx c, int first, int count) {
   return sync_read(c);
 }
 
+// ------------------------------------------------------------ profiling
+hipEvent_t next_event(sibfa_ctx c) {
+  if (c->evused < c->evpool.size()) return c->evpool[c->evused++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  c->evpool.push_back(e);
+  c->evused++;
+  return e;
+}
+
+void fold_marks(sibfa_ctx c) {
+  if (c->marks.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& m : c->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      c->prof_ms[m.phase] += ms;
+      c->prof_calls[m.phase] += 1;
+    }
+  }
+  c->marks.clear();
+  c->evused = 0;
+}
+
+// Brackets the launches of one phase with events when profiling is on.
+struct Phase {
+  sibfa_ctx c;
+  int ph;
+  hipEvent_t a = nullptr;
+  Phase(sibfa_ctx cc, int p) : c(cc), ph(p) {
+    if (c->prof) {
+      if (c->marks.size() > 4096) fold_marks(c);
+      a = next_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Phase() {
+    if (c->prof && a) {
+      hipEvent_t b = next_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->marks.push_back({ph, a, b});
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------ preparation
 sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
   for (int k = 0; k < 4; ++k) {
@@ -326,7 +383,10 @@ sibfa_status build_lists(sibfa_ctx c) {
     a.nb_ipol = c->nb[3]; a.nc_ipol = c->ncnt[3]; a.cap_ipol = c->cap[3];
     a.maxcnt = c->dints;
     a.err = c->dints + 4;
-    launch_nlist(a, c->ncell, c->stream);
+    {
+      Phase ph(c, SIBFA_PH_LISTS);
+      launch_nlist(a, c->ncell, c->stream);
+    }
     HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     sibfa_status s2 = sync_read(c);
     if (s2 != SIBFA_OK) return s2;
@@ -337,7 +397,18 @@ sibfa_status build_lists(sibfa_ctx c) {
     for (int k = 0; k < 4; ++k)
       if (c->h_ints[k] > c->cap[k]) { over = true; want[k] = c->h_ints[k] + 16; }
     c->stats.max_neighbors = c->h_ints[0];
-    if (!over) return SIBFA_OK;
+    if (!over) {
+      launch_fill_int(reinterpret_cast<int*>(c->dsums), 0, 8, c->stream);
+      const int rows[4] = {c->n, c->n, c->npol, c->npol};
+      for (int k = 0; k < 4; ++k) launch_sum_ints(c->ncnt[k], rows[k], c->dsums + k, c->stream);
+      HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->dsums, 4 * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, c->stream));
+      sibfa_status s3 = sync_read(c);
+      if (s3 != SIBFA_OK) return s3;
+      for (int k = 0; k < 4; ++k)
+        c->pair_totals[k] = (long long)reinterpret_cast<unsigned long long*>(c->h_pinned + 32)[k];
+      return SIBFA_OK;
+    }
   }
   return fail(c, SIBFA_E_NOMEM, "neighbour lists kept overflowing");
 }
@@ -380,11 +451,14 @@ sibfa_status prepare(sibfa_ctx c) {
     }
     b.xyz = c->xyz_c; b.mol = c->mol_c; b.cell_of = c->cell_of; b.cell_count = c->cell_count;
     b.mol_count = c->mol_count; b.err = c->dints + 4;
-    launch_bin(b, s);
-    launch_exclusive_scan(c->cell_count, c->cell_start, c->ncell + 1, c->scan_tmp, s);
-    launch_scatter(c->cell_of, c->cell_start, c->cursor, c->perm, c->n, s);
-    launch_sort_cells(c->cell_start, c->ncell, c->perm, s);
-    launch_rec_pos(ra, s);
+    {
+      Phase ph(c, SIBFA_PH_LISTS);
+      launch_bin(b, s);
+      launch_exclusive_scan(c->cell_count, c->cell_start, c->ncell + 1, c->scan_tmp, s);
+      launch_scatter(c->cell_of, c->cell_start, c->cursor, c->perm, c->n, s);
+      launch_sort_cells(c->cell_start, c->ncell, c->perm, s);
+      launch_rec_pos(ra, s);
+    }
     HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
     sibfa_status st = sync_read(c);
     if (st != SIBFA_OK) return st;
@@ -435,17 +509,26 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     du.upd = 0;
     du.p = v;
     du.p32 = v32;
-    launch_spread_dip(s, c->pm, c->red, du, mix, c->stream);
+    {
+      Phase ph(c, SIBFA_PH_SPREAD);
+      launch_spread_dip(s, c->pm, c->red, du, mix, c->stream);
+    }
+    Phase ph(c, SIBFA_PH_FFT);
     conv(c, mix);
   }
+  Phase ph(c, SIBFA_PH_MATVEC);
   launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, c->stream);
 }
 
 sibfa_status compute_E0(sibfa_ctx c) {
   SysView s = make_view(c);
   const bool mix = mixed(c);
-  launch_perm(s, c->red, c->E0, mix, c->stream);
+  {
+    Phase ph(c, SIBFA_PH_FIELD_REAL);
+    launch_perm(s, c->red, c->E0, mix, c->stream);
+  }
   if (c->periodic) {
+    Phase ph(c, SIBFA_PH_FIELD_RECIP);
     launch_spread_mult(s, c->pm, nullptr, mix, c->stream);
     conv(c, mix);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
@@ -503,9 +586,14 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         du.p = c->p;
         du.p32 = c->p32;
         if (c->periodic) {
-          launch_spread_dip(s, c->pm, c->red, du, mix, st);
+          {
+            Phase ph(c, SIBFA_PH_SPREAD);
+            launch_spread_dip(s, c->pm, c->red, du, mix, st);
+          }
+          Phase ph(c, SIBFA_PH_FFT);
           conv(c, mix);
         } else {
+          Phase ph(c, SIBFA_PH_SPREAD);
           launch_direction(s, c->red, du.num, du.den, c->z, c->p, c->p32, st);
         }
       } else if (c->periodic) {
@@ -513,12 +601,22 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         du.upd = 0;
         du.p = c->p;
         du.p32 = c->p32;
-        launch_spread_dip(s, c->pm, c->red, du, mix, st);
+        {
+          Phase ph(c, SIBFA_PH_SPREAD);
+          launch_spread_dip(s, c->pm, c->red, du, mix, st);
+        }
+        Phase ph(c, SIBFA_PH_FFT);
         conv(c, mix);
       }
-      launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
-      launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
-                    c->q, st);
+      {
+        Phase ph(c, SIBFA_PH_MATVEC);
+        launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
+      }
+      {
+        Phase ph(c, SIBFA_PH_UPDATE);
+        launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
+                      c->q, st);
+      }
       ++k;
       ++it;
       HIP_TRY(hipMemcpyAsync(c->h_pinned + S_PQ, c->red.scalars + S_PQ, 7 * sizeof(double),
@@ -686,6 +784,7 @@ void sibfa_destroy(sibfa_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   release_system(c);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
   delete c;
@@ -764,7 +863,7 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->polidx, n) && alloc_into(c, L, c->polsite, n) &&
             alloc_into(c, L, c->pp, n) && alloc_into(c, L, c->pp32, n) && alloc_into(c, L, c->pa, n) &&
             alloc_into(c, L, c->alpha_s, 6 * n) && alloc_into(c, L, c->ainv_s, 6 * n) &&
-            alloc_into(c, L, c->dints, 16) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
+            alloc_into(c, L, c->dints, 16) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
             alloc_into(c, L, c->r, n) && alloc_into(c, L, c->z, n) && alloc_into(c, L, c->p, n) &&
             alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
             alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->mu_s, n) &&
@@ -920,8 +1019,12 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   }
   if (forces) {
     launch_mu_sites(s, c->x, c->mu_s, c->mu_s32, sm);
-    launch_force(s, c->mu_s, c->mu_s32, c->Freal, mix, sm);
+    {
+      Phase ph(c, SIBFA_PH_FORCE_REAL);
+      launch_force(s, c->mu_s, c->mu_s32, c->Freal, mix, sm);
+    }
     if (c->periodic) {
+      Phase ph(c, SIBFA_PH_FORCE_RECIP);
       launch_spread_mult(s, c->pm, c->mu_s, mix, sm);
       conv(c, mix);
       launch_gather_force(s, c->pm, c->mu_s, c->Freal, c->perm, forces, mix, sm);
@@ -975,6 +1078,30 @@ sibfa_status sibfa_neighbor_counts(sibfa_ctx c, int32_t* counts_out) {
   if (st != SIBFA_OK) return st;
   launch_counts_out(c->n, c->perm, c->ncnt[0], counts_out, c->stream);
   return sync_read(c);
+}
+
+sibfa_status sibfa_set_profiling(sibfa_ctx c, int enable) {
+  if (!c) return SIBFA_E_ARG;
+  HIP_TRY(hipSetDevice(c->device));
+  fold_marks(c);
+  c->prof = enable != 0;
+  for (int k = 0; k < 16; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_calls[k] = 0;
+  }
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_get_profile(sibfa_ctx c, sibfa_profile* out) {
+  if (!c || !out) return SIBFA_E_ARG;
+  HIP_TRY(hipSetDevice(c->device));
+  fold_marks(c);
+  for (int k = 0; k < 16; ++k) {
+    out->ms[k] = c->prof_ms[k];
+    out->calls[k] = c->prof_calls[k];
+  }
+  for (int k = 0; k < 4; ++k) out->pairs[k] = c->pair_totals[k];
+  return SIBFA_OK;
 }
 
 sibfa_status sibfa_get_stats(sibfa_ctx c, sibfa_stats* out) {

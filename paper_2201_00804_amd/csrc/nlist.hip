@@ -162,6 +162,21 @@ __global__ void k_max_int(const int* v, int n, int* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
+__global__ void k_sum_ints(const int* v, int n, unsigned long long* out) {
+  unsigned long long m = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    m += (unsigned long long)v[i];
+  for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, m);
+}
+
+void launch_sum_ints(const int* v, int n, unsigned long long* out, hipStream_t s) {
+  int blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_sum_ints, dim3(blocks), dim3(kBlock), 0, s, v, n, out);
+}
+
 void launch_bin(const BinArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_bin, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
 }

@@ -167,6 +167,18 @@ class Engine:
         self._check(self.lib.sibfa_neighbor_counts(self.h, _ptr(out)))
         return out
 
+    def set_profiling(self, enable=True):
+        self._check(self.lib.sibfa_set_profiling(self.h, int(bool(enable))))
+
+    def profile(self):
+        """Accumulated per-phase event times (ms), launch groups and list sizes."""
+        pr = _lib.Profile()
+        self._check(self.lib.sibfa_get_profile(self.h, ctypes.byref(pr)))
+        return {"ms": {name: pr.ms[k] for k, name in enumerate(_lib.PHASES)},
+                "calls": {name: pr.calls[k] for k, name in enumerate(_lib.PHASES)},
+                "pairs": {"all": pr.pairs[0], "same_molecule": pr.pairs[1],
+                          "pol": pr.pairs[2], "pol_same_molecule": pr.pairs[3]}}
+
     def stats(self):
         s = _lib.Stats()
         self._check(self.lib.sibfa_get_stats(self.h, ctypes.byref(s)))
