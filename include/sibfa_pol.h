@@ -186,6 +186,7 @@ typedef enum {
   SIBFA_PH_UPDATE,        /* solver: x, r, z updates and dot products       */
   SIBFA_PH_FORCE_REAL,    /* real-space forces                              */
   SIBFA_PH_FORCE_RECIP,   /* combined-density PME forces                    */
+  SIBFA_PH_PAIRCOEF,      /* solver: damped pair coefficients, once a solve  */
   SIBFA_PH_COUNT
 } sibfa_phase;
 

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -91,9 +92,19 @@ struct sibfa_ctx_s {
   // PME
   PmeView pm{};
   std::vector<DevBuf> pmebufs;
+  int nbricks = 0;
+  int *bcount = nullptr, *bcursor = nullptr, *brick_of = nullptr, *bscan_tmp = nullptr;
+  int *bstart_pol = nullptr, *border_pol = nullptr, *bstart_all = nullptr, *border_all = nullptr;
+  // cached pol-list pair coefficients (FP64, or FP32 in mixed mode)
+  DevBuf coefbuf;
+  bool coef_valid = false;
+  // second direction buffer (the spread kernel reads one and writes the other)
+  double4* p2 = nullptr;
+  float4* p2_32 = nullptr;
   // reductions
   Reduce red{};
-  double* h_pinned = nullptr;   // host copies of the reduction scalars
+  double* h_pinned = nullptr;   // small host staging (list totals)
+  double* h_part = nullptr;     // host copies of reduction partials [S_COUNT][max_blocks]
   int* h_ints = nullptr;
   unsigned long long* dsums = nullptr;   // list entry totals
   long long pair_totals[4] = {0, 0, 0, 0};
@@ -223,6 +234,9 @@ SysView make_view(sibfa_ctx c) {
   s.nb_in = c->nb[1]; s.nc_in = c->ncnt[1]; s.cap_in = c->cap[1];
   s.nb_pol = c->nb[2]; s.nc_pol = c->ncnt[2]; s.cap_pol = c->cap[2];
   s.nb_ipol = c->nb[3]; s.nc_ipol = c->ncnt[3]; s.cap_ipol = c->cap[3];
+  const bool mix = c->prm.precision == SIBFA_MIXED;
+  s.cpol = mix ? nullptr : static_cast<const double2*>(c->coefbuf.p);
+  s.cpol32 = mix ? static_cast<const float2*>(c->coefbuf.p) : nullptr;
   return s;
 }
 
@@ -263,6 +277,13 @@ void release_system(sibfa_ctx c) {
     c->nb[k] = nullptr;
     c->cap[k] = 0;
   }
+  dev_free(c, c->coefbuf.p);
+  c->coefbuf = DevBuf{};
+  if (c->h_part) {
+    (void)hipHostFree(c->h_part);
+    c->h_part = nullptr;
+  }
+  c->coef_valid = false;
   c->have_sys = c->have_mult = c->have_pol = false;
   c->e0_valid = c->mu_valid = c->mu_have = false;
 }
@@ -275,10 +296,26 @@ sibfa_status sync_read(sibfa_ctx c) {
   return SIBFA_OK;
 }
 
-sibfa_status read_scalars(sibfa_ctx c, int first, int count) {
-  HIP_TRY(hipMemcpyAsync(c->h_pinned + first, c->red.scalars + first, count * sizeof(double),
-                         hipMemcpyDeviceToHost, c->stream));
-  return sync_read(c);
+// Totals of reduction slots: the partials written by each slot's last
+// producer are copied to the host and added in index order.
+sibfa_status read_totals(sibfa_ctx c, std::initializer_list<int> slots, double* out) {
+  for (int sl : slots) {
+    const int n = c->red.nparts[sl];
+    if (n > 0)
+      HIP_TRY(hipMemcpyAsync(c->h_part + (size_t)sl * c->red.max_blocks,
+                             c->red.partials + (size_t)sl * c->red.max_blocks, n * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  sibfa_status st = sync_read(c);
+  if (st != SIBFA_OK) return st;
+  int k = 0;
+  for (int sl : slots) {
+    double t = 0.0;
+    const double* p = c->h_part + (size_t)sl * c->red.max_blocks;
+    for (int b = 0; b < c->red.nparts[sl]; ++b) t += p[b];
+    out[k++] = t;
+  }
+  return SIBFA_OK;
 }
 
 // ------------------------------------------------------------ profiling
@@ -342,6 +379,15 @@ sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
     c->nb[k] = static_cast<int*>(ptr);
     c->cap[k] = want[k];
   }
+  const size_t cbytes = (size_t)std::max(c->npol, 1) * c->cap[2] *
+                        (c->prm.precision == SIBFA_MIXED ? sizeof(float2) : sizeof(double2));
+  if (c->coefbuf.bytes < cbytes) {
+    dev_free(c, c->coefbuf.p);
+    void* ptr = dev_alloc(c, cbytes);
+    if (!ptr) { c->coefbuf = DevBuf{}; return fail(c, SIBFA_E_NOMEM, "pair coefficient allocation failed"); }
+    c->coefbuf = {ptr, cbytes};
+  }
+  c->coef_valid = false;
   return SIBFA_OK;
 }
 
@@ -492,6 +538,20 @@ sibfa_status prepare(sibfa_ctx c) {
   if (c->dirty_lists) {
     sibfa_status st = build_lists(c);
     if (st != SIBFA_OK) return st;
+    if (c->periodic) {
+      Phase ph(c, SIBFA_PH_LISTS);
+      SysView sv = make_view(c);
+      for (int pol = 0; pol < 2; ++pol) {
+        int* start = pol ? c->bstart_pol : c->bstart_all;
+        int* order = pol ? c->border_pol : c->border_all;
+        const int cnt = pol ? c->npol : c->n;
+        launch_fill_int(c->bcount, 0, c->nbricks + 1, s);
+        launch_fill_int(c->bcursor, 0, c->nbricks, s);
+        launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, s);
+        launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, s);
+        if (cnt > 0) launch_scatter(c->brick_of, start, c->bcursor, order, cnt, s);
+      }
+    }
     c->dirty_lists = false;
     c->e0_valid = false;
   }
@@ -502,13 +562,25 @@ sibfa_status prepare(sibfa_ctx c) {
 void conv(sibfa_ctx c, bool mix) { launch_convolution(c->pm, c->red, mix, c->stream); }
 
 // t = T v (v in pol order, double + float copy)
+sibfa_status ensure_coef(sibfa_ctx c) {
+  if (c->coef_valid || c->npol == 0) return SIBFA_OK;
+  Phase ph(c, SIBFA_PH_PAIRCOEF);
+  SysView s = make_view(c);
+  if (mixed(c)) launch_pol_coef(s, nullptr, static_cast<float2*>(c->coefbuf.p), c->stream);
+  else launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p), nullptr, c->stream);
+  c->coef_valid = true;
+  return SIBFA_OK;
+}
+
+// t = T v.  mix: FP32 pair/PME arithmetic; the cached coefficients are used
+// when their precision matches (FP64 requests in mixed mode evaluate the
+// pairs afresh in FP64).
 void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
   SysView s = make_view(c);
   if (c->periodic) {
     DirUpdate du{};
     du.upd = 0;
-    du.p = v;
-    du.p32 = v32;
+    du.p_old = v;
     {
       Phase ph(c, SIBFA_PH_SPREAD);
       launch_spread_dip(s, c->pm, c->red, du, mix, c->stream);
@@ -517,7 +589,8 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     conv(c, mix);
   }
   Phase ph(c, SIBFA_PH_MATVEC);
-  launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, c->stream);
+  const bool coef = c->coef_valid && (mix == mixed(c));
+  launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
 }
 
 sibfa_status compute_E0(sibfa_ctx c) {
@@ -533,11 +606,13 @@ sibfa_status compute_E0(sibfa_ctx c) {
     conv(c, mix);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
   }
-  sibfa_status st = read_scalars(c, 0, S_COUNT);
+  double tot[3] = {0, 0, 0};
+  sibfa_status st = c->periodic ? read_totals(c, {S_EREAL, S_ESELF, S_EREC}, tot)
+                                : read_totals(c, {S_EREAL}, tot);
   if (st != SIBFA_OK) return st;
-  c->e_real = c->h_pinned[S_EREAL];
-  c->e_self = c->periodic ? c->h_pinned[S_ESELF] : 0.0;
-  c->e_rec = c->periodic ? c->h_pinned[S_EREC] : 0.0;
+  c->e_real = tot[0];
+  c->e_self = c->periodic ? tot[1] : 0.0;
+  c->e_rec = c->periodic ? tot[2] : 0.0;
   c->e0_valid = true;
   return SIBFA_OK;
 }
@@ -558,6 +633,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     launch_fill_double(c->mu_c, 0.0, 3 * (size_t)c->n, st);
     return SIBFA_OK;
   }
+  ensure_coef(c);
   if (warm && c->mu_have) launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
   else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
@@ -569,38 +645,43 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     // residual from scratch (FP64 operator)
     matvec(c, c->x, c->x32, c->t, -1, false);
     launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
-    sibfa_status e = read_scalars(c, S_ZZ, 1);
+    double zz0 = 0.0;
+    sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
     if (e != SIBFA_OK) return e;
-    rho_true = rms_debye(c, c->h_pinned[S_ZZ]);
+    rho_true = rms_debye(c, zz0);
     if (rho_true <= tol) break;
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
     if (it > 0) ++restarts;
     int k = 0;
     for (;;) {
       if (k > 0) {
-        DirUpdate du{};
-        du.upd = 1;
-        du.num = S_RZ0 + (k & 1);
-        du.den = S_RZ0 + ((k - 1) & 1);
-        du.z = c->z;
-        du.p = c->p;
-        du.p32 = c->p32;
+        const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
         if (c->periodic) {
+          // p_new = z + beta p_old is formed inside the spreading kernel
+          DirUpdate du{};
+          du.upd = 1;
+          du.num = num;
+          du.den = den;
+          du.z = c->z;
+          du.p_old = c->p;
+          du.p_new = c->p2;
+          du.p_new32 = c->p2_32;
           {
             Phase ph(c, SIBFA_PH_SPREAD);
             launch_spread_dip(s, c->pm, c->red, du, mix, st);
           }
+          std::swap(c->p, c->p2);
+          std::swap(c->p32, c->p2_32);
           Phase ph(c, SIBFA_PH_FFT);
           conv(c, mix);
         } else {
           Phase ph(c, SIBFA_PH_SPREAD);
-          launch_direction(s, c->red, du.num, du.den, c->z, c->p, c->p32, st);
+          launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
         }
       } else if (c->periodic) {
         DirUpdate du{};
         du.upd = 0;
-        du.p = c->p;
-        du.p32 = c->p32;
+        du.p_old = c->p;
         {
           Phase ph(c, SIBFA_PH_SPREAD);
           launch_spread_dip(s, c->pm, c->red, du, mix, st);
@@ -610,7 +691,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       }
       {
         Phase ph(c, SIBFA_PH_MATVEC);
-        launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
+        launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
       }
       {
         Phase ph(c, SIBFA_PH_UPDATE);
@@ -619,15 +700,14 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       }
       ++k;
       ++it;
-      HIP_TRY(hipMemcpyAsync(c->h_pinned + S_PQ, c->red.scalars + S_PQ, 7 * sizeof(double),
-                             hipMemcpyDeviceToHost, st));
-      e = sync_read(c);
+      double pz[2] = {0.0, 0.0};
+      e = read_totals(c, {S_PQ, S_ZZ}, pz);
       if (e != SIBFA_OK) return e;
-      if (!(c->h_pinned[S_PQ] > 0.0)) {
+      if (!(pz[0] > 0.0)) {
         result = SIBFA_E_NOT_SPD;
         break;
       }
-      const double rho = rms_debye(c, c->h_pinned[S_ZZ]);
+      const double rho = rms_debye(c, pz[1]);
       if (rho <= tol || it >= c->prm.max_iter) break;
     }
     if (result == SIBFA_E_NOT_SPD) break;
@@ -662,6 +742,36 @@ sibfa_status setup_pme(sibfa_ctx c) {
     factor_radices(pm.K[a], pm.rad[a], &pm.nrad[a]);
   }
   pm.kxh = pm.K[0] / 2 + 1;
+  // spreading bricks: the largest size <= kBrick whose last (partial) brick
+  // still spans order - 1 points, so a brick only receives contributions
+  // from sites homed in it or in its successor along each axis
+  for (int a = 0; a < 3; ++a) {
+    int best = 0;
+    for (int b = kBrick; b >= order - 1 && b >= 1; --b) {
+      const int rem = pm.K[a] % b;
+      if (rem == 0 || rem >= order - 1) { best = b; break; }
+    }
+    if (best == 0) return fail(c, SIBFA_E_ARG, "no spreading brick size fits this grid");
+    pm.Bb[a] = best;
+    pm.nb[a] = (pm.K[a] + best - 1) / best;
+  }
+  c->nbricks = pm.nb[0] * pm.nb[1] * pm.nb[2];
+  {
+    const size_t nbk = (size_t)c->nbricks;
+    if (!alloc_into(c, c->pmebufs, c->bcount, nbk + 1) ||
+        !alloc_into(c, c->pmebufs, c->bcursor, nbk) ||
+        !alloc_into(c, c->pmebufs, c->brick_of, (size_t)c->n) ||
+        !alloc_into(c, c->pmebufs, c->bscan_tmp, scan_temp_ints((int)nbk + 1) + 16) ||
+        !alloc_into(c, c->pmebufs, c->bstart_pol, nbk + 1) ||
+        !alloc_into(c, c->pmebufs, c->border_pol, (size_t)c->n) ||
+        !alloc_into(c, c->pmebufs, c->bstart_all, nbk + 1) ||
+        !alloc_into(c, c->pmebufs, c->border_all, (size_t)c->n))
+      return fail(c, SIBFA_E_NOMEM, "PME brick allocation failed");
+    pm.bstart_pol = c->bstart_pol;
+    pm.border_pol = c->border_pol;
+    pm.bstart_all = c->bstart_all;
+    pm.border_all = c->border_all;
+  }
   const size_t nr = (size_t)pm.K[0] * pm.K[1] * pm.K[2];
   const size_t nh = (size_t)pm.kxh * pm.K[1] * pm.K[2];
   double *Q, *phi, *G;
@@ -866,25 +976,29 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->dints, 16) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
             alloc_into(c, L, c->r, n) && alloc_into(c, L, c->z, n) && alloc_into(c, L, c->p, n) &&
             alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
-            alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->mu_s, n) &&
+            alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->p2, n) && alloc_into(c, L, c->p2_32, n) && alloc_into(c, L, c->mu_s, n) &&
             alloc_into(c, L, c->mu_s32, n) && alloc_into(c, L, c->Freal, n);
   for (int k = 0; k < 4 && ok; ++k) ok = alloc_into(c, L, c->ncnt[k], n);
-  const int max_blocks = (int)(n / 4 + 8192);
+  // partial sums: one per block of the largest reducing launch (site
+  // kernels use >= 16 sites per block; the z pass at most K1 * (K0/2+1))
+  size_t mb = n / 4 + 8192;
+  if (c->periodic) mb += (size_t)c->prm.grid[1] * (c->prm.grid[0] / 2 + 1);
+  const int max_blocks = (int)mb;
   double* partials;
-  unsigned* counters;
-  double* scalars;
-  ok = ok && alloc_into(c, L, partials, (size_t)S_COUNT * max_blocks) &&
-       alloc_into(c, L, counters, S_COUNT) && alloc_into(c, L, scalars, 64);
+  ok = ok && alloc_into(c, L, partials, (size_t)S_COUNT * max_blocks);
+  if (ok && hipHostMalloc((void**)&c->h_part, (size_t)S_COUNT * max_blocks * sizeof(double),
+                          hipHostMallocDefault) != hipSuccess) {
+    c->h_part = nullptr;
+    ok = false;
+  }
   if (!ok) {
     release_system(c);
     return fail(c, SIBFA_E_NOMEM, "device allocation failed");
   }
+  c->red = Reduce{};
   c->red.partials = partials;
-  c->red.counters = counters;
-  c->red.scalars = scalars;
   c->red.max_blocks = max_blocks;
-  launch_fill_int(reinterpret_cast<int*>(counters), 0, S_COUNT, c->stream);
-  launch_fill_double(scalars, 0.0, 64, c->stream);
+  launch_fill_double(partials, 0.0, (size_t)S_COUNT * max_blocks, c->stream);
   launch_fill_int(c->is_pol + n, 0, 1, c->stream);
   HIP_TRY(hipMemcpyAsync(c->xyz_c, xyz, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->mol_c, mol, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -972,6 +1086,7 @@ sibfa_status sibfa_apply_T(sibfa_ctx c, const double* pin, double* tp_out) {
   HIP_TRY(hipSetDevice(c->device));
   sibfa_status st = prepare(c);
   if (st != SIBFA_OK) return st;
+  ensure_coef(c);
   SysView s = make_view(c);
   launch_caller_to_pol(s, c->perm, pin, c->q, c->p32, c->stream);
   matvec(c, c->q, c->p32, c->t, -1, mixed(c));
@@ -1014,7 +1129,6 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
     matvec(c, c->x, c->x32, c->t, -1, false);
     launch_dot(s, c->red, c->x, c->t, S_MUTMU, sm);
   } else {
-    launch_fill_double(c->red.scalars + S_MUE, 0.0, 2, sm);
     launch_fill_double(reinterpret_cast<double*>(c->x), 0.0, 4, sm);
   }
   if (forces) {
@@ -1032,9 +1146,15 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
       launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
     }
   }
-  st = read_scalars(c, 0, S_COUNT);
-  if (st != SIBFA_OK) return st;
-  const double mue = c->h_pinned[S_MUE], mutmu = c->h_pinned[S_MUTMU];
+  double mm[2] = {0.0, 0.0};
+  if (c->npol > 0) {
+    st = read_totals(c, {S_MUE, S_MUTMU}, mm);
+    if (st != SIBFA_OK) return st;
+  } else {
+    st = sync_read(c);
+    if (st != SIBFA_OK) return st;
+  }
+  const double mue = mm[0], mutmu = mm[1];
   c->stats.e_pol = -0.5 * kCoulomb * mue;
   c->stats.e_pol_variational = kCoulomb * (0.5 * mutmu - mue);
   c->stats.e_elec_real = kCoulomb * c->e_real;

@@ -69,6 +69,9 @@ struct SysView {
   const int* nb_in;   const int* nc_in;   int cap_in;     // same molecule
   const int* nb_pol;  const int* nc_pol;  int cap_pol;    // pol-pol, inter, r < rc
   const int* nb_ipol; const int* nc_ipol; int cap_ipol;   // pol-pol, same molecule
+  // cached damped dipole-dipole coefficients (c1, c2) of the pol list
+  const double2* cpol;
+  const float2* cpol32;
 };
 
 struct PmeView {
@@ -88,13 +91,40 @@ struct PmeView {
   const float2* tw32[3];
   int nrad[3];
   int rad[3][16];
+  // spreading bricks: Bb[0] x Bb[1] x Bb[2] grid points per workgroup (each
+  // <= kBrick; the last brick along an axis may be shorter but never below
+  // order - 1 points), sites binned by the brick holding their base index
+  int Bb[3];
+  int nb[3];
+  const int* bstart_pol;   // [nbricks + 1]
+  const int* border_pol;   // polarizable indices grouped by brick
+  const int* bstart_all;
+  const int* border_all;   // sorted-site indices grouped by brick
 };
 
+constexpr int kBrick = 8;
+
+// Grid base index of a coordinate along one axis: floor(x K / L) wrapped
+// into [0, K), and the fractional offset.
+__device__ __forceinline__ int grid_base(double x, double scale, int K, double* frac) {
+  const double u = x * scale;
+  const double fl = floor(u);
+  int k = (int)fl;
+  if (k >= K) k -= K;
+  if (k < 0) k += K;
+  *frac = u - fl;
+  return k;
+}
+
+// Deterministic reductions without device-wide fences: a producing kernel
+// writes one partial sum per block (block_partial); whoever needs the total
+// -- a later kernel (slot_total, every block summing the same partials in
+// the same order) or the host -- adds the partials in index order.  The
+// host records how many partials each slot's last producer wrote.
 struct Reduce {
   double* partials;      // [S_COUNT][max_blocks]
-  unsigned* counters;    // [S_COUNT]
-  double* scalars;       // [S_COUNT]
   int max_blocks;
+  int nparts[S_COUNT];
 };
 
 // ---------------------------------------------------------------- helpers
@@ -110,42 +140,38 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// Deterministic block reduction followed by a grid-level finalisation: the
-// last block to finish sums the per-block partials in index order and stores
-// the scalar.  Every thread of the block must call it.
-__device__ __forceinline__ void block_reduce_to_slot(double v, Reduce red, int slot) {
+// Block sum of v written as this block's partial of the slot.  Every thread
+// of the block must call it (blockDim.x <= kBlock).
+__device__ __forceinline__ void block_partial(double v, const Reduce& red, int slot) {
   __shared__ double sh[kBlock / 64];
-  __shared__ bool last;
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = v;
   __syncthreads();
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
-    red.partials[slot * red.max_blocks + blockIdx.x] = s;
-    __threadfence();
-    unsigned prev = atomicAdd(&red.counters[slot], 1u);
-    last = (prev == (unsigned)(nb - 1));
+    red.partials[(size_t)slot * red.max_blocks + blockIdx.x] = s;
   }
   __syncthreads();
-  if (last) {
-    __threadfence();
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-      s += red.partials[slot * red.max_blocks + b];
-    s = wave_sum(s);
-    if (lane == 0) sh[wid] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-      red.scalars[slot] = t;
-      red.counters[slot] = 0u;
-    }
-  }
-  __syncthreads();   // the shared staging is reused by the next call
+}
+
+// Total of a slot written by an earlier kernel, returned to every thread.
+// Every thread of the block must call it.
+__device__ __forceinline__ double slot_total(const Reduce& red, int slot) {
+  __shared__ double sh[kBlock / 64];
+  const int n = red.nparts[slot];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x)
+    v += red.partials[(size_t)slot * red.max_blocks + b];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  __syncthreads();
+  return s;
 }
 
 template <typename R>

@@ -4,8 +4,7 @@
 // with the half spectrum kx = 0..K0/2 kept after the real-to-complex x pass.
 // Five passes, each a kernel in which one workgroup loads a batch of lines
 // into LDS, transforms them there and writes them back:
-//   x  r2c        rows of Q -> half-spectrum rows (Q is zeroed as it is read,
-//                 ready for the next spreading)
+//   x  r2c        rows of Q -> half-spectrum rows
 //   y  forward    lines along y, a block of consecutive kx per workgroup so
 //                 global accesses stay coalesced
 //   z  forward, multiply by G (and accumulate E_rec = 1/2 sum G |F|^2 over
@@ -164,15 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
   const int nrows = pm.K[1] * pm.K[2];
   const int row0 = blockIdx.x * nl;
   const int rows = min(nl, nrows - row0);
-  T* Q = gQ<T>(pm);
+  const T* Q = gQ<T>(pm);
   for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
     const int l = e / N, x = e - l * N;
     cplx<T> v;
     v.x = T(0); v.y = T(0);
     if (l < rows) {
-      const size_t g = (size_t)(row0 + l) * N + x;
-      v.x = Q[g];
-      Q[g] = T(0);
+      v.x = Q[(size_t)(row0 + l) * N + x];
     }
     a[e] = v;
   }
@@ -251,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     const int z = e / nb, c = e - z * nb;
     if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * N + z];
   }
-  block_reduce_to_slot(e_part, red, S_EREC);
+  block_partial(e_part, red, S_EREC);
 }
 
 // ---- x pass, half complex to real.
@@ -296,7 +293,7 @@ static int pick_batch(int h) {
 }
 
 template <typename T>
-static void convolution_t(const PmeView& pm, const Reduce& red, hipStream_t st) {
+static void convolution_t(const PmeView& pm, Reduce& red, hipStream_t st) {
   const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2], h = pm.kxh;
   const size_t csz = sizeof(cplx<T>);
   const int budget = 48 * 1024;
@@ -318,12 +315,13 @@ static void convolution_t(const PmeView& pm, const Reduce& red, hipStream_t st) 
   const int nbz = nb < lines_for(K2) ? nb : lines_for(K2);
   const int nkbz = (h + nbz - 1) / nbz;
   const size_t shz = 2 * (size_t)nbz * K2 * csz;
+  red.nparts[S_EREC] = K1 * nkbz;
   hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(1));
   hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3((nrows + nlx - 1) / nlx), dim3(kBlock), shx, st, pm, nlx);
 }
 
-void launch_convolution(const PmeView& pm, const Reduce& red, bool mixed, hipStream_t st) {
+void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
   if (mixed) convolution_t<float>(pm, red, st);
   else convolution_t<double>(pm, red, st);
 }

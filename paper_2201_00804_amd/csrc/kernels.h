@@ -5,9 +5,14 @@
 namespace sibfa {
 
 // pair.hip
-void launch_perm(const SysView& s, const Reduce& red, double4* E0, bool mixed, hipStream_t st);
-void launch_matvec(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
-                   const float4* p32, double4* out, int dot_slot, bool mixed, hipStream_t st);
+void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStream_t st);
+// coef: read the cached pair coefficients of the context's precision
+void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
+                   const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
+                   hipStream_t st);
+// cache the pol-list pair coefficients: FP64 into out, or FP32 into out32
+// when out is NULL
+void launch_pol_coef(const SysView& s, double2* out, float2* out32, hipStream_t st);
 void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
                   hipStream_t st);
 
@@ -16,16 +21,21 @@ void launch_force(const SysView& s, const double4* mu, const float4* mu32, doubl
 // when mu != NULL, sorted-site indexing) onto the real grid.
 void launch_spread_mult(const SysView& s, const PmeView& pm, const double4* mu, bool mixed,
                         hipStream_t st);
-// Spread of polarizable-site dipoles.  With upd != 0 first sets
-// p = z + beta p, beta = scalars[num] / scalars[den], and writes p (and its
-// FP32 copy).
+// Spread of polarizable-site dipoles p_old.  With upd != 0 the spread
+// dipole is p_new = z + beta p_old, beta = total(num) / total(den),
+// written to p_new (and its FP32 copy); p_old is only read.
 struct DirUpdate {
   int upd;
   int num, den;          // reduction slots
   const double4* z;
-  double4* p;
-  float4* p32;
+  const double4* p_old;
+  double4* p_new;
+  float4* p_new32;
 };
+// Home-brick binning of the sites for the spreading kernels (counts must be
+// zeroed; pol = 1 bins polarizable sites, 0 all sites).
+void launch_brick_bin(const SysView& s, const PmeView& pm, int pol, int* brick_of, int* counts,
+                      hipStream_t st);
 void launch_spread_dip(const SysView& s, const PmeView& pm, const Reduce& red, DirUpdate du,
                        bool mixed, hipStream_t st);
 // E0[pi] += -grad phi at polarizable sites.
@@ -37,24 +47,23 @@ void launch_gather_force(const SysView& s, const PmeView& pm, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
                          hipStream_t st);
 
-// fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec into S_EREC;
-// Q is zeroed on the way.
-void launch_convolution(const PmeView& pm, const Reduce& red, bool mixed, hipStream_t st);
+// fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec into S_EREC.
+void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st);
 
 // vec.hip
 // PCG kernels over polarizable sites (double4 vectors, w unused).
-void launch_init_residual(const SysView& s, const Reduce& red, const double4* E0,
+void launch_init_residual(const SysView& s, Reduce& red, const double4* E0,
                           const double4* t, double4* r, double4* z, double4* p, float4* p32,
                           int rz_slot, hipStream_t st);
-void launch_update(const SysView& s, const Reduce& red, int rz_slot, int rz_next_slot,
+void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    double4* x, double4* r, double4* z, const double4* p, const double4* q,
                    hipStream_t st);
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
-void launch_dot(const SysView& s, const Reduce& red, const double4* a, const double4* b, int slot,
+void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st);
-void launch_residual_norm(const SysView& s, const Reduce& red, const double4* E0, const double4* t,
+void launch_residual_norm(const SysView& s, Reduce& red, const double4* E0, const double4* t,
                           hipStream_t st);
 void launch_copy4(const double4* in, double4* out, float4* out32, int n, hipStream_t st);
 // sorted-site mu (zero at non-polarizable sites) from polarizable-index x

@@ -166,8 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
     acc[0] += sf * d.x; acc[1] += sf * d.y; acc[2] += sf * d.z;
   }
   if (sub == 0 && pi >= 0) E0[pi] = make_double4(acc[0], acc[1], acc[2], 0.0);
-  block_reduce_to_slot(U, red, S_EREAL);
-  block_reduce_to_slot(Uself, red, S_ESELF);
+  block_partial(U, red, S_EREAL);
+  block_partial(Uself, red, S_ESELF);
 }
 
 // ------------------------------------------------------------------ matvec
@@ -243,7 +243,50 @@ __device__ __forceinline__ void gather_field_share(const PmeView& pm, const doub
   }
 }
 
-template <typename R, int G, int P, bool PME>
+// Damped, screened dipole-dipole coefficients of the intermolecular pol
+// pairs, c1 = E_1 - P_1 e^-x c0_1 and c2 = E_2 - P_2 e^-x c0_2, in the
+// ELL layout of the pol list.  Positions are fixed during a solve, so the
+// matvec reads them instead of re-evaluating erfc/exp per pair.
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, float2* out32) {
+  const int sub = threadIdx.x % G;
+  const int pi = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (pi >= s.npol) return;
+  R xr[3], sr;
+  load_pp<R>(s, pi, xr, sr);
+  const int cnt = s.nc_pol[pi];
+  for (int k = sub; k < cnt; k += G) {
+    const size_t e = (size_t)pi * s.cap_pol + k;
+    const int j = s.nb_pol[e];
+    R xj[3], sj, Rv[3];
+    load_pp<R>(s, j, xj, sj);
+    displacement<R>(s, xr, xj, Rv);
+    const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+    const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+    R Eb[3], c0[3], tp[5];
+    base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
+    bare_coeffs<R, 2>(rinv, rinv2, c0);
+    thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+    const R c1 = Eb[1] - tp[1] * c0[1], c2 = Eb[2] - tp[2] * c0[2];
+    if (out) out[e] = make_double2((double)c1, (double)c2);
+    else out32[e] = make_float2((float)c1, (float)c2);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_coef(const SysView& s, size_t e, R& c1, R& c2);
+template <>
+__device__ __forceinline__ void load_coef<double>(const SysView& s, size_t e, double& c1, double& c2) {
+  const double2 c = s.cpol[e];
+  c1 = c.x; c2 = c.y;
+}
+template <>
+__device__ __forceinline__ void load_coef<float>(const SysView& s, size_t e, float& c1, float& c2) {
+  const float2 c = s.cpol32[e];
+  c1 = c.x; c2 = c.y;
+}
+
+template <typename R, int G, int P, bool PME, bool COEF>
 __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce red,
                                                    const double4* p, const float4* p32,
                                                    double4* out, int dot_slot) {
@@ -276,19 +319,27 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce
     load_pp<R>(s, pi, xr, sr);
     const int cnt = s.nc_pol[pi];
     for (int k = sub; k < cnt; k += G) {
-      const int j = s.nb_pol[(size_t)pi * s.cap_pol + k];
+      const size_t e = (size_t)pi * s.cap_pol + k;
+      const int j = s.nb_pol[e];
       R xj[3], sj, Rv[3], pj[3];
       load_pp<R>(s, j, xj, sj);
       load_p<R>(p, p32, j, pj);
       displacement<R>(s, xr, xj, Rv);
-      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      R Eb[3], c0[3], tp[5];
-      base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
-      bare_coeffs<R, 2>(rinv, rinv2, c0);
-      thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+      R c1, c2;
+      if (COEF) {
+        load_coef<R>(s, e, c1, c2);
+      } else {
+        const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+        const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+        R Eb[3], c0[3], tp[5];
+        base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
+        bare_coeffs<R, 2>(rinv, rinv2, c0);
+        thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+        c1 = Eb[1] - tp[1] * c0[1];
+        c2 = Eb[2] - tp[2] * c0[2];
+      }
       R E[3];
-      dip_field<R>(Eb[1] - tp[1] * c0[1], Eb[2] - tp[2] * c0[2], pj, Rv, E);
+      dip_field<R>(c1, c2, pj, Rv, E);
       f[0] += (double)E[0]; f[1] += (double)E[1]; f[2] += (double)E[2];
     }
     if (PME) gather_field_share<R, P, G>(pm, xi, sub, f);
@@ -310,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce
     out[pi] = make_double4(q[0], q[1], q[2], 0.0);
     dot = pv.x * q[0] + pv.y * q[1] + pv.z * q[2];
   }
-  if (dot_slot >= 0) block_reduce_to_slot(dot, red, dot_slot);
+  if (dot_slot >= 0) block_partial(dot, red, dot_slot);
 }
 
 // ------------------------------------------------------------------ forces
@@ -450,36 +501,54 @@ static int blocks_for(int items, int G) {
   return b < 1 ? 1 : b;
 }
 
-void launch_perm(const SysView& s, const Reduce& red, double4* E0, bool mixed, hipStream_t st) {
+void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStream_t st) {
   const dim3 g(blocks_for(s.n, kG)), b(kBlock);
+  red.nparts[S_EREAL] = red.nparts[S_ESELF] = (int)g.x;
   if (mixed) hipLaunchKernelGGL((k_perm<float, kG>), g, b, 0, st, s, red, E0);
   else hipLaunchKernelGGL((k_perm<double, kG>), g, b, 0, st, s, red, E0);
 }
 
+template <typename R, int P, bool COEF>
+static void matvec_rp(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
+                      const float4* p32, double4* out, int dot_slot, hipStream_t st) {
+  const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
+  if (s.periodic)
+    hipLaunchKernelGGL((k_matvec<R, kG, P, true, COEF>), g, b, 0, st, s, pm, red, p, p32, out,
+                       dot_slot);
+  else
+    hipLaunchKernelGGL((k_matvec<R, kG, P, false, COEF>), g, b, 0, st, s, pm, red, p, p32, out,
+                       dot_slot);
+}
+
 template <int P>
 static void matvec_p(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
-                     const float4* p32, double4* out, int dot_slot, bool mixed, hipStream_t st) {
-  const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (s.periodic) {
-    if (mixed)
-      hipLaunchKernelGGL((k_matvec<float, kG, P, true>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
-    else
-      hipLaunchKernelGGL((k_matvec<double, kG, P, true>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+                     const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
+                     hipStream_t st) {
+  if (mixed) {
+    if (coef) matvec_rp<float, P, true>(s, pm, red, p, p32, out, dot_slot, st);
+    else matvec_rp<float, P, false>(s, pm, red, p, p32, out, dot_slot, st);
   } else {
-    if (mixed)
-      hipLaunchKernelGGL((k_matvec<float, kG, P, false>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
-    else
-      hipLaunchKernelGGL((k_matvec<double, kG, P, false>), g, b, 0, st, s, pm, red, p, p32, out, dot_slot);
+    if (coef) matvec_rp<double, P, true>(s, pm, red, p, p32, out, dot_slot, st);
+    else matvec_rp<double, P, false>(s, pm, red, p, p32, out, dot_slot, st);
   }
 }
 
-void launch_matvec(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
-                   const float4* p32, double4* out, int dot_slot, bool mixed, hipStream_t st) {
+void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
+                   const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
+                   hipStream_t st) {
+  if (dot_slot >= 0) red.nparts[dot_slot] = blocks_for(s.npol, kG);
   switch (pm.order) {
-    case 4: matvec_p<4>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
-    case 6: matvec_p<6>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
-    default: matvec_p<5>(s, pm, red, p, p32, out, dot_slot, mixed, st); break;
+    case 4: matvec_p<4>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
+    case 6: matvec_p<6>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
+    default: matvec_p<5>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
   }
+}
+
+void launch_pol_coef(const SysView& s, double2* out, float2* out32, hipStream_t st) {
+  if (s.npol <= 0) return;
+  const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
+  if (out) hipLaunchKernelGGL((k_pol_coef<double, kG>), g, b, 0, st, s, out, out32);
+  else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, out, out32);
 }
 
 void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,

@@ -33,8 +33,8 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(SysView s, Reduce red,
     rz = rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
     zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
   }
-  block_reduce_to_slot(rz, red, rz_slot);
-  block_reduce_to_slot(zz, red, S_ZZ);
+  block_partial(rz, red, rz_slot);
+  block_partial(zz, red, S_ZZ);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz_slot,
@@ -42,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
                                                    double4* z, const double4* p, const double4* q) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0, zz = 0.0;
+  const double gamma = slot_total(red, rz_slot) / slot_total(red, S_PQ);
   if (i < s.npol) {
-    const double gamma = red.scalars[rz_slot] / red.scalars[S_PQ];
     const double4 pv = p[i], qv = q[i];
     double4 xv = x[i], rv = r[i];
     xv.x += gamma * pv.x; xv.y += gamma * pv.y; xv.z += gamma * pv.z;
@@ -55,16 +55,16 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
     rz = rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
     zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
   }
-  block_reduce_to_slot(rz, red, rz_next_slot);
-  block_reduce_to_slot(zz, red, S_ZZ);
+  block_partial(rz, red, rz_next_slot);
+  block_partial(zz, red, S_ZZ);
 }
 
 // p = z + beta p with beta = scalars[num] / scalars[den] (no grid to spread)
 __global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int num, int den,
                                                       const double4* z, double4* p, float4* p32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = slot_total(red, num) / slot_total(red, den);
   if (i >= s.npol) return;
-  const double beta = red.scalars[num] / red.scalars[den];
   const double4 zv = z[i], pv = p[i];
   const double4 o = make_double4(zv.x + beta * pv.x, zv.y + beta * pv.y, zv.z + beta * pv.z, 0.0);
   p[i] = o;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(SysView s, Reduce red, const dou
     const double4 u = a[i], v = b[i];
     d = u.x * v.x + u.y * v.y + u.z * v.z;
   }
-  block_reduce_to_slot(d, red, slot);
+  block_partial(d, red, slot);
 }
 
 __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red, const double4* E0,
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
     const double3 zv = amul(s.alpha + 6 * (size_t)i, rv);
     zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
   }
-  block_reduce_to_slot(zz, red, S_ZZ);
+  block_partial(zz, red, S_ZZ);
 }
 
 __global__ void k_copy4(const double4* in, double4* out, float4* out32, int n) {
@@ -157,16 +157,19 @@ __global__ void k_counts_out(int n, const int* perm, const int* counts, int* out
 
 static dim3 grid_for(int n) { return dim3(n > 0 ? (n + kBlock - 1) / kBlock : 1); }
 
-void launch_init_residual(const SysView& s, const Reduce& red, const double4* E0, const double4* t,
+void launch_init_residual(const SysView& s, Reduce& red, const double4* E0, const double4* t,
                           double4* r, double4* z, double4* p, float4* p32, int rz_slot,
                           hipStream_t st) {
+  red.nparts[rz_slot] = red.nparts[S_ZZ] = (int)grid_for(s.npol).x;
   hipLaunchKernelGGL(k_init_residual, grid_for(s.npol), dim3(kBlock), 0, st, s, red, E0, t, r, z,
                      p, p32, rz_slot);
 }
-void launch_update(const SysView& s, const Reduce& red, int rz_slot, int rz_next_slot, double4* x,
+void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot, double4* x,
                    double4* r, double4* z, const double4* p, const double4* q, hipStream_t st) {
+  // reads the totals of rz_slot and S_PQ (launched with the current counts)
   hipLaunchKernelGGL(k_update, grid_for(s.npol), dim3(kBlock), 0, st, s, red, rz_slot,
                      rz_next_slot, x, r, z, p, q);
+  red.nparts[rz_next_slot] = red.nparts[S_ZZ] = (int)grid_for(s.npol).x;
 }
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st) {
@@ -175,12 +178,14 @@ void launch_direction(const SysView& s, const Reduce& red, int num, int den, con
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
 }
-void launch_dot(const SysView& s, const Reduce& red, const double4* a, const double4* b, int slot,
+void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st) {
+  red.nparts[slot] = (int)grid_for(s.npol).x;
   hipLaunchKernelGGL(k_dot, grid_for(s.npol), dim3(kBlock), 0, st, s, red, a, b, slot);
 }
-void launch_residual_norm(const SysView& s, const Reduce& red, const double4* E0, const double4* t,
+void launch_residual_norm(const SysView& s, Reduce& red, const double4* E0, const double4* t,
                           hipStream_t st) {
+  red.nparts[S_ZZ] = (int)grid_for(s.npol).x;
   hipLaunchKernelGGL(k_residual_norm, grid_for(s.npol), dim3(kBlock), 0, st, s, red, E0, t);
 }
 void launch_copy4(const double4* in, double4* out, float4* out32, int n, hipStream_t st) {
