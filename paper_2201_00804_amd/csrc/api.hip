@@ -96,7 +96,7 @@ struct sibfa_ctx_s {
   int *bcount = nullptr, *bcursor = nullptr, *brick_of = nullptr, *bscan_tmp = nullptr;
   int *bstart_pol = nullptr, *border_pol = nullptr, *bstart_all = nullptr, *border_all = nullptr;
   // cached pol-list pair coefficients (FP64, or FP32 in mixed mode)
-  DevBuf coefbuf;
+  DevBuf coefbuf, icoefbuf, coef32buf;   // FP64 always; FP32 in mixed mode
   bool coef_valid = false;
   // second direction buffer (the spread kernel reads one and writes the other)
   double4* p2 = nullptr;
@@ -234,9 +234,9 @@ SysView make_view(sibfa_ctx c) {
   s.nb_in = c->nb[1]; s.nc_in = c->ncnt[1]; s.cap_in = c->cap[1];
   s.nb_pol = c->nb[2]; s.nc_pol = c->ncnt[2]; s.cap_pol = c->cap[2];
   s.nb_ipol = c->nb[3]; s.nc_ipol = c->ncnt[3]; s.cap_ipol = c->cap[3];
-  const bool mix = c->prm.precision == SIBFA_MIXED;
-  s.cpol = mix ? nullptr : static_cast<const double2*>(c->coefbuf.p);
-  s.cpol32 = mix ? static_cast<const float2*>(c->coefbuf.p) : nullptr;
+  s.cpol = static_cast<const double2*>(c->coefbuf.p);
+  s.cpol32 = static_cast<const float2*>(c->coef32buf.p);
+  s.cipol = static_cast<const double2*>(c->icoefbuf.p);
   return s;
 }
 
@@ -279,6 +279,10 @@ void release_system(sibfa_ctx c) {
   }
   dev_free(c, c->coefbuf.p);
   c->coefbuf = DevBuf{};
+  dev_free(c, c->icoefbuf.p);
+  c->icoefbuf = DevBuf{};
+  dev_free(c, c->coef32buf.p);
+  c->coef32buf = DevBuf{};
   if (c->h_part) {
     (void)hipHostFree(c->h_part);
     c->h_part = nullptr;
@@ -379,13 +383,28 @@ sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
     c->nb[k] = static_cast<int*>(ptr);
     c->cap[k] = want[k];
   }
-  const size_t cbytes = (size_t)std::max(c->npol, 1) * c->cap[2] *
-                        (c->prm.precision == SIBFA_MIXED ? sizeof(float2) : sizeof(double2));
+  const size_t cbytes = (size_t)std::max(c->npol, 1) * c->cap[2] * sizeof(double2);
   if (c->coefbuf.bytes < cbytes) {
     dev_free(c, c->coefbuf.p);
     void* ptr = dev_alloc(c, cbytes);
     if (!ptr) { c->coefbuf = DevBuf{}; return fail(c, SIBFA_E_NOMEM, "pair coefficient allocation failed"); }
     c->coefbuf = {ptr, cbytes};
+  }
+  if (c->prm.precision == SIBFA_MIXED) {
+    const size_t fbytes = (size_t)std::max(c->npol, 1) * c->cap[2] * sizeof(float2);
+    if (c->coef32buf.bytes < fbytes) {
+      dev_free(c, c->coef32buf.p);
+      void* ptr = dev_alloc(c, fbytes);
+      if (!ptr) { c->coef32buf = DevBuf{}; return fail(c, SIBFA_E_NOMEM, "pair coefficient allocation failed"); }
+      c->coef32buf = {ptr, fbytes};
+    }
+  }
+  const size_t ibytes = (size_t)std::max(c->npol, 1) * c->cap[3] * sizeof(double2);
+  if (c->icoefbuf.bytes < ibytes) {
+    dev_free(c, c->icoefbuf.p);
+    void* ptr = dev_alloc(c, ibytes);
+    if (!ptr) { c->icoefbuf = DevBuf{}; return fail(c, SIBFA_E_NOMEM, "pair coefficient allocation failed"); }
+    c->icoefbuf = {ptr, ibytes};
   }
   c->coef_valid = false;
   return SIBFA_OK;
@@ -566,15 +585,15 @@ sibfa_status ensure_coef(sibfa_ctx c) {
   if (c->coef_valid || c->npol == 0) return SIBFA_OK;
   Phase ph(c, SIBFA_PH_PAIRCOEF);
   SysView s = make_view(c);
-  if (mixed(c)) launch_pol_coef(s, nullptr, static_cast<float2*>(c->coefbuf.p), c->stream);
-  else launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p), nullptr, c->stream);
+  double2* icoef = static_cast<double2*>(c->icoefbuf.p);
+  launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p), nullptr, icoef, c->stream);
+  if (mixed(c)) launch_pol_coef(s, nullptr, static_cast<float2*>(c->coef32buf.p), icoef, c->stream);
   c->coef_valid = true;
   return SIBFA_OK;
 }
 
-// t = T v.  mix: FP32 pair/PME arithmetic; the cached coefficients are used
-// when their precision matches (FP64 requests in mixed mode evaluate the
-// pairs afresh in FP64).
+// t = T v.  mix: FP32 pair/PME arithmetic (cached FP32 coefficients);
+// otherwise FP64 (cached FP64 coefficients, kept in both modes).
 void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
   SysView s = make_view(c);
   if (c->periodic) {
@@ -589,7 +608,7 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     conv(c, mix);
   }
   Phase ph(c, SIBFA_PH_MATVEC);
-  const bool coef = c->coef_valid && (mix == mixed(c));
+  const bool coef = c->coef_valid;
   launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
 }
 
@@ -606,13 +625,13 @@ sibfa_status compute_E0(sibfa_ctx c) {
     conv(c, mix);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
   }
-  double tot[3] = {0, 0, 0};
-  sibfa_status st = c->periodic ? read_totals(c, {S_EREAL, S_ESELF, S_EREC}, tot)
-                                : read_totals(c, {S_EREAL}, tot);
+  double tot[4] = {0, 0, 0, 0};
+  sibfa_status st = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC}, tot)
+                                : read_totals(c, {S_EREAL, S_AUX}, tot);
   if (st != SIBFA_OK) return st;
-  c->e_real = tot[0];
-  c->e_self = c->periodic ? tot[1] : 0.0;
-  c->e_rec = c->periodic ? tot[2] : 0.0;
+  c->e_real = tot[0] + tot[1];
+  c->e_self = c->periodic ? tot[2] : 0.0;
+  c->e_rec = c->periodic ? tot[3] : 0.0;
   c->e0_valid = true;
   return SIBFA_OK;
 }
@@ -652,64 +671,87 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     if (rho_true <= tol) break;
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
     if (it > 0) ++restarts;
-    int k = 0;
+    // Iterations are enqueued in batches; after each update a one-block
+    // kernel tests z.z and p.Tp on the device and raises a stop flag that
+    // makes the remaining enqueued kernels return at once, so the host reads
+    // the flag once per batch instead of synchronising every iteration.
+    int* flag = c->dints + 8;
+    launch_fill_int(flag, 0, 4, st);
+    c->red.stop = flag;
+    c->pm.stop = flag;
+    const double zz_stop = (tol / kDebye) * (tol / kDebye) * c->npol;
+    const int kBatch = 4;
+    int k = 0, k_done = 0, reason = 0;
     for (;;) {
-      if (k > 0) {
-        const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
-        if (c->periodic) {
-          // p_new = z + beta p_old is formed inside the spreading kernel
+      for (int b = 0; b < kBatch && it + k < c->prm.max_iter; ++b) {
+        if (k > 0) {
+          const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
+          if (c->periodic) {
+            // p_new = z + beta p_old is formed inside the spreading kernel
+            DirUpdate du{};
+            du.upd = 1;
+            du.num = num;
+            du.den = den;
+            du.z = c->z;
+            du.p_old = c->p;
+            du.p_new = c->p2;
+            du.p_new32 = c->p2_32;
+            {
+              Phase ph(c, SIBFA_PH_SPREAD);
+              launch_spread_dip(s, c->pm, c->red, du, mix, st);
+            }
+            std::swap(c->p, c->p2);
+            std::swap(c->p32, c->p2_32);
+            Phase ph(c, SIBFA_PH_FFT);
+            conv(c, mix);
+          } else {
+            Phase ph(c, SIBFA_PH_SPREAD);
+            launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
+          }
+        } else if (c->periodic) {
           DirUpdate du{};
-          du.upd = 1;
-          du.num = num;
-          du.den = den;
-          du.z = c->z;
+          du.upd = 0;
           du.p_old = c->p;
-          du.p_new = c->p2;
-          du.p_new32 = c->p2_32;
           {
             Phase ph(c, SIBFA_PH_SPREAD);
             launch_spread_dip(s, c->pm, c->red, du, mix, st);
           }
-          std::swap(c->p, c->p2);
-          std::swap(c->p32, c->p2_32);
           Phase ph(c, SIBFA_PH_FFT);
           conv(c, mix);
-        } else {
-          Phase ph(c, SIBFA_PH_SPREAD);
-          launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
         }
-      } else if (c->periodic) {
-        DirUpdate du{};
-        du.upd = 0;
-        du.p_old = c->p;
         {
-          Phase ph(c, SIBFA_PH_SPREAD);
-          launch_spread_dip(s, c->pm, c->red, du, mix, st);
+          Phase ph(c, SIBFA_PH_MATVEC);
+          launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
         }
-        Phase ph(c, SIBFA_PH_FFT);
-        conv(c, mix);
+        {
+          Phase ph(c, SIBFA_PH_UPDATE);
+          launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
+                        c->q, st);
+          launch_check(c->red, flag, k + 1, zz_stop, st);
+        }
+        ++k;
       }
-      {
-        Phase ph(c, SIBFA_PH_MATVEC);
-        launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
+      HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+      e = sync_read(c);
+      if (e != SIBFA_OK) {
+        c->red.stop = nullptr;
+        c->pm.stop = nullptr;
+        return e;
       }
-      {
-        Phase ph(c, SIBFA_PH_UPDATE);
-        launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
-                      c->q, st);
-      }
-      ++k;
-      ++it;
-      double pz[2] = {0.0, 0.0};
-      e = read_totals(c, {S_PQ, S_ZZ}, pz);
-      if (e != SIBFA_OK) return e;
-      if (!(pz[0] > 0.0)) {
-        result = SIBFA_E_NOT_SPD;
+      if (c->h_ints[8]) {
+        k_done = c->h_ints[10];
+        reason = c->h_ints[9];
         break;
       }
-      const double rho = rms_debye(c, pz[1]);
-      if (rho <= tol || it >= c->prm.max_iter) break;
+      if (it + k >= c->prm.max_iter) {
+        k_done = k;
+        break;
+      }
     }
+    c->red.stop = nullptr;
+    c->pm.stop = nullptr;
+    it += k_done;
+    if (reason == 2) result = SIBFA_E_NOT_SPD;
     if (result == SIBFA_E_NOT_SPD) break;
     launch_copy4(c->x, c->x, c->x32, c->npol, st);
   }

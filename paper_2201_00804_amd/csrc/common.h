@@ -26,7 +26,7 @@ enum Slot {
   S_ZZ,          // z.z
   S_MUE,         // mu.E0
   S_MUTMU,       // mu.T mu
-  S_AUX,         // scratch
+  S_AUX,         // real-space energy of same-molecule (excluded) pairs
   S_COUNT
 };
 
@@ -69,9 +69,11 @@ struct SysView {
   const int* nb_in;   const int* nc_in;   int cap_in;     // same molecule
   const int* nb_pol;  const int* nc_pol;  int cap_pol;    // pol-pol, inter, r < rc
   const int* nb_ipol; const int* nc_ipol; int cap_ipol;   // pol-pol, same molecule
-  // cached damped dipole-dipole coefficients (c1, c2) of the pol list
+  // cached damped dipole-dipole coefficients (c1, c2) of the pol list (in
+  // the context's precision) and of the same-molecule pol list (FP64)
   const double2* cpol;
   const float2* cpol32;
+  const double2* cipol;
 };
 
 struct PmeView {
@@ -100,6 +102,7 @@ struct PmeView {
   const int* border_pol;   // polarizable indices grouped by brick
   const int* bstart_all;
   const int* border_all;   // sorted-site indices grouped by brick
+  const int* stop;         // see Reduce::stop
 };
 
 constexpr int kBrick = 8;
@@ -125,7 +128,10 @@ struct Reduce {
   double* partials;      // [S_COUNT][max_blocks]
   int max_blocks;
   int nparts[S_COUNT];
+  const int* stop;       // solver iterations: kernels return at once when *stop != 0
 };
+
+__device__ __forceinline__ bool stopped(const int* stop) { return stop && *stop; }
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ double wave_sum(double v) {

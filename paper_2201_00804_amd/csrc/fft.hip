@@ -156,6 +156,7 @@ template <> __device__ __forceinline__ const float* gG<float>(const PmeView& pm)
 // ---- x pass, real to half complex.  Block: nl rows.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
+  if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
   const int N = pm.K[0];
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
 // ---- y pass (both directions).  Block: (z, block of nb consecutive kx).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
+  if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
   const int N = pm.K[1], h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
@@ -211,6 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
 // ---- z pass: forward, influence function, inverse.  Block: (y, kx block).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, int nb) {
+  if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
   const int N = pm.K[2], K1 = pm.K[1], h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
 // ---- x pass, half complex to real.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
+  if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
   const int N = pm.K[0], h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);

@@ -11,8 +11,9 @@ void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const doubl
                    const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
                    hipStream_t st);
 // cache the pol-list pair coefficients: FP64 into out, or FP32 into out32
-// when out is NULL
-void launch_pol_coef(const SysView& s, double2* out, float2* out32, hipStream_t st);
+// when out is NULL; the same-molecule pol list always in FP64 into out_in
+void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out_in,
+                     hipStream_t st);
 void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
                   hipStream_t st);
 
@@ -60,6 +61,8 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    hipStream_t st);
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st);
+// device-side convergence test (see k_check)
+void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st);

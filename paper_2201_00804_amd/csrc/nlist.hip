@@ -312,12 +312,14 @@ void launch_rec_polsites(const RecArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ neighbour lists
-constexpr int kNlIB = 128;   // i-sites of a cell handled per pass
+constexpr int kNlIB = 64;   // i-sites of a cell handled per pass (one per lane)
 
+// The running count of each list for i-site t lives in lane t (cnt_*), read
+// back wave-uniformly with readlane, so the inner loop needs neither LDS
+// counters nor barriers; the block is a single wavefront.
 __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
   __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
   __shared__ int moli[kNlIB], poli[kNlIB];
-  __shared__ int cnt[4][kNlIB];
   const int lane = threadIdx.x;
   const int cell = blockIdx.x;
   const int cx = cell % a.nc[0];
@@ -326,6 +328,7 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
   const int i0 = a.cell_start[cell], i1 = a.cell_start[cell + 1];
   const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
   const double iL0 = a.ibox[0], iL1 = a.ibox[1], iL2 = a.ibox[2];
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   // stencil extents per axis: all cells when the axis has fewer than 5
   int span[3], lo[3];
   const int c3[3] = {cx, cy, cz};
@@ -335,14 +338,14 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
   }
   for (int ib = i0; ib < i1; ib += kNlIB) {
     const int ni = min(kNlIB, i1 - ib);
-    for (int t = lane; t < ni; t += 64) {
-      const double4 p = a.sp[ib + t];
-      xi[t] = p.x; yi[t] = p.y; zi[t] = p.z;
-      moli[t] = a.mol_s[ib + t];
-      poli[t] = a.polidx[ib + t];
-      cnt[0][t] = cnt[1][t] = cnt[2][t] = cnt[3][t] = 0;
+    if (lane < ni) {
+      const double4 p = a.sp[ib + lane];
+      xi[lane] = p.x; yi[lane] = p.y; zi[lane] = p.z;
+      moli[lane] = a.mol_s[ib + lane];
+      poli[lane] = a.polidx[ib + lane];
     }
     __syncthreads();
+    int cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;   // counts of i-site `lane`
     for (int sz = 0; sz < span[2]; ++sz) {
       int zz = lo[2] + sz;
       zz = (zz + a.nc[2]) % a.nc[2];
@@ -387,70 +390,58 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
               }
               const double r2 = dx * dx + dy * dy + dz * dz;
               const int i = ib + t;
-              const bool same = valid && (molj == moli[t]) && (j != i);
-              const bool inter = valid && (molj != moli[t]) && (r2 < a.cutoff2);
-              const bool pi = poli[t] >= 0;
+              const int mi = moli[t], pi_ = poli[t];
+              const bool same = valid && (molj == mi) && (j != i);
+              const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
+              const bool pi = pi_ >= 0;
               const bool pj = polj >= 0;
               const unsigned long long b0 = __ballot(inter);
               const unsigned long long b1 = __ballot(same);
               const unsigned long long b2 = __ballot(inter && pi && pj);
               const unsigned long long b3 = __ballot(same && pi && pj);
-              const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-              if (b0) {
-                const int base = cnt[0][t];
-                if (inter) {
-                  const int k = base + __popcll(b0 & below);
-                  if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
-                }
+              const int base0 = __shfl(cnt0, t, 64), base1 = __shfl(cnt1, t, 64);
+              const int base2 = __shfl(cnt2, t, 64), base3 = __shfl(cnt3, t, 64);
+              if (inter) {
+                const int k = base0 + __popcll(b0 & below);
+                if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
               }
-              if (b1) {
-                const int base = cnt[1][t];
-                if (same) {
-                  const int k = base + __popcll(b1 & below);
-                  if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
-                }
+              if (same) {
+                const int k = base1 + __popcll(b1 & below);
+                if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
               }
-              if (b2) {
-                const int base = cnt[2][t];
-                if (inter && pi && pj) {
-                  const int k = base + __popcll(b2 & below);
-                  if (k < a.cap_pol) a.nb_pol[(size_t)poli[t] * a.cap_pol + k] = polj;
-                }
+              if (inter && pi && pj) {
+                const int k = base2 + __popcll(b2 & below);
+                if (k < a.cap_pol) a.nb_pol[(size_t)pi_ * a.cap_pol + k] = polj;
               }
-              if (b3) {
-                const int base = cnt[3][t];
-                if (same && pi && pj) {
-                  const int k = base + __popcll(b3 & below);
-                  if (k < a.cap_ipol) a.nb_ipol[(size_t)poli[t] * a.cap_ipol + k] = polj;
-                }
+              if (same && pi && pj) {
+                const int k = base3 + __popcll(b3 & below);
+                if (k < a.cap_ipol) a.nb_ipol[(size_t)pi_ * a.cap_ipol + k] = polj;
               }
-              __syncthreads();   // every lane has read cnt[*][t]
-              if (lane == 0) {
-                cnt[0][t] += __popcll(b0);
-                cnt[1][t] += __popcll(b1);
-                cnt[2][t] += __popcll(b2);
-                cnt[3][t] += __popcll(b3);
+              if (lane == t) {
+                cnt0 += __popcll(b0);
+                cnt1 += __popcll(b1);
+                cnt2 += __popcll(b2);
+                cnt3 += __popcll(b3);
               }
-              __syncthreads();
             }
           }
         }
       }
     }
     // counts, overflow maxima and the same-molecule completeness check
-    for (int t = lane; t < ni; t += 64) {
-      const int i = ib + t;
-      a.nc_all[i] = cnt[0][t];
-      a.nc_in[i] = cnt[1][t];
-      atomicMax(&a.maxcnt[0], cnt[0][t]);
-      atomicMax(&a.maxcnt[1], cnt[1][t]);
-      if (poli[t] >= 0) {
-        a.nc_pol[poli[t]] = cnt[2][t];
-        a.nc_ipol[poli[t]] = cnt[3][t];
-        atomicMax(&a.maxcnt[2], cnt[2][t]);
-        atomicMax(&a.maxcnt[3], cnt[3][t]);
+    if (lane < ni) {
+      const int i = ib + lane;
+      a.nc_all[i] = cnt0;
+      a.nc_in[i] = cnt1;
+      atomicMax(&a.maxcnt[0], cnt0);
+      atomicMax(&a.maxcnt[1], cnt1);
+      if (poli[lane] >= 0) {
+        a.nc_pol[poli[lane]] = cnt2;
+        a.nc_ipol[poli[lane]] = cnt3;
+        atomicMax(&a.maxcnt[2], cnt2);
+        atomicMax(&a.maxcnt[3], cnt3);
       }
-      if (cnt[1][t] != a.mol_count[moli[t]] - 1) atomicOr(a.err, 1);
+      if (cnt1 != a.mol_count[moli[lane]] - 1) atomicOr(a.err, 1);
     }
     __syncthreads();
   }

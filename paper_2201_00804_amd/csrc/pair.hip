@@ -10,9 +10,9 @@
 //  k_perm    : permanent field E at polarizable sites (Thole-damped Mmu
 //              class, excluded within a molecule) and the MM real-space
 //              energy, plus Ewald self terms.
-//  k_matvec  : (T p)_i = alpha_i^-1 p_i - [damped dipole field of p + PME
-//              field of p (gathered from the potential grid, fused) + self],
-//              with p.Tp for the solver.
+//  k_matvec  : real-space part of (T p)_i = alpha_i^-1 p_i - [damped dipole
+//              field of p + PME field of p + self]; k_matvec_recip gathers
+//              the PME field from the potential grid and forms p.Tp.
 //  k_force   : real-space forces of MM, Mmu and mumu classes at fixed mu.
 #include "common.h"
 #include "pairmath.h"
@@ -77,16 +77,17 @@ __device__ __forceinline__ double thole_a_polpair(const SysView& s, int i, int j
 }
 
 // ------------------------------------------------------------------ E0 + E_elec
-template <typename R, int G>
-__global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4* E0) {
-  const int sub = threadIdx.x % G;
-  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+// Same-molecule pairs (excluded, E_n - c0_n; FP64; periodic only) and the
+// Ewald self terms, one thread per site: writes E0 of polarizable sites
+// and the energy partials S_AUX (pairs) and S_ESELF.
+__global__ __launch_bounds__(kBlock) void k_perm_intra(SysView s, Reduce red, double4* E0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = 0, G = 1;
   double acc[3] = {0.0, 0.0, 0.0};
   double U = 0.0, Uself = 0.0;
   int pi = -1;
   if (i < s.n) {
     pi = s.polidx[i];
-    // same-molecule pairs: excluded (E_n - c0_n), FP64; nothing for clusters
     if (s.periodic) {
       MP<double> Mi;
       double xi[3];
@@ -116,7 +117,34 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
         }
       }
     }
-    // intermolecular pairs within the cutoff, precision R
+  }
+  if (i < s.n && s.periodic) {
+    const double4 p = s.sp[i], d = s.sd[i], t = s.sth[i];
+    const double2 t2 = s.sth2[i];
+    const double b = s.beta, b3 = b * b * b, b5 = b3 * b * b;
+    const double tt = t.x * t.x + t.w * t.w + t2.y * t2.y +
+                      2.0 * (t.y * t.y + t.z * t.z + t2.x * t2.x);
+    Uself = -(b / kSqrtPi * p.w * p.w + 2.0 * b3 / (3.0 * kSqrtPi) * (d.x * d.x + d.y * d.y + d.z * d.z) +
+              8.0 * b5 / (45.0 * kSqrtPi) * tt);
+    const double sf = 4.0 * b3 / (3.0 * kSqrtPi);
+    acc[0] += sf * d.x; acc[1] += sf * d.y; acc[2] += sf * d.z;
+  }
+  if (pi >= 0) E0[pi] = make_double4(acc[0], acc[1], acc[2], 0.0);
+  block_partial(U, red, S_AUX);
+  block_partial(Uself, red, S_ESELF);
+}
+
+// Intermolecular pairs within the cutoff (precision R): MM energy partials
+// (S_EREAL) and the damped field added to E0 of polarizable sites.
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4* E0) {
+  const int sub = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double acc[3] = {0.0, 0.0, 0.0};
+  double U = 0.0;
+  int pi = -1;
+  if (i < s.n) {
+    pi = s.polidx[i];
     MP<R> Mi;
     R xi[3];
     load_mp<R>(s, i, Mi, xi);
@@ -154,20 +182,12 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) acc[a] = group_sum<G>(acc[a]);
-  if (sub == 0 && i < s.n && s.periodic) {
-    const double4 p = s.sp[i], d = s.sd[i], t = s.sth[i];
-    const double2 t2 = s.sth2[i];
-    const double b = s.beta, b3 = b * b * b, b5 = b3 * b * b;
-    const double tt = t.x * t.x + t.w * t.w + t2.y * t2.y +
-                      2.0 * (t.y * t.y + t.z * t.z + t2.x * t2.x);
-    Uself = -(b / kSqrtPi * p.w * p.w + 2.0 * b3 / (3.0 * kSqrtPi) * (d.x * d.x + d.y * d.y + d.z * d.z) +
-              8.0 * b5 / (45.0 * kSqrtPi) * tt);
-    const double sf = 4.0 * b3 / (3.0 * kSqrtPi);
-    acc[0] += sf * d.x; acc[1] += sf * d.y; acc[2] += sf * d.z;
+  if (sub == 0 && pi >= 0) {
+    double4 e = E0[pi];
+    e.x += acc[0]; e.y += acc[1]; e.z += acc[2];
+    E0[pi] = e;
   }
-  if (sub == 0 && pi >= 0) E0[pi] = make_double4(acc[0], acc[1], acc[2], 0.0);
   block_partial(U, red, S_EREAL);
-  block_partial(Uself, red, S_ESELF);
 }
 
 // ------------------------------------------------------------------ matvec
@@ -204,54 +224,36 @@ __device__ __forceinline__ double grid_at<double>(const PmeView& pm, size_t idx)
 template <>
 __device__ __forceinline__ float grid_at<float>(const PmeView& pm, size_t idx) { return pm.phi32[idx]; }
 
-// Minus the gradient of the interpolated potential at x (this lane's share
-// of the P*P (y, z) columns), added to f.
-template <typename R, int P, int G>
-__device__ __forceinline__ void gather_field_share(const PmeView& pm, const double x[3], int sub,
-                                                   double f[3]) {
-  int base[3];
-  R th[3][2][P];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double u = x[a] * pm.scale[a];
-    double fl = floor(u);
-    const R w = (R)(u - fl);
-    int k = (int)fl;
-    if (k >= pm.K[a]) k -= pm.K[a];
-    base[a] = k;
-    bspline_weights<R, P, 1>(w, th[a]);
-  }
-  const R s0 = (R)pm.scale[0], s1 = (R)pm.scale[1], s2 = (R)pm.scale[2];
-  for (int c = sub; c < P * P; c += G) {
-    const int ty = c % P, tz = c / P;
-    int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
-    int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
-    const size_t row = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
-    R gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int tx = 0; tx < P; ++tx) {
-      int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
-      const R g = grid_at<R>(pm, row + ix);
-      gx += g * th[0][1][tx];
-      gy += g * th[0][0][tx];
-    }
-    gz = gy;
-    // gx: sum g th'x ; gy: sum g thx (shared for y and z derivatives)
-    f[0] -= (double)(gx * th[1][0][ty] * th[2][0][tz] * s0);
-    f[1] -= (double)(gy * th[1][1][ty] * th[2][0][tz] * s1);
-    f[2] -= (double)(gz * th[1][0][ty] * th[2][1][tz] * s2);
-  }
-}
-
 // Damped, screened dipole-dipole coefficients of the intermolecular pol
 // pairs, c1 = E_1 - P_1 e^-x c0_1 and c2 = E_2 - P_2 e^-x c0_2, in the
 // ELL layout of the pol list.  Positions are fixed during a solve, so the
 // matvec reads them instead of re-evaluating erfc/exp per pair.
 template <typename R, int G>
-__global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, float2* out32) {
+__global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, float2* out32,
+                                                     double2* out_in) {
   const int sub = threadIdx.x % G;
   const int pi = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   if (pi >= s.npol) return;
+  {
+    // same-molecule polarizable pairs, always FP64
+    double xi[3], si;
+    load_pp<double>(s, pi, xi, si);
+    const int cin = s.nc_ipol[pi];
+    for (int k = sub; k < cin; k += G) {
+      const size_t e = (size_t)pi * s.cap_ipol + k;
+      const int j = s.nb_ipol[e];
+      double xj[3], sj, Rv[3];
+      load_pp<double>(s, j, xj, sj);
+      displacement<double>(s, xi, xj, Rv);
+      const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double Eb[3], c0[3], tp[5];
+      base_coeffs<double, 2>(s, r, rinv, rinv2, Eb);
+      bare_coeffs<double, 2>(rinv, rinv2, c0);
+      thole_tp<double>(thole_a_polpair(s, pi, j) * r2 * r * si * sj, tp);
+      out_in[e] = make_double2(Eb[1] - tp[1] * c0[1], Eb[2] - tp[2] * c0[2]);
+    }
+  }
   R xr[3], sr;
   load_pp<R>(s, pi, xr, sr);
   const int cnt = s.nc_pol[pi];
@@ -286,10 +288,40 @@ __device__ __forceinline__ void load_coef<float>(const SysView& s, size_t e, flo
   c1 = c.x; c2 = c.y;
 }
 
-template <typename R, int G, int P, bool PME, bool COEF>
-__global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce red,
-                                                   const double4* p, const float4* p32,
-                                                   double4* out, int dot_slot) {
+// One intermolecular pol pair of the matvec: field at i of the dipole p_j.
+template <typename R, bool COEF>
+__device__ __forceinline__ void matvec_pair(const SysView& s, const double4* p, const float4* p32,
+                                            int pi, size_t e, const R xr[3], R sr, double f[3]) {
+  const int j = s.nb_pol[e];
+  R xj[3], sj, Rv[3], pj[3];
+  load_pp<R>(s, j, xj, sj);
+  load_p<R>(p, p32, j, pj);
+  R c1, c2;
+  if (COEF) load_coef<R>(s, e, c1, c2);
+  displacement<R>(s, xr, xj, Rv);
+  if (!COEF) {
+    const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+    const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+    R Eb[3], c0[3], tp[5];
+    base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
+    bare_coeffs<R, 2>(rinv, rinv2, c0);
+    thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+    c1 = Eb[1] - tp[1] * c0[1];
+    c2 = Eb[2] - tp[2] * c0[2];
+  }
+  R E[3];
+  dip_field<R>(c1, c2, pj, Rv, E);
+  f[0] += (double)E[0]; f[1] += (double)E[1]; f[2] += (double)E[2];
+}
+
+// Real-space part of (T p)_i = alpha_i^-1 p_i - [real field + self field]
+// (minus the reciprocal field, subtracted by k_matvec_recip when periodic;
+// clusters finish here, with p.Tp).
+template <typename R, int G, bool COEF>
+__global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const double4* p,
+                                                   const float4* p32, double4* out,
+                                                   int dot_slot) {
+  if (stopped(red.stop)) return;
   const int sub = threadIdx.x % G;
   const int pi = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   double f[3] = {0.0, 0.0, 0.0};
@@ -299,50 +331,42 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce
     // same-molecule polarizable pairs (damped, FP64)
     const int cin = s.nc_ipol[pi];
     for (int k = sub; k < cin; k += G) {
-      const int j = s.nb_ipol[(size_t)pi * s.cap_ipol + k];
+      const size_t e = (size_t)pi * s.cap_ipol + k;
+      const int j = s.nb_ipol[e];
       double xj[3], sj, Rv[3], pj[3];
       load_pp<double>(s, j, xj, sj);
       load_p<double>(p, p32, j, pj);
       displacement<double>(s, xi, xj, Rv);
-      const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      double Eb[3], c0[3], tp[5];
-      base_coeffs<double, 2>(s, r, rinv, rinv2, Eb);
-      bare_coeffs<double, 2>(rinv, rinv2, c0);
-      thole_tp<double>(thole_a_polpair(s, pi, j) * r2 * r * si * sj, tp);
-      double E[3];
-      dip_field<double>(Eb[1] - tp[1] * c0[1], Eb[2] - tp[2] * c0[2], pj, Rv, E);
-      f[0] += E[0]; f[1] += E[1]; f[2] += E[2];
-    }
-    // intermolecular polarizable pairs within the cutoff, precision R
-    R xr[3], sr;
-    load_pp<R>(s, pi, xr, sr);
-    const int cnt = s.nc_pol[pi];
-    for (int k = sub; k < cnt; k += G) {
-      const size_t e = (size_t)pi * s.cap_pol + k;
-      const int j = s.nb_pol[e];
-      R xj[3], sj, Rv[3], pj[3];
-      load_pp<R>(s, j, xj, sj);
-      load_p<R>(p, p32, j, pj);
-      displacement<R>(s, xr, xj, Rv);
-      R c1, c2;
+      double c1, c2;
       if (COEF) {
-        load_coef<R>(s, e, c1, c2);
+        const double2 cc = s.cipol[e];
+        c1 = cc.x; c2 = cc.y;
       } else {
-        const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-        const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-        R Eb[3], c0[3], tp[5];
-        base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
-        bare_coeffs<R, 2>(rinv, rinv2, c0);
-        thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
+        const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+        const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+        double Eb[3], c0[3], tp[5];
+        base_coeffs<double, 2>(s, r, rinv, rinv2, Eb);
+        bare_coeffs<double, 2>(rinv, rinv2, c0);
+        thole_tp<double>(thole_a_polpair(s, pi, j) * r2 * r * si * sj, tp);
         c1 = Eb[1] - tp[1] * c0[1];
         c2 = Eb[2] - tp[2] * c0[2];
       }
-      R E[3];
-      dip_field<R>(c1, c2, pj, Rv, E);
-      f[0] += (double)E[0]; f[1] += (double)E[1]; f[2] += (double)E[2];
+      double E[3];
+      dip_field<double>(c1, c2, pj, Rv, E);
+      f[0] += E[0]; f[1] += E[1]; f[2] += E[2];
     }
-    if (PME) gather_field_share<R, P, G>(pm, xi, sub, f);
+    // intermolecular polarizable pairs within the cutoff, precision R; two
+    // entries per lane and step so that their gathers overlap
+    R xr[3], sr;
+    load_pp<R>(s, pi, xr, sr);
+    const int cnt = s.nc_pol[pi];
+    const size_t row = (size_t)pi * s.cap_pol;
+    int k = sub;
+    for (; k + G < cnt; k += 2 * G) {
+      matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
+      matvec_pair<R, COEF>(s, p, p32, pi, row + k + G, xr, sr, f);
+    }
+    if (k < cnt) matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
@@ -360,6 +384,56 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, PmeView pm, Reduce
     q[2] = ai[2] * pv.x + ai[4] * pv.y + ai[5] * pv.z - f[2];
     out[pi] = make_double4(q[0], q[1], q[2], 0.0);
     dot = pv.x * q[0] + pv.y * q[1] + pv.z * q[2];
+  }
+  if (!s.periodic && dot_slot >= 0) block_partial(dot, red, dot_slot);
+}
+
+// Reciprocal part of the matvec: q_i -= E_rec,i = -grad phi(r_i) with phi
+// the potential grid of the spread p; then p.Tp.  One thread per site.
+template <typename R, int P>
+__global__ __launch_bounds__(kBlock) void k_matvec_recip(SysView s, PmeView pm, Reduce red,
+                                                         const double4* p, double4* out,
+                                                         int dot_slot) {
+  if (stopped(red.stop)) return;
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  double dot = 0.0;
+  if (pi < s.npol) {
+    const double4 x = s.pp[pi];
+    int base[3];
+    R th[3][2][P];
+    const double xs[3] = {x.x, x.y, x.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double fr;
+      base[a] = grid_base(xs[a], pm.scale[a], pm.K[a], &fr);
+      bspline_weights<R, P, 1>((R)fr, th[a]);
+    }
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int tz = 0; tz < P; ++tz) {
+      int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
+      for (int ty = 0; ty < P; ++ty) {
+        int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
+        const size_t rowi = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
+        R s0 = 0, s1 = 0;
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) {
+          int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
+          const R v = grid_at<R>(pm, rowi + ix);
+          s0 += v * th[0][0][tx];
+          s1 += v * th[0][1][tx];
+        }
+        g[0] += (double)(s1 * th[1][0][ty] * th[2][0][tz]);
+        g[1] += (double)(s0 * th[1][1][ty] * th[2][0][tz]);
+        g[2] += (double)(s0 * th[1][0][ty] * th[2][1][tz]);
+      }
+    }
+    double4 q = out[pi];
+    q.x += g[0] * pm.scale[0];
+    q.y += g[1] * pm.scale[1];
+    q.z += g[2] * pm.scale[2];
+    out[pi] = q;
+    const double4 pv = p[pi];
+    dot = pv.x * q.x + pv.y * q.y + pv.z * q.z;
   }
   if (dot_slot >= 0) block_partial(dot, red, dot_slot);
 }
@@ -388,39 +462,31 @@ __device__ __forceinline__ MP<R> dipole_only(const R d[3]) {
   return m;
 }
 
-template <typename R>
-__device__ __forceinline__ void accumulate_classes(const R cMM[6], const R cT[6], bool mm,
-                                                   const MP<R>& Mi, const MP<R>& Mj,
-                                                   const R mui[3], const R muj[3],
-                                                   const R Rv[3], double F[3]) {
-  R u, f[3];
-  if (mm) {
-    mp_pair<R, false, true>(cMM, Mi, Mj, Rv, u, f);
-    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
-  }
-  const MP<R> Ui = dipole_only<R>(mui), Uj = dipole_only<R>(muj);
-  if (mm) {
-    mp_pair<R, false, true>(cT, Ui, Mj, Rv, u, f);
-    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
-    mp_pair<R, false, true>(cT, Mi, Uj, Rv, u, f);
-    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
-  }
-}
-
-template <typename R, int G>
-__global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, const float4* mu32,
-                                                  double4* Fout) {
-  const int sub = threadIdx.x % G;
-  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+// Real-space forces at fixed mu.  Writing M' = (q, d + mu, Theta) and using
+// that every class term is bilinear in the multipoles of the two sites:
+//  intermolecular pair: MM(B) + Mmu(cT) + mumu(cT) = F(M', M'; cT)
+//                       + F(M, M; B - cT),  cT_n = B_n - P_n e^-x c0_n,
+//    and B - cT vanishes unless both sites are polarizable and close enough
+//    for the Thole factor to matter (x < 50), so the second term is skipped
+//    for almost every pair;
+//  same-molecule pair:  MM and Mmu excluded (E - c0), mumu damped
+//                       = F(M', M'; E - c0) + F(mu, mu; lambda c0)
+//    (the first term is zero for clusters, where E = c0).
+// Same-molecule pairs (FP64, one thread per site); writes Fout.
+__global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, const double4* mu,
+                                                        double4* Fout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double F[3] = {0.0, 0.0, 0.0};
   if (i < s.n) {
     {
-      // same-molecule pairs, FP64: MM and Mmu excluded (E_n - c0_n, periodic
-      // only), mumu damped
+      const int sub = 0, G = 1;
+      const float4* mu32 = nullptr;
       MP<double> Mi;
       double xi[3], mui[3];
       load_mp<double>(s, i, Mi, xi);
       load_mu<double>(mu, mu32, i, mui);
+      MP<double> Pi = Mi;
+      Pi.d[0] += mui[0]; Pi.d[1] += mui[1]; Pi.d[2] += mui[2];
       const double si = s.sd[i].w;
       const int cnt = s.nc_in[i];
       for (int k = sub; k < cnt; k += G) {
@@ -432,31 +498,50 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
         displacement<double>(s, xi, xj, Rv);
         const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
         const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-        double Eb[6], c0[6], cx[6], cd[6];
+        double Eb[6], c0[6], c[6];
         base_coeffs<double, 5>(s, r, rinv, rinv2, Eb);
         bare_coeffs<double, 5>(rinv, rinv2, c0);
         double u, f[3];
         if (s.periodic) {
 #pragma unroll
-          for (int n = 0; n < 6; ++n) cx[n] = Eb[n] - c0[n];
-          accumulate_classes<double>(cx, cx, true, Mi, Mj, mui, muj, Rv, F);
+          for (int n = 0; n < 6; ++n) c[n] = Eb[n] - c0[n];
+          MP<double> Pj = Mj;
+          Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
+          mp_pair<double, false, true>(c, Pi, Pj, Rv, u, f);
+          F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
         }
         const double sj = s.sd[j].w;
         if (si > 0.0 && sj > 0.0) {
           double tp[5];
           thole_tp<double>(thole_a_pair(s, i, j) * r2 * r * si * sj, tp);
+          c[0] = 0.0;
+          c[5] = 0.0;
 #pragma unroll
-          for (int n = 0; n < 6; ++n) cd[n] = Eb[n] - (n >= 1 && n <= 4 ? tp[n] : 0.0) * c0[n];
+          for (int n = 1; n <= 4; ++n) c[n] = (1.0 - tp[n]) * c0[n];
           const MP<double> Ui = dipole_only<double>(mui), Uj = dipole_only<double>(muj);
-          mp_pair<double, false, true>(cd, Ui, Uj, Rv, u, f);
+          mp_pair<double, false, true>(c, Ui, Uj, Rv, u, f);
           F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
         }
       }
     }
+    Fout[i] = make_double4(F[0], F[1], F[2], 0.0);
+  }
+}
+
+// Intermolecular pairs within the cutoff (precision R); adds to Fout.
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, const float4* mu32,
+                                                  double4* Fout) {
+  const int sub = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double F[3] = {0.0, 0.0, 0.0};
+  if (i < s.n) {
     MP<R> Mi;
     R xi[3], mui[3];
     load_mp<R>(s, i, Mi, xi);
     load_mu<R>(mu, mu32, i, mui);
+    MP<R> Pi = Mi;
+    Pi.d[0] += mui[0]; Pi.d[1] += mui[1]; Pi.d[2] += mui[2];
     const R si = site_s<R>(s, i);
     const int cnt = s.nc_all[i];
     for (int k = sub; k < cnt; k += G) {
@@ -468,28 +553,41 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
       displacement<R>(s, xi, xj, Rv);
       const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
       const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      R Eb[6], cT[6];
-      base_coeffs<R, 5>(s, r, rinv, rinv2, Eb);
-#pragma unroll
-      for (int n = 0; n < 6; ++n) cT[n] = Eb[n];
+      R c[6];
+      base_coeffs<R, 5>(s, r, rinv, rinv2, c);
       const R sj = site_s<R>(s, j);
-      if (si > R(0) && sj > R(0)) {
+      R x = R(0);
+      const bool damp = si > R(0) && sj > R(0) &&
+                        (x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj) < R(50);
+      R D[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+      if (damp) {
         R tp[5], c0[5];
-        thole_tp<R>(R(thole_a_pair(s, i, j)) * r2 * r * si * sj, tp);
+        thole_tp<R>(x, tp);
         bare_coeffs<R, 4>(rinv, rinv2, c0);
 #pragma unroll
-        for (int n = 1; n <= 4; ++n) cT[n] -= tp[n] * c0[n];
+        for (int n = 1; n <= 4; ++n) {
+          D[n] = tp[n] * c0[n];
+          c[n] -= D[n];
+        }
       }
-      accumulate_classes<R>(Eb, cT, true, Mi, Mj, mui, muj, Rv, F);
+      MP<R> Pj = Mj;
+      Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
       R u, f[3];
-      const MP<R> Ui = dipole_only<R>(mui), Uj = dipole_only<R>(muj);
-      mp_pair<R, false, true>(cT, Ui, Uj, Rv, u, f);
+      mp_pair<R, false, true>(c, Pi, Pj, Rv, u, f);
       F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+      if (damp) {
+        mp_pair<R, false, true>(D, Mi, Mj, Rv, u, f);
+        F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+      }
     }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
-  if (sub == 0 && i < s.n) Fout[i] = make_double4(F[0], F[1], F[2], 0.0);
+  if (sub == 0 && i < s.n) {
+    double4 f = Fout[i];
+    f.x += F[0]; f.y += F[1]; f.z += F[2];
+    Fout[i] = f;
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -502,41 +600,42 @@ static int blocks_for(int items, int G) {
 }
 
 void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStream_t st) {
+  const dim3 gi((s.n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_perm_intra, gi, dim3(kBlock), 0, st, s, red, E0);
+  red.nparts[S_AUX] = red.nparts[S_ESELF] = (int)gi.x;
   const dim3 g(blocks_for(s.n, kG)), b(kBlock);
-  red.nparts[S_EREAL] = red.nparts[S_ESELF] = (int)g.x;
+  red.nparts[S_EREAL] = (int)g.x;
   if (mixed) hipLaunchKernelGGL((k_perm<float, kG>), g, b, 0, st, s, red, E0);
   else hipLaunchKernelGGL((k_perm<double, kG>), g, b, 0, st, s, red, E0);
 }
 
-template <typename R, int P, bool COEF>
-static void matvec_rp(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
-                      const float4* p32, double4* out, int dot_slot, hipStream_t st) {
+template <typename R, int P>
+static void matvec_r(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
+                     const float4* p32, double4* out, int dot_slot, bool coef, hipStream_t st) {
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (s.periodic)
-    hipLaunchKernelGGL((k_matvec<R, kG, P, true, COEF>), g, b, 0, st, s, pm, red, p, p32, out,
-                       dot_slot);
-  else
-    hipLaunchKernelGGL((k_matvec<R, kG, P, false, COEF>), g, b, 0, st, s, pm, red, p, p32, out,
-                       dot_slot);
+  if (coef) hipLaunchKernelGGL((k_matvec<R, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+  else hipLaunchKernelGGL((k_matvec<R, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+  if (s.periodic) {
+    const dim3 g2((s.npol + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_matvec_recip<R, P>), g2, b, 0, st, s, pm, red, p, out, dot_slot);
+    if (dot_slot >= 0) red.nparts[dot_slot] = (int)g2.x;
+  } else if (dot_slot >= 0) {
+    red.nparts[dot_slot] = (int)g.x;
+  }
 }
 
 template <int P>
-static void matvec_p(const SysView& s, const PmeView& pm, const Reduce& red, const double4* p,
+static void matvec_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
                      const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
                      hipStream_t st) {
-  if (mixed) {
-    if (coef) matvec_rp<float, P, true>(s, pm, red, p, p32, out, dot_slot, st);
-    else matvec_rp<float, P, false>(s, pm, red, p, p32, out, dot_slot, st);
-  } else {
-    if (coef) matvec_rp<double, P, true>(s, pm, red, p, p32, out, dot_slot, st);
-    else matvec_rp<double, P, false>(s, pm, red, p, p32, out, dot_slot, st);
-  }
+  if (mixed) matvec_r<float, P>(s, pm, red, p, p32, out, dot_slot, coef, st);
+  else matvec_r<double, P>(s, pm, red, p, p32, out, dot_slot, coef, st);
 }
 
 void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
                    const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
                    hipStream_t st) {
-  if (dot_slot >= 0) red.nparts[dot_slot] = blocks_for(s.npol, kG);
+  if (s.npol <= 0) return;
   switch (pm.order) {
     case 4: matvec_p<4>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
     case 6: matvec_p<6>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
@@ -544,15 +643,18 @@ void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const doubl
   }
 }
 
-void launch_pol_coef(const SysView& s, double2* out, float2* out32, hipStream_t st) {
+void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out_in,
+                     hipStream_t st) {
   if (s.npol <= 0) return;
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (out) hipLaunchKernelGGL((k_pol_coef<double, kG>), g, b, 0, st, s, out, out32);
-  else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, out, out32);
+  if (out) hipLaunchKernelGGL((k_pol_coef<double, kG>), g, b, 0, st, s, out, out32, out_in);
+  else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, out, out32, out_in);
 }
 
 void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
                   hipStream_t st) {
+  hipLaunchKernelGGL(k_force_intra, dim3((s.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, mu,
+                     F);
   const dim3 g(blocks_for(s.n, kG)), b(kBlock);
   if (mixed) hipLaunchKernelGGL((k_force<float, kG>), g, b, 0, st, s, mu, mu32, F);
   else hipLaunchKernelGGL((k_force<double, kG>), g, b, 0, st, s, mu, mu32, F);

@@ -120,6 +120,7 @@ struct Stage {
 template <typename R, int P, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_spread_brick(SysView s, PmeView pm, Reduce red,
                                                          DirUpdate du, const double4* mu) {
+  if (stopped(red.stop)) return;
   using St = Stage<R, P, FULL>;
   constexpr int ND = St::ND, CH = St::CH, NW = kBlock / 64;
   __shared__ R tile[kBrick * kBrick * kBrick];

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(SysView s, Reduce red,
 __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz_slot,
                                                    int rz_next_slot, double4* x, double4* r,
                                                    double4* z, const double4* p, const double4* q) {
+  if (stopped(red.stop)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0, zz = 0.0;
   const double gamma = slot_total(red, rz_slot) / slot_total(red, S_PQ);
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
 // p = z + beta p with beta = scalars[num] / scalars[den] (no grid to spread)
 __global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int num, int den,
                                                       const double4* z, double4* p, float4* p32) {
+  if (stopped(red.stop)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = slot_total(red, num) / slot_total(red, den);
   if (i >= s.npol) return;
@@ -100,6 +102,22 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
     zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
   }
   block_partial(zz, red, S_ZZ);
+}
+
+// Convergence test on the device after iteration `iter`: stop when
+// z.z <= zz_stop (the tolerance) or p.Tp <= 0 (not positive definite).
+// flag: [0] stop, [1] reason (1 converged, 2 not SPD), [2] iterations done.
+__global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int iter, double zz_stop) {
+  if (flag[0]) return;
+  const double pq = slot_total(red, S_PQ);
+  const double zz = slot_total(red, S_ZZ);
+  if (threadIdx.x == 0) {
+    if (!(pq > 0.0)) {
+      flag[1] = 2; flag[2] = iter; flag[0] = 1;
+    } else if (zz <= zz_stop) {
+      flag[1] = 1; flag[2] = iter; flag[0] = 1;
+    }
+  }
 }
 
 __global__ void k_copy4(const double4* in, double4* out, float4* out32, int n) {
@@ -174,6 +192,9 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st) {
   hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32);
+}
+void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, iter, zz_stop);
 }
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
