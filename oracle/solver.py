@@ -25,6 +25,9 @@ class NotSPD(RuntimeError):
 
 
 def rms_debye(z):
+    """RMS over sites in Debye; zero for an empty set of sites."""
+    if len(z) == 0:
+        return 0.0
     return DEBYE * float(np.sqrt(np.sum(z * z) / len(z)))
 
 

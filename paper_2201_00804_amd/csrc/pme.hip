@@ -421,6 +421,7 @@ void launch_spread_dip(const SysView& s, const PmeView& pm, const Reduce& red, D
 template <int P>
 static void gather_field_p(const SysView& s, const PmeView& pm, double4* E0, bool mixed,
                            hipStream_t st) {
+  if (s.npol <= 0) return;
   const dim3 g((s.npol + kBlock - 1) / kBlock), b(kBlock);
   if (mixed) hipLaunchKernelGGL((k_gather_field<float, P>), g, b, 0, st, s, pm, E0);
   else hipLaunchKernelGGL((k_gather_field<double, P>), g, b, 0, st, s, pm, E0);

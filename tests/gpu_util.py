@@ -21,10 +21,10 @@ def oracle_params(sysd, beta=0.4, cutoff=9.0, grid=32, order=5, tol=1e-10):
 
 
 def gpu_params(sysd, beta=0.4, cutoff=9.0, grid=32, order=5, tol=1e-10, precision="fp64",
-               max_iter=200):
+               max_iter=200, **extra):
     from paper_2201_00804_amd import default_params
     return default_params(beta=beta, cutoff=cutoff, grid=grid, order=order, tol=tol,
-                          precision=precision, max_iter=max_iter)
+                          precision=precision, max_iter=max_iter, **extra)
 
 
 def engine_for(sysd, prm):
