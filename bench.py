@@ -35,14 +35,50 @@ WORKLOAD = "box32000"
 PEAK_ALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic flop counts (FMA = 2, each erfc/exp/rsqrt = 1), see the design doc:
-# one damped dipole-dipole pair of the matvec, and the per-site share of the
-# fused PME gather (order 5: 25 columns x 5 points x 4 + 25 x 9 + splines
-# + alpha^-1 p and the residual bookkeeping).
-FLOPS_MATVEC_PAIR = 69
-FLOPS_MATVEC_SITE = 855
+# Algorithmic flop counts (FMA = 2, each erfc/exp/rsqrt = 1) of one pair of
+# the real-space force and permanent-field kernels.
 FLOPS_FORCE_PAIR = 560
 FLOPS_FIELD_PAIR = 190
+
+# Algorithmic bytes of the real-space matvec kernel k_matvec, streamed once
+# per launch (operands gathered for neighbour j are shared by every row that
+# lists j and are counted once, with the site's own row):
+#   per intermolecular polarizable list entry: 4 B neighbour index + the
+#     cached coefficient pair (c1, c2): 16 B in FP64, 8 B in FP32;
+#   per same-molecule list entry: 4 B index + 16 B FP64 coefficients;
+#   per polarizable site: position/Thole record (32 B FP64; + 16 B FP32 in
+#     mixed), p (32 B; + 16 B FP32 copy in mixed), alpha^-1 (48 B),
+#     T p written (32 B), two list counts (8 B).
+MATVEC_ENTRY_BYTES = {"fp64": 20, "mixed": 12}
+MATVEC_SAME_BYTES = 20
+MATVEC_SITE_BYTES = {"fp64": 152, "mixed": 184}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_matvec_box32000_traffic.md")
+
+
+def matvec_bytes(pairs, npol, precision):
+    return (pairs["pol"] * MATVEC_ENTRY_BYTES[precision]
+            + pairs["pol_same_molecule"] * MATVEC_SAME_BYTES
+            + npol * MATVEC_SITE_BYTES[precision])
+
+
+def measured_traffic(precision):
+    """HBM bytes per k_matvec launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or None when
+    that summary is absent or was taken from other kernel sources."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        parts = line.strip().strip("|").split("|")
+        if len(parts) >= 2:
+            vals[parts[0].strip()] = parts[1].strip().strip("`")
+    from paper_2201_00804_amd.profsum import source_hash
+    if vals.get("kernel sources sha256[:16]") != source_hash("k_matvec"):
+        return None
+    v = vals.get(f"traffic bytes per launch ({precision})")
+    return float(v) if v else None
 
 
 def _percentile(xs, q):
@@ -98,38 +134,53 @@ def run_gpu(sysd, prm, precision, steps, warmup):
     return out
 
 
-def roofline(res, steps):
+def roofline(res, precision):
+    """Roofline point of the kernel with the largest share of the timed
+    region.  The real-space matvec streams its list and coefficient arrays
+    (HBM-bound); the force and field pair kernels are priced in flops
+    against the vector-ALU peak."""
     prof = res["profile"]
-    ms = prof["ms"]
-    calls = prof["calls"]
-    pairs = prof["pairs"]
+    ms, calls, pairs = prof["ms"], prof["calls"], prof["pairs"]
     npol = res["stats"]["n_polarizable"]
-    n = res["stats"]["n_sites"]
+    total = max(sum(ms.values()), 1e-30)
+    share = {k: round(v / total, 4) for k, v in ms.items() if v > 0}
     dom = max(ms, key=lambda k: ms[k])
-    share = {k: round(v / max(sum(ms.values()), 1e-30), 4) for k, v in ms.items()}
     avg_ms = ms[dom] / max(calls[dom], 1)
+    base = dict(phase=dom, avg_launch_ms=round(avg_ms, 5), launches=calls[dom],
+                phase_share=share)
     if dom == "matvec":
-        flops = (pairs["pol"] + pairs["pol_same_molecule"]) * FLOPS_MATVEC_PAIR + \
-            npol * FLOPS_MATVEC_SITE
-    elif dom == "force_real":
-        flops = (pairs["all"] + pairs["same_molecule"]) * FLOPS_FORCE_PAIR
-    elif dom == "field_real":
-        flops = (pairs["all"] + pairs["same_molecule"]) * FLOPS_FIELD_PAIR
-    else:
-        flops = None
-    if flops is None:
-        return dict(kernel=dom, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=None, traffic=None, avg_launch_ms=avg_ms, phase_share=share)
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    return dict(kernel={"matvec": "k_matvec", "force_real": "k_force",
-                        "field_real": "k_perm"}[dom],
-                bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS,
-                unit="TFLOP/s", frac=round(achieved / PEAK_ALU_TFLOPS, 4), traffic=None,
-                avg_launch_ms=round(avg_ms, 4), flops_per_launch=int(flops),
-                launches=calls[dom], phase_share=share)
+        b = matvec_bytes(pairs, npol, precision)
+        gbs = b / (avg_ms * 1e-3) / 1e9
+        return dict(kernel="k_matvec", bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS,
+                    unit="GB/s", frac=round(gbs / PEAK_HBM_GBS, 4),
+                    traffic=measured_traffic(precision), bytes_per_launch=int(b), **base)
+    if dom in ("force_real", "field_real"):
+        fl = (pairs["all"] + pairs["same_molecule"]) * \
+            (FLOPS_FORCE_PAIR if dom == "force_real" else FLOPS_FIELD_PAIR)
+        tf = fl / (avg_ms * 1e-3) / 1e12
+        return dict(kernel="k_force" if dom == "force_real" else "k_perm", bound="alu",
+                    achieved=round(tf, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
+                    frac=round(tf / PEAK_ALU_TFLOPS, 4), traffic=None,
+                    flops_per_launch=int(fl), **base)
+    return dict(kernel=dom, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=None, traffic=None, **base)
 
 
-def cpu_baseline(sysd, prm, iters, sample=24):
+def copy_probe(mib, reps):
+    """A plain device copy of known size, the reference point that scales the
+    FETCH_SIZE / WRITE_SIZE counters of the kernels to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "reps": reps}), flush=True)
+
+
+def cpu_baseline(sysd, prm, iters, sample=64):
     """The FP64 oracle on a bounded sample of the same box, scaled to one
     evaluation: the oracle's real-space pair sums for `sample` sites
     (polarizable ones for E and T p, arbitrary ones for forces and the MM
@@ -214,12 +265,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is built for a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, max(args.steps, 1))
+        return
 
     from synth import config_system
     sysd, prm = config_system(WORKLOAD)
@@ -265,7 +321,7 @@ def main():
                    "n_waters": 32000, "n_sites": len(sysd["pos"]), "precision": head},
         "latency_ms": {"p50": round(1e3 * _percentile(main_r["step_s"], 0.5), 3),
                        "p99": round(1e3 * _percentile(main_r["step_s"], 0.99), 3)},
-        "roofline": roofline(main_r, args.steps),
+        "roofline": roofline(main_r, head),
     }
     for k, r in results.items():
         out[k] = summary(r)

@@ -182,11 +182,12 @@ typedef enum {
   SIBFA_PH_FIELD_RECIP,   /* permanent PME: spread, convolution, gather     */
   SIBFA_PH_SPREAD,        /* solver: direction update + dipole spreading    */
   SIBFA_PH_FFT,           /* solver: 3D FFT convolution (5 passes)          */
-  SIBFA_PH_MATVEC,        /* solver: real-space T p with fused PME gather   */
+  SIBFA_PH_MATVEC,        /* solver: real-space part of T p                  */
   SIBFA_PH_UPDATE,        /* solver: x, r, z updates and dot products       */
   SIBFA_PH_FORCE_REAL,    /* real-space forces                              */
   SIBFA_PH_FORCE_RECIP,   /* combined-density PME forces                    */
   SIBFA_PH_PAIRCOEF,      /* solver: damped pair coefficients, once a solve  */
+  SIBFA_PH_MATVEC_RECIP,  /* solver: PME field gather of T p and p.Tp        */
   SIBFA_PH_COUNT
 } sibfa_phase;
 

@@ -37,7 +37,7 @@ class Profile(ctypes.Structure):
 
 
 PHASES = ["lists", "field_real", "field_recip", "spread", "fft", "matvec", "update",
-          "force_real", "force_recip", "paircoef"]
+          "force_real", "force_recip", "paircoef", "matvec_recip"]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)

@@ -112,8 +112,12 @@ struct sibfa_ctx_s {
   bool prof = false;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
-  struct Mark { int phase; hipEvent_t a, b; };
+  // tag: solver iteration of a batched launch (-1 outside batches); launches
+  // enqueued after the device stop flag was raised return at once and are
+  // counted in the phase time but not in its launch count
+  struct Mark { int phase; hipEvent_t a, b; int tag; bool work; };
   std::vector<Mark> marks;
+  int cur_tag = -1;
   double prof_ms[16] = {0};
   int prof_calls[16] = {0};
 };
@@ -339,7 +343,7 @@ void fold_marks(sibfa_ctx c) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
       c->prof_ms[m.phase] += ms;
-      c->prof_calls[m.phase] += 1;
+      c->prof_calls[m.phase] += m.work ? 1 : 0;
     }
   }
   c->marks.clear();
@@ -353,7 +357,7 @@ struct Phase {
   hipEvent_t a = nullptr;
   Phase(sibfa_ctx cc, int p) : c(cc), ph(p) {
     if (c->prof) {
-      if (c->marks.size() > 4096) fold_marks(c);
+      if (c->marks.size() > 4096 && c->cur_tag < 0) fold_marks(c);
       a = next_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -363,7 +367,7 @@ struct Phase {
       hipEvent_t b = next_event(c);
       if (b) {
         (void)hipEventRecord(b, c->stream);
-        c->marks.push_back({ph, a, b});
+        c->marks.push_back({ph, a, b, c->cur_tag, true});
       }
     }
   }
@@ -607,9 +611,13 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     Phase ph(c, SIBFA_PH_FFT);
     conv(c, mix);
   }
-  Phase ph(c, SIBFA_PH_MATVEC);
   const bool coef = c->coef_valid;
-  launch_matvec(s, c->pm, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
+  {
+    Phase ph2(c, SIBFA_PH_MATVEC);
+    launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
+  }
+  Phase ph3(c, SIBFA_PH_MATVEC_RECIP);
+  launch_matvec_recip(s, c->pm, c->red, v, out, dot_slot, mix, c->stream);
 }
 
 sibfa_status compute_E0(sibfa_ctx c) {
@@ -683,7 +691,9 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     const int kBatch = 4;
     int k = 0, k_done = 0, reason = 0;
     for (;;) {
+      if (c->prof && c->marks.size() > 4096) fold_marks(c);
       for (int b = 0; b < kBatch && it + k < c->prm.max_iter; ++b) {
+        c->cur_tag = k;
         if (k > 0) {
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
           if (c->periodic) {
@@ -721,7 +731,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         }
         {
           Phase ph(c, SIBFA_PH_MATVEC);
-          launch_matvec(s, c->pm, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
+          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
+        }
+        {
+          Phase ph(c, SIBFA_PH_MATVEC_RECIP);
+          launch_matvec_recip(s, c->pm, c->red, c->p, c->q, S_PQ, mix, st);
         }
         {
           Phase ph(c, SIBFA_PH_UPDATE);
@@ -731,6 +745,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         }
         ++k;
       }
+      c->cur_tag = -1;
       HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
       e = sync_read(c);
       if (e != SIBFA_OK) {
@@ -741,8 +756,12 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       if (c->h_ints[8]) {
         k_done = c->h_ints[10];
         reason = c->h_ints[9];
+        for (auto& m : c->marks)
+          if (m.tag >= k_done) m.work = false;
+        for (auto& m : c->marks) m.tag = -1;
         break;
       }
+      for (auto& m : c->marks) m.tag = -1;
       if (it + k >= c->prm.max_iter) {
         k_done = k;
         break;

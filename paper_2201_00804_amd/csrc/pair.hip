@@ -609,37 +609,36 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
   else hipLaunchKernelGGL((k_perm<double, kG>), g, b, 0, st, s, red, E0);
 }
 
-template <typename R, int P>
-static void matvec_r(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
-                     const float4* p32, double4* out, int dot_slot, bool coef, hipStream_t st) {
+void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
+                        double4* out, int dot_slot, bool mixed, bool coef, hipStream_t st) {
+  if (s.npol <= 0) return;
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (coef) hipLaunchKernelGGL((k_matvec<R, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-  else hipLaunchKernelGGL((k_matvec<R, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-  if (s.periodic) {
-    const dim3 g2((s.npol + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_matvec_recip<R, P>), g2, b, 0, st, s, pm, red, p, out, dot_slot);
-    if (dot_slot >= 0) red.nparts[dot_slot] = (int)g2.x;
-  } else if (dot_slot >= 0) {
-    red.nparts[dot_slot] = (int)g.x;
+  if (mixed) {
+    if (coef) hipLaunchKernelGGL((k_matvec<float, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+    else hipLaunchKernelGGL((k_matvec<float, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+  } else {
+    if (coef) hipLaunchKernelGGL((k_matvec<double, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+    else hipLaunchKernelGGL((k_matvec<double, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
   }
+  if (!s.periodic && dot_slot >= 0) red.nparts[dot_slot] = (int)g.x;
 }
 
 template <int P>
-static void matvec_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
-                     const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
-                     hipStream_t st) {
-  if (mixed) matvec_r<float, P>(s, pm, red, p, p32, out, dot_slot, coef, st);
-  else matvec_r<double, P>(s, pm, red, p, p32, out, dot_slot, coef, st);
+static void matvec_recip_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
+                           double4* out, int dot_slot, bool mixed, hipStream_t st) {
+  const dim3 g((s.npol + kBlock - 1) / kBlock), b(kBlock);
+  if (mixed) hipLaunchKernelGGL((k_matvec_recip<float, P>), g, b, 0, st, s, pm, red, p, out, dot_slot);
+  else hipLaunchKernelGGL((k_matvec_recip<double, P>), g, b, 0, st, s, pm, red, p, out, dot_slot);
+  if (dot_slot >= 0) red.nparts[dot_slot] = (int)g.x;
 }
 
-void launch_matvec(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
-                   const float4* p32, double4* out, int dot_slot, bool mixed, bool coef,
-                   hipStream_t st) {
-  if (s.npol <= 0) return;
+void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
+                         double4* out, int dot_slot, bool mixed, hipStream_t st) {
+  if (s.npol <= 0 || !s.periodic) return;
   switch (pm.order) {
-    case 4: matvec_p<4>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
-    case 6: matvec_p<6>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
-    default: matvec_p<5>(s, pm, red, p, p32, out, dot_slot, mixed, coef, st); break;
+    case 4: matvec_recip_p<4>(s, pm, red, p, out, dot_slot, mixed, st); break;
+    case 6: matvec_recip_p<6>(s, pm, red, p, out, dot_slot, mixed, st); break;
+    default: matvec_recip_p<5>(s, pm, red, p, out, dot_slot, mixed, st); break;
   }
 }
 

@@ -1,0 +1,146 @@
+"""Text summaries of rocprofv3 output for the kernels of the library.
+
+    python -m paper_2201_00804_amd.profsum stats TRACE_CSV STATS_CSV --command CMD
+    python -m paper_2201_00804_amd.profsum traffic --kernel k_matvec \
+        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
+        --copy-bytes N --command CMD
+
+`stats` lists the per-kernel totals of `--kernel-trace --stats` and, for
+each kernel, the mean over its working launches: the solver enqueues its
+iterations in batches of four and launches queued after the device-side stop
+flag was raised return at once (a few microseconds); those are counted
+separately.  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
+dispatch) into bytes per launch, each scaled by the ratio of a plain copy
+kernel's known bytes to what the same counter reads for it.
+
+The library's HIP-event profile counts the same working launches, so the two
+mean durations are comparable.
+"""
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# sources whose change makes a stored traffic figure stale
+TRAFFIC_SOURCES = {
+    "k_matvec": ["paper_2201_00804_amd/csrc/pair.hip", "paper_2201_00804_amd/csrc/pairmath.h",
+                 "paper_2201_00804_amd/csrc/common.h"],
+}
+IDLE_FRACTION = 0.25   # a launch under this share of the kernel's longest is idle
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name):
+    """'void ns::k<float, 5>(args)' -> 'k<float, 5>'."""
+    n = name.split("(")[0]
+    if n.startswith("void "):
+        n = n[5:]
+    return n.replace("sibfa::", "")
+
+
+def precision_of(name):
+    return "mixed" if "<float" in name else "fp64"
+
+
+def stats(args):
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(args.trace)):
+        per[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    rows = list(csv.DictReader(open(args.stats)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows) / 1e3
+    out = [f"# {args.title}", "", "Command:", "", "```", args.command, "```", "",
+           f"Total kernel time {total / 1e3:.3f} ms over {len(rows)} kernels.", "",
+           "| kernel | calls | total us | avg us (rocprof) | % | working calls | "
+           "working avg us | idle calls |",
+           "|---|---|---|---|---|---|---|---|"]
+    for r in rows[:args.top]:
+        d = per.get(r["Name"], [])
+        mx = max(d) if d else 0.0
+        work = [x for x in d if x >= IDLE_FRACTION * mx]
+        wavg = sum(work) / len(work) if work else 0.0
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f}"
+                   f" | {float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} | "
+                   f"{len(work)} | {wavg:.2f} | {len(d) - len(work)} |")
+    print("\n".join(out))
+
+
+def counter_means(path, kernel):
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if short(r["Kernel_Name"]).split("<")[0] == kernel:
+            vals[precision_of(short(r["Kernel_Name"]))].append(float(r["Counter_Value"]))
+    out = {}
+    for p, v in vals.items():
+        mx = max(v)
+        work = [x for x in v if x >= IDLE_FRACTION * mx]
+        out[p] = (sum(work) / len(work), len(work), len(v))
+    return out
+
+
+def copy_value(path):
+    v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+         if "copyBuffer" in r["Kernel_Name"]]
+    return sum(v) / len(v)
+
+
+def traffic(args):
+    f_copy = args.copy_bytes / (copy_value(args.copy_fetch) * 1024.0)
+    w_copy = args.copy_bytes / (copy_value(args.copy_write) * 1024.0)
+    fm = counter_means(args.fetch, args.kernel)
+    wm = counter_means(args.write, args.kernel)
+    out = [f"# HBM traffic of {args.kernel}, {args.workload}", "", "Commands:", "", "```"]
+    out += args.command
+    out += ["```", "",
+            "FETCH_SIZE and WRITE_SIZE are KiB per dispatch.  A plain device copy of "
+            f"{args.copy_bytes} bytes reads {copy_value(args.copy_fetch):.1f} KiB of FETCH_SIZE "
+            f"and {copy_value(args.copy_write):.1f} KiB of WRITE_SIZE, so the counters are "
+            f"scaled by {f_copy:.4f} (fetch) and {w_copy:.4f} (write) bytes per KiB/1024.  "
+            "Means are over working launches (idle launches after the solver's stop flag "
+            "excluded).", "",
+            "| key | value |", "|---|---|",
+            f"| kernel sources sha256[:16] | `{source_hash(args.kernel)}` |",
+            f"| fetch scale | {f_copy:.5f} |", f"| write scale | {w_copy:.5f} |"]
+    for p in sorted(fm):
+        fk, nw, nall = fm[p]
+        wk = wm.get(p, (0.0, 0, 0))[0]
+        b = fk * 1024.0 * f_copy + wk * 1024.0 * w_copy
+        out += [f"| FETCH_SIZE KiB ({p}) | {fk:.1f} ({nw} of {nall} launches) |",
+                f"| WRITE_SIZE KiB ({p}) | {wk:.1f} |",
+                f"| traffic bytes per launch ({p}) | {b:.0f} |"]
+    print("\n".join(out))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("trace")
+    a.add_argument("stats")
+    a.add_argument("--command", required=True)
+    a.add_argument("--title", default="Kernel time")
+    a.add_argument("--top", type=int, default=30)
+    b = sub.add_parser("traffic")
+    b.add_argument("--kernel", required=True, choices=sorted(TRAFFIC_SOURCES))
+    b.add_argument("--workload", default="")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--copy-fetch", required=True)
+    b.add_argument("--copy-write", required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--command", action="append", required=True)
+    args = ap.parse_args(argv)
+    (stats if args.cmd == "stats" else traffic)(args)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
