@@ -988,6 +988,10 @@ size_t sibfa_footprint_bytes(int n_sites, int n_polarizable, const double* box,
   }
   bytes += (n * (cap_all + 8) + np * (cap_pol + 8)) * sizeof(int);
   bytes += 4 * n * sizeof(int);
+  // cached pair coefficients: FP64 for the polarizable and same-molecule
+  // lists, plus an FP32 copy of the former in mixed precision
+  bytes += np * (cap_pol + 8) * 2 * sizeof(double);
+  if (p->precision == SIBFA_MIXED) bytes += np * cap_pol * 2 * sizeof(float);
   return bytes + (1 << 20);
 }
 
