@@ -201,6 +201,66 @@ sibfa_status sibfa_set_profiling(sibfa_ctx ctx, int enable);
 /* Synchronizes the stream and returns the accumulated times. */
 sibfa_status sibfa_get_profile(sibfa_ctx ctx, sibfa_profile* out);
 
+/* ------------------------------------------------------------------------
+ * Batched gas-phase clusters (serving many small independent systems).
+ *
+ * Same mathematics as a cluster context (direct sums, no cutoff; the
+ * permanent field, the PCG solve of T mu = E (Eq. 18), E_pol (Eq. 19),
+ * E_elec and forces), for many clusters in one call: one workgroup owns one
+ * cluster and keeps its whole solve on the device, so a batch costs three
+ * kernel launches and no host synchronisation.  A cluster's results are
+ * bitwise independent of the other clusters in the batch.
+ *
+ * Limits per cluster: at most SIBFA_BATCH_MAX_SITES sites and
+ * SIBFA_BATCH_MAX_POLARIZABLE polarizable sites (larger systems use a
+ * context).
+ * ------------------------------------------------------------------------ */
+#define SIBFA_BATCH_MAX_SITES 1024
+#define SIBFA_BATCH_MAX_POLARIZABLE 640
+
+typedef struct sibfa_batch_s* sibfa_batch;
+
+/* A batch executor on `device`, enqueuing on `hip_stream`; alloc/free as
+ * for sibfa_create.  It owns scratch memory that grows to the largest batch
+ * seen (about 240 bytes per site) and pinned staging for the offsets. */
+sibfa_status sibfa_batch_create(sibfa_batch* out, int device, void* hip_stream,
+                                sibfa_alloc_fn alloc_fn, sibfa_free_fn free_fn,
+                                void* user);
+/* Waits for the batch stream, then releases everything. */
+void sibfa_batch_destroy(sibfa_batch b);
+const char* sibfa_batch_last_error(sibfa_batch b);
+
+/* Evaluate n_clusters clusters stored back to back.
+ *  site_offsets [n_clusters + 1] (HOST): cluster c owns sites
+ *    [site_offsets[c], site_offsets[c+1]); site_offsets[0] = 0; each
+ *    cluster has 1..SIBFA_BATCH_MAX_SITES sites.
+ *  warm_start [n_clusters] (HOST) or NULL: nonzero = start cluster c's
+ *    solve from the dipoles found in mu instead of alpha E.
+ *  xyz [n][3], mol [n], q [n], dip [n][3], quad [n][6], alpha [n][6],
+ *    thole [n] or NULL: DEVICE, caller layout as for a context; molecule
+ *    ids only need to compare equal within a molecule.
+ *  params (HOST): thole_a, tol_debye, max_iter and precision are used;
+ *    the Ewald/PME fields are ignored.
+ * Outputs (DEVICE), written when the batch's kernels complete on the
+ * stream (the call itself only enqueues work):
+ *  mu [n][3] (also the warm-start input), forces [n][3] or NULL,
+ *  e_pol, e_elec [n_clusters] kcal/mol, iterations [n_clusters],
+ *  rms_debye [n_clusters] (true residual), status [n_clusters]:
+ *  SIBFA_OK, SIBFA_E_ARG (alpha not positive definite, or too many
+ *  polarizable sites: zero mu and forces, NaN e_pol), SIBFA_E_NOT_SPD or
+ *  SIBFA_E_NOT_CONVERGED (mu and forces at the last iterate).
+ * Input arrays must stay valid and unchanged until the batch completes;
+ * batches on one executor run in call order. */
+sibfa_status sibfa_batch_clusters(sibfa_batch b, int n_clusters,
+                                  const int* site_offsets, const int* warm_start,
+                                  const double* xyz, const int32_t* mol,
+                                  const double* q, const double* dip,
+                                  const double* quad, const double* alpha,
+                                  const double* thole, const sibfa_params* params,
+                                  double* mu, double* forces, double* e_pol,
+                                  double* e_elec, int* iterations,
+                                  double* rms_debye, int* status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,7 +66,15 @@ SIGNATURES = [
     ("sibfa_get_stats", ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     ("sibfa_set_profiling", ctypes.c_int, [_P, ctypes.c_int]),
     ("sibfa_get_profile", ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
+    ("sibfa_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, _P]),
+    ("sibfa_batch_destroy", None, [_P]),
+    ("sibfa_batch_last_error", ctypes.c_char_p, [_P]),
+    ("sibfa_batch_clusters", ctypes.c_int, [_P, ctypes.c_int, _P, _P] + [_P] * 7 +
+     [ctypes.POINTER(Params)] + [_P] * 7),
 ]
+
+BATCH_MAX_SITES = 1024
+BATCH_MAX_POLARIZABLE = 640
 
 _lib = None
 

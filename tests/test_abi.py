@@ -59,3 +59,22 @@ def test_struct_layout_matches_header():
     mod, _ = _lib()
     assert ctypes.sizeof(mod.Params) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(mod.Stats) == 4 + 4 + 7 * 8 + 3 * 4 + 4   # tail padding to 8
+
+
+def _prototypes():
+    """name -> number of parameters, from the header's declarations."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(sibfa_[A-Za-z_]+)\s*\(([^;{]*?)\)\s*;", txt, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else len(args.split(","))
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    from paper_2201_00804_amd import _lib
+    protos = _prototypes()
+    for name, _, args in _lib.SIGNATURES:
+        assert name in protos, name
+        assert len(args) == protos[name], (name, len(args), protos[name])
