@@ -258,6 +258,41 @@ def cpu_baseline(sysd, prm, iters, sample=64):
                 parts_s={k: round(v, 2) for k, v in t.items()})
 
 
+def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0):
+    """Open-loop serving stream on the synthetic pool (48 clusters of
+    U{2..64} waters, boxes of 216, 1,024 and 4,096 waters, two of each;
+    70% cluster requests; repeats are MD steps of 0.01 A), mixed precision
+    at 1e-8 D.  A warm-up stream at 200 requests/s admits every box and
+    measures the box worker's mean service time S; the timed stream then
+    arrives at the Poisson rate that loads that worker to `utilisation`
+    (rate = utilisation / (0.3 S))."""
+    from paper_2201_00804_amd.serve import Server, serving_pool, request_stream, summarize
+    systems = serving_pool(seed)
+    srv = Server(systems, precision="mixed", tol=1e-8)
+    stream = request_stream(systems, n_warmup + n_requests, rate=1.0, seed=seed + 1)
+    warm, timed = stream[:n_warmup], stream[n_warmup:]
+    for q in warm:
+        q.arrival /= 200.0
+    srv.run(warm)
+    n_box = sum(q.kind == "box" for q in warm)
+    s_box = srv.busy["box"] / max(n_box, 1)
+    rate = utilisation / (0.3 * s_box)
+    t_first = timed[0].arrival
+    for q in timed:
+        q.arrival = (q.arrival - t_first) / rate
+    srv.busy = {"box": 0.0, "cluster": 0.0}
+    srv.batches.clear()
+    wall = srv.run(timed)
+    out = summarize(timed, wall, srv)
+    out.update(rate_per_s=round(rate, 1), warmup_requests=n_warmup,
+               warmup_box_service_ms=round(1e3 * s_box, 3),
+               pool="48 clusters U{2..64} waters + boxes 216, 1024, 4096 (x2); 70% clusters; "
+                    "MD steps of 0.01 A; mixed precision, 1e-8 D",
+               resident_mb=round(srv.resident_bytes / 2 ** 20, 1))
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +300,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=300)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -336,6 +374,13 @@ def main():
                                            np.mean(a["forces"] ** 2))),
             "mu_rms_debye": float(4.803204 * np.sqrt(np.mean(np.sum((b["mu"] - a["mu"]) ** 2, 1)))),
         }
+    if not args.no_serve:
+        print(f"[bench] serving: {args.serve_warmup} warm-up + {args.serve_requests} requests",
+              file=sys.stderr, flush=True)
+        out["serving"] = run_serving(args.serve_requests, args.serve_warmup)
+        sv = out["serving"]
+        print(f"[bench] serving: {sv['throughput_per_s']} req/s at {sv['rate_per_s']}/s, p50 "
+              f"{sv['p50_ms']} ms, p99 {sv['p99_ms']} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         iters = results.get("fp64", main_r)["iters"]
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
