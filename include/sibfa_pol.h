@@ -198,6 +198,10 @@ typedef struct {
 } sibfa_profile;
 
 sibfa_status sibfa_set_profiling(sibfa_ctx ctx, int enable);
+/* As sibfa_set_profiling, timing only the phases whose bit (1 << phase) is
+ * set in phase_mask (0 = off): fewer events, less perturbation.  Each timed
+ * phase boundary costs the stream a few microseconds. */
+sibfa_status sibfa_set_profiling_phases(sibfa_ctx ctx, unsigned phase_mask);
 /* Synchronizes the stream and returns the accumulated times. */
 sibfa_status sibfa_get_profile(sibfa_ctx ctx, sibfa_profile* out);
 

@@ -65,6 +65,7 @@ SIGNATURES = [
     ("sibfa_neighbor_counts", ctypes.c_int, [_P, _P]),
     ("sibfa_get_stats", ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     ("sibfa_set_profiling", ctypes.c_int, [_P, ctypes.c_int]),
+    ("sibfa_set_profiling_phases", ctypes.c_int, [_P, ctypes.c_uint]),
     ("sibfa_get_profile", ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
     ("sibfa_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, _P]),
     ("sibfa_batch_destroy", None, [_P]),

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <string>
@@ -40,6 +41,11 @@ struct DevBuf {
 struct sibfa_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  // library-owned second stream: the reciprocal half of each PME step
+  // (spreading + FFT convolution) runs on it concurrently with the
+  // real-space kernel on `stream`; ev_fork / ev_join order the two
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   sibfa_alloc_fn af = nullptr;
   sibfa_free_fn ff = nullptr;
   void* user = nullptr;
@@ -110,6 +116,7 @@ struct sibfa_ctx_s {
   long long pair_totals[4] = {0, 0, 0, 0};
   // profiling: HIP events on the context stream around each phase
   bool prof = false;
+  unsigned prof_mask = ~0u;   // phases timed while profiling
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   // tag: solver iteration of a batched launch (-1 outside batches); launches
@@ -339,6 +346,7 @@ hipEvent_t next_event(sibfa_ctx c) {
 void fold_marks(sibfa_ctx c) {
   if (c->marks.empty()) return;
   (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->aux);
   for (auto& m : c->marks) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
@@ -354,19 +362,20 @@ void fold_marks(sibfa_ctx c) {
 struct Phase {
   sibfa_ctx c;
   int ph;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  Phase(sibfa_ctx cc, int p) : c(cc), ph(p) {
-    if (c->prof) {
+  Phase(sibfa_ctx cc, int p, hipStream_t s = nullptr) : c(cc), ph(p), st(s ? s : cc->stream) {
+    if (c->prof && ((c->prof_mask >> p) & 1u)) {
       if (c->marks.size() > 4096 && c->cur_tag < 0) fold_marks(c);
       a = next_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~Phase() {
     if (c->prof && a) {
       hipEvent_t b = next_event(c);
       if (b) {
-        (void)hipEventRecord(b, c->stream);
+        (void)hipEventRecord(b, st);
         c->marks.push_back({ph, a, b, c->cur_tag, true});
       }
     }
@@ -582,7 +591,22 @@ sibfa_status prepare(sibfa_ctx c) {
 }
 
 // ------------------------------------------------------------ compute steps
-void conv(sibfa_ctx c, bool mix) { launch_convolution(c->pm, c->red, mix, c->stream); }
+void conv(sibfa_ctx c, bool mix, hipStream_t st) { launch_convolution(c->pm, c->red, mix, st); }
+
+// The auxiliary stream starts after everything enqueued so far on the main
+// stream; the main stream continues once the auxiliary work is done.
+// With the overlap switched off (environment SIBFA_PME_OVERLAP=0) the
+// auxiliary stream is the main stream and both are no-ops.
+void fork(sibfa_ctx c) {
+  if (c->aux == c->stream) return;
+  (void)hipEventRecord(c->ev_fork, c->stream);
+  (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+}
+void join(sibfa_ctx c) {
+  if (c->aux == c->stream) return;
+  (void)hipEventRecord(c->ev_join, c->aux);
+  (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+}
 
 // t = T v (v in pol order, double + float copy)
 sibfa_status ensure_coef(sibfa_ctx c) {
@@ -601,21 +625,20 @@ sibfa_status ensure_coef(sibfa_ctx c) {
 void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
   SysView s = make_view(c);
   if (c->periodic) {
-    DirUpdate du{};
-    du.upd = 0;
-    du.p_old = v;
+    fork(c);
     {
-      Phase ph(c, SIBFA_PH_SPREAD);
-      launch_spread_dip(s, c->pm, c->red, du, mix, c->stream);
+      Phase ph(c, SIBFA_PH_SPREAD, c->aux);
+      launch_spread_dip(s, c->pm, v, mix, c->aux);
     }
-    Phase ph(c, SIBFA_PH_FFT);
-    conv(c, mix);
+    Phase ph(c, SIBFA_PH_FFT, c->aux);
+    conv(c, mix, c->aux);
   }
   const bool coef = c->coef_valid;
   {
     Phase ph2(c, SIBFA_PH_MATVEC);
     launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
   }
+  if (c->periodic) join(c);
   Phase ph3(c, SIBFA_PH_MATVEC_RECIP);
   launch_matvec_recip(s, c->pm, c->red, v, out, dot_slot, mix, c->stream);
 }
@@ -623,14 +646,19 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
 sibfa_status compute_E0(sibfa_ctx c) {
   SysView s = make_view(c);
   const bool mix = mixed(c);
+  if (c->periodic) {
+    fork(c);
+    Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
+    launch_spread_mult(s, c->pm, nullptr, mix, c->aux);
+    conv(c, mix, c->aux);
+  }
   {
     Phase ph(c, SIBFA_PH_FIELD_REAL);
     launch_perm(s, c->red, c->E0, mix, c->stream);
   }
   if (c->periodic) {
+    join(c);
     Phase ph(c, SIBFA_PH_FIELD_RECIP);
-    launch_spread_mult(s, c->pm, nullptr, mix, c->stream);
-    conv(c, mix);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
   }
   double tot[4] = {0, 0, 0, 0};
@@ -695,44 +723,25 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       for (int b = 0; b < kBatch && it + k < c->prm.max_iter; ++b) {
         c->cur_tag = k;
         if (k > 0) {
+          // p = z + beta p
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
-          if (c->periodic) {
-            // p_new = z + beta p_old is formed inside the spreading kernel
-            DirUpdate du{};
-            du.upd = 1;
-            du.num = num;
-            du.den = den;
-            du.z = c->z;
-            du.p_old = c->p;
-            du.p_new = c->p2;
-            du.p_new32 = c->p2_32;
-            {
-              Phase ph(c, SIBFA_PH_SPREAD);
-              launch_spread_dip(s, c->pm, c->red, du, mix, st);
-            }
-            std::swap(c->p, c->p2);
-            std::swap(c->p32, c->p2_32);
-            Phase ph(c, SIBFA_PH_FFT);
-            conv(c, mix);
-          } else {
-            Phase ph(c, SIBFA_PH_SPREAD);
-            launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
-          }
-        } else if (c->periodic) {
-          DirUpdate du{};
-          du.upd = 0;
-          du.p_old = c->p;
+          Phase ph(c, SIBFA_PH_UPDATE);
+          launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
+        }
+        if (c->periodic) {
+          fork(c);
           {
-            Phase ph(c, SIBFA_PH_SPREAD);
-            launch_spread_dip(s, c->pm, c->red, du, mix, st);
+            Phase ph(c, SIBFA_PH_SPREAD, c->aux);
+            launch_spread_dip(s, c->pm, c->p, mix, c->aux);
           }
-          Phase ph(c, SIBFA_PH_FFT);
-          conv(c, mix);
+          Phase ph(c, SIBFA_PH_FFT, c->aux);
+          conv(c, mix, c->aux);
         }
         {
           Phase ph(c, SIBFA_PH_MATVEC);
           launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
         }
+        if (c->periodic) join(c);
         {
           Phase ph(c, SIBFA_PH_MATVEC_RECIP);
           launch_matvec_recip(s, c->pm, c->red, c->p, c->q, S_PQ, mix, st);
@@ -787,6 +796,18 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   return SIBFA_OK;
 }
 
+// Spreading brick edge along an axis of K points: the largest size <=
+// kBrick whose last (partial) brick still spans order - 1 points, so that
+// every grid point lies in the tiles of at most two bricks per axis; 0 if
+// none fits.
+int brick_edge(int K, int order) {
+  for (int b = kBrick; b >= order - 1 && b >= 1; --b) {
+    const int rem = K % b;
+    if (rem == 0 || rem >= order - 1) return b;
+  }
+  return 0;
+}
+
 sibfa_status setup_pme(sibfa_ctx c) {
   free_list(c, c->pmebufs);
   PmeView& pm = c->pm;
@@ -803,20 +824,13 @@ sibfa_status setup_pme(sibfa_ctx c) {
     factor_radices(pm.K[a], pm.rad[a], &pm.nrad[a]);
   }
   pm.kxh = pm.K[0] / 2 + 1;
-  // spreading bricks: the largest size <= kBrick whose last (partial) brick
-  // still spans order - 1 points, so a brick only receives contributions
-  // from sites homed in it or in its successor along each axis
   for (int a = 0; a < 3; ++a) {
-    int best = 0;
-    for (int b = kBrick; b >= order - 1 && b >= 1; --b) {
-      const int rem = pm.K[a] % b;
-      if (rem == 0 || rem >= order - 1) { best = b; break; }
-    }
-    if (best == 0) return fail(c, SIBFA_E_ARG, "no spreading brick size fits this grid");
-    pm.Bb[a] = best;
-    pm.nb[a] = (pm.K[a] + best - 1) / best;
+    pm.Bb[a] = brick_edge(pm.K[a], order);
+    if (pm.Bb[a] == 0) return fail(c, SIBFA_E_ARG, "no spreading brick size fits this grid");
+    pm.nb[a] = (pm.K[a] + pm.Bb[a] - 1) / pm.Bb[a];
   }
   c->nbricks = pm.nb[0] * pm.nb[1] * pm.nb[2];
+  pm.tile_size = (pm.Bb[0] + order - 1) * (pm.Bb[1] + order - 1) * (pm.Bb[2] + order - 1);
   {
     const size_t nbk = (size_t)c->nbricks;
     if (!alloc_into(c, c->pmebufs, c->bcount, nbk + 1) ||
@@ -842,7 +856,9 @@ sibfa_status setup_pme(sibfa_ctx c) {
   if (!alloc_into(c, c->pmebufs, Q, nr) || !alloc_into(c, c->pmebufs, phi, nr) ||
       !alloc_into(c, c->pmebufs, C, nh) || !alloc_into(c, c->pmebufs, G, nh) ||
       !alloc_into(c, c->pmebufs, Q32, nr) || !alloc_into(c, c->pmebufs, phi32, nr) ||
-      !alloc_into(c, c->pmebufs, C32, nh) || !alloc_into(c, c->pmebufs, G32, nh))
+      !alloc_into(c, c->pmebufs, C32, nh) || !alloc_into(c, c->pmebufs, G32, nh) ||
+      !alloc_into(c, c->pmebufs, pm.tiles, (size_t)c->nbricks * pm.tile_size) ||
+      !alloc_into(c, c->pmebufs, pm.tiles32, (size_t)c->nbricks * pm.tile_size))
     return fail(c, SIBFA_E_NOMEM, "PME grid allocation failed");
   pm.Q = Q; pm.phi = phi; pm.C = C; pm.G = G;
   pm.Q32 = Q32; pm.phi32 = phi32; pm.C32 = C32; pm.G32 = G32;
@@ -943,8 +959,17 @@ sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream, sibfa_al
   sibfa_default_params(&c->prm);
   if (hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ints, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    delete c;
+    sibfa_destroy(c);
     return SIBFA_E_NOMEM;
+  }
+  const char* ov = std::getenv("SIBFA_PME_OVERLAP");
+  if (ov && std::atoi(ov) == 0) {
+    c->aux = c->stream;
+  } else if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    sibfa_destroy(c);
+    return SIBFA_E_DEVICE;
   }
   *out = c;
   return SIBFA_OK;
@@ -954,8 +979,12 @@ void sibfa_destroy(sibfa_ctx c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->aux && c->aux != c->stream) (void)hipStreamSynchronize(c->aux);
   release_system(c);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux && c->aux != c->stream) (void)hipStreamDestroy(c->aux);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
   delete c;
@@ -982,6 +1011,12 @@ size_t sibfa_footprint_bytes(int n_sites, int n_polarizable, const double* box,
     const size_t nr = (size_t)p->grid[0] * p->grid[1] * p->grid[2];
     const size_t nh = (size_t)(p->grid[0] / 2 + 1) * p->grid[1] * p->grid[2];
     bytes += nr * 2 * (8 + 4) + nh * (16 + 8 + 8 + 4);
+    size_t tiles = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int e = std::max(brick_edge(p->grid[a], p->order), 1);
+      tiles *= (size_t)((p->grid[a] + e - 1) / e) * (e + p->order - 1);
+    }
+    bytes += tiles * (8 + 4);
   } else {
     cap_all = n;
     cap_pol = np;
@@ -1189,23 +1224,30 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   hipStream_t sm = c->stream;
   const bool mix = mixed(c);
   if (c->npol > 0) {
+    // mu came from the last solve, which ended on the FP64 true residual
+    // r = E - T x of exactly these dipoles: x.T x = x.E - x.r gives the
+    // variational energy (Eq. 17) without another matvec
     launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, sm);
     launch_dot(s, c->red, c->x, c->E0, S_MUE, sm);
-    matvec(c, c->x, c->x32, c->t, -1, false);
-    launch_dot(s, c->red, c->x, c->t, S_MUTMU, sm);
+    launch_dot(s, c->red, c->x, c->r, S_MUTMU, sm);
   } else {
     launch_fill_double(reinterpret_cast<double*>(c->x), 0.0, 4, sm);
   }
   if (forces) {
     launch_mu_sites(s, c->x, c->mu_s, c->mu_s32, sm);
+    if (c->periodic) {
+      fork(c);
+      Phase ph(c, SIBFA_PH_FORCE_RECIP, c->aux);
+      launch_spread_mult(s, c->pm, c->mu_s, mix, c->aux);
+      conv(c, mix, c->aux);
+    }
     {
       Phase ph(c, SIBFA_PH_FORCE_REAL);
       launch_force(s, c->mu_s, c->mu_s32, c->Freal, mix, sm);
     }
     if (c->periodic) {
+      join(c);
       Phase ph(c, SIBFA_PH_FORCE_RECIP);
-      launch_spread_mult(s, c->pm, c->mu_s, mix, sm);
-      conv(c, mix);
       launch_gather_force(s, c->pm, c->mu_s, c->Freal, c->perm, forces, mix, sm);
     } else {
       launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
@@ -1219,7 +1261,7 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
     st = sync_read(c);
     if (st != SIBFA_OK) return st;
   }
-  const double mue = mm[0], mutmu = mm[1];
+  const double mue = mm[0], mutmu = mm[0] - mm[1];
   c->stats.e_pol = -0.5 * kCoulomb * mue;
   c->stats.e_pol_variational = kCoulomb * (0.5 * mutmu - mue);
   c->stats.e_elec_real = kCoulomb * c->e_real;
@@ -1265,11 +1307,19 @@ sibfa_status sibfa_neighbor_counts(sibfa_ctx c, int32_t* counts_out) {
   return sync_read(c);
 }
 
+sibfa_status sibfa_set_profiling_phases(sibfa_ctx c, unsigned phase_mask) {
+  if (!c) return SIBFA_E_ARG;
+  sibfa_status st = sibfa_set_profiling(c, phase_mask != 0);
+  c->prof_mask = phase_mask;
+  return st;
+}
+
 sibfa_status sibfa_set_profiling(sibfa_ctx c, int enable) {
   if (!c) return SIBFA_E_ARG;
   HIP_TRY(hipSetDevice(c->device));
   fold_marks(c);
   c->prof = enable != 0;
+  c->prof_mask = ~0u;
   for (int k = 0; k < 16; ++k) {
     c->prof_ms[k] = 0.0;
     c->prof_calls[k] = 0;

@@ -98,6 +98,9 @@ struct PmeView {
   // order - 1 points), sites binned by the brick holding their base index
   int Bb[3];
   int nb[3];
+  double* tiles;           // [nbricks][tile_size] spreading tiles
+  float* tiles32;
+  int tile_size;           // (Bb0 + p - 1)(Bb1 + p - 1)(Bb2 + p - 1)
   const int* bstart_pol;   // [nbricks + 1]
   const int* border_pol;   // polarizable indices grouped by brick
   const int* bstart_all;

@@ -25,23 +25,13 @@ void launch_force(const SysView& s, const double4* mu, const float4* mu32, doubl
 // when mu != NULL, sorted-site indexing) onto the real grid.
 void launch_spread_mult(const SysView& s, const PmeView& pm, const double4* mu, bool mixed,
                         hipStream_t st);
-// Spread of polarizable-site dipoles p_old.  With upd != 0 the spread
-// dipole is p_new = z + beta p_old, beta = total(num) / total(den),
-// written to p_new (and its FP32 copy); p_old is only read.
-struct DirUpdate {
-  int upd;
-  int num, den;          // reduction slots
-  const double4* z;
-  const double4* p_old;
-  double4* p_new;
-  float4* p_new32;
-};
 // Home-brick binning of the sites for the spreading kernels (counts must be
 // zeroed; pol = 1 bins polarizable sites, 0 all sites).
 void launch_brick_bin(const SysView& s, const PmeView& pm, int pol, int* brick_of, int* counts,
                       hipStream_t st);
-void launch_spread_dip(const SysView& s, const PmeView& pm, const Reduce& red, DirUpdate du,
-                       bool mixed, hipStream_t st);
+// Spread of the polarizable-site dipoles p (polarizable order).
+void launch_spread_dip(const SysView& s, const PmeView& pm, const double4* p, bool mixed,
+                       hipStream_t st);
 // E0[pi] += -grad phi at polarizable sites.
 void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool mixed,
                          hipStream_t st);

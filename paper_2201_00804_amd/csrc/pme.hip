@@ -39,13 +39,18 @@ __device__ __forceinline__ void site_splines(const PmeView& pm, double x, double
 }
 
 // ------------------------------------------------------------ spreading
-// One workgroup per brick of B^3 grid points, accumulated in LDS.  A site
-// with base index b touches points b - t, t = 0..p-1, so a brick receives
-// contributions from the sites whose home brick (the brick holding b) is the
-// brick itself or its successor along any axis: 8 home bricks.  Each site
-// adds its in-brick points with LDS atomics; the finished tile is stored
-// with plain coalesced writes, every grid point by exactly one brick, so the
-// grid needs no clearing and no global atomics are used.
+// Sites are binned by home brick, the brick of B^3 grid points (B <= 8, per
+// axis; the last brick along an axis never has fewer than p - 1 points)
+// holding their base index b.  A site touches points b - t, t = 0..p-1, so
+// all contributions of a brick's sites fall in the brick extended by p - 1
+// points towards lower indices: its tile, (B + p - 1)^3 points.
+//
+//  k_spread_tile : one workgroup per brick spreads its own sites into the
+//                  tile (every site is evaluated once) and stores the tile;
+//  k_spread_fold : every grid point sums the tiles that cover it -- its own
+//                  brick's and, along each axis where it lies within p - 1
+//                  points of the next brick, that brick's -- in a fixed
+//                  order.  No global atomics, no clearing, deterministic.
 
 __global__ void k_brick_bin(SysView s, PmeView pm, int pol, int* brick_of, int* counts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,208 +84,184 @@ template <>
 __device__ __forceinline__ double* grid_out<double>(const PmeView& pm) { return pm.Q; }
 template <>
 __device__ __forceinline__ float* grid_out<float>(const PmeView& pm) { return pm.Q32; }
+template <typename R>
+__device__ __forceinline__ R* tile_buf(const PmeView& pm);
+template <>
+__device__ __forceinline__ double* tile_buf<double>(const PmeView& pm) { return pm.tiles; }
+template <>
+__device__ __forceinline__ float* tile_buf<float>(const PmeView& pm) { return pm.tiles32; }
 
-// Per-axis setup of a site against a brick: base index, offset d of the
-// base from the brick origin (mod K) and the contributing t range.
-struct AxisSpan {
-  int d, tlo, thi;
-};
-
-template <int P>
-__device__ __forceinline__ bool axis_span(int base, int x0, int Bx, int K, AxisSpan& a) {
-  int d = base - x0;
-  if (d < 0) d += K;
-  a.d = d;
-  a.tlo = d - Bx + 1 > 0 ? d - Bx + 1 : 0;
-  a.thi = d < P - 1 ? d : P - 1;
-  return a.tlo <= a.thi;
-}
-
-// FULL: multipoles (q, d [+ mu], Theta) of all sites; otherwise dipoles of
-// the polarizable sites (with the optional direction update).
+// FULL: multipoles (q, d [+ mu], Theta) of all sites; otherwise the dipoles
+// of the polarizable sites.
 //
-// Work split: the brick's candidate sites (the 8 home bricks' lists, taken
-// as one concatenated range) are handled in chunks of CH per wavefront.  A
-// wave stages its chunk in LDS -- the sites that reach the brick, compacted
-// with a ballot, with their B-spline weights, amplitudes and in-brick t
-// ranges -- and then spreads (site, ty, tz) work items over its 64 lanes,
-// each adding one row of up to p points to the LDS tile with LDS atomics.
-template <typename R, int P, bool FULL>
-struct Stage {
-  static constexpr int ND = FULL ? 2 : 1;
-  static constexpr int NA = FULL ? 10 : 3;
-  static constexpr int CH = FULL ? 16 : 32;
-  R th[3][ND + 1][P][CH];
-  R amp[NA][CH];
-  int d[3][CH];
-  int lo[3][CH];
-  int hi[3][CH];
+// Owner-computes, no atomics: thread (x, y) of the workgroup owns one tile
+// column and keeps its T2 values in registers.  A site's contribution is a
+// sum of separable terms  A theta_x^(kx)(x) theta_y^(ky)(y) theta_z^(kz)(z),
+// regrouped by kz as  sum_kz U_kz(x, y) theta_z^(kz)(z).  Sites are staged
+// in chunks with their B-spline weights expanded to the tile width (zeros
+// outside the p-point support), so the inner loop is a few LDS reads (the z
+// weights are the same address for every lane) and FMAs.  The brick's
+// sites are taken in increasing index order, so the tile sums -- and the
+// grid -- are reproducible bit for bit.
+constexpr int kSpreadBlock = 192;      // >= (kBrick + p - 1)^2 columns, p <= 6
+constexpr int kSpreadSorted = 512;     // bricks with more sites keep list order
+
+template <bool FULL>
+struct SpreadShape {
+  static constexpr int ND = FULL ? 2 : 1;   // highest derivative order
+  static constexpr int NA = FULL ? 10 : 3;  // amplitudes per site
+  static constexpr int CH = FULL ? 32 : 64; // sites per staged chunk
 };
 
 template <typename R, int P, bool FULL>
-__global__ __launch_bounds__(kBlock) void k_spread_brick(SysView s, PmeView pm, Reduce red,
-                                                         DirUpdate du, const double4* mu) {
-  if (stopped(red.stop)) return;
-  using St = Stage<R, P, FULL>;
-  constexpr int ND = St::ND, CH = St::CH, NW = kBlock / 64;
-  __shared__ R tile[kBrick * kBrick * kBrick];
-  __shared__ St stage[NW];
-  const int S0 = pm.Bb[0], S1 = pm.Bb[1], S2 = pm.Bb[2];   // full brick sizes (tile strides)
-  const int nb0 = pm.nb[0], nb1 = pm.nb[1], nb2 = pm.nb[2];
-  const int bx = blockIdx.x % nb0, by = (blockIdx.x / nb0) % nb1, bz = blockIdx.x / (nb0 * nb1);
-  const int o[3] = {bx * S0, by * S1, bz * S2};
-  const int Bs[3] = {min(S0, pm.K[0] - o[0]), min(S1, pm.K[1] - o[1]), min(S2, pm.K[2] - o[2])};
-  const int ntile = S0 * S1 * S2;
-  for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = R(0);
-  double beta = 0.0;
-  if (!FULL && du.upd) {
-    const double num = slot_total(red, du.num);
-    const double den = slot_total(red, du.den);
-    beta = num / den;
-  }
+__global__ __launch_bounds__(kSpreadBlock) void k_spread_tile(SysView s, PmeView pm,
+                                                              const double4* vec) {
+  if (stopped(pm.stop)) return;
+  using Sh = SpreadShape<FULL>;
+  constexpr int ND = Sh::ND, NA = Sh::NA, CH = Sh::CH;
+  constexpr int TM = kBrick + P - 1;
+  __shared__ R w[3][ND + 1][CH][TM];
+  __shared__ R amp[NA][CH];
+  __shared__ int ids_in[kSpreadSorted];
+  __shared__ int ids[kSpreadSorted];
+  const int tid = threadIdx.x;
+  const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1, T2 = pm.Bb[2] + P - 1;
+  const int nb0 = pm.nb[0], nb1 = pm.nb[1];
+  const int b = blockIdx.x;
+  const int o[3] = {(b % nb0) * pm.Bb[0], ((b / nb0) % nb1) * pm.Bb[1], (b / (nb0 * nb1)) * pm.Bb[2]};
   const int* start = FULL ? pm.bstart_all : pm.bstart_pol;
   const int* order = FULL ? pm.border_all : pm.border_pol;
-  // the candidate ranges of the (up to) 8 home bricks, concatenated
-  int rs[8], rl[8], total = 0;
-#pragma unroll
-  for (int h = 0; h < 8; ++h) {
-    const int dx = h & 1, dy = (h >> 1) & 1, dz = h >> 2;
-    rs[h] = 0; rl[h] = 0;
-    if ((dx && nb0 == 1) || (dy && nb1 == 1) || (dz && nb2 == 1)) continue;
-    const int hid = (bx + dx) % nb0 + nb0 * ((by + dy) % nb1 + nb1 * ((bz + dz) % nb2));
-    rs[h] = start[hid];
-    rl[h] = start[hid + 1] - rs[h];
-    total += rl[h];
+  const int s0 = start[b], total = start[b + 1] - s0;
+  // increasing site index (rank sort of distinct indices)
+  const bool sorted = total <= kSpreadSorted;
+  if (sorted) {
+    for (int e = tid; e < total; e += kSpreadBlock) ids_in[e] = order[s0 + e];
+    __syncthreads();
+    for (int e = tid; e < total; e += kSpreadBlock) {
+      const int v = ids_in[e];
+      int r = 0;
+      for (int k = 0; k < total; ++k) r += ids_in[k] < v ? 1 : 0;
+      ids[r] = v;
+    }
   }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  St& sg = stage[wv];
+  const bool owner = tid < T0 * T1;
+  const int cx = owner ? tid % T0 : 0, cy = owner ? tid / T0 : 0;
+  R acc[TM];
+#pragma unroll
+  for (int z = 0; z < TM; ++z) acc[z] = R(0);
   const R sc[3] = {(R)pm.scale[0], (R)pm.scale[1], (R)pm.scale[2]};
-  const int rounds = (total + NW * CH - 1) / (NW * CH);
-  __syncthreads();
-  for (int rd = 0; rd < rounds; ++rd) {
-    // ---- stage this wave's chunk
-    const int c = (rd * NW + wv) * CH + lane;
-    bool contrib = false;
-    int idx = -1, hh = 0;
-    if (lane < CH && c < total) {
-      int rem = c;
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int n = min(CH, total - c0);
+    __syncthreads();
+    if (tid < 3 * n) {
+      const int j = tid / 3, ax = tid - 3 * j;
+      const int idx = sorted ? ids[c0 + j] : order[s0 + c0 + j];
+      const double4 p = FULL ? s.sp[idx] : s.pp[idx];
+      const double xa = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
+      double fr;
+      const int base = grid_base(xa, pm.scale[ax], pm.K[ax], &fr);
+      R th[ND + 1][P];
+      bspline_weights<R, P, ND>((R)fr, th);
+      const int top = base - o[ax] + P - 1;
 #pragma unroll
-      for (int h = 0; h < 8; ++h) {
-        if (idx < 0) {
-          if (rem < rl[h]) { idx = order[rs[h] + rem]; hh = h; }
-          else rem -= rl[h];
+      for (int k = 0; k <= ND; ++k)
+#pragma unroll
+        for (int z = 0; z < TM; ++z) {
+          const int d = top - z;
+          R v = R(0);
+#pragma unroll
+          for (int t = 0; t < P; ++t) v = d == t ? th[k][t] : v;
+          w[ax][k][j][z] = v;
         }
-      }
-    }
-    double x[3] = {0, 0, 0};
-    double4 pv = make_double4(0.0, 0.0, 0.0, 0.0);
-    int base[3] = {0, 0, 0};
-    double fr[3] = {0, 0, 0};
-    AxisSpan sp[3];
-    if (idx >= 0) {
-      if (FULL) {
-        const double4 p = s.sp[idx];
-        x[0] = p.x; x[1] = p.y; x[2] = p.z;
-      } else {
-        const double4 p = s.pp[idx];
-        x[0] = p.x; x[1] = p.y; x[2] = p.z;
-        pv = du.p_old[idx];
-        if (du.upd) {
-          const double4 z = du.z[idx];
-          pv = make_double4(z.x + beta * pv.x, z.y + beta * pv.y, z.z + beta * pv.z, 0.0);
-          if (hh == 0) {
-            du.p_new[idx] = pv;
-            du.p_new32[idx] = make_float4((float)pv.x, (float)pv.y, (float)pv.z, 0.f);
+      if (ax == 0) {
+        if (FULL) {
+          const double4 d4 = s.sd[idx], t4 = s.sth[idx];
+          const double2 t2 = s.sth2[idx];
+          double ddx = d4.x, ddy = d4.y, ddz = d4.z;
+          if (vec) {
+            const double4 m = vec[idx];
+            ddx += m.x; ddy += m.y; ddz += m.z;
           }
+          const R third = R(1.0 / 3.0);
+          amp[0][j] = (R)p.w;
+          amp[1][j] = (R)ddx * sc[0];
+          amp[2][j] = (R)ddy * sc[1];
+          amp[3][j] = (R)ddz * sc[2];
+          amp[4 % NA][j] = (R)t4.x * sc[0] * sc[0] * third;
+          amp[5 % NA][j] = (R)t4.w * sc[1] * sc[1] * third;
+          amp[6 % NA][j] = (R)t2.y * sc[2] * sc[2] * third;
+          amp[7 % NA][j] = R(2) * third * (R)t4.y * sc[0] * sc[1];
+          amp[8 % NA][j] = R(2) * third * (R)t4.z * sc[0] * sc[2];
+          amp[9 % NA][j] = R(2) * third * (R)t2.x * sc[1] * sc[2];
+        } else {
+          const double4 pv = vec[idx];
+          amp[0][j] = (R)pv.x * sc[0];
+          amp[1][j] = (R)pv.y * sc[1];
+          amp[2][j] = (R)pv.z * sc[2];
         }
-      }
-      contrib = true;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        base[a] = grid_base(x[a], pm.scale[a], pm.K[a], &fr[a]);
-        contrib = contrib && axis_span<P>(base[a], o[a], Bs[a], pm.K[a], sp[a]);
-      }
-    }
-    const unsigned long long mask = __ballot(contrib);
-    const int cnt = __popcll(mask);
-    if (contrib) {
-      const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-      const int slot = __popcll(mask & below);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        R th[ND + 1][P];
-        bspline_weights<R, P, ND>((R)fr[a], th);
-#pragma unroll
-        for (int k = 0; k <= ND; ++k)
-#pragma unroll
-          for (int t = 0; t < P; ++t) sg.th[a][k][t][slot] = th[k][t];
-        sg.d[a][slot] = sp[a].d;
-        sg.lo[a][slot] = sp[a].tlo;
-        sg.hi[a][slot] = sp[a].thi;
-      }
-      if (FULL) {
-        const double4 p = s.sp[idx], d4 = s.sd[idx], t4 = s.sth[idx];
-        const double2 t2 = s.sth2[idx];
-        double ddx = d4.x, ddy = d4.y, ddz = d4.z;
-        if (mu) {
-          const double4 m = mu[idx];
-          ddx += m.x; ddy += m.y; ddz += m.z;
-        }
-        const R third = R(1.0 / 3.0);
-        sg.amp[0][slot] = (R)p.w;
-        sg.amp[1][slot] = (R)ddx * sc[0];
-        sg.amp[2][slot] = (R)ddy * sc[1];
-        sg.amp[3][slot] = (R)ddz * sc[2];
-        sg.amp[4 % St::NA][slot] = (R)t4.x * sc[0] * sc[0] * third;
-        sg.amp[5 % St::NA][slot] = (R)t4.w * sc[1] * sc[1] * third;
-        sg.amp[6 % St::NA][slot] = (R)t2.y * sc[2] * sc[2] * third;
-        sg.amp[7 % St::NA][slot] = R(2) * third * (R)t4.y * sc[0] * sc[1];
-        sg.amp[8 % St::NA][slot] = R(2) * third * (R)t4.z * sc[0] * sc[2];
-        sg.amp[9 % St::NA][slot] = R(2) * third * (R)t2.x * sc[1] * sc[2];
-      } else {
-        sg.amp[0][slot] = (R)pv.x * sc[0];
-        sg.amp[1][slot] = (R)pv.y * sc[1];
-        sg.amp[2][slot] = (R)pv.z * sc[2];
       }
     }
     __syncthreads();
-    // ---- spread (site, ty, tz) rows of the staged sites
-    for (int it = lane; it < cnt * P * P; it += 64) {
-      const int slot = it / (P * P), r = it - slot * (P * P);
-      const int ty = r % P, tz = r / P;
-      if (ty < sg.lo[1][slot] || ty > sg.hi[1][slot] || tz < sg.lo[2][slot] || tz > sg.hi[2][slot])
-        continue;
-      const R y0 = sg.th[1][0][ty][slot], y1 = sg.th[1][1][ty][slot];
-      const R z0 = sg.th[2][0][tz][slot], z1 = sg.th[2][1][tz][slot];
-      R c0, c1, c2 = R(0);
-      if (FULL) {
-        const R y2 = sg.th[1][ND][ty][slot], z2 = sg.th[2][ND][tz][slot];
-        const R* A = &sg.amp[0][0];
-        c0 = A[0 * CH + slot] * y0 * z0 + A[2 * CH + slot] * y1 * z0 + A[3 * CH + slot] * y0 * z1 +
-             A[5 * CH + slot] * y2 * z0 + A[6 * CH + slot] * y0 * z2 + A[9 * CH + slot] * y1 * z1;
-        c1 = A[1 * CH + slot] * y0 * z0 + A[7 * CH + slot] * y1 * z0 + A[8 * CH + slot] * y0 * z1;
-        c2 = A[4 * CH + slot] * y0 * z0;
-      } else {
-        c0 = sg.amp[1][slot] * y1 * z0 + sg.amp[2][slot] * y0 * z1;
-        c1 = sg.amp[0][slot] * y0 * z0;
-      }
-      const int oy = sg.d[1][slot] - ty, oz = sg.d[2][slot] - tz, dx = sg.d[0][slot];
-      R* row = tile + (oz * S1 + oy) * S0;
-      const int lo = sg.lo[0][slot], hi = sg.hi[0][slot];
-      for (int tx = lo; tx <= hi; ++tx) {
-        R v = c0 * sg.th[0][0][tx][slot] + c1 * sg.th[0][1][tx][slot];
-        if (FULL) v += c2 * sg.th[0][ND][tx][slot];
-        atomicAdd(row + (dx - tx), v);
+    if (owner) {
+      for (int j = 0; j < n; ++j) {
+        const R x0 = w[0][0][j][cx], x1 = w[0][1][j][cx];
+        const R y0 = w[1][0][j][cy], y1 = w[1][1][j][cy];
+        if (FULL) {
+          const R x2 = w[0][ND][j][cx], y2 = w[1][ND][j][cy];
+          const R U0 = x0 * (amp[0][j] * y0 + amp[2][j] * y1 + amp[5 % NA][j] * y2) +
+                       x1 * (amp[1][j] * y0 + amp[7 % NA][j] * y1) + x2 * amp[4 % NA][j] * y0;
+          const R U1 = x0 * (amp[3][j] * y0 + amp[9 % NA][j] * y1) + x1 * amp[8 % NA][j] * y0;
+          const R U2 = x0 * amp[6 % NA][j] * y0;
+          if (U0 == R(0) && U1 == R(0) && U2 == R(0)) continue;
+#pragma unroll
+          for (int z = 0; z < TM; ++z)
+            acc[z] += U0 * w[2][0][j][z] + U1 * w[2][1][j][z] + U2 * w[2][ND][j][z];
+        } else {
+          const R U0 = amp[0][j] * x1 * y0 + amp[1][j] * x0 * y1;
+          const R U1 = amp[2][j] * x0 * y0;
+          if (U0 == R(0) && U1 == R(0)) continue;
+#pragma unroll
+          for (int z = 0; z < TM; ++z) acc[z] += U0 * w[2][0][j][z] + U1 * w[2][1][j][z];
+        }
       }
     }
-    __syncthreads();
   }
-  R* Q = grid_out<R>(pm);
-  for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
-    const int ox = e % S0, oy = (e / S0) % S1, oz = e / (S0 * S1);
-    if (ox < Bs[0] && oy < Bs[1] && oz < Bs[2])
-      Q[((size_t)(o[2] + oz) * pm.K[1] + (o[1] + oy)) * pm.K[0] + (o[0] + ox)] = tile[e];
+  if (owner) {
+    R* out = tile_buf<R>(pm) + (size_t)b * pm.tile_size;
+#pragma unroll
+    for (int z = 0; z < TM; ++z)
+      if (z < T2) out[(z * T1 + cy) * T0 + cx] = acc[z];
   }
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(kBlock) void k_spread_fold(PmeView pm) {
+  if (stopped(pm.stop)) return;
+  const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2];
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)K0 * K1 * K2) return;
+  const int g[3] = {(int)(idx % K0), (int)((idx / K0) % K1), (int)(idx / ((size_t)K0 * K1))};
+  int bi[3][2], ti[3][2], nd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int B = pm.Bb[a], b = g[a] / B, ox = g[a] - b * B;
+    const int Bs = min(B, pm.K[a] - b * B);
+    bi[a][0] = b;
+    ti[a][0] = ox + P - 1;
+    bi[a][1] = b + 1 < pm.nb[a] ? b + 1 : 0;
+    ti[a][1] = ox - Bs + P - 1;
+    nd[a] = ti[a][1] >= 0 ? 2 : 1;
+  }
+  const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1;
+  const R* tiles = tile_buf<R>(pm);
+  R sum = R(0);
+  for (int dz = 0; dz < nd[2]; ++dz)
+    for (int dy = 0; dy < nd[1]; ++dy)
+      for (int dx = 0; dx < nd[0]; ++dx) {
+        const int bb = bi[0][dx] + pm.nb[0] * (bi[1][dy] + pm.nb[1] * bi[2][dz]);
+        sum += tiles[(size_t)bb * pm.tile_size + (ti[2][dz] * T1 + ti[1][dy]) * T0 + ti[0][dx]];
+      }
+  grid_out<R>(pm)[idx] = sum;
 }
 
 // ------------------------------------------------------------ gathering
@@ -389,33 +370,38 @@ __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, 
 
 // ------------------------------------------------------------ launchers
 template <int P, bool FULL>
-static void spread_brick_p(const SysView& s, const PmeView& pm, const Reduce& red, DirUpdate du,
-                           const double4* mu, bool mixed, hipStream_t st) {
-  const dim3 g(pm.nb[0] * pm.nb[1] * pm.nb[2]), b(kBlock);
-  if (mixed) hipLaunchKernelGGL((k_spread_brick<float, P, FULL>), g, b, 0, st, s, pm, red, du, mu);
-  else hipLaunchKernelGGL((k_spread_brick<double, P, FULL>), g, b, 0, st, s, pm, red, du, mu);
+static void spread_p(const PmeView& pm, const SysView& s, const double4* vec, bool mixed,
+                     hipStream_t st) {
+  const dim3 g(pm.nb[0] * pm.nb[1] * pm.nb[2]), bt(kSpreadBlock), b(kBlock);
+  const size_t npts = (size_t)pm.K[0] * pm.K[1] * pm.K[2];
+  const dim3 gf((unsigned)((npts + kBlock - 1) / kBlock));
+  if (mixed) {
+    hipLaunchKernelGGL((k_spread_tile<float, P, FULL>), g, bt, 0, st, s, pm, vec);
+    hipLaunchKernelGGL((k_spread_fold<float, P>), gf, b, 0, st, pm);
+  } else {
+    hipLaunchKernelGGL((k_spread_tile<double, P, FULL>), g, bt, 0, st, s, pm, vec);
+    hipLaunchKernelGGL((k_spread_fold<double, P>), gf, b, 0, st, pm);
+  }
 }
 
 template <bool FULL>
-static void spread_brick(const SysView& s, const PmeView& pm, const Reduce& red, DirUpdate du,
-                         const double4* mu, bool mixed, hipStream_t st) {
+static void spread(const PmeView& pm, const SysView& s, const double4* vec, bool mixed,
+                   hipStream_t st) {
   switch (pm.order) {
-    case 4: spread_brick_p<4, FULL>(s, pm, red, du, mu, mixed, st); break;
-    case 6: spread_brick_p<6, FULL>(s, pm, red, du, mu, mixed, st); break;
-    default: spread_brick_p<5, FULL>(s, pm, red, du, mu, mixed, st); break;
+    case 4: spread_p<4, FULL>(pm, s, vec, mixed, st); break;
+    case 6: spread_p<6, FULL>(pm, s, vec, mixed, st); break;
+    default: spread_p<5, FULL>(pm, s, vec, mixed, st); break;
   }
 }
 
 void launch_spread_mult(const SysView& s, const PmeView& pm, const double4* mu, bool mixed,
                         hipStream_t st) {
-  DirUpdate du{};
-  Reduce red{};
-  spread_brick<true>(s, pm, red, du, mu, mixed, st);
+  spread<true>(pm, s, mu, mixed, st);
 }
 
-void launch_spread_dip(const SysView& s, const PmeView& pm, const Reduce& red, DirUpdate du,
-                       bool mixed, hipStream_t st) {
-  spread_brick<false>(s, pm, red, du, nullptr, mixed, st);
+void launch_spread_dip(const SysView& s, const PmeView& pm, const double4* p, bool mixed,
+                       hipStream_t st) {
+  spread<false>(pm, s, p, mixed, st);
 }
 
 template <int P>

@@ -167,8 +167,15 @@ class Engine:
         self._check(self.lib.sibfa_neighbor_counts(self.h, _ptr(out)))
         return out
 
-    def set_profiling(self, enable=True):
-        self._check(self.lib.sibfa_set_profiling(self.h, int(bool(enable))))
+    def set_profiling(self, enable=True, phases=None):
+        """Time every phase (or only the named ones) with HIP events."""
+        if phases is None or not enable:
+            self._check(self.lib.sibfa_set_profiling(self.h, int(bool(enable))))
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << _lib.PHASES.index(name)
+            self._check(self.lib.sibfa_set_profiling_phases(self.h, mask))
 
     def profile(self):
         """Accumulated per-phase event times (ms), launch groups and list sizes."""
