@@ -114,6 +114,7 @@ struct sibfa_ctx_s {
   int* h_ints = nullptr;
   unsigned long long* dsums = nullptr;   // list entry totals
   long long pair_totals[4] = {0, 0, 0, 0};
+  bool totals_valid = false;
   // profiling: HIP events on the context stream around each phase
   bool prof = false;
   unsigned prof_mask = ~0u;   // phases timed while profiling
@@ -476,15 +477,7 @@ sibfa_status build_lists(sibfa_ctx c) {
       if (c->h_ints[k] > c->cap[k]) { over = true; want[k] = c->h_ints[k] + 16; }
     c->stats.max_neighbors = c->h_ints[0];
     if (!over) {
-      launch_fill_int(reinterpret_cast<int*>(c->dsums), 0, 8, c->stream);
-      const int rows[4] = {c->n, c->n, c->npol, c->npol};
-      for (int k = 0; k < 4; ++k) launch_sum_ints(c->ncnt[k], rows[k], c->dsums + k, c->stream);
-      HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->dsums, 4 * sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, c->stream));
-      sibfa_status s3 = sync_read(c);
-      if (s3 != SIBFA_OK) return s3;
-      for (int k = 0; k < 4; ++k)
-        c->pair_totals[k] = (long long)reinterpret_cast<unsigned long long*>(c->h_pinned + 32)[k];
+      c->totals_valid = false;   // list entry totals: summed when asked for
       return SIBFA_OK;
     }
   }
@@ -1334,6 +1327,19 @@ sibfa_status sibfa_get_profile(sibfa_ctx c, sibfa_profile* out) {
   for (int k = 0; k < 16; ++k) {
     out->ms[k] = c->prof_ms[k];
     out->calls[k] = c->prof_calls[k];
+  }
+  if (!c->totals_valid && c->nb[0]) {
+    launch_fill_int(reinterpret_cast<int*>(c->dsums), 0, 8, c->stream);
+    const int rows[4] = {c->n, c->n, c->npol, c->npol};
+    for (int k = 0; k < 4; ++k)
+      if (rows[k] > 0) launch_sum_ints(c->ncnt[k], rows[k], c->dsums + k, c->stream);
+    HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->dsums, 4 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
+    sibfa_status s3 = sync_read(c);
+    if (s3 != SIBFA_OK) return s3;
+    for (int k = 0; k < 4; ++k)
+      c->pair_totals[k] = (long long)reinterpret_cast<unsigned long long*>(c->h_pinned + 32)[k];
+    c->totals_valid = true;
   }
   for (int k = 0; k < 4; ++k) out->pairs[k] = c->pair_totals[k];
   return SIBFA_OK;

@@ -137,6 +137,16 @@ struct Reduce {
 __device__ __forceinline__ bool stopped(const int* stop) { return stop && *stop; }
 
 // ---------------------------------------------------------------- helpers
+// Workgroups are dealt to the GPU's XCDs round robin (blockIdx % kXcd), and
+// each XCD has its own L2.  Site-parallel kernels over the cell-sorted order
+// map the launch index so that each XCD processes one contiguous, spatially
+// compact range of sites: the neighbours it gathers then stay in its L2.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
+  return x * per + (x < extra ? x : extra) + b / kXcd;
+}
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

@@ -102,7 +102,7 @@ __device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, 
     for (int r = 0; r < R; ++r) {
       cplx<T> a = src[j + r * nb];
       if (r > 0 && Ns > 1) {
-        cplx<T> w = tw[(k * r * twstep) % N];
+        cplx<T> w = tw[k * r * twstep];   // < N: k < Ns, r < R, twstep = N / (Ns R)
         w.y *= -sgn;   // table holds exp(-2 pi i m/N); inverse uses the conjugate
         a = cmul<T>(a, w);
       }
@@ -135,6 +135,14 @@ __device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, const int* ra
   }
   __syncthreads();
   return in;
+}
+
+// Copies the axis' twiddle table into LDS (after the two line buffers);
+// the caller's first barrier (inside lds_fft) orders it before use.
+template <typename T>
+__device__ __forceinline__ const cplx<T>* stage_twiddles(const cplx<T>* src, cplx<T>* dst, int N) {
+  for (int k = threadIdx.x; k < N; k += blockDim.x) dst[k] = src[k];
+  return dst;
 }
 
 template <typename T> __device__ __forceinline__ T* gQ(const PmeView& pm);
@@ -174,7 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
     }
     a[e] = v;
   }
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], gTw<T>(pm, 0), T(-1));
+  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
+  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], tw, T(-1));
   cplx<T>* C = gC<T>(pm);
   const int h = pm.kxh;
   for (int e = threadIdx.x; e < nl * h; e += blockDim.x) {
@@ -203,7 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
     if (c < cols) v = C[((size_t)z * N + y) * h + kx0 + c];
     a[c * N + y] = v;
   }
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[1], pm.nrad[1], gTw<T>(pm, 1), sgn);
+  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 1), b + nb * N, N);
+  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[1], pm.nrad[1], tw, sgn);
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
     const int y = e / nb, c = e - y * nb;
     if (c < cols) C[((size_t)z * N + y) * h + kx0 + c] = res[c * N + y];
@@ -230,7 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     if (c < cols) v = C[((size_t)z * K1 + y) * h + kx0 + c];
     a[c * N + z] = v;
   }
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[2], pm.nrad[2], gTw<T>(pm, 2), T(-1));
+  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 2), b + nb * N, N);
+  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[2], pm.nrad[2], tw, T(-1));
   const T* G = gG<T>(pm);
   double e_part = 0.0;
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     }
   }
   cplx<T>* other = (res == a) ? b : a;
-  cplx<T>* res2 = lds_fft<T>(res, other, N, nb, pm.rad[2], pm.nrad[2], gTw<T>(pm, 2), T(1));
+  cplx<T>* res2 = lds_fft<T>(res, other, N, nb, pm.rad[2], pm.nrad[2], tw, T(1));
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
     const int z = e / nb, c = e - z * nb;
     if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * N + z];
@@ -280,7 +291,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
     }
     a[e] = v;
   }
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], gTw<T>(pm, 0), T(1));
+  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
+  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], tw, T(1));
   T* phi = gPhi<T>(pm);
   for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
     const int l = e / N, x = e - l * N;
@@ -309,16 +321,16 @@ static void convolution_t(const PmeView& pm, Reduce& red, hipStream_t st) {
   };
   const int nlx = lines_for(K0);
   const int nrows = K1 * K2;
-  const size_t shx = 2 * (size_t)nlx * K0 * csz;
+  const size_t shx = (2 * (size_t)nlx + 1) * K0 * csz;
   hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3((nrows + nlx - 1) / nlx), dim3(kBlock), shx, st, pm, nlx);
   const int nb = pick_batch(h);
   const int nby = nb < lines_for(K1) ? nb : lines_for(K1);
   const int nkby = (h + nby - 1) / nby;
-  const size_t shy = 2 * (size_t)nby * K1 * csz;
+  const size_t shy = (2 * (size_t)nby + 1) * K1 * csz;
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(-1));
   const int nbz = nb < lines_for(K2) ? nb : lines_for(K2);
   const int nkbz = (h + nbz - 1) / nbz;
-  const size_t shz = 2 * (size_t)nbz * K2 * csz;
+  const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
   red.nparts[S_EREC] = K1 * nkbz;
   hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(1));

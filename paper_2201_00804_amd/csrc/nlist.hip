@@ -139,18 +139,36 @@ __global__ void k_scatter(const int* cell_of, const int* cell_start, int* cursor
 }
 
 // One thread per cell: insertion sort of the cell's segment by caller index.
-__global__ void k_sort_cells(const int* cell_start, int ncell, int* perm) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+// Sorts each cell's entries of perm (distinct site indices) in increasing
+// order, which makes the cell-sorted order independent of the order in
+// which the scatter's atomics ran.  One wavefront per cell: the entries are
+// ranked in LDS (rank = number of smaller entries); cells too large for the
+// LDS buffer fall back to an insertion sort by one lane.
+constexpr int kSortLds = 256;
+__global__ __launch_bounds__(64) void k_sort_cells(const int* cell_start, int ncell, int* perm) {
+  __shared__ int v[kSortLds];
+  const int cell = blockIdx.x;
   if (cell >= ncell) return;
-  const int s = cell_start[cell], e = cell_start[cell + 1];
-  for (int i = s + 1; i < e; ++i) {
-    const int v = perm[i];
-    int j = i - 1;
-    while (j >= s && perm[j] > v) {
-      perm[j + 1] = perm[j];
-      --j;
+  const int s = cell_start[cell], e = cell_start[cell + 1], n = e - s;
+  if (n <= kSortLds) {
+    for (int k = threadIdx.x; k < n; k += 64) v[k] = perm[s + k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += 64) {
+      const int x = v[k];
+      int r = 0;
+      for (int m = 0; m < n; ++m) r += v[m] < x ? 1 : 0;
+      perm[s + r] = x;
     }
-    perm[j + 1] = v;
+  } else if (threadIdx.x == 0) {
+    for (int i = s + 1; i < e; ++i) {
+      const int x = perm[i];
+      int j = i - 1;
+      while (j >= s && perm[j] > x) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = x;
+    }
   }
 }
 
@@ -186,8 +204,7 @@ void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int*
                      cell_of, cell_start, cursor, perm, n);
 }
 void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_cells, dim3((ncell + 63) / 64), dim3(64), 0, s, cell_start,
-                     ncell, perm);
+  hipLaunchKernelGGL(k_sort_cells, dim3(ncell), dim3(64), 0, s, cell_start, ncell, perm);
 }
 void launch_max_int(const int* v, int n, int* out, hipStream_t s) {
   int blocks = (n + kBlock - 1) / kBlock;
@@ -447,8 +464,155 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
   }
 }
 
+// Periodic boxes with at least five cells along every axis.  Same lists, in
+// the same order, as k_nlist, with two changes that cut the work per
+// candidate pair:
+//  * the 5 x 5 rows of the stencil give at most 50 runs of consecutive
+//    cells, each with a fixed periodic image shift (the stencil reaches a
+//    wrapped cell through exactly one image), so a candidate's displacement
+//    is x_i - (x_j + shift) without a per-pair rint;
+//  * the runs are concatenated into one virtual candidate range processed
+//    64 at a time (a lane finds its run by binary search over the run
+//    offsets), so chunks are full;
+//  * polarizable-pair masks come from one ballot per chunk.
+__global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
+  __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
+  __shared__ int moli[kNlIB], poli[kNlIB];
+  __shared__ int run_s[50], run_off[51], run_code[50];
+  const int lane = threadIdx.x;
+  const int cell = blockIdx.x;
+  const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
+  const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
+  const int i0 = a.cell_start[cell], i1 = a.cell_start[cell + 1];
+  const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (lane < 25) {
+    const int dz = lane / 5 - 2, dy = lane % 5 - 2;
+    int zz = cz + dz, zc = 1;
+    if (zz < 0) { zz += nc2; zc = 0; } else if (zz >= nc2) { zz -= nc2; zc = 2; }
+    int yy = cy + dy, yc = 1;
+    if (yy < 0) { yy += nc1; yc = 0; } else if (yy >= nc1) { yy -= nc1; yc = 2; }
+    const int row = nc0 * (yy + nc1 * zz);
+    const int x0 = cx - 2, x1 = cx + 2;
+    int f0, l0, c0, f1 = 0, l1 = -1, c1 = 1;   // cell ranges [f, l] and x image codes
+    if (x0 >= 0 && x1 < nc0) { f0 = x0; l0 = x1; c0 = 1; }
+    else if (x0 < 0) { f0 = 0; l0 = x1; c0 = 1; f1 = nc0 + x0; l1 = nc0 - 1; c1 = 0; }
+    else { f0 = x0; l0 = nc0 - 1; c0 = 1; f1 = 0; l1 = x1 - nc0; c1 = 2; }
+    const int yzc = 3 * yc + 9 * zc;
+    run_s[2 * lane] = a.cell_start[row + f0];
+    run_off[2 * lane + 1] = a.cell_start[row + l0 + 1] - a.cell_start[row + f0];
+    run_code[2 * lane] = c0 + yzc;
+    if (l1 >= f1) {
+      run_s[2 * lane + 1] = a.cell_start[row + f1];
+      run_off[2 * lane + 2] = a.cell_start[row + l1 + 1] - a.cell_start[row + f1];
+    } else {
+      run_s[2 * lane + 1] = 0;
+      run_off[2 * lane + 2] = 0;
+    }
+    run_code[2 * lane + 1] = c1 + yzc;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    run_off[0] = 0;
+    for (int r = 1; r <= 50; ++r) run_off[r] += run_off[r - 1];
+  }
+  __syncthreads();
+  const int ncand = run_off[50];
+  for (int ib = i0; ib < i1; ib += kNlIB) {
+    const int ni = min(kNlIB, i1 - ib);
+    if (lane < ni) {
+      const double4 p = a.sp[ib + lane];
+      xi[lane] = p.x; yi[lane] = p.y; zi[lane] = p.z;
+      moli[lane] = a.mol_s[ib + lane];
+      poli[lane] = a.polidx[ib + lane];
+    }
+    __syncthreads();
+    int cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;   // counts of i-site `lane`
+    for (int c = 0; c < ncand; c += 64) {
+      const int cidx = c + lane;
+      const bool valid = cidx < ncand;
+      double xj = 0, yj = 0, zj = 0;
+      int j = -1, molj = -1, polj = -1;
+      if (valid) {
+        int lo = 0, hi = 50;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (run_off[mid] <= cidx) lo = mid; else hi = mid;
+        }
+        j = run_s[lo] + (cidx - run_off[lo]);
+        const int code = run_code[lo];
+        const double4 p = a.sp[j];
+        xj = p.x + L0 * (double)(code % 3 - 1);
+        yj = p.y + L1 * (double)((code / 3) % 3 - 1);
+        zj = p.z + L2 * (double)(code / 9 - 1);
+        molj = a.mol_s[j];
+        polj = a.polidx[j];
+      }
+      const bool pj = valid && polj >= 0;
+      const unsigned long long pjmask = __ballot(pj);
+      for (int t = 0; t < ni; ++t) {
+        const double dx = xi[t] - xj, dy = yi[t] - yj, dz = zi[t] - zj;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const int i = ib + t;
+        const int mi = moli[t], pi_ = poli[t];
+        const bool same = valid && (molj == mi) && (j != i);
+        const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
+        const unsigned long long b0 = __ballot(inter);
+        const unsigned long long b1 = __ballot(same);
+        const int base0 = __shfl(cnt0, t, 64), base1 = __shfl(cnt1, t, 64);
+        if (inter) {
+          const int k = base0 + __popcll(b0 & below);
+          if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
+        }
+        if (same) {
+          const int k = base1 + __popcll(b1 & below);
+          if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
+        }
+        if (pi_ >= 0) {
+          const unsigned long long b2 = b0 & pjmask, b3 = b1 & pjmask;
+          const int base2 = __shfl(cnt2, t, 64), base3 = __shfl(cnt3, t, 64);
+          if (inter && pj) {
+            const int k = base2 + __popcll(b2 & below);
+            if (k < a.cap_pol) a.nb_pol[(size_t)pi_ * a.cap_pol + k] = polj;
+          }
+          if (same && pj) {
+            const int k = base3 + __popcll(b3 & below);
+            if (k < a.cap_ipol) a.nb_ipol[(size_t)pi_ * a.cap_ipol + k] = polj;
+          }
+          if (lane == t) {
+            cnt2 += __popcll(b2);
+            cnt3 += __popcll(b3);
+          }
+        }
+        if (lane == t) {
+          cnt0 += __popcll(b0);
+          cnt1 += __popcll(b1);
+        }
+      }
+    }
+    if (lane < ni) {
+      const int i = ib + lane;
+      a.nc_all[i] = cnt0;
+      a.nc_in[i] = cnt1;
+      atomicMax(&a.maxcnt[0], cnt0);
+      atomicMax(&a.maxcnt[1], cnt1);
+      if (poli[lane] >= 0) {
+        a.nc_pol[poli[lane]] = cnt2;
+        a.nc_ipol[poli[lane]] = cnt3;
+        atomicMax(&a.maxcnt[2], cnt2);
+        atomicMax(&a.maxcnt[3], cnt3);
+      }
+      if (cnt1 != a.mol_count[moli[lane]] - 1) atomicOr(a.err, 1);
+    }
+    __syncthreads();
+  }
+}
+
 void launch_nlist(const NlistArgs& a, int ncell, hipStream_t s) {
-  hipLaunchKernelGGL(k_nlist, dim3(ncell), dim3(64), 0, s, a);
+  if (a.periodic && a.nc[0] >= 5 && a.nc[1] >= 5 && a.nc[2] >= 5)
+    hipLaunchKernelGGL(k_nlist_shift, dim3(ncell), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_nlist, dim3(ncell), dim3(64), 0, s, a);
 }
 
 }  // namespace sibfa

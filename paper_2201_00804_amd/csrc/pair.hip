@@ -275,16 +275,20 @@ __global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, fl
   }
 }
 
+// The coefficient and index streams are read once per matvec: non-temporal
+// loads keep them from evicting the gathered neighbour records from L2.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
 template <typename R>
 __device__ __forceinline__ void load_coef(const SysView& s, size_t e, R& c1, R& c2);
 template <>
 __device__ __forceinline__ void load_coef<double>(const SysView& s, size_t e, double& c1, double& c2) {
-  const double2 c = s.cpol[e];
+  const nt_double2 c = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(s.cpol + e));
   c1 = c.x; c2 = c.y;
 }
 template <>
 __device__ __forceinline__ void load_coef<float>(const SysView& s, size_t e, float& c1, float& c2) {
-  const float2 c = s.cpol32[e];
+  const nt_float2 c = __builtin_nontemporal_load(reinterpret_cast<const nt_float2*>(s.cpol32 + e));
   c1 = c.x; c2 = c.y;
 }
 
@@ -292,7 +296,7 @@ __device__ __forceinline__ void load_coef<float>(const SysView& s, size_t e, flo
 template <typename R, bool COEF>
 __device__ __forceinline__ void matvec_pair(const SysView& s, const double4* p, const float4* p32,
                                             int pi, size_t e, const R xr[3], R sr, double f[3]) {
-  const int j = s.nb_pol[e];
+  const int j = __builtin_nontemporal_load(&s.nb_pol[e]);
   R xj[3], sj, Rv[3], pj[3];
   load_pp<R>(s, j, xj, sj);
   load_p<R>(p, p32, j, pj);
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const 
                                                    int dot_slot) {
   if (stopped(red.stop)) return;
   const int sub = threadIdx.x % G;
-  const int pi = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int pi = xcd_block() * (kBlock / G) + threadIdx.x / G;
   double f[3] = {0.0, 0.0, 0.0};
   if (pi < s.npol) {
     double xi[3], si;
@@ -362,11 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const 
     const int cnt = s.nc_pol[pi];
     const size_t row = (size_t)pi * s.cap_pol;
     int k = sub;
-    for (; k + G < cnt; k += 2 * G) {
+    for (; k + 3 * G < cnt; k += 4 * G) {
       matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
       matvec_pair<R, COEF>(s, p, p32, pi, row + k + G, xr, sr, f);
+      matvec_pair<R, COEF>(s, p, p32, pi, row + k + 2 * G, xr, sr, f);
+      matvec_pair<R, COEF>(s, p, p32, pi, row + k + 3 * G, xr, sr, f);
     }
-    if (k < cnt) matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
+    for (; k < cnt; k += G) matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
