@@ -110,6 +110,44 @@ struct PmeView {
 
 constexpr int kBrick = 8;
 
+// Spreading tiles (see the spreading kernels): the grid value at (gx, gy,
+// gz) is the sum, in a fixed order, of the entries of the tiles that cover
+// it -- its own brick's and, along each axis where it lies within order - 1
+// points of the next brick, that brick's.
+template <typename T>
+__device__ __forceinline__ const T* tile_data(const PmeView& pm);
+template <>
+__device__ __forceinline__ const double* tile_data<double>(const PmeView& pm) { return pm.tiles; }
+template <>
+__device__ __forceinline__ const float* tile_data<float>(const PmeView& pm) { return pm.tiles32; }
+
+template <typename T>
+__device__ __forceinline__ T fold_point(const PmeView& pm, int gx, int gy, int gz) {
+  const int P = pm.order;
+  const int g[3] = {gx, gy, gz};
+  int bi[3][2], ti[3][2], nd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int B = pm.Bb[a], b = g[a] / B, ox = g[a] - b * B;
+    const int Bs = min(B, pm.K[a] - b * B);
+    bi[a][0] = b;
+    ti[a][0] = ox + P - 1;
+    bi[a][1] = b + 1 < pm.nb[a] ? b + 1 : 0;
+    ti[a][1] = ox - Bs + P - 1;
+    nd[a] = ti[a][1] >= 0 ? 2 : 1;
+  }
+  const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1;
+  const T* tiles = tile_data<T>(pm);
+  T sum = T(0);
+  for (int dz = 0; dz < nd[2]; ++dz)
+    for (int dy = 0; dy < nd[1]; ++dy)
+      for (int dx = 0; dx < nd[0]; ++dx) {
+        const int bb = bi[0][dx] + pm.nb[0] * (bi[1][dy] + pm.nb[1] * bi[2][dz]);
+        sum += tiles[(size_t)bb * pm.tile_size + (ti[2][dz] * T1 + ti[1][dy]) * T0 + ti[0][dx]];
+      }
+  return sum;
+}
+
 // Grid base index of a coordinate along one axis: floor(x K / L) wrapped
 // into [0, K), and the fractional offset.
 __device__ __forceinline__ int grid_base(double x, double scale, int K, double* frac) {
@@ -141,6 +179,7 @@ __device__ __forceinline__ bool stopped(const int* stop) { return stop && *stop;
 // each XCD has its own L2.  Site-parallel kernels over the cell-sorted order
 // map the launch index so that each XCD processes one contiguous, spatially
 // compact range of sites: the neighbours it gathers then stay in its L2.
+// The map is a bijection of [0, gridDim.x) for any grid size.
 constexpr int kXcd = 8;
 __device__ __forceinline__ int xcd_block() {
   const int nb = gridDim.x, b = blockIdx.x;

@@ -16,10 +16,15 @@
 // Line transforms are mixed-radix Stockham autosort (radices 4, 2, 3, 5),
 // ping-ponging between two LDS buffers; twiddles come from a per-axis table
 // exp(-2 pi i k/K_a), conjugated for the inverse.
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace sibfa {
+
+constexpr size_t kPlaneLdsMax = 160 * 1024;   // LDS a gfx950 workgroup may use
 
 template <typename T> struct CT;
 template <> struct CT<double> { using type = double2; };
@@ -89,13 +94,13 @@ __device__ __forceinline__ void dft_small(cplx<T>* v, T sgn) {
 
 template <typename T, int R>
 __device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, int N, int nl,
-                                               int Ns, const cplx<T>* tw, T sgn) {
+                                               int ls, int Ns, const cplx<T>* tw, T sgn) {
   const int nb = N / R;
   const int twstep = N / (Ns * R);
   for (int bt = threadIdx.x; bt < nl * nb; bt += blockDim.x) {
     const int line = bt / nb, j = bt - line * nb;
-    const cplx<T>* src = in + line * N;
-    cplx<T>* dst = out + line * N;
+    const cplx<T>* src = in + line * ls;
+    cplx<T>* dst = out + line * ls;
     const int k = j % Ns;
     cplx<T> v[R];
 #pragma unroll
@@ -115,21 +120,22 @@ __device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, 
   }
 }
 
-// Transform nl lines of length N held in a (scratch b); returns the buffer
-// holding the result.  Every thread of the block must call it.
+// Transform nl lines of length N, line stride ls, held in a (scratch b);
+// returns the buffer holding the result.  Every thread of the block must
+// call it.
 template <typename T>
-__device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, const int* rad, int nrad,
-                            const cplx<T>* tw, T sgn) {
+__device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, int ls, const int* rad,
+                            int nrad, const cplx<T>* tw, T sgn) {
   int Ns = 1;
   cplx<T>* in = a;
   cplx<T>* out = b;
   for (int st = 0; st < nrad; ++st) {
     __syncthreads();
     const int R = rad[st];
-    if (R == 4) stockham_stage<T, 4>(in, out, N, nl, Ns, tw, sgn);
-    else if (R == 2) stockham_stage<T, 2>(in, out, N, nl, Ns, tw, sgn);
-    else if (R == 3) stockham_stage<T, 3>(in, out, N, nl, Ns, tw, sgn);
-    else stockham_stage<T, 5>(in, out, N, nl, Ns, tw, sgn);
+    if (R == 4) stockham_stage<T, 4>(in, out, N, nl, ls, Ns, tw, sgn);
+    else if (R == 2) stockham_stage<T, 2>(in, out, N, nl, ls, Ns, tw, sgn);
+    else if (R == 3) stockham_stage<T, 3>(in, out, N, nl, ls, Ns, tw, sgn);
+    else stockham_stage<T, 5>(in, out, N, nl, ls, Ns, tw, sgn);
     Ns *= R;
     cplx<T>* t = in; in = out; out = t;
   }
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
     a[e] = v;
   }
   const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], tw, T(-1));
+  cplx<T>* res = lds_fft<T>(a, b, N, nl, N, pm.rad[0], pm.nrad[0], tw, T(-1));
   cplx<T>* C = gC<T>(pm);
   const int h = pm.kxh;
   for (int e = threadIdx.x; e < nl * h; e += blockDim.x) {
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
     a[c * N + y] = v;
   }
   const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 1), b + nb * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[1], pm.nrad[1], tw, sgn);
+  cplx<T>* res = lds_fft<T>(a, b, N, nb, N, pm.rad[1], pm.nrad[1], tw, sgn);
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
     const int y = e / nb, c = e - y * nb;
     if (c < cols) C[((size_t)z * N + y) * h + kx0 + c] = res[c * N + y];
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     a[c * N + z] = v;
   }
   const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 2), b + nb * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, pm.rad[2], pm.nrad[2], tw, T(-1));
+  cplx<T>* res = lds_fft<T>(a, b, N, nb, N, pm.rad[2], pm.nrad[2], tw, T(-1));
   const T* G = gG<T>(pm);
   double e_part = 0.0;
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     }
   }
   cplx<T>* other = (res == a) ? b : a;
-  cplx<T>* res2 = lds_fft<T>(res, other, N, nb, pm.rad[2], pm.nrad[2], tw, T(1));
+  cplx<T>* res2 = lds_fft<T>(res, other, N, nb, N, pm.rad[2], pm.nrad[2], tw, T(1));
   for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
     const int z = e / nb, c = e - z * nb;
     if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * N + z];
@@ -292,12 +298,122 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
     a[e] = v;
   }
   const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, pm.rad[0], pm.nrad[0], tw, T(1));
+  cplx<T>* res = lds_fft<T>(a, b, N, nl, N, pm.rad[0], pm.nrad[0], tw, T(1));
   T* phi = gPhi<T>(pm);
   for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
     const int l = e / N, x = e - l * N;
     if (l < rows) phi[(size_t)(row0 + l) * N + x] = res[e].x;
   }
+}
+
+// ---- whole z-planes in LDS (grids whose planes fit in a workgroup's LDS)
+// Forward: transform pairs of real rows of Q (folded from the spreading
+// tiles by k_spread_fold) as one complex line (rows y and y + 1 as real and imaginary
+// parts), split them into the two half spectra, then transform the columns
+// (one per kx) along y; writes C[z][y][kx].
+// Inverse: columns along y, then pairs of Hermitian-completed rows combined
+// as X + iY into one complex line, inverse, real and imaginary parts ->
+// rows y and y + 1 of phi.  The imaginary parts of the kx = 0 and kx = K0/2
+// entries are dropped, as a real inverse does.
+constexpr int kPlaneThreads = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_fwd(PmeView pm) {
+  if (stopped(pm.stop)) return;
+  extern __shared__ char smem[];
+  const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
+  const int cs = K1 + 1;                        // column stride (odd: no bank conflicts)
+  const int bufsz = max((K1 / 2) * K0, h * cs);
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* B = A + bufsz;
+  cplx<T>* tw0 = B + bufsz;
+  cplx<T>* tw1 = tw0 + K0;
+  stage_twiddles<T>(gTw<T>(pm, 0), tw0, K0);
+  stage_twiddles<T>(gTw<T>(pm, 1), tw1, K1);
+  const T* Q = gQ<T>(pm) + (size_t)z * K1 * K0;
+  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
+    const int m = e / K0, x = e - m * K0;
+    cplx<T> v;
+    v.x = Q[(2 * m) * K0 + x];
+    v.y = Q[(2 * m + 1) * K0 + x];
+    A[e] = v;
+  }
+  cplx<T>* rows = lds_fft<T>(A, B, K0, K1 / 2, K0, pm.rad[0], pm.nrad[0], tw0, T(-1));
+  cplx<T>* cols = rows == A ? B : A;
+  for (int e = threadIdx.x; e < (K1 / 2) * h; e += blockDim.x) {
+    const int m = e / h, k = e - m * h;
+    const cplx<T> zk = rows[m * K0 + k];
+    const cplx<T> zn = rows[m * K0 + (k == 0 ? 0 : K0 - k)];
+    cplx<T> X, Y;
+    X.x = T(0.5) * (zk.x + zn.x);
+    X.y = T(0.5) * (zk.y - zn.y);
+    Y.x = T(0.5) * (zk.y + zn.y);
+    Y.y = T(0.5) * (zn.x - zk.x);
+    cols[k * cs + 2 * m] = X;
+    cols[k * cs + 2 * m + 1] = Y;
+  }
+  cplx<T>* res = lds_fft<T>(cols, rows, K1, h, cs, pm.rad[1], pm.nrad[1], tw1, T(-1));
+  cplx<T>* C = gC<T>(pm);
+  for (int e = threadIdx.x; e < K1 * h; e += blockDim.x) {
+    const int y = e / h, k = e - y * h;
+    C[((size_t)z * K1 + y) * h + k] = res[k * cs + y];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_inv(PmeView pm) {
+  if (stopped(pm.stop)) return;
+  extern __shared__ char smem[];
+  const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
+  const int cs = K1 + 1;
+  const int bufsz = max((K1 / 2) * K0, h * cs);
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* B = A + bufsz;
+  cplx<T>* tw0 = B + bufsz;
+  cplx<T>* tw1 = tw0 + K0;
+  stage_twiddles<T>(gTw<T>(pm, 0), tw0, K0);
+  stage_twiddles<T>(gTw<T>(pm, 1), tw1, K1);
+  const cplx<T>* C = gC<T>(pm);
+  for (int e = threadIdx.x; e < K1 * h; e += blockDim.x) {
+    const int y = e / h, k = e - y * h;
+    A[k * cs + y] = C[((size_t)z * K1 + y) * h + k];
+  }
+  cplx<T>* cols = lds_fft<T>(A, B, K1, h, cs, pm.rad[1], pm.nrad[1], tw1, T(1));
+  cplx<T>* rows = cols == A ? B : A;
+  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
+    const int m = e / K0, k = e - m * K0;
+    cplx<T> X, Y;
+    if (k < h) {
+      X = cols[k * cs + 2 * m];
+      Y = cols[k * cs + 2 * m + 1];
+      if (k == 0 || 2 * k == K0) { X.y = T(0); Y.y = T(0); }
+    } else {
+      X = cols[(K0 - k) * cs + 2 * m];
+      Y = cols[(K0 - k) * cs + 2 * m + 1];
+      X.y = -X.y;
+      Y.y = -Y.y;
+    }
+    cplx<T> v;
+    v.x = X.x - Y.y;
+    v.y = X.y + Y.x;
+    rows[m * K0 + k] = v;
+  }
+  cplx<T>* res = lds_fft<T>(rows, cols, K0, K1 / 2, K0, pm.rad[0], pm.nrad[0], tw0, T(1));
+  T* phi = gPhi<T>(pm);
+  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
+    const int m = e / K0, x = e - m * K0;
+    const cplx<T> v = res[e];
+    phi[((size_t)z * K1 + 2 * m) * K0 + x] = v.x;
+    phi[((size_t)z * K1 + 2 * m + 1) * K0 + x] = v.y;
+  }
+}
+
+// LDS bytes of the plane kernels; 0 when the planes do not fit.
+static size_t plane_lds(const PmeView& pm, size_t csz) {
+  const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh;
+  const size_t bufsz = std::max<size_t>((size_t)(K1 / 2) * K0, (size_t)h * (K1 + 1));
+  const size_t bytes = (2 * bufsz + K0 + K1) * csz;
+  return bytes <= kPlaneLdsMax ? bytes : 0;
 }
 
 // ------------------------------------------------------------ launcher
@@ -309,9 +425,36 @@ static int pick_batch(int h) {
 }
 
 template <typename T>
-static void convolution_t(const PmeView& pm, Reduce& red, hipStream_t st) {
+static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
   const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2], h = pm.kxh;
   const size_t csz = sizeof(cplx<T>);
+  // SIBFA_FFT_PLANES=0 forces the five-pass path (used to test it on grids
+  // whose planes would fit)
+  const char* env = std::getenv("SIBFA_FFT_PLANES");
+  const size_t lds = (env && std::atoi(env) == 0) ? 0 : plane_lds(pm, csz);
+  if (lds) {
+    static bool attr = false;   // raise the dynamic LDS limit once per kernel
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr = true;
+    }
+    const int nb = pick_batch(h);
+    const int budget = 48 * 1024;
+    int nbz = (int)(budget / (2 * K2 * csz));
+    nbz = std::max(1, std::min(nbz, std::min(nb, 24)));
+    const int nkbz = (h + nbz - 1) / nbz;
+    const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
+    launch_spread_fold(pm, mixed, st);
+    hipLaunchKernelGGL(k_fft_plane_fwd<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
+    red.nparts[S_EREC] = K1 * nkbz;
+    hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
+    hipLaunchKernelGGL(k_fft_plane_inv<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
+    return;
+  }
+  launch_spread_fold(pm, mixed, st);
   const int budget = 48 * 1024;
   auto lines_for = [&](int N) {
     int nl = (int)(budget / (2 * N * csz));
@@ -338,8 +481,8 @@ static void convolution_t(const PmeView& pm, Reduce& red, hipStream_t st) {
 }
 
 void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
-  if (mixed) convolution_t<float>(pm, red, st);
-  else convolution_t<double>(pm, red, st);
+  if (mixed) convolution_t<float>(pm, red, mixed, st);
+  else convolution_t<double>(pm, red, mixed, st);
 }
 
 }  // namespace sibfa

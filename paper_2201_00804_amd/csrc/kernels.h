@@ -29,6 +29,8 @@ void launch_spread_mult(const SysView& s, const PmeView& pm, const double4* mu, 
 // zeroed; pol = 1 bins polarizable sites, 0 all sites).
 void launch_brick_bin(const SysView& s, const PmeView& pm, int pol, int* brick_of, int* counts,
                       hipStream_t st);
+// Real grid Q from the spreading tiles (used by the multi-pass convolution).
+void launch_spread_fold(const PmeView& pm, bool mixed, hipStream_t st);
 // Spread of the polarizable-site dipoles p (polarizable order).
 void launch_spread_dip(const SysView& s, const PmeView& pm, const double4* p, bool mixed,
                        hipStream_t st);

@@ -47,10 +47,12 @@ __device__ __forceinline__ void site_splines(const PmeView& pm, double x, double
 //
 //  k_spread_tile : one workgroup per brick spreads its own sites into the
 //                  tile (every site is evaluated once) and stores the tile;
-//  k_spread_fold : every grid point sums the tiles that cover it -- its own
+//  fold          : every grid point sums the tiles that cover it -- its own
 //                  brick's and, along each axis where it lies within p - 1
 //                  points of the next brick, that brick's -- in a fixed
 //                  order.  No global atomics, no clearing, deterministic.
+//                  k_spread_fold writes the real grid Q the convolution
+//                  starts from.
 
 __global__ void k_brick_bin(SysView s, PmeView pm, int pol, int* brick_of, int* counts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,34 +236,21 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_tile(SysView s, PmeView
   }
 }
 
-template <typename R, int P>
+template <typename R>
 __global__ __launch_bounds__(kBlock) void k_spread_fold(PmeView pm) {
   if (stopped(pm.stop)) return;
   const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2];
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)K0 * K1 * K2) return;
-  const int g[3] = {(int)(idx % K0), (int)((idx / K0) % K1), (int)(idx / ((size_t)K0 * K1))};
-  int bi[3][2], ti[3][2], nd[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int B = pm.Bb[a], b = g[a] / B, ox = g[a] - b * B;
-    const int Bs = min(B, pm.K[a] - b * B);
-    bi[a][0] = b;
-    ti[a][0] = ox + P - 1;
-    bi[a][1] = b + 1 < pm.nb[a] ? b + 1 : 0;
-    ti[a][1] = ox - Bs + P - 1;
-    nd[a] = ti[a][1] >= 0 ? 2 : 1;
-  }
-  const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1;
-  const R* tiles = tile_buf<R>(pm);
-  R sum = R(0);
-  for (int dz = 0; dz < nd[2]; ++dz)
-    for (int dy = 0; dy < nd[1]; ++dy)
-      for (int dx = 0; dx < nd[0]; ++dx) {
-        const int bb = bi[0][dx] + pm.nb[0] * (bi[1][dy] + pm.nb[1] * bi[2][dz]);
-        sum += tiles[(size_t)bb * pm.tile_size + (ti[2][dz] * T1 + ti[1][dy]) * T0 + ti[0][dx]];
-      }
-  grid_out<R>(pm)[idx] = sum;
+  grid_out<R>(pm)[idx] = fold_point<R>(pm, (int)(idx % K0), (int)((idx / K0) % K1),
+                                       (int)(idx / ((size_t)K0 * K1)));
+}
+
+void launch_spread_fold(const PmeView& pm, bool mixed, hipStream_t st) {
+  const size_t npts = (size_t)pm.K[0] * pm.K[1] * pm.K[2];
+  const dim3 g((unsigned)((npts + kBlock - 1) / kBlock)), b(kBlock);
+  if (mixed) hipLaunchKernelGGL(k_spread_fold<float>, g, b, 0, st, pm);
+  else hipLaunchKernelGGL(k_spread_fold<double>, g, b, 0, st, pm);
 }
 
 // ------------------------------------------------------------ gathering
@@ -372,16 +361,9 @@ __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, 
 template <int P, bool FULL>
 static void spread_p(const PmeView& pm, const SysView& s, const double4* vec, bool mixed,
                      hipStream_t st) {
-  const dim3 g(pm.nb[0] * pm.nb[1] * pm.nb[2]), bt(kSpreadBlock), b(kBlock);
-  const size_t npts = (size_t)pm.K[0] * pm.K[1] * pm.K[2];
-  const dim3 gf((unsigned)((npts + kBlock - 1) / kBlock));
-  if (mixed) {
-    hipLaunchKernelGGL((k_spread_tile<float, P, FULL>), g, bt, 0, st, s, pm, vec);
-    hipLaunchKernelGGL((k_spread_fold<float, P>), gf, b, 0, st, pm);
-  } else {
-    hipLaunchKernelGGL((k_spread_tile<double, P, FULL>), g, bt, 0, st, s, pm, vec);
-    hipLaunchKernelGGL((k_spread_fold<double, P>), gf, b, 0, st, pm);
-  }
+  const dim3 g(pm.nb[0] * pm.nb[1] * pm.nb[2]), bt(kSpreadBlock);
+  if (mixed) hipLaunchKernelGGL((k_spread_tile<float, P, FULL>), g, bt, 0, st, s, pm, vec);
+  else hipLaunchKernelGGL((k_spread_tile<double, P, FULL>), g, bt, 0, st, s, pm, vec);
 }
 
 template <bool FULL>

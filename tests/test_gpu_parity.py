@@ -85,6 +85,29 @@ def test_small_box_other_orders():
                                                   tol=1e-10), f"box27-order{order}")
 
 
+def test_multipass_fft_matches_plane_fft(monkeypatch):
+    """The convolution runs as whole z-planes in LDS when a plane fits and as
+    five line passes otherwise; both give the same field, T p, dipoles and
+    forces (and the five-pass path alone meets the oracle)."""
+    d = water_box(27, 9.5, 7)
+    kw = dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-10)
+    res = {}
+    for planes in ("1", "0"):
+        monkeypatch.setenv("SIBFA_FFT_PLANES", planes)
+        eng = engine_for(d, gpu_params(d, **kw))
+        E0 = eng.permanent_field().cpu().numpy()
+        mu, it, _ = eng.solve()
+        ep, ee, F = eng.energy_forces()
+        res[planes] = (E0, mu.cpu().numpy(), ep, ee, F.cpu().numpy())
+        eng.close()
+    a, b = res["1"], res["0"]
+    assert rel_err(a[0], b[0]) < 1e-12 and rel_err(a[1], b[1]) < 1e-10
+    assert a[2] == pytest.approx(b[2], rel=1e-11) and a[3] == pytest.approx(b[3], rel=1e-12)
+    assert rms_rel(a[4], b[4]) < 1e-11
+    monkeypatch.setenv("SIBFA_FFT_PLANES", "0")
+    _compare_full(d, kw, "box27-multipass")
+
+
 @pytest.mark.slow
 def test_box216_parity():
     d, prm = config_system("box216")
