@@ -104,6 +104,9 @@ struct sibfa_ctx_s {
   // cached pol-list pair coefficients (FP64, or FP32 in mixed mode)
   DevBuf coefbuf, icoefbuf, coef32buf;   // FP64 always; FP32 in mixed mode
   bool coef_valid = false;
+  // the potential grid holds (or, on the auxiliary stream, will hold) the
+  // permanent multipoles' potential, started while the lists were built
+  bool phi_e0 = false;
   // second direction buffer (the spread kernel reads one and writes the other)
   double4* p2 = nullptr;
   float4* p2_32 = nullptr;
@@ -383,6 +386,26 @@ struct Phase {
   }
 };
 
+void conv(sibfa_ctx c, bool mix, hipStream_t st) {
+  launch_convolution(c->pm, c->red, mix, st);
+  c->phi_e0 = false;
+}
+
+// The auxiliary stream starts after everything enqueued so far on the main
+// stream; the main stream continues once the auxiliary work is done.
+// With the overlap switched off (environment SIBFA_PME_OVERLAP=0) the
+// auxiliary stream is the main stream and both are no-ops.
+void fork(sibfa_ctx c) {
+  if (c->aux == c->stream) return;
+  (void)hipEventRecord(c->ev_fork, c->stream);
+  (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+}
+void join(sibfa_ctx c) {
+  if (c->aux == c->stream) return;
+  (void)hipEventRecord(c->ev_join, c->aux);
+  (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+}
+
 // ------------------------------------------------------------ preparation
 sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
   for (int k = 0; k < 4; ++k) {
@@ -561,22 +584,36 @@ sibfa_status prepare(sibfa_ctx c) {
     c->e0_valid = false;
   }
   if (c->dirty_lists) {
+    if (c->periodic) {
+      {
+        Phase ph(c, SIBFA_PH_LISTS);
+        SysView sv = make_view(c);
+        for (int pol = 0; pol < 2; ++pol) {
+          int* start = pol ? c->bstart_pol : c->bstart_all;
+          int* order = pol ? c->border_pol : c->border_all;
+          const int cnt = pol ? c->npol : c->n;
+          launch_fill_int(c->bcount, 0, c->nbricks + 1, s);
+          launch_fill_int(c->bcursor, 0, c->nbricks, s);
+          launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, s);
+          launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, s);
+          if (cnt > 0) {
+            launch_scatter(c->brick_of, start, c->bcursor, order, cnt, s);
+            // increasing site index within each brick: reproducible sums
+            launch_sort_cells(start, c->nbricks, order, s);
+          }
+        }
+      }
+      // the reciprocal potential of the permanent multipoles needs the
+      // brick lists but not the neighbour lists: start it on the auxiliary
+      // stream while the lists are built
+      fork(c);
+      Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
+      launch_spread_mult(make_view(c), c->pm, nullptr, mixed(c), c->aux);
+      conv(c, mixed(c), c->aux);
+      c->phi_e0 = true;
+    }
     sibfa_status st = build_lists(c);
     if (st != SIBFA_OK) return st;
-    if (c->periodic) {
-      Phase ph(c, SIBFA_PH_LISTS);
-      SysView sv = make_view(c);
-      for (int pol = 0; pol < 2; ++pol) {
-        int* start = pol ? c->bstart_pol : c->bstart_all;
-        int* order = pol ? c->border_pol : c->border_all;
-        const int cnt = pol ? c->npol : c->n;
-        launch_fill_int(c->bcount, 0, c->nbricks + 1, s);
-        launch_fill_int(c->bcursor, 0, c->nbricks, s);
-        launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, s);
-        launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, s);
-        if (cnt > 0) launch_scatter(c->brick_of, start, c->bcursor, order, cnt, s);
-      }
-    }
     c->dirty_lists = false;
     c->e0_valid = false;
   }
@@ -584,32 +621,22 @@ sibfa_status prepare(sibfa_ctx c) {
 }
 
 // ------------------------------------------------------------ compute steps
-void conv(sibfa_ctx c, bool mix, hipStream_t st) { launch_convolution(c->pm, c->red, mix, st); }
-
-// The auxiliary stream starts after everything enqueued so far on the main
-// stream; the main stream continues once the auxiliary work is done.
-// With the overlap switched off (environment SIBFA_PME_OVERLAP=0) the
-// auxiliary stream is the main stream and both are no-ops.
-void fork(sibfa_ctx c) {
-  if (c->aux == c->stream) return;
-  (void)hipEventRecord(c->ev_fork, c->stream);
-  (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
-}
-void join(sibfa_ctx c) {
-  if (c->aux == c->stream) return;
-  (void)hipEventRecord(c->ev_join, c->aux);
-  (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
-}
 
 // t = T v (v in pol order, double + float copy)
+// The pair coefficients of the polarizable list, computed once in FP64
+// (and rounded to the FP32 table in mixed mode), on stream st.
+void enqueue_coef(sibfa_ctx c, hipStream_t st) {
+  Phase ph(c, SIBFA_PH_PAIRCOEF, st);
+  SysView s = make_view(c);
+  launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p),
+                  mixed(c) ? static_cast<float2*>(c->coef32buf.p) : nullptr,
+                  static_cast<double2*>(c->icoefbuf.p), st);
+  c->coef_valid = true;
+}
+
 sibfa_status ensure_coef(sibfa_ctx c) {
   if (c->coef_valid || c->npol == 0) return SIBFA_OK;
-  Phase ph(c, SIBFA_PH_PAIRCOEF);
-  SysView s = make_view(c);
-  double2* icoef = static_cast<double2*>(c->icoefbuf.p);
-  launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p), nullptr, icoef, c->stream);
-  if (mixed(c)) launch_pol_coef(s, nullptr, static_cast<float2*>(c->coef32buf.p), icoef, c->stream);
-  c->coef_valid = true;
+  enqueue_coef(c, c->stream);
   return SIBFA_OK;
 }
 
@@ -639,18 +666,29 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
 sibfa_status compute_E0(sibfa_ctx c) {
   SysView s = make_view(c);
   const bool mix = mixed(c);
-  if (c->periodic) {
+  // auxiliary stream: the reciprocal permanent potential (unless already
+  // started beside the list build) and the polarizable-pair coefficients,
+  // both beside the real-space field on the main stream
+  bool forked = false;
+  if (c->periodic && !c->phi_e0) {
     fork(c);
+    forked = true;
     Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
     launch_spread_mult(s, c->pm, nullptr, mix, c->aux);
     conv(c, mix, c->aux);
+  }
+  if (!c->coef_valid && c->npol > 0) {
+    if (!forked) fork(c);
+    forked = true;
+    enqueue_coef(c, c->aux);
   }
   {
     Phase ph(c, SIBFA_PH_FIELD_REAL);
     launch_perm(s, c->red, c->E0, mix, c->stream);
   }
+  join(c);
+  c->phi_e0 = false;
   if (c->periodic) {
-    join(c);
     Phase ph(c, SIBFA_PH_FIELD_RECIP);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
   }
@@ -1073,9 +1111,18 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->mu_s32, n) && alloc_into(c, L, c->Freal, n);
   for (int k = 0; k < 4 && ok; ++k) ok = alloc_into(c, L, c->ncnt[k], n);
   // partial sums: one per block of the largest reducing launch (site
-  // kernels use >= 16 sites per block; the z pass at most K1 * (K0/2+1))
+  // kernels use >= 16 sites per block; the z pass at most K1 * (K0/2+1);
+  // the brick-parallel PME gathers one per spreading brick)
   size_t mb = n / 4 + 8192;
-  if (c->periodic) mb += (size_t)c->prm.grid[1] * (c->prm.grid[0] / 2 + 1);
+  if (c->periodic) {
+    mb += (size_t)c->prm.grid[1] * (c->prm.grid[0] / 2 + 1);
+    size_t bricks = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int e = std::max(brick_edge(c->prm.grid[a], c->prm.order), 1);
+      bricks *= (size_t)((c->prm.grid[a] + e - 1) / e);
+    }
+    mb = std::max(mb, bricks);
+  }
   const int max_blocks = (int)mb;
   double* partials;
   ok = ok && alloc_into(c, L, partials, (size_t)S_COUNT * max_blocks);

@@ -227,7 +227,9 @@ __device__ __forceinline__ float grid_at<float>(const PmeView& pm, size_t idx) {
 // Damped, screened dipole-dipole coefficients of the intermolecular pol
 // pairs, c1 = E_1 - P_1 e^-x c0_1 and c2 = E_2 - P_2 e^-x c0_2, in the
 // ELL layout of the pol list.  Positions are fixed during a solve, so the
-// matvec reads them instead of re-evaluating erfc/exp per pair.
+// matvec reads them instead of re-evaluating erfc/exp per pair.  Computed
+// in FP64 (R = double: FP64 table, and its FP32 rounding when out32 is
+// given) or in FP32 (R = float: FP32 table only).
 template <typename R, int G>
 __global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, float2* out32,
                                                      double2* out_in) {
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, fl
     thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
     const R c1 = Eb[1] - tp[1] * c0[1], c2 = Eb[2] - tp[2] * c0[2];
     if (out) out[e] = make_double2((double)c1, (double)c2);
-    else out32[e] = make_float2((float)c1, (float)c2);
+    if (out32) out32[e] = make_float2((float)c1, (float)c2);
   }
 }
 
@@ -653,7 +655,7 @@ void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out
   if (s.npol <= 0) return;
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
   if (out) hipLaunchKernelGGL((k_pol_coef<double, kG>), g, b, 0, st, s, out, out32, out_in);
-  else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, out, out32, out_in);
+  else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, nullptr, out32, out_in);
 }
 
 void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,

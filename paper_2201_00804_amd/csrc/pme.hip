@@ -102,11 +102,10 @@ __device__ __forceinline__ float* tile_buf<float>(const PmeView& pm) { return pm
 // regrouped by kz as  sum_kz U_kz(x, y) theta_z^(kz)(z).  Sites are staged
 // in chunks with their B-spline weights expanded to the tile width (zeros
 // outside the p-point support), so the inner loop is a few LDS reads (the z
-// weights are the same address for every lane) and FMAs.  The brick's
-// sites are taken in increasing index order, so the tile sums -- and the
+// weights are the same address for every lane) and FMAs.  The brick lists
+// are sorted by site index when they are built, so the tile sums -- and the
 // grid -- are reproducible bit for bit.
 constexpr int kSpreadBlock = 192;      // >= (kBrick + p - 1)^2 columns, p <= 6
-constexpr int kSpreadSorted = 512;     // bricks with more sites keep list order
 
 template <bool FULL>
 struct SpreadShape {
@@ -124,8 +123,6 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_tile(SysView s, PmeView
   constexpr int TM = kBrick + P - 1;
   __shared__ R w[3][ND + 1][CH][TM];
   __shared__ R amp[NA][CH];
-  __shared__ int ids_in[kSpreadSorted];
-  __shared__ int ids[kSpreadSorted];
   const int tid = threadIdx.x;
   const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1, T2 = pm.Bb[2] + P - 1;
   const int nb0 = pm.nb[0], nb1 = pm.nb[1];
@@ -134,18 +131,6 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_tile(SysView s, PmeView
   const int* start = FULL ? pm.bstart_all : pm.bstart_pol;
   const int* order = FULL ? pm.border_all : pm.border_pol;
   const int s0 = start[b], total = start[b + 1] - s0;
-  // increasing site index (rank sort of distinct indices)
-  const bool sorted = total <= kSpreadSorted;
-  if (sorted) {
-    for (int e = tid; e < total; e += kSpreadBlock) ids_in[e] = order[s0 + e];
-    __syncthreads();
-    for (int e = tid; e < total; e += kSpreadBlock) {
-      const int v = ids_in[e];
-      int r = 0;
-      for (int k = 0; k < total; ++k) r += ids_in[k] < v ? 1 : 0;
-      ids[r] = v;
-    }
-  }
   const bool owner = tid < T0 * T1;
   const int cx = owner ? tid % T0 : 0, cy = owner ? tid / T0 : 0;
   R acc[TM];
@@ -157,7 +142,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_tile(SysView s, PmeView
     __syncthreads();
     if (tid < 3 * n) {
       const int j = tid / 3, ax = tid - 3 * j;
-      const int idx = sorted ? ids[c0 + j] : order[s0 + c0 + j];
+      const int idx = order[s0 + c0 + j];
       const double4 p = FULL ? s.sp[idx] : s.pp[idx];
       const double xa = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
       double fr;
