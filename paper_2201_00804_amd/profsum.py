@@ -8,8 +8,8 @@
 `stats` lists the per-kernel totals of `--kernel-trace --stats` and, for
 each kernel, the mean over its working launches: the solver enqueues its
 iterations in batches of four and launches queued after the device-side stop
-flag was raised return at once (a few microseconds); those are counted
-separately.  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
+flag was raised return at once (a few microseconds); launches shorter than a
+quarter of the kernel's median are counted separately as idle.  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
 dispatch) into bytes per launch, each scaled by the ratio of a plain copy
 kernel's known bytes to what the same counter reads for it.
 
@@ -29,7 +29,7 @@ TRAFFIC_SOURCES = {
     "k_matvec": ["paper_2201_00804_amd/csrc/pair.hip", "paper_2201_00804_amd/csrc/pairmath.h",
                  "paper_2201_00804_amd/csrc/common.h"],
 }
-IDLE_FRACTION = 0.25   # a launch under this share of the kernel's longest is idle
+IDLE_FRACTION = 0.25   # a launch under this share of the kernel's median is idle
 
 
 def source_hash(kernel):
@@ -65,8 +65,8 @@ def stats(args):
            "|---|---|---|---|---|---|---|---|"]
     for r in rows[:args.top]:
         d = per.get(r["Name"], [])
-        mx = max(d) if d else 0.0
-        work = [x for x in d if x >= IDLE_FRACTION * mx]
+        med = sorted(d)[len(d) // 2] if d else 0.0
+        work = [x for x in d if x >= IDLE_FRACTION * med]
         wavg = sum(work) / len(work) if work else 0.0
         out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f}"
                    f" | {float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} | "
@@ -81,8 +81,8 @@ def counter_means(path, kernel):
             vals[precision_of(short(r["Kernel_Name"]))].append(float(r["Counter_Value"]))
     out = {}
     for p, v in vals.items():
-        mx = max(v)
-        work = [x for x in v if x >= IDLE_FRACTION * mx]
+        med = sorted(v)[len(v) // 2]
+        work = [x for x in v if x >= IDLE_FRACTION * med]
         out[p] = (sum(work) / len(work), len(work), len(v))
     return out
 
