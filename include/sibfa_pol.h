@@ -126,7 +126,9 @@ sibfa_status sibfa_set_system(sibfa_ctx ctx, int n_sites, const double* xyz,
                               const int32_t* mol, const double* box,
                               const sibfa_params* params);
 
-/* New positions for the same sites; keeps mu for a warm start. */
+/* New positions for the same sites; keeps mu for a warm start.  Only
+ * enqueues the copy: NaN/Inf coordinates are reported (SIBFA_E_ARG) by the
+ * next call that computes. */
 sibfa_status sibfa_update_positions(sibfa_ctx ctx, const double* xyz);
 
 /* Permanent multipoles (device): q [n], dip [n][3], quad [n][6] traceless.

@@ -57,6 +57,7 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st);
 // device-side convergence test (see k_check)
+void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
 void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,

@@ -14,7 +14,7 @@ struct BinArgs {
   int* cell_of;          // [n]
   int* cell_count;       // [ncell + 1], zeroed
   int* mol_count;        // [n], zeroed
-  int* err;              // bit 1: molecule id out of range
+  int* err;              // bit 2: molecule id out of range; bit 8: NaN/Inf position
 };
 
 struct RecArgs {

@@ -113,6 +113,8 @@ __global__ void k_bin(BinArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n) return;
   int cell = 0;
+  const double x0 = a.xyz[3 * c], x1 = a.xyz[3 * c + 1], x2 = a.xyz[3 * c + 2];
+  if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(a.err, 8);
   if (a.periodic) {
     int ci[3];
     for (int d = 0; d < 3; ++d) {

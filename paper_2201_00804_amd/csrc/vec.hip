@@ -193,6 +193,22 @@ void launch_direction(const SysView& s, const Reduce& red, int num, int den, con
                       double4* p, float4* p32, hipStream_t st) {
   hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32);
 }
+// flag (zeroed by the caller) becomes nonzero if any of v[0..n) is NaN or Inf.
+__global__ void k_nonfinite(const double* v, size_t n, int* flag) {
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(v[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st) {
+  size_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(kBlock), 0, st, v, n, flag);
+}
+
 void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st) {
   hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, iter, zz_stop);
 }

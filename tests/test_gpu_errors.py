@@ -78,6 +78,24 @@ def test_bad_arguments():
     eng.close()
 
 
+def test_nonfinite_positions_after_update():
+    """update_positions only enqueues the copy; a NaN coordinate is reported
+    by the next call that computes, and the context stays usable."""
+    from paper_2201_00804_amd import SibfaError
+    d = water_box(27, 9.5, 3)
+    eng = engine_for(d, gpu_params(d, beta=0.45, cutoff=4.5, grid=24))
+    e0 = eng.energy_forces()[0]
+    bad = d["pos"].copy()
+    bad[7, 2] = np.inf
+    eng.update_positions(_t(bad))
+    with pytest.raises(SibfaError) as e:
+        eng.solve()
+    assert _status(e) == -1 and "NaN or Inf" in str(e.value)
+    eng.update_positions(_t(d["pos"]))
+    assert eng.energy_forces()[0] == e0
+    eng.close()
+
+
 def test_molecule_ids_out_of_range_and_spread_molecule():
     from paper_2201_00804_amd import SibfaError
     d = water_box(27, 9.5, 3)
