@@ -56,6 +56,10 @@ struct sibfa_ctx_s {
   double box[3] = {0, 0, 0};
   bool have_sys = false, have_mult = false, have_pol = false, has_thole = false;
   bool dirty_sort = true, dirty_mult = true, dirty_pol = true, dirty_lists = true;
+  // molecule ids and polarizabilities validated since they were last set:
+  // later re-sorts report position errors at the list build's readback and
+  // skip their own
+  bool ids_ok = false, pol_ok = false;
   bool e0_valid = false, mu_valid = false, mu_have = false;
   double e_real = 0, e_rec = 0, e_self = 0;
   sibfa_stats stats{};
@@ -87,7 +91,10 @@ struct sibfa_ctx_s {
   int* nb[4] = {nullptr, nullptr, nullptr, nullptr};
   int* ncnt[4] = {nullptr, nullptr, nullptr, nullptr};
   DevBuf nbbuf[4];
-  int* dints = nullptr;   // [0..3] max counts, [4] error bits, [5] npol, [6..] spare
+  // [0..3] list maxima, [4] binning errors (bits 2, 8), [5] list errors
+  // (bit 1), [6] finiteness flag, [7] polarizability errors (bit 4),
+  // [8] spare flag, [16..31] eight slot totals (doubles)
+  int* dints = nullptr;
   // solver vectors (pol order)
   double4 *E0 = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
           *t = nullptr;
@@ -315,25 +322,22 @@ sibfa_status sync_read(sibfa_ctx c) {
   return SIBFA_OK;
 }
 
-// Totals of reduction slots: the partials written by each slot's last
-// producer are copied to the host and added in index order.
+// Totals of up to 8 slots: summed on the device (one block per slot, fixed
+// order) and read back with one copy.
 sibfa_status read_totals(sibfa_ctx c, std::initializer_list<int> slots, double* out) {
-  for (int sl : slots) {
-    const int n = c->red.nparts[sl];
-    if (n > 0)
-      HIP_TRY(hipMemcpyAsync(c->h_part + (size_t)sl * c->red.max_blocks,
-                             c->red.partials + (size_t)sl * c->red.max_blocks, n * sizeof(double),
-                             hipMemcpyDeviceToHost, c->stream));
+  SlotList sl{};
+  for (int s : slots) {
+    sl.slot[sl.n] = s;
+    sl.nparts[sl.n] = c->red.nparts[s];
+    ++sl.n;
   }
+  double* dtot = reinterpret_cast<double*>(c->dints + 16);
+  launch_slot_totals(c->red, sl, dtot, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 48, dtot, sl.n * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
   sibfa_status st = sync_read(c);
   if (st != SIBFA_OK) return st;
-  int k = 0;
-  for (int sl : slots) {
-    double t = 0.0;
-    const double* p = c->h_part + (size_t)sl * c->red.max_blocks;
-    for (int b = 0; b < c->red.nparts[sl]; ++b) t += p[b];
-    out[k++] = t;
-  }
+  for (int k = 0; k < sl.n; ++k) out[k] = c->h_pinned[48 + k];
   return SIBFA_OK;
 }
 
@@ -386,8 +390,10 @@ struct Phase {
   }
 };
 
-void conv(sibfa_ctx c, bool mix, hipStream_t st) {
-  launch_convolution(c->pm, c->red, mix, st);
+void conv(sibfa_ctx c, bool mix, hipStream_t st, int erec_slot = S_EREC) {
+  PmeView pm = c->pm;
+  pm.erec_slot = erec_slot;
+  launch_convolution(pm, c->red, mix, st);
   c->phi_e0 = false;
 }
 
@@ -407,6 +413,13 @@ void join(sibfa_ctx c) {
 }
 
 // ------------------------------------------------------------ preparation
+// Errors of the last binning (h_ints[4] holds the device word).
+sibfa_status binning_errors(sibfa_ctx c) {
+  if (c->h_ints[4] & 2) return fail(c, SIBFA_E_ARG, "molecule ids must lie in [0, n_sites)");
+  if (c->h_ints[4] & 8) return fail(c, SIBFA_E_ARG, "xyz contains NaN or Inf");
+  return SIBFA_OK;
+}
+
 sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
   for (int k = 0; k < 4; ++k) {
     const int rows = (k < 2) ? c->n : std::max(c->npol, 1);
@@ -465,7 +478,8 @@ sibfa_status build_lists(sibfa_ctx c) {
     for (int k = 0; k < 4; ++k) want[k] = std::max(want[k], c->cap[k]);
     sibfa_status st = alloc_lists(c, want);
     if (st != SIBFA_OK) return st;
-    launch_fill_int(c->dints, 0, 8, c->stream);
+    launch_fill_int(c->dints, 0, 4, c->stream);
+    launch_fill_int(c->dints + 5, 0, 1, c->stream);
     NlistArgs a{};
     a.periodic = c->periodic;
     for (int d = 0; d < 3; ++d) {
@@ -484,7 +498,7 @@ sibfa_status build_lists(sibfa_ctx c) {
     a.nb_pol = c->nb[2]; a.nc_pol = c->ncnt[2]; a.cap_pol = c->cap[2];
     a.nb_ipol = c->nb[3]; a.nc_ipol = c->ncnt[3]; a.cap_ipol = c->cap[3];
     a.maxcnt = c->dints;
-    a.err = c->dints + 4;
+    a.err = c->dints + 5;
     {
       Phase ph(c, SIBFA_PH_LISTS);
       launch_nlist(a, c->ncell, c->stream);
@@ -492,7 +506,8 @@ sibfa_status build_lists(sibfa_ctx c) {
     HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     sibfa_status s2 = sync_read(c);
     if (s2 != SIBFA_OK) return s2;
-    if (c->h_ints[4] & 1)
+    if ((s2 = binning_errors(c)) != SIBFA_OK) return s2;
+    if (c->h_ints[5] & 1)
       return fail(c, SIBFA_E_ARG,
                   "the sites of a molecule must lie within the cutoff of each other");
     bool over = false;
@@ -528,13 +543,16 @@ sibfa_status prepare(sibfa_ctx c) {
   ra.sa = c->sa; ra.mol_s = c->mol_s; ra.inv_perm = c->inv_perm; ra.is_pol = c->is_pol;
   ra.pol_scan = c->pol_scan; ra.polidx = c->polidx; ra.polsite = c->polsite;
   ra.pp = c->pp; ra.pp32 = c->pp32; ra.pa = c->pa; ra.alpha_s = c->alpha_s; ra.ainv_s = c->ainv_s;
-  ra.err = c->dints + 4;
+  ra.err = c->dints + 7;
+  // work still queued on the auxiliary stream by an earlier call that
+  // failed reads the records rewritten below
+  if (c->dirty_sort || c->dirty_mult || c->dirty_pol || c->dirty_lists) join(c);
 
   if (c->dirty_sort) {
     launch_fill_int(c->cell_count, 0, c->ncell + 1, s);
     launch_fill_int(c->cursor, 0, c->ncell, s);
     launch_fill_int(c->mol_count, 0, c->n, s);
-    launch_fill_int(c->dints, 0, 8, s);
+    launch_fill_int(c->dints + 4, 0, 1, s);
     BinArgs b{};
     b.n = c->n;
     b.periodic = c->periodic;
@@ -553,11 +571,13 @@ sibfa_status prepare(sibfa_ctx c) {
       launch_sort_cells(c->cell_start, c->ncell, c->perm, s);
       launch_rec_pos(ra, s);
     }
-    HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-    sibfa_status st = sync_read(c);
-    if (st != SIBFA_OK) return st;
-    if (c->h_ints[4] & 2) return fail(c, SIBFA_E_ARG, "molecule ids must lie in [0, n_sites)");
-    if (c->h_ints[4] & 8) return fail(c, SIBFA_E_ARG, "xyz contains NaN or Inf");
+    if (!c->ids_ok) {
+      HIP_TRY(hipMemcpyAsync(c->h_ints + 4, c->dints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+      sibfa_status st = sync_read(c);
+      if (st != SIBFA_OK) return st;
+      if ((st = binning_errors(c)) != SIBFA_OK) return st;
+      c->ids_ok = true;
+    }
     c->dirty_sort = false;
     c->dirty_mult = c->dirty_pol = c->dirty_lists = true;
     c->e0_valid = false;
@@ -568,17 +588,22 @@ sibfa_status prepare(sibfa_ctx c) {
     c->e0_valid = false;
   }
   if (c->dirty_pol) {
-    launch_fill_int(c->dints, 0, 8, s);
+    launch_fill_int(c->dints + 7, 0, 1, s);
     launch_rec_pol(ra, s);
     launch_exclusive_scan(c->is_pol, c->pol_scan, c->n + 1, c->scan_tmp, s);
     launch_rec_polsites(ra, s);
-    HIP_TRY(hipMemcpyAsync(c->h_ints, c->pol_scan + c->n, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(c->h_ints + 4, c->dints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
-    sibfa_status st = sync_read(c);
-    if (st != SIBFA_OK) return st;
-    if (c->h_ints[4] & 4)
-      return fail(c, SIBFA_E_ARG, "every nonzero polarizability must be positive definite");
-    c->npol = c->h_ints[0];
+    // a re-sort permutes the same polarizabilities: count and definiteness
+    // are unchanged
+    if (!c->pol_ok) {
+      HIP_TRY(hipMemcpyAsync(c->h_ints, c->pol_scan + c->n, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(c->h_ints + 7, c->dints + 7, sizeof(int), hipMemcpyDeviceToHost, s));
+      sibfa_status st = sync_read(c);
+      if (st != SIBFA_OK) return st;
+      if (c->h_ints[7] & 4)
+        return fail(c, SIBFA_E_ARG, "every nonzero polarizability must be positive definite");
+      c->npol = c->h_ints[0];
+      c->pol_ok = true;
+    }
     c->stats.n_polarizable = c->npol;
     c->dirty_pol = false;
     c->dirty_lists = true;
@@ -610,7 +635,7 @@ sibfa_status prepare(sibfa_ctx c) {
       fork(c);
       Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
       launch_spread_mult(make_view(c), c->pm, nullptr, mixed(c), c->aux);
-      conv(c, mixed(c), c->aux);
+      conv(c, mixed(c), c->aux, S_EREC0);
       c->phi_e0 = true;
     }
     sibfa_status st = build_lists(c);
@@ -676,7 +701,7 @@ sibfa_status compute_E0(sibfa_ctx c) {
     forked = true;
     Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
     launch_spread_mult(s, c->pm, nullptr, mix, c->aux);
-    conv(c, mix, c->aux);
+    conv(c, mix, c->aux, S_EREC0);
   }
   if (!c->coef_valid && c->npol > 0) {
     if (!forked) fork(c);
@@ -693,13 +718,8 @@ sibfa_status compute_E0(sibfa_ctx c) {
     Phase ph(c, SIBFA_PH_FIELD_RECIP);
     launch_gather_field(s, c->pm, c->E0, mix, c->stream);
   }
-  double tot[4] = {0, 0, 0, 0};
-  sibfa_status st = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC}, tot)
-                                : read_totals(c, {S_EREAL, S_AUX}, tot);
-  if (st != SIBFA_OK) return st;
-  c->e_real = tot[0] + tot[1];
-  c->e_self = c->periodic ? tot[2] : 0.0;
-  c->e_rec = c->periodic ? tot[3] : 0.0;
+  // the energy partials stay in their slots (nothing else writes them)
+  // and are read with the polarization energy
   c->e0_valid = true;
   return SIBFA_OK;
 }
@@ -1106,7 +1126,7 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->polidx, n) && alloc_into(c, L, c->polsite, n) &&
             alloc_into(c, L, c->pp, n) && alloc_into(c, L, c->pp32, n) && alloc_into(c, L, c->pa, n) &&
             alloc_into(c, L, c->alpha_s, 6 * n) && alloc_into(c, L, c->ainv_s, 6 * n) &&
-            alloc_into(c, L, c->dints, 16) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
+            alloc_into(c, L, c->dints, 16 + 16) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
             alloc_into(c, L, c->r, n) && alloc_into(c, L, c->z, n) && alloc_into(c, L, c->p, n) &&
             alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
             alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->p2, n) && alloc_into(c, L, c->p2_32, n) && alloc_into(c, L, c->mu_s, n) &&
@@ -1150,6 +1170,7 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
   if (st != SIBFA_OK) { release_system(c); return st; }
   c->have_sys = true;
   c->dirty_sort = true;
+  c->ids_ok = c->pol_ok = false;
   return SIBFA_OK;
 }
 
@@ -1205,6 +1226,7 @@ sibfa_status sibfa_set_polarizabilities(sibfa_ctx c, const double* alpha, const 
   if (st != SIBFA_OK) return st;
   c->have_pol = true;
   c->dirty_pol = true;
+  c->pol_ok = false;
   c->e0_valid = false;
   c->mu_valid = false;
   c->mu_have = false;
@@ -1295,15 +1317,20 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
       launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
     }
   }
-  double mm[2] = {0.0, 0.0};
-  if (c->npol > 0) {
-    st = read_totals(c, {S_MUE, S_MUTMU}, mm);
-    if (st != SIBFA_OK) return st;
-  } else {
-    st = sync_read(c);
-    if (st != SIBFA_OK) return st;
-  }
-  const double mue = mm[0], mutmu = mm[0] - mm[1];
+  double tot[6] = {0, 0, 0, 0, 0, 0};
+  if (c->npol > 0)
+    st = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC0, S_MUE, S_MUTMU}, tot)
+                     : read_totals(c, {S_EREAL, S_AUX, S_MUE, S_MUTMU}, tot);
+  else
+    st = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC0}, tot)
+                     : read_totals(c, {S_EREAL, S_AUX}, tot);
+  if (st != SIBFA_OK) return st;
+  c->e_real = tot[0] + tot[1];
+  c->e_self = c->periodic ? tot[2] : 0.0;
+  c->e_rec = c->periodic ? tot[3] : 0.0;
+  const int mk = c->periodic ? 4 : 2;
+  const double mue = c->npol > 0 ? tot[mk] : 0.0;
+  const double mutmu = c->npol > 0 ? tot[mk] - tot[mk + 1] : 0.0;
   c->stats.e_pol = -0.5 * kCoulomb * mue;
   c->stats.e_pol_variational = kCoulomb * (0.5 * mutmu - mue);
   c->stats.e_elec_real = kCoulomb * c->e_real;

@@ -27,6 +27,7 @@ enum Slot {
   S_MUE,         // mu.E0
   S_MUTMU,       // mu.T mu
   S_AUX,         // real-space energy of same-molecule (excluded) pairs
+  S_EREC0,       // reciprocal energy of the permanent multipoles
   S_COUNT
 };
 
@@ -106,6 +107,7 @@ struct PmeView {
   const int* bstart_all;
   const int* border_all;   // sorted-site indices grouped by brick
   const int* stop;         // see Reduce::stop
+  int erec_slot;           // reduction slot of the convolution's E_rec partials
 };
 
 constexpr int kBrick = 8;

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     const int z = e / nb, c = e - z * nb;
     if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * N + z];
   }
-  block_partial(e_part, red, S_EREC);
+  block_partial(e_part, red, pm.erec_slot);
 }
 
 // ---- x pass, half complex to real.
@@ -449,7 +449,7 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
     const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
     launch_spread_fold(pm, mixed, st);
     hipLaunchKernelGGL(k_fft_plane_fwd<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
-    red.nparts[S_EREC] = K1 * nkbz;
+    red.nparts[pm.erec_slot] = K1 * nkbz;
     hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
     hipLaunchKernelGGL(k_fft_plane_inv<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
     return;
@@ -474,7 +474,7 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
   const int nbz = nb < lines_for(K2) ? nb : lines_for(K2);
   const int nkbz = (h + nbz - 1) / nbz;
   const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
-  red.nparts[S_EREC] = K1 * nkbz;
+  red.nparts[pm.erec_slot] = K1 * nkbz;
   hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(1));
   hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3((nrows + nlx - 1) / nlx), dim3(kBlock), shx, st, pm, nlx);

@@ -43,7 +43,8 @@ void launch_gather_force(const SysView& s, const PmeView& pm, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
                          hipStream_t st);
 
-// fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec into S_EREC.
+// fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec partials in
+// the slot pm.erec_slot.
 void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st);
 
 // vec.hip
@@ -58,6 +59,13 @@ void launch_direction(const SysView& s, const Reduce& red, int num, int den, con
                       double4* p, float4* p32, hipStream_t st);
 // device-side convergence test (see k_check)
 void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
+// Totals of up to 8 reduction slots (one block each, fixed order) into out.
+struct SlotList {
+  int n;
+  int slot[8];
+  int nparts[8];
+};
+void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipStream_t st);
 void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,

@@ -217,12 +217,17 @@ void launch_max_int(const int* v, int n, int* out, hipStream_t s) {
 
 // ------------------------------------------------------------ records
 // Positions (wrapped when periodic) and molecule ids in sorted order; the
-// inverse permutation.
+// inverse permutation.  A non-finite coordinate (flagged by the binning, the
+// call then fails) is stored as 0 and an out-of-range molecule id as 0, so
+// that every kernel queued before the error is read back indexes in bounds.
 __global__ void k_rec_pos(RecArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int c = a.perm[i];
   double x = a.xyz[3 * c], y = a.xyz[3 * c + 1], z = a.xyz[3 * c + 2];
+  if (!isfinite(x)) x = 0.0;
+  if (!isfinite(y)) y = 0.0;
+  if (!isfinite(z)) z = 0.0;
   if (a.periodic) {
     x = wrap(x, a.box[0], a.ibox[0]);
     y = wrap(y, a.box[1], a.ibox[1]);
@@ -234,7 +239,8 @@ __global__ void k_rec_pos(RecArgs a) {
   float4 p32 = a.sp32[i];
   p32.x = (float)x; p32.y = (float)y; p32.z = (float)z;
   a.sp32[i] = p32;
-  a.mol_s[i] = a.mol[c];
+  const int m = a.mol[c];
+  a.mol_s[i] = (m >= 0 && m < a.n) ? m : 0;
   a.inv_perm[c] = i;
 }
 
@@ -561,6 +567,7 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
         const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
         const unsigned long long b0 = __ballot(inter);
         const unsigned long long b1 = __ballot(same);
+        if ((b0 | b1) == 0ull) continue;   // no neighbour of site t in this chunk
         const int base0 = __shfl(cnt0, t, 64), base1 = __shfl(cnt1, t, 64);
         if (inter) {
           const int k = base0 + __popcll(b0 & below);

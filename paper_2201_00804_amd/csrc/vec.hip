@@ -193,6 +193,29 @@ void launch_direction(const SysView& s, const Reduce& red, int num, int den, con
                       double4* p, float4* p32, hipStream_t st) {
   hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32);
 }
+// One block per slot: the slot's partials summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_slot_totals(Reduce red, SlotList sl, double* out) {
+  const int k = blockIdx.x;
+  const int slot = sl.slot[k], n = sl.nparts[k];
+  const double* p = red.partials + (size_t)slot * red.max_blocks;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) v += p[b];
+  __shared__ double sh[kBlock / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    out[k] = t;
+  }
+}
+
+void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipStream_t st) {
+  if (sl.n > 0)
+    hipLaunchKernelGGL(k_slot_totals, dim3(sl.n), dim3(kBlock), 0, st, red, sl, out);
+}
+
 // flag (zeroed by the caller) becomes nonzero if any of v[0..n) is NaN or Inf.
 __global__ void k_nonfinite(const double* v, size_t n, int* flag) {
   bool bad = false;
