@@ -76,14 +76,15 @@ typedef struct {
   int order;            /* B-spline order: 4, 5 or 6                         */
   double thole_a;       /* default Thole factor (0.28 in the paper's model)  */
   double tol_debye;     /* solver tolerance: RMS of alpha*(E - T mu), Debye  */
-  int max_iter;         /* PCG iteration limit (including restarts)          */
+  int max_iter;         /* PCG iteration limit, all sequences together       */
   sibfa_precision precision; /* FP64, or FP32 pair/PME math with FP64
                                 accumulation, reductions and residuals      */
 } sibfa_params;
 
 typedef struct {
   int iterations;          /* PCG iterations of the last solve              */
-  int restarts;            /* true-residual restarts of the last solve      */
+  int restarts;            /* FP64 true-residual replacements of the last
+                              solve (the final confirmation not counted)   */
   double true_rms_debye;   /* RMS of alpha*(E - T mu), recomputed in FP64    */
   double e_pol;            /* kcal/mol, Eq. 19                               */
   double e_pol_variational;/* kcal/mol, Eq. 17 at the returned mu            */

@@ -3,14 +3,15 @@
 //
 // Solver (paper: Tinker-HP's preconditioned conjugate gradient, Eq. 18):
 // block-Jacobi PCG with z = alpha r.  One iteration enqueues
-//   spread(p = z + beta p) -> 5 FFT passes (z pass fused with the
-//   influence function) -> real-space + PME-gather matvec (with p.Tp)
-//   -> update (x, r, z, r.z, z.z)
-// and reads z.z back to test  DEBYE * sqrt(z.z / N_pol) <= tol.  On exit the
-// residual is recomputed from scratch in FP64 and the iteration restarts
-// from x while that true residual is above the tolerance; in mixed mode
-// (FP32 pair and PME arithmetic inside the iteration) this is iterative
-// refinement against the FP64 operator.
+//   direction p = z + beta p -> spread and FFT convolution of p (auxiliary
+//   stream) beside the real-space matvec -> PME gather (with p.Tp)
+//   -> update (x, r, z, r.z, z.z) -> device-side test of
+//   DEBYE * sqrt(z.z / N_pol) <= tol.
+// When the test passes the residual is recomputed from scratch in FP64; if
+// that true residual is still above the tolerance it replaces the recurrence
+// residual and the same sequence continues.  In mixed mode (FP32 pair and
+// PME arithmetic inside the iteration) one such replacement is also made
+// early, which keeps the FP32 drift below the tolerance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -745,20 +746,42 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
   const double tol = c->prm.tol_debye;
+  const double zz_stop = (tol / kDebye) * (tol / kDebye) * c->npol;
+  // Mixed precision: the FP32 matvec makes the recurrence residual drift
+  // from E - T x by about the FP32 rounding of T p per iteration.  The
+  // residual is replaced by the FP64 true residual once, when the recurrence
+  // has fallen by kReplace in z.z, and the sequence goes on with the same
+  // directions; the drift accumulated after that point is proportional to
+  // the (by then small) residual.  Each later stop is confirmed the same
+  // way, also in FP64, and the sequence continues if the true residual is
+  // still above the tolerance.
+  constexpr double kReplace = 1e-8;
   int it = 0, restarts = 0;
+  int kk = 0;            // iterations of the running sequence (slot parity)
+  bool fresh = true;     // no sequence yet: the first true residual sets p = z
+  double zz_replace = -1.0;
   double rho_true = 0.0;
   sibfa_status result = SIBFA_OK;
   for (;;) {
     // residual from scratch (FP64 operator)
     matvec(c, c->x, c->x32, c->t, -1, false);
-    launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
+    if (fresh)
+      launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
+    else
+      launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, nullptr, nullptr,
+                           S_RZ0 + (kk & 1), st);
     double zz0 = 0.0;
     sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
     if (e != SIBFA_OK) return e;
     rho_true = rms_debye(c, zz0);
     if (rho_true <= tol) break;
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
-    if (it > 0) ++restarts;
+    if (fresh) {
+      if (mix) zz_replace = kReplace * zz0;
+    } else {
+      ++restarts;
+    }
+    fresh = false;
     // Iterations are enqueued in batches; after each update a one-block
     // kernel tests z.z and p.Tp on the device and raises a stop flag that
     // makes the remaining enqueued kernels return at once, so the host reads
@@ -767,13 +790,13 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     launch_fill_int(flag, 0, 4, st);
     c->red.stop = flag;
     c->pm.stop = flag;
-    const double zz_stop = (tol / kDebye) * (tol / kDebye) * c->npol;
     const int kBatch = 4;
-    int k = 0, k_done = 0, reason = 0;
+    int j = 0, j_done = 0, reason = 0;   // iterations of this run
     for (;;) {
       if (c->prof && c->marks.size() > 4096) fold_marks(c);
-      for (int b = 0; b < kBatch && it + k < c->prm.max_iter; ++b) {
-        c->cur_tag = k;
+      for (int b = 0; b < kBatch && it + j < c->prm.max_iter; ++b) {
+        const int k = kk + j;
+        c->cur_tag = j;
         if (k > 0) {
           // p = z + beta p
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
@@ -802,9 +825,9 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           Phase ph(c, SIBFA_PH_UPDATE);
           launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
                         c->q, st);
-          launch_check(c->red, flag, k + 1, zz_stop, st);
+          launch_check(c->red, flag, j + 1, zz_stop, zz_replace, st);
         }
-        ++k;
+        ++j;
       }
       c->cur_tag = -1;
       HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -815,22 +838,24 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         return e;
       }
       if (c->h_ints[8]) {
-        k_done = c->h_ints[10];
+        j_done = c->h_ints[10];
         reason = c->h_ints[9];
         for (auto& m : c->marks)
-          if (m.tag >= k_done) m.work = false;
+          if (m.tag >= j_done) m.work = false;
         for (auto& m : c->marks) m.tag = -1;
         break;
       }
       for (auto& m : c->marks) m.tag = -1;
-      if (it + k >= c->prm.max_iter) {
-        k_done = k;
+      if (it + j >= c->prm.max_iter) {
+        j_done = j;
         break;
       }
     }
     c->red.stop = nullptr;
     c->pm.stop = nullptr;
-    it += k_done;
+    it += j_done;
+    kk += j_done;
+    if (reason == 3) zz_replace = -1.0;
     if (reason == 2) result = SIBFA_E_NOT_SPD;
     if (result == SIBFA_E_NOT_SPD) break;
     launch_copy4(c->x, c->x, c->x32, c->npol, st);

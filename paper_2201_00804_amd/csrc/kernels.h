@@ -49,6 +49,8 @@ void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t 
 
 // vec.hip
 // PCG kernels over polarizable sites (double4 vectors, w unused).
+// r = E0 - t, z = alpha r, p = z (skipped when p is null: the residual of a
+// running sequence is replaced), r.z into rz_slot and z.z into S_ZZ.
 void launch_init_residual(const SysView& s, Reduce& red, const double4* E0,
                           const double4* t, double4* r, double4* z, double4* p, float4* p32,
                           int rz_slot, hipStream_t st);
@@ -57,7 +59,6 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    hipStream_t st);
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, hipStream_t st);
-// device-side convergence test (see k_check)
 void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
 // Totals of up to 8 reduction slots (one block each, fixed order) into out.
 struct SlotList {
@@ -66,7 +67,9 @@ struct SlotList {
   int nparts[8];
 };
 void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipStream_t st);
-void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st);
+// device-side convergence test (see k_check)
+void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, double zz_replace,
+                  hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st);

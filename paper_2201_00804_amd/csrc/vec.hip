@@ -28,8 +28,10 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(SysView s, Reduce red,
     r[i] = rv;
     const double4 z4 = make_double4(zv.x, zv.y, zv.z, 0.0);
     z[i] = z4;
-    p[i] = z4;
-    p32[i] = make_float4((float)zv.x, (float)zv.y, (float)zv.z, 0.f);
+    if (p) {
+      p[i] = z4;
+      p32[i] = make_float4((float)zv.x, (float)zv.y, (float)zv.z, 0.f);
+    }
     rz = rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
     zz = zv.x * zv.x + zv.y * zv.y + zv.z * zv.z;
   }
@@ -105,9 +107,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
 }
 
 // Convergence test on the device after iteration `iter`: stop when
-// z.z <= zz_stop (the tolerance) or p.Tp <= 0 (not positive definite).
-// flag: [0] stop, [1] reason (1 converged, 2 not SPD), [2] iterations done.
-__global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int iter, double zz_stop) {
+// z.z <= zz_stop (the tolerance), p.Tp <= 0 (not positive definite) or
+// z.z <= zz_replace (time to replace the recurrence residual by the true
+// one; a negative value never triggers).
+// flag: [0] stop, [1] reason (1 converged, 2 not SPD, 3 replace),
+// [2] iterations done.
+__global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int iter, double zz_stop,
+                                                  double zz_replace) {
   if (flag[0]) return;
   const double pq = slot_total(red, S_PQ);
   const double zz = slot_total(red, S_ZZ);
@@ -116,6 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int ite
       flag[1] = 2; flag[2] = iter; flag[0] = 1;
     } else if (zz <= zz_stop) {
       flag[1] = 1; flag[2] = iter; flag[0] = 1;
+    } else if (zz <= zz_replace) {
+      flag[1] = 3; flag[2] = iter; flag[0] = 1;
     }
   }
 }
@@ -232,8 +240,10 @@ void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(kBlock), 0, st, v, n, flag);
 }
 
-void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, iter, zz_stop);
+void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, double zz_replace,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, iter, zz_stop,
+                     zz_replace);
 }
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
