@@ -898,7 +898,10 @@ sibfa_status setup_pme(sibfa_ctx c) {
   for (int a = 0; a < 3; ++a) {
     pm.K[a] = c->prm.grid[a];
     pm.scale[a] = pm.K[a] / c->box[a];
-    factor_radices(pm.K[a], pm.rad[a], &pm.nrad[a]);
+    int rad[16];
+    factor_radices(pm.K[a], rad, &pm.nrad[a]);
+    pm.radcode[a] = 0;
+    for (int k = 0; k < pm.nrad[a]; ++k) pm.radcode[a] |= (unsigned)(rad[k] - 2) << (2 * k);
   }
   pm.kxh = pm.K[0] / 2 + 1;
   for (int a = 0; a < 3; ++a) {

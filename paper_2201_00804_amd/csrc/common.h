@@ -92,8 +92,10 @@ struct PmeView {
   const float* G32;
   const double2* tw[3];   // twiddles exp(-2 pi i k / K_a), k < K_a
   const float2* tw32[3];
+  // FFT radices per axis, stage st in bits 2 st .. 2 st + 1 as radix - 2
+  // (radices 2, 3, 4, 5), so the stage loop decodes them from a scalar
   int nrad[3];
-  int rad[3][16];
+  unsigned radcode[3];
   // spreading bricks: Bb[0] x Bb[1] x Bb[2] grid points per workgroup (each
   // <= kBrick; the last brick along an axis may be shorter but never below
   // order - 1 points), sites binned by the brick holding their base index
@@ -140,13 +142,21 @@ __device__ __forceinline__ T fold_point(const PmeView& pm, int gx, int gy, int g
   }
   const int T0 = pm.Bb[0] + P - 1, T1 = pm.Bb[1] + P - 1;
   const T* tiles = tile_data<T>(pm);
+  // all (up to eight) loads issued before the first add
+  T v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+    v[k] = T(0);
+    if (dx < nd[0] && dy < nd[1] && dz < nd[2]) {
+      const int bb = bi[0][dx] + pm.nb[0] * (bi[1][dy] + pm.nb[1] * bi[2][dz]);
+      v[k] = tiles[(size_t)bb * pm.tile_size + (ti[2][dz] * T1 + ti[1][dy]) * T0 + ti[0][dx]];
+    }
+  }
   T sum = T(0);
-  for (int dz = 0; dz < nd[2]; ++dz)
-    for (int dy = 0; dy < nd[1]; ++dy)
-      for (int dx = 0; dx < nd[0]; ++dx) {
-        const int bb = bi[0][dx] + pm.nb[0] * (bi[1][dy] + pm.nb[1] * bi[2][dz]);
-        sum += tiles[(size_t)bb * pm.tile_size + (ti[2][dz] * T1 + ti[1][dy]) * T0 + ti[0][dx]];
-      }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if ((k & 1) < nd[0] && ((k >> 1) & 1) < nd[1] && (k >> 2) < nd[2]) sum += v[k];
   return sum;
 }
 

@@ -92,50 +92,122 @@ __device__ __forceinline__ void dft_small(cplx<T>* v, T sgn) {
   }
 }
 
+// ---- workgroup-level helpers.  NT is the workgroup size, a constant, so
+// that no loop re-reads the block size after a barrier.
+
+// f(i, j) over [0, I) x [0, J), j fastest across threads.
+template <int NT, typename F>
+__device__ __forceinline__ void for2d(int I, int J, F f) {
+  if (J <= NT) {
+    const int is = NT / J, j = threadIdx.x % J, i0 = threadIdx.x / J;
+    if (i0 < is)
+      for (int i = i0; i < I; i += is) f(i, j);
+  } else {
+    for (int i = 0; i < I; ++i)
+      for (int j = threadIdx.x; j < J; j += NT) f(i, j);
+  }
+}
+
+// The same traversal with up to kLoadU loads in flight per thread:
+// v = ld(i, j), then st(i, j, v).
+constexpr int kLoadU = 6;
+template <int NT, typename V, typename LD, typename ST>
+__device__ __forceinline__ void stage2d(int I, int J, LD ld, ST st) {
+  if (J <= NT) {
+    const int is = NT / J, j = threadIdx.x % J, i0 = threadIdx.x / J;
+    if (i0 >= is) return;
+    for (int ib = i0; ib < I; ib += kLoadU * is) {
+      V v[kLoadU];
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        const int i = ib + u * is;
+        if (i < I) v[u] = ld(i, j);
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        const int i = ib + u * is;
+        if (i < I) st(i, j, v[u]);
+      }
+    }
+  } else {
+    for (int i = 0; i < I; ++i)
+      for (int jb = threadIdx.x; jb < J; jb += kLoadU * NT) {
+        V v[kLoadU];
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u) {
+          const int j = jb + u * NT;
+          if (j < J) v[u] = ld(i, j);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u) {
+          const int j = jb + u * NT;
+          if (j < J) st(i, j, v[u]);
+        }
+      }
+  }
+}
+
+// One Stockham stage of radix R on one line (src, dst already offset to
+// the line), butterflies j = lt, lt + tpl, ... < N / R.  Ns (the product of
+// the earlier radices) is a power of two until the first radix 3 or 5, so
+// the index split is a shift and a mask for most stages.
 template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, int N, int nl,
-                                               int ls, int Ns, const cplx<T>* tw, T sgn) {
+__device__ __forceinline__ void stockham_stage(const cplx<T>* src, cplx<T>* dst, int N, int Ns,
+                                               int lt, int tpl, const cplx<T>* tw, T sgn) {
   const int nb = N / R;
   const int twstep = N / (Ns * R);
-  for (int bt = threadIdx.x; bt < nl * nb; bt += blockDim.x) {
-    const int line = bt / nb, j = bt - line * nb;
-    const cplx<T>* src = in + line * ls;
-    cplx<T>* dst = out + line * ls;
-    const int k = j % Ns;
+  const bool p2 = (Ns & (Ns - 1)) == 0;
+  const int sh = __builtin_ctz((unsigned)Ns);
+  for (int j = lt; j < nb; j += tpl) {
+    int q, k;
+    if (p2) {
+      q = j >> sh;
+      k = j & (Ns - 1);
+    } else {
+      q = j / Ns;
+      k = j - q * Ns;
+    }
+    const int kt = k * twstep;   // twiddle index k r twstep < N (k < Ns, r < R)
     cplx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cplx<T> a = src[j + r * nb];
       if (r > 0 && Ns > 1) {
-        cplx<T> w = tw[k * r * twstep];   // < N: k < Ns, r < R, twstep = N / (Ns R)
+        cplx<T> w = tw[kt * r];
         w.y *= -sgn;   // table holds exp(-2 pi i m/N); inverse uses the conjugate
         a = cmul<T>(a, w);
       }
       v[r] = a;
     }
     dft_small<T, R>(v, sgn);
-    const int o = (j / Ns) * Ns * R + k;
+    const int o = q * (Ns * R) + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) dst[o + r * Ns] = v[r];
   }
 }
 
-// Transform nl lines of length N, line stride ls, held in a (scratch b);
-// returns the buffer holding the result.  Every thread of the block must
-// call it.
-template <typename T>
-__device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, int ls, const int* rad,
+// Transform nl <= NT lines of length N, line stride ls, held in a (scratch
+// b); returns the buffer holding the result.  Each line is served by a
+// fixed group of NT / nl threads.  Every thread of the block must call it.
+template <typename T, int NT>
+__device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, int ls, unsigned radcode,
                             int nrad, const cplx<T>* tw, T sgn) {
+  const int tpl = NT / nl;
+  const int line = threadIdx.x / tpl, lt = threadIdx.x - line * tpl;
+  const bool act = line < nl;
+  const int off = line * ls;
   int Ns = 1;
   cplx<T>* in = a;
   cplx<T>* out = b;
   for (int st = 0; st < nrad; ++st) {
     __syncthreads();
-    const int R = rad[st];
-    if (R == 4) stockham_stage<T, 4>(in, out, N, nl, ls, Ns, tw, sgn);
-    else if (R == 2) stockham_stage<T, 2>(in, out, N, nl, ls, Ns, tw, sgn);
-    else if (R == 3) stockham_stage<T, 3>(in, out, N, nl, ls, Ns, tw, sgn);
-    else stockham_stage<T, 5>(in, out, N, nl, ls, Ns, tw, sgn);
+    const int R = 2 + (int)((radcode >> (2 * st)) & 3u);
+    if (act) {
+      if (R == 4) stockham_stage<T, 4>(in + off, out + off, N, Ns, lt, tpl, tw, sgn);
+      else if (R == 2) stockham_stage<T, 2>(in + off, out + off, N, Ns, lt, tpl, tw, sgn);
+      else if (R == 3) stockham_stage<T, 3>(in + off, out + off, N, Ns, lt, tpl, tw, sgn);
+      else stockham_stage<T, 5>(in + off, out + off, N, Ns, lt, tpl, tw, sgn);
+    }
     Ns *= R;
     cplx<T>* t = in; in = out; out = t;
   }
@@ -145,9 +217,9 @@ __device__ cplx<T>* lds_fft(cplx<T>* a, cplx<T>* b, int N, int nl, int ls, const
 
 // Copies the axis' twiddle table into LDS (after the two line buffers);
 // the caller's first barrier (inside lds_fft) orders it before use.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ const cplx<T>* stage_twiddles(const cplx<T>* src, cplx<T>* dst, int N) {
-  for (int k = threadIdx.x; k < N; k += blockDim.x) dst[k] = src[k];
+  for (int k = threadIdx.x; k < N; k += NT) dst[k] = src[k];
   return dst;
 }
 
@@ -167,35 +239,33 @@ template <typename T> __device__ __forceinline__ const T* gG(const PmeView& pm);
 template <> __device__ __forceinline__ const double* gG<double>(const PmeView& pm) { return pm.G; }
 template <> __device__ __forceinline__ const float* gG<float>(const PmeView& pm) { return pm.G32; }
 
+// LDS line buffers use a stride of length + 1 (an odd number of complex
+// values), so lines handled side by side in a wave fall in different banks.
+
 // ---- x pass, real to half complex.  Block: nl rows.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(PmeView pm, int nl) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  const int N = pm.K[0];
+  const int N = pm.K[0], ls = N + 1, h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* b = a + nl * N;
+  cplx<T>* b = a + nl * ls;
   const int nrows = pm.K[1] * pm.K[2];
   const int row0 = blockIdx.x * nl;
   const int rows = min(nl, nrows - row0);
   const T* Q = gQ<T>(pm);
-  for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
-    const int l = e / N, x = e - l * N;
+  stage2d<kBlock, cplx<T>>(nl, N, [&](int l, int x) {
     cplx<T> v;
     v.x = T(0); v.y = T(0);
-    if (l < rows) {
-      v.x = Q[(size_t)(row0 + l) * N + x];
-    }
-    a[e] = v;
-  }
-  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, N, pm.rad[0], pm.nrad[0], tw, T(-1));
+    if (l < rows) v.x = Q[(size_t)(row0 + l) * N + x];
+    return v;
+  }, [&](int l, int x, cplx<T> v) { a[l * ls + x] = v; });
+  const cplx<T>* tw = stage_twiddles<T, kBlock>(gTw<T>(pm, 0), b + nl * ls, N);
+  cplx<T>* res = lds_fft<T, kBlock>(a, b, N, nl, ls, pm.radcode[0], pm.nrad[0], tw, T(-1));
   cplx<T>* C = gC<T>(pm);
-  const int h = pm.kxh;
-  for (int e = threadIdx.x; e < nl * h; e += blockDim.x) {
-    const int l = e / h, k = e - l * h;
-    if (l < rows) C[(size_t)(row0 + l) * h + k] = res[l * N + k];
-  }
+  for2d<kBlock>(nl, h, [&](int l, int k) {
+    if (l < rows) C[(size_t)(row0 + l) * h + k] = res[l * ls + k];
+  });
 }
 
 // ---- y pass (both directions).  Block: (z, block of nb consecutive kx).
@@ -203,27 +273,25 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  const int N = pm.K[1], h = pm.kxh;
+  const int N = pm.K[1], ls = N + 1, h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* b = a + nb * N;
+  cplx<T>* b = a + nb * ls;
   const int nkb = (h + nb - 1) / nb;
   const int z = blockIdx.x / nkb;
   const int kx0 = (blockIdx.x - z * nkb) * nb;
   const int cols = min(nb, h - kx0);
   cplx<T>* C = gC<T>(pm);
-  for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
-    const int y = e / nb, c = e - y * nb;
+  stage2d<kBlock, cplx<T>>(N, nb, [&](int y, int c) {
     cplx<T> v;
     v.x = T(0); v.y = T(0);
     if (c < cols) v = C[((size_t)z * N + y) * h + kx0 + c];
-    a[c * N + y] = v;
-  }
-  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 1), b + nb * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, N, pm.rad[1], pm.nrad[1], tw, sgn);
-  for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
-    const int y = e / nb, c = e - y * nb;
-    if (c < cols) C[((size_t)z * N + y) * h + kx0 + c] = res[c * N + y];
-  }
+    return v;
+  }, [&](int y, int c, cplx<T> v) { a[c * ls + y] = v; });
+  const cplx<T>* tw = stage_twiddles<T, kBlock>(gTw<T>(pm, 1), b + nb * ls, N);
+  cplx<T>* res = lds_fft<T, kBlock>(a, b, N, nb, ls, pm.radcode[1], pm.nrad[1], tw, sgn);
+  for2d<kBlock>(N, nb, [&](int y, int c) {
+    if (c < cols) C[((size_t)z * N + y) * h + kx0 + c] = res[c * ls + y];
+  });
 }
 
 // ---- z pass: forward, influence function, inverse.  Block: (y, kx block).
@@ -231,43 +299,55 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, int nb) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  const int N = pm.K[2], K1 = pm.K[1], h = pm.kxh;
+  const int N = pm.K[2], ls = N + 1, K1 = pm.K[1], h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* b = a + nb * N;
+  cplx<T>* b = a + nb * ls;
   const int nkb = (h + nb - 1) / nb;
   const int y = blockIdx.x / nkb;
   const int kx0 = (blockIdx.x - y * nkb) * nb;
   const int cols = min(nb, h - kx0);
   cplx<T>* C = gC<T>(pm);
-  for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
-    const int z = e / nb, c = e - z * nb;
+  const T* G = gG<T>(pm);
+  // this thread's (z, c) in the multiply step (nb <= kBlock); its first
+  // influence-function values are fetched while the forward transform runs
+  const int zs = kBlock / nb, cth = threadIdx.x % nb, z0 = threadIdx.x / nb;
+  const bool mact = z0 < zs && cth < cols;
+  T gpre[kLoadU];
+#pragma unroll
+  for (int u = 0; u < kLoadU; ++u) {
+    const int z = z0 + u * zs;
+    gpre[u] = (mact && z < N) ? G[((size_t)z * K1 + y) * h + kx0 + cth] : T(0);
+  }
+  stage2d<kBlock, cplx<T>>(N, nb, [&](int z, int c) {
     cplx<T> v;
     v.x = T(0); v.y = T(0);
     if (c < cols) v = C[((size_t)z * K1 + y) * h + kx0 + c];
-    a[c * N + z] = v;
-  }
-  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 2), b + nb * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nb, N, pm.rad[2], pm.nrad[2], tw, T(-1));
-  const T* G = gG<T>(pm);
+    return v;
+  }, [&](int z, int c, cplx<T> v) { a[c * ls + z] = v; });
+  const cplx<T>* tw = stage_twiddles<T, kBlock>(gTw<T>(pm, 2), b + nb * ls, N);
+  cplx<T>* res = lds_fft<T, kBlock>(a, b, N, nb, ls, pm.radcode[2], pm.nrad[2], tw, T(-1));
   double e_part = 0.0;
-  for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
-    const int c = e / N, z = e - c * N;
-    if (c < cols) {
-      const int kx = kx0 + c;
-      const T g = G[((size_t)z * K1 + y) * h + kx];
-      cplx<T> v = res[e];
-      const double mult = (kx == 0 || 2 * kx == pm.K[0]) ? 1.0 : 2.0;
+  if (mact) {
+    const int kx = kx0 + cth;
+    const double mult = (kx == 0 || 2 * kx == pm.K[0]) ? 1.0 : 2.0;
+    auto apply = [&](int z, T g) {
+      cplx<T> v = res[cth * ls + z];
       e_part += 0.5 * mult * (double)g * ((double)v.x * v.x + (double)v.y * v.y);
       v.x *= g; v.y *= g;
-      res[e] = v;
+      res[cth * ls + z] = v;
+    };
+#pragma unroll
+    for (int u = 0; u < kLoadU; ++u) {
+      const int z = z0 + u * zs;
+      if (z < N) apply(z, gpre[u]);
     }
+    for (int z = z0 + kLoadU * zs; z < N; z += zs) apply(z, G[((size_t)z * K1 + y) * h + kx]);
   }
   cplx<T>* other = (res == a) ? b : a;
-  cplx<T>* res2 = lds_fft<T>(res, other, N, nb, N, pm.rad[2], pm.nrad[2], tw, T(1));
-  for (int e = threadIdx.x; e < nb * N; e += blockDim.x) {
-    const int z = e / nb, c = e - z * nb;
-    if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * N + z];
-  }
+  cplx<T>* res2 = lds_fft<T, kBlock>(res, other, N, nb, ls, pm.radcode[2], pm.nrad[2], tw, T(1));
+  for2d<kBlock>(N, nb, [&](int z, int c) {
+    if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * ls + z];
+  });
   block_partial(e_part, red, pm.erec_slot);
 }
 
@@ -276,15 +356,14 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  const int N = pm.K[0], h = pm.kxh;
+  const int N = pm.K[0], ls = N + 1, h = pm.kxh;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* b = a + nl * N;
+  cplx<T>* b = a + nl * ls;
   const int nrows = pm.K[1] * pm.K[2];
   const int row0 = blockIdx.x * nl;
   const int rows = min(nl, nrows - row0);
   const cplx<T>* C = gC<T>(pm);
-  for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
-    const int l = e / N, k = e - l * N;
+  stage2d<kBlock, cplx<T>>(nl, N, [&](int l, int k) {
     cplx<T> v;
     v.x = T(0); v.y = T(0);
     if (l < rows) {
@@ -295,22 +374,21 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
         v.y = -v.y;
       }
     }
-    a[e] = v;
-  }
-  const cplx<T>* tw = stage_twiddles<T>(gTw<T>(pm, 0), b + nl * N, N);
-  cplx<T>* res = lds_fft<T>(a, b, N, nl, N, pm.rad[0], pm.nrad[0], tw, T(1));
+    return v;
+  }, [&](int l, int k, cplx<T> v) { a[l * ls + k] = v; });
+  const cplx<T>* tw = stage_twiddles<T, kBlock>(gTw<T>(pm, 0), b + nl * ls, N);
+  cplx<T>* res = lds_fft<T, kBlock>(a, b, N, nl, ls, pm.radcode[0], pm.nrad[0], tw, T(1));
   T* phi = gPhi<T>(pm);
-  for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
-    const int l = e / N, x = e - l * N;
-    if (l < rows) phi[(size_t)(row0 + l) * N + x] = res[e].x;
-  }
+  for2d<kBlock>(nl, N, [&](int l, int x) {
+    if (l < rows) phi[(size_t)(row0 + l) * N + x] = res[l * ls + x].x;
+  });
 }
 
 // ---- whole z-planes in LDS (grids whose planes fit in a workgroup's LDS)
 // Forward: transform pairs of real rows of Q (folded from the spreading
-// tiles by k_spread_fold) as one complex line (rows y and y + 1 as real and imaginary
-// parts), split them into the two half spectra, then transform the columns
-// (one per kx) along y; writes C[z][y][kx].
+// tiles by k_spread_fold) as one complex line (rows y and y + 1 as real and
+// imaginary parts), split them into the two half spectra, then transform
+// the columns (one per kx) along y; writes C[z][y][kx].
 // Inverse: columns along y, then pairs of Hermitian-completed rows combined
 // as X + iY into one complex line, inverse, real and imaginary parts ->
 // rows y and y + 1 of phi.  The imaginary parts of the kx = 0 and kx = K0/2
@@ -321,29 +399,28 @@ template <typename T>
 __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_fwd(PmeView pm) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
+  constexpr int NT = kPlaneThreads;
   const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
-  const int cs = K1 + 1;                        // column stride (odd: no bank conflicts)
-  const int bufsz = max((K1 / 2) * K0, h * cs);
+  const int rs = K0 + 1, cs = K1 + 1;           // row and column strides
+  const int bufsz = max((K1 / 2) * rs, h * cs);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + bufsz;
   cplx<T>* tw0 = B + bufsz;
   cplx<T>* tw1 = tw0 + K0;
-  stage_twiddles<T>(gTw<T>(pm, 0), tw0, K0);
-  stage_twiddles<T>(gTw<T>(pm, 1), tw1, K1);
+  stage_twiddles<T, NT>(gTw<T>(pm, 0), tw0, K0);
+  stage_twiddles<T, NT>(gTw<T>(pm, 1), tw1, K1);
   const T* Q = gQ<T>(pm) + (size_t)z * K1 * K0;
-  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
-    const int m = e / K0, x = e - m * K0;
+  stage2d<NT, cplx<T>>(K1 / 2, K0, [&](int m, int x) {
     cplx<T> v;
     v.x = Q[(2 * m) * K0 + x];
     v.y = Q[(2 * m + 1) * K0 + x];
-    A[e] = v;
-  }
-  cplx<T>* rows = lds_fft<T>(A, B, K0, K1 / 2, K0, pm.rad[0], pm.nrad[0], tw0, T(-1));
+    return v;
+  }, [&](int m, int x, cplx<T> v) { A[m * rs + x] = v; });
+  cplx<T>* rows = lds_fft<T, NT>(A, B, K0, K1 / 2, rs, pm.radcode[0], pm.nrad[0], tw0, T(-1));
   cplx<T>* cols = rows == A ? B : A;
-  for (int e = threadIdx.x; e < (K1 / 2) * h; e += blockDim.x) {
-    const int m = e / h, k = e - m * h;
-    const cplx<T> zk = rows[m * K0 + k];
-    const cplx<T> zn = rows[m * K0 + (k == 0 ? 0 : K0 - k)];
+  for2d<NT>(K1 / 2, h, [&](int m, int k) {
+    const cplx<T> zk = rows[m * rs + k];
+    const cplx<T> zn = rows[m * rs + (k == 0 ? 0 : K0 - k)];
     cplx<T> X, Y;
     X.x = T(0.5) * (zk.x + zn.x);
     X.y = T(0.5) * (zk.y - zn.y);
@@ -351,37 +428,32 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_fwd(PmeView pm) {
     Y.y = T(0.5) * (zn.x - zk.x);
     cols[k * cs + 2 * m] = X;
     cols[k * cs + 2 * m + 1] = Y;
-  }
-  cplx<T>* res = lds_fft<T>(cols, rows, K1, h, cs, pm.rad[1], pm.nrad[1], tw1, T(-1));
-  cplx<T>* C = gC<T>(pm);
-  for (int e = threadIdx.x; e < K1 * h; e += blockDim.x) {
-    const int y = e / h, k = e - y * h;
-    C[((size_t)z * K1 + y) * h + k] = res[k * cs + y];
-  }
+  });
+  cplx<T>* res = lds_fft<T, NT>(cols, rows, K1, h, cs, pm.radcode[1], pm.nrad[1], tw1, T(-1));
+  cplx<T>* C = gC<T>(pm) + (size_t)z * K1 * h;
+  for2d<NT>(K1, h, [&](int y, int k) { C[y * h + k] = res[k * cs + y]; });
 }
 
 template <typename T>
 __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_inv(PmeView pm) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
+  constexpr int NT = kPlaneThreads;
   const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
-  const int cs = K1 + 1;
-  const int bufsz = max((K1 / 2) * K0, h * cs);
+  const int rs = K0 + 1, cs = K1 + 1;
+  const int bufsz = max((K1 / 2) * rs, h * cs);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + bufsz;
   cplx<T>* tw0 = B + bufsz;
   cplx<T>* tw1 = tw0 + K0;
-  stage_twiddles<T>(gTw<T>(pm, 0), tw0, K0);
-  stage_twiddles<T>(gTw<T>(pm, 1), tw1, K1);
-  const cplx<T>* C = gC<T>(pm);
-  for (int e = threadIdx.x; e < K1 * h; e += blockDim.x) {
-    const int y = e / h, k = e - y * h;
-    A[k * cs + y] = C[((size_t)z * K1 + y) * h + k];
-  }
-  cplx<T>* cols = lds_fft<T>(A, B, K1, h, cs, pm.rad[1], pm.nrad[1], tw1, T(1));
+  stage_twiddles<T, NT>(gTw<T>(pm, 0), tw0, K0);
+  stage_twiddles<T, NT>(gTw<T>(pm, 1), tw1, K1);
+  const cplx<T>* C = gC<T>(pm) + (size_t)z * K1 * h;
+  stage2d<NT, cplx<T>>(K1, h, [&](int y, int k) { return C[y * h + k]; },
+                       [&](int y, int k, cplx<T> v) { A[k * cs + y] = v; });
+  cplx<T>* cols = lds_fft<T, NT>(A, B, K1, h, cs, pm.radcode[1], pm.nrad[1], tw1, T(1));
   cplx<T>* rows = cols == A ? B : A;
-  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
-    const int m = e / K0, k = e - m * K0;
+  for2d<NT>(K1 / 2, K0, [&](int m, int k) {
     cplx<T> X, Y;
     if (k < h) {
       X = cols[k * cs + 2 * m];
@@ -396,22 +468,22 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_inv(PmeView pm) {
     cplx<T> v;
     v.x = X.x - Y.y;
     v.y = X.y + Y.x;
-    rows[m * K0 + k] = v;
-  }
-  cplx<T>* res = lds_fft<T>(rows, cols, K0, K1 / 2, K0, pm.rad[0], pm.nrad[0], tw0, T(1));
-  T* phi = gPhi<T>(pm);
-  for (int e = threadIdx.x; e < (K1 / 2) * K0; e += blockDim.x) {
-    const int m = e / K0, x = e - m * K0;
-    const cplx<T> v = res[e];
-    phi[((size_t)z * K1 + 2 * m) * K0 + x] = v.x;
-    phi[((size_t)z * K1 + 2 * m + 1) * K0 + x] = v.y;
-  }
+    rows[m * rs + k] = v;
+  });
+  cplx<T>* res = lds_fft<T, NT>(rows, cols, K0, K1 / 2, rs, pm.radcode[0], pm.nrad[0], tw0, T(1));
+  T* phi = gPhi<T>(pm) + (size_t)z * K1 * K0;
+  for2d<NT>(K1 / 2, K0, [&](int m, int x) {
+    const cplx<T> v = res[m * rs + x];
+    phi[(2 * m) * K0 + x] = v.x;
+    phi[(2 * m + 1) * K0 + x] = v.y;
+  });
 }
 
 // LDS bytes of the plane kernels; 0 when the planes do not fit.
 static size_t plane_lds(const PmeView& pm, size_t csz) {
   const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh;
-  const size_t bufsz = std::max<size_t>((size_t)(K1 / 2) * K0, (size_t)h * (K1 + 1));
+  const size_t bufsz =
+      std::max<size_t>((size_t)(K1 / 2) * (K0 + 1), (size_t)h * (K1 + 1));
   const size_t bytes = (2 * bufsz + K0 + K1) * csz;
   return bytes <= kPlaneLdsMax ? bytes : 0;
 }
@@ -428,6 +500,20 @@ template <typename T>
 static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
   const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2], h = pm.kxh;
   const size_t csz = sizeof(cplx<T>);
+  const int budget = 48 * 1024;
+  // lines of length N per workgroup whose two buffers (stride N + 1) fit
+  // the budget, at most 24
+  auto lines_for = [&](int N) {
+    int nl = (int)(budget / (2 * (size_t)(N + 1) * csz));
+    if (nl > 24) nl = 24;
+    if (nl < 1) nl = 1;
+    return nl;
+  };
+  auto lds_for = [&](int nl, int N) { return (2 * (size_t)nl * (N + 1) + N) * csz; };
+  const int nb = pick_batch(h);
+  const int nbz = std::min(nb, lines_for(K2));
+  const int nkbz = (h + nbz - 1) / nbz;
+  const size_t shz = lds_for(nbz, K2);
   // SIBFA_FFT_PLANES=0 forces the five-pass path (used to test it on grids
   // whose planes would fit)
   const char* env = std::getenv("SIBFA_FFT_PLANES");
@@ -436,17 +522,11 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
     static bool attr = false;   // raise the dynamic LDS limit once per kernel
     if (!attr) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<T>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<T>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);
       attr = true;
     }
-    const int nb = pick_batch(h);
-    const int budget = 48 * 1024;
-    int nbz = (int)(budget / (2 * K2 * csz));
-    nbz = std::max(1, std::min(nbz, std::min(nb, 24)));
-    const int nkbz = (h + nbz - 1) / nbz;
-    const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
     launch_spread_fold(pm, mixed, st);
     hipLaunchKernelGGL(k_fft_plane_fwd<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
     red.nparts[pm.erec_slot] = K1 * nkbz;
@@ -455,25 +535,14 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
     return;
   }
   launch_spread_fold(pm, mixed, st);
-  const int budget = 48 * 1024;
-  auto lines_for = [&](int N) {
-    int nl = (int)(budget / (2 * N * csz));
-    if (nl > 24) nl = 24;
-    if (nl < 1) nl = 1;
-    return nl;
-  };
   const int nlx = lines_for(K0);
   const int nrows = K1 * K2;
-  const size_t shx = (2 * (size_t)nlx + 1) * K0 * csz;
+  const size_t shx = lds_for(nlx, K0);
   hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3((nrows + nlx - 1) / nlx), dim3(kBlock), shx, st, pm, nlx);
-  const int nb = pick_batch(h);
-  const int nby = nb < lines_for(K1) ? nb : lines_for(K1);
+  const int nby = std::min(nb, lines_for(K1));
   const int nkby = (h + nby - 1) / nby;
-  const size_t shy = (2 * (size_t)nby + 1) * K1 * csz;
+  const size_t shy = lds_for(nby, K1);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(-1));
-  const int nbz = nb < lines_for(K2) ? nb : lines_for(K2);
-  const int nkbz = (h + nbz - 1) / nbz;
-  const size_t shz = (2 * (size_t)nbz + 1) * K2 * csz;
   red.nparts[pm.erec_slot] = K1 * nkbz;
   hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(1));
