@@ -91,10 +91,15 @@ struct sibfa_ctx_s {
   int cap[4] = {0, 0, 0, 0};
   int* nb[4] = {nullptr, nullptr, nullptr, nullptr};
   int* ncnt[4] = {nullptr, nullptr, nullptr, nullptr};
+  int* ncnear = nullptr;   // near entries of the all list
+  // all-list split radius squared: every polarizable pair beyond it has a
+  // Thole exponent x = a r^3 s_i s_j >= 50 (no damping)
+  double rsplit2 = 0.0;
   DevBuf nbbuf[4];
   // [0..3] list maxima, [4] binning errors (bits 2, 8), [5] list errors
   // (bit 1), [6] finiteness flag, [7] polarizability errors (bit 4),
-  // [8] spare flag, [16..31] eight slot totals (doubles)
+  // [8..11] solver stop flag, [16..31] eight slot totals (doubles),
+  // [32..35] polarizability extents (doubles)
   int* dints = nullptr;
   // solver vectors (pol order)
   double4 *E0 = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
@@ -254,6 +259,7 @@ SysView make_view(sibfa_ctx c) {
   s.polsite = c->polsite; s.pp = c->pp; s.pp32 = c->pp32; s.pa = c->pa;
   s.alpha = c->alpha_s; s.ainv = c->ainv_s;
   s.nb_all = c->nb[0]; s.nc_all = c->ncnt[0]; s.cap_all = c->cap[0];
+  s.nc_near = c->ncnear;
   s.nb_in = c->nb[1]; s.nc_in = c->ncnt[1]; s.cap_in = c->cap[1];
   s.nb_pol = c->nb[2]; s.nc_pol = c->ncnt[2]; s.cap_pol = c->cap[2];
   s.nb_ipol = c->nb[3]; s.nc_ipol = c->ncnt[3]; s.cap_ipol = c->cap[3];
@@ -495,6 +501,8 @@ sibfa_status build_lists(sibfa_ctx c) {
     a.polidx = c->polidx;
     a.mol_count = c->mol_count;
     a.nb_all = c->nb[0]; a.nc_all = c->ncnt[0]; a.cap_all = c->cap[0];
+    a.nc_near = c->ncnear;
+    a.rsplit2 = c->rsplit2;
     a.nb_in = c->nb[1]; a.nc_in = c->ncnt[1]; a.cap_in = c->cap[1];
     a.nb_pol = c->nb[2]; a.nc_pol = c->ncnt[2]; a.cap_pol = c->cap[2];
     a.nb_ipol = c->nb[3]; a.nc_ipol = c->ncnt[3]; a.cap_ipol = c->cap[3];
@@ -593,16 +601,28 @@ sibfa_status prepare(sibfa_ctx c) {
     launch_rec_pol(ra, s);
     launch_exclusive_scan(c->is_pol, c->pol_scan, c->n + 1, c->scan_tmp, s);
     launch_rec_polsites(ra, s);
-    // a re-sort permutes the same polarizabilities: count and definiteness
-    // are unchanged
+    // a re-sort permutes the same polarizabilities: count, definiteness
+    // and extents are unchanged
     if (!c->pol_ok) {
+      double* dext = reinterpret_cast<double*>(c->dints + 32);
+      launch_pol_extents(ra, dext, s);
       HIP_TRY(hipMemcpyAsync(c->h_ints, c->pol_scan + c->n, sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipMemcpyAsync(c->h_ints + 7, c->dints + 7, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(c->h_pinned + 56, dext, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       sibfa_status st = sync_read(c);
       if (st != SIBFA_OK) return st;
       if (c->h_ints[7] & 4)
         return fail(c, SIBFA_E_ARG, "every nonzero polarizability must be positive definite");
       c->npol = c->h_ints[0];
+      // x = a r^3 s_i s_j with s = abar^-1/2 is at least
+      // a_min r^3 / abar_max, so x >= 50 beyond r^3 = 50 abar_max / a_min
+      const double amax = c->h_pinned[56], tmin = c->h_pinned[57];
+      if (c->npol == 0 || !(amax > 0.0)) c->rsplit2 = 0.0;
+      else if (!(tmin > 0.0)) c->rsplit2 = INFINITY;
+      else {
+        const double rs = 1.001 * std::cbrt(50.0 * amax / tmin);
+        c->rsplit2 = rs * rs;
+      }
       c->pol_ok = true;
     }
     c->stats.n_polarizable = c->npol;
@@ -1154,12 +1174,13 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->polidx, n) && alloc_into(c, L, c->polsite, n) &&
             alloc_into(c, L, c->pp, n) && alloc_into(c, L, c->pp32, n) && alloc_into(c, L, c->pa, n) &&
             alloc_into(c, L, c->alpha_s, 6 * n) && alloc_into(c, L, c->ainv_s, 6 * n) &&
-            alloc_into(c, L, c->dints, 16 + 16) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
+            alloc_into(c, L, c->dints, 16 + 16 + 8) && alloc_into(c, L, c->dsums, 8) && alloc_into(c, L, c->E0, n) && alloc_into(c, L, c->x, n) &&
             alloc_into(c, L, c->r, n) && alloc_into(c, L, c->z, n) && alloc_into(c, L, c->p, n) &&
             alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
             alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->p2, n) && alloc_into(c, L, c->p2_32, n) && alloc_into(c, L, c->mu_s, n) &&
             alloc_into(c, L, c->mu_s32, n) && alloc_into(c, L, c->Freal, n);
   for (int k = 0; k < 4 && ok; ++k) ok = alloc_into(c, L, c->ncnt[k], n);
+  ok = ok && alloc_into(c, L, c->ncnear, n);
   // partial sums: one per block of the largest reducing launch (site
   // kernels use >= 16 sites per block; the z pass at most K1 * (K0/2+1);
   // the brick-parallel PME gathers one per spreading brick)

@@ -67,6 +67,7 @@ struct SysView {
   const double* ainv;   // [npol][6]
   // neighbour lists (ELL: row i holds count[i] entries starting at i*cap)
   const int* nb_all;  const int* nc_all;  int cap_all;    // intermolecular, r < rc
+  const int* nc_near;   // near pairs of the all list (see NlistArgs)
   const int* nb_in;   const int* nc_in;   int cap_in;     // same molecule
   const int* nb_pol;  const int* nc_pol;  int cap_pol;    // pol-pol, inter, r < rc
   const int* nb_ipol; const int* nc_ipol; int cap_ipol;   // pol-pol, same molecule

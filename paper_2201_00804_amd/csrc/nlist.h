@@ -50,7 +50,12 @@ struct NlistArgs {
   const int* mol_s;
   const int* polidx;
   const int* mol_count;
+  // all: pairs with r^2 < rsplit2 ("near") from the front of the row in
+  // candidate order, the others from the back (entry cap - 1 - k holds the
+  // k-th far pair); nc_all counts both, nc_near the near ones
   int* nb_all; int* nc_all; int cap_all;
+  int* nc_near;
+  double rsplit2;
   int* nb_in; int* nc_in; int cap_in;
   int* nb_pol; int* nc_pol; int cap_pol;
   int* nb_ipol; int* nc_ipol; int cap_ipol;
@@ -65,6 +70,9 @@ void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t 
 void launch_max_int(const int* v, int n, int* out, hipStream_t s);
 void launch_sum_ints(const int* v, int n, unsigned long long* out, hipStream_t s);
 void launch_rec_pos(const RecArgs& a, hipStream_t s);
+// out[0] = largest mean polarizability, out[1] = smallest Thole factor over
+// the polarizable sites (after launch_rec_pol); 0 and +inf when none.
+void launch_pol_extents(const RecArgs& a, double* out, hipStream_t s);
 void launch_rec_mult(const RecArgs& a, hipStream_t s);
 void launch_rec_pol(const RecArgs& a, hipStream_t s);
 void launch_rec_polsites(const RecArgs& a, hipStream_t s);

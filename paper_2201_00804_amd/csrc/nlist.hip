@@ -336,6 +336,36 @@ void launch_rec_polsites(const RecArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_rec_polsites, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
 }
 
+// One block: extremes over the polarizable sites (fixed reduction order).
+__global__ __launch_bounds__(kBlock) void k_pol_extents(RecArgs a, double* out) {
+  __shared__ double smax[kBlock], smin[kBlock];
+  double amax = 0.0, tmin = INFINITY;
+  for (int i = threadIdx.x; i < a.n; i += kBlock) {
+    if (!a.is_pol[i]) continue;
+    const double s = a.sd[i].w;   // 1 / sqrt(mean polarizability)
+    amax = fmax(amax, 1.0 / (s * s));
+    tmin = fmin(tmin, a.sa[i]);
+  }
+  smax[threadIdx.x] = amax;
+  smin[threadIdx.x] = tmin;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smax[0];
+    out[1] = smin[0];
+  }
+}
+
+void launch_pol_extents(const RecArgs& a, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pol_extents, dim3(1), dim3(kBlock), 0, s, a, out);
+}
+
 // ------------------------------------------------------------ neighbour lists
 constexpr int kNlIB = 64;   // i-sites of a cell handled per pass (one per lane)
 
@@ -370,7 +400,8 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
       poli[lane] = a.polidx[ib + lane];
     }
     __syncthreads();
-    int cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;   // counts of i-site `lane`
+    // counts of i-site `lane`: all near (cnt0) and far (cntf), in, pol, ipol
+    int cnt0 = 0, cntf = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
     for (int sz = 0; sz < span[2]; ++sz) {
       int zz = lo[2] + sz;
       zz = (zz + a.nc[2]) % a.nc[2];
@@ -418,17 +449,24 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
               const int mi = moli[t], pi_ = poli[t];
               const bool same = valid && (molj == mi) && (j != i);
               const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
+              const bool near = r2 < a.rsplit2;
               const bool pi = pi_ >= 0;
               const bool pj = polj >= 0;
-              const unsigned long long b0 = __ballot(inter);
+              const unsigned long long b0 = __ballot(inter && near);
+              const unsigned long long bf = __ballot(inter && !near);
               const unsigned long long b1 = __ballot(same);
               const unsigned long long b2 = __ballot(inter && pi && pj);
               const unsigned long long b3 = __ballot(same && pi && pj);
-              const int base0 = __shfl(cnt0, t, 64), base1 = __shfl(cnt1, t, 64);
+              const int base0 = __shfl(cnt0, t, 64), basef = __shfl(cntf, t, 64);
+              const int base1 = __shfl(cnt1, t, 64);
               const int base2 = __shfl(cnt2, t, 64), base3 = __shfl(cnt3, t, 64);
-              if (inter) {
+              if (inter && near) {
                 const int k = base0 + __popcll(b0 & below);
                 if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
+              }
+              if (inter && !near) {
+                const int k = basef + __popcll(bf & below);
+                if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + a.cap_all - 1 - k] = j;
               }
               if (same) {
                 const int k = base1 + __popcll(b1 & below);
@@ -444,6 +482,7 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
               }
               if (lane == t) {
                 cnt0 += __popcll(b0);
+                cntf += __popcll(bf);
                 cnt1 += __popcll(b1);
                 cnt2 += __popcll(b2);
                 cnt3 += __popcll(b3);
@@ -456,9 +495,10 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
     // counts, overflow maxima and the same-molecule completeness check
     if (lane < ni) {
       const int i = ib + lane;
-      a.nc_all[i] = cnt0;
+      a.nc_all[i] = cnt0 + cntf;
+      a.nc_near[i] = cnt0;
       a.nc_in[i] = cnt1;
-      atomicMax(&a.maxcnt[0], cnt0);
+      atomicMax(&a.maxcnt[0], cnt0 + cntf);
       atomicMax(&a.maxcnt[1], cnt1);
       if (poli[lane] >= 0) {
         a.nc_pol[poli[lane]] = cnt2;
@@ -535,7 +575,8 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
       poli[lane] = a.polidx[ib + lane];
     }
     __syncthreads();
-    int cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;   // counts of i-site `lane`
+    // counts of i-site `lane`: all near (cnt0) and far (cntf), in, pol, ipol
+    int cnt0 = 0, cntf = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
     for (int c = 0; c < ncand; c += 64) {
       const int cidx = c + lane;
       const bool valid = cidx < ncand;
@@ -565,13 +606,17 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
         const int mi = moli[t], pi_ = poli[t];
         const bool same = valid && (molj == mi) && (j != i);
         const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
+        const bool near = r2 < a.rsplit2;
         const unsigned long long b0 = __ballot(inter);
         const unsigned long long b1 = __ballot(same);
         if ((b0 | b1) == 0ull) continue;   // no neighbour of site t in this chunk
-        const int base0 = __shfl(cnt0, t, 64), base1 = __shfl(cnt1, t, 64);
+        const unsigned long long bn = __ballot(inter && near), bf = b0 & ~bn;
+        const int basen = __shfl(cnt0, t, 64), basef = __shfl(cntf, t, 64);
+        const int base1 = __shfl(cnt1, t, 64);
         if (inter) {
-          const int k = base0 + __popcll(b0 & below);
-          if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + k] = j;
+          const int k = near ? basen + __popcll(bn & below) : basef + __popcll(bf & below);
+          const int e = near ? k : a.cap_all - 1 - k;
+          if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + e] = j;
         }
         if (same) {
           const int k = base1 + __popcll(b1 & below);
@@ -594,16 +639,18 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
           }
         }
         if (lane == t) {
-          cnt0 += __popcll(b0);
+          cnt0 += __popcll(bn);
+          cntf += __popcll(bf);
           cnt1 += __popcll(b1);
         }
       }
     }
     if (lane < ni) {
       const int i = ib + lane;
-      a.nc_all[i] = cnt0;
+      a.nc_all[i] = cnt0 + cntf;
+      a.nc_near[i] = cnt0;
       a.nc_in[i] = cnt1;
-      atomicMax(&a.maxcnt[0], cnt0);
+      atomicMax(&a.maxcnt[0], cnt0 + cntf);
       atomicMax(&a.maxcnt[1], cnt1);
       if (poli[lane] >= 0) {
         a.nc_pol[poli[lane]] = cnt2;

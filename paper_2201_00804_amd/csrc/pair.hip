@@ -134,8 +134,47 @@ __global__ __launch_bounds__(kBlock) void k_perm_intra(SysView s, Reduce red, do
   block_partial(Uself, red, S_ESELF);
 }
 
+// One intermolecular pair of k_perm: MM energy (half, the pair is seen from
+// both sites) and, for a polarizable site i, the field of M_j, Thole-damped
+// when j is polarizable too.  Far pairs (see the list layout) have x >= 50
+// for every polarizable pair, where the damping factor e^-x < 2e-22 is
+// dropped, as it is for near pairs with x >= 50.
+template <typename R, bool NEAR>
+__device__ __forceinline__ void perm_pair(const SysView& s, int i, int j, int pi, const MP<R>& Mi,
+                                          const R xi[3], R si, double& U, double acc[3]) {
+  MP<R> Mj;
+  R xj[3], Rv[3];
+  load_mp<R>(s, j, Mj, xj);
+  displacement<R>(s, xi, xj, Rv);
+  const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+  const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+  R c[6];
+  base_coeffs<R, 4>(s, r, rinv, rinv2, c);
+  c[5] = R(0);
+  R u, fdum[3];
+  mp_pair<R, true, false>(c, Mi, Mj, Rv, u, fdum);
+  U += 0.5 * (double)u;
+  if (pi >= 0) {
+    if (NEAR) {
+      const R sj = site_s<R>(s, j);
+      R x = R(0);
+      if (sj > R(0) && (x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj) < R(50)) {
+        R tp[5], c0[4];
+        thole_tp<R>(x, tp);
+        bare_coeffs<R, 3>(rinv, rinv2, c0);
+#pragma unroll
+        for (int n = 1; n <= 3; ++n) c[n] -= tp[n] * c0[n];
+      }
+    }
+    R E[3];
+    mp_field<R>(c, Mj, Rv, E);
+    acc[0] += (double)E[0]; acc[1] += (double)E[1]; acc[2] += (double)E[2];
+  }
+}
+
 // Intermolecular pairs within the cutoff (precision R): MM energy partials
-// (S_EREAL) and the damped field added to E0 of polarizable sites.
+// (S_EREAL) and the damped field added to E0 of polarizable sites.  Near
+// entries first, then far ones (no damping).
 template <typename R, int G>
 __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4* E0) {
   const int sub = threadIdx.x % G;
@@ -149,36 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
     R xi[3];
     load_mp<R>(s, i, Mi, xi);
     const R si = site_s<R>(s, i);
-    const int cnt = s.nc_all[i];
-    for (int k = sub; k < cnt; k += G) {
-      const int j = s.nb_all[(size_t)i * s.cap_all + k];
-      MP<R> Mj;
-      R xj[3], Rv[3];
-      load_mp<R>(s, j, Mj, xj);
-      displacement<R>(s, xi, xj, Rv);
-      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      R c[6];
-      base_coeffs<R, 4>(s, r, rinv, rinv2, c);
-      c[5] = R(0);
-      R u, fdum[3];
-      mp_pair<R, true, false>(c, Mi, Mj, Rv, u, fdum);
-      U += 0.5 * (double)u;
-      if (pi >= 0) {
-        const R sj = site_s<R>(s, j);
-        if (sj > R(0)) {
-          const R x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj;
-          R tp[5], c0[4];
-          thole_tp<R>(x, tp);
-          bare_coeffs<R, 3>(rinv, rinv2, c0);
-#pragma unroll
-          for (int n = 1; n <= 3; ++n) c[n] -= tp[n] * c0[n];
-        }
-        R E[3];
-        mp_field<R>(c, Mj, Rv, E);
-        acc[0] += (double)E[0]; acc[1] += (double)E[1]; acc[2] += (double)E[2];
-      }
-    }
+    const int* row = s.nb_all + (size_t)i * s.cap_all;
+    const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
+    for (int k = sub; k < nn; k += G) perm_pair<R, true>(s, i, row[k], pi, Mi, xi, si, U, acc);
+    for (int k = sub; k < nf; k += G)
+      perm_pair<R, false>(s, i, row[s.cap_all - 1 - k], pi, Mi, xi, si, U, acc);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) acc[a] = group_sum<G>(acc[a]);
@@ -536,7 +550,51 @@ __global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, const double4
   }
 }
 
+// One intermolecular pair of k_force (see the identity above).  NEAR: the
+// pair may be damped (x < 50); far pairs never are.
+template <typename R, bool NEAR>
+__device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const MP<R>& Mi,
+                                           const MP<R>& Pi, const R xi[3], R si,
+                                           const double4* mu, const float4* mu32, double F[3]) {
+  MP<R> Mj;
+  R xj[3], Rv[3], muj[3];
+  load_mp<R>(s, j, Mj, xj);
+  load_mu<R>(mu, mu32, j, muj);
+  displacement<R>(s, xi, xj, Rv);
+  const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+  const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+  R c[6];
+  base_coeffs<R, 5>(s, r, rinv, rinv2, c);
+  bool damp = false;
+  R D[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (NEAR) {
+    const R sj = site_s<R>(s, j);
+    R x = R(0);
+    damp = si > R(0) && sj > R(0) && (x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj) < R(50);
+    if (damp) {
+      R tp[5], c0[5];
+      thole_tp<R>(x, tp);
+      bare_coeffs<R, 4>(rinv, rinv2, c0);
+#pragma unroll
+      for (int n = 1; n <= 4; ++n) {
+        D[n] = tp[n] * c0[n];
+        c[n] -= D[n];
+      }
+    }
+  }
+  MP<R> Pj = Mj;
+  Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
+  R u, f[3];
+  mp_pair<R, false, true>(c, Pi, Pj, Rv, u, f);
+  F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+  if (NEAR && damp) {
+    mp_pair<R, false, true>(D, Mi, Mj, Rv, u, f);
+    F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+  }
+}
+
 // Intermolecular pairs within the cutoff (precision R); adds to Fout.
+// Near entries first (the damped ones are among them), then far ones.
 template <typename R, int G>
 __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, const float4* mu32,
                                                   double4* Fout) {
@@ -551,43 +609,12 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
     MP<R> Pi = Mi;
     Pi.d[0] += mui[0]; Pi.d[1] += mui[1]; Pi.d[2] += mui[2];
     const R si = site_s<R>(s, i);
-    const int cnt = s.nc_all[i];
-    for (int k = sub; k < cnt; k += G) {
-      const int j = s.nb_all[(size_t)i * s.cap_all + k];
-      MP<R> Mj;
-      R xj[3], Rv[3], muj[3];
-      load_mp<R>(s, j, Mj, xj);
-      load_mu<R>(mu, mu32, j, muj);
-      displacement<R>(s, xi, xj, Rv);
-      const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-      const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      R c[6];
-      base_coeffs<R, 5>(s, r, rinv, rinv2, c);
-      const R sj = site_s<R>(s, j);
-      R x = R(0);
-      const bool damp = si > R(0) && sj > R(0) &&
-                        (x = R(thole_a_pair(s, i, j)) * r2 * r * si * sj) < R(50);
-      R D[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-      if (damp) {
-        R tp[5], c0[5];
-        thole_tp<R>(x, tp);
-        bare_coeffs<R, 4>(rinv, rinv2, c0);
-#pragma unroll
-        for (int n = 1; n <= 4; ++n) {
-          D[n] = tp[n] * c0[n];
-          c[n] -= D[n];
-        }
-      }
-      MP<R> Pj = Mj;
-      Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
-      R u, f[3];
-      mp_pair<R, false, true>(c, Pi, Pj, Rv, u, f);
-      F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
-      if (damp) {
-        mp_pair<R, false, true>(D, Mi, Mj, Rv, u, f);
-        F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
-      }
-    }
+    const int* row = s.nb_all + (size_t)i * s.cap_all;
+    const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
+    for (int k = sub; k < nn; k += G)
+      force_pair<R, true>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F);
+    for (int k = sub; k < nf; k += G)
+      force_pair<R, false>(s, i, row[s.cap_all - 1 - k], Mi, Pi, xi, si, mu, mu32, F);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
