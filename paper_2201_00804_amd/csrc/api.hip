@@ -783,8 +783,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   double rho_true = 0.0;
   sibfa_status result = SIBFA_OK;
   for (;;) {
-    // residual from scratch (FP64 operator)
-    matvec(c, c->x, c->x32, c->t, -1, false);
+    // residual from scratch: FP64 operator, except the very first residual
+    // of a cold start in mixed mode (FP32 operator; the early replacement
+    // below removes its rounding)
+    const bool fp32_res = fresh && mix && !(warm && c->mu_have);
+    matvec(c, c->x, c->x32, c->t, -1, fp32_res);
     if (fresh)
       launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
     else
@@ -794,7 +797,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
     if (e != SIBFA_OK) return e;
     rho_true = rms_debye(c, zz0);
-    if (rho_true <= tol) break;
+    if (rho_true <= tol) {
+      if (!fp32_res) break;
+      fresh = false;   // confirm with the FP64 operator
+      continue;
+    }
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
     if (fresh) {
       if (mix) zz_replace = kReplace * zz0;
@@ -818,10 +825,12 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         const int k = kk + j;
         c->cur_tag = j;
         if (k > 0) {
-          // p = z + beta p
+          // p = z + beta p, after the stop test of the previous iteration
+          // when that was enqueued in this batch
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
           Phase ph(c, SIBFA_PH_UPDATE);
-          launch_direction(s, c->red, num, den, c->z, c->p, c->p32, st);
+          launch_direction(s, c->red, num, den, c->z, c->p, c->p32, b > 0 ? flag : nullptr, j,
+                           zz_stop, zz_replace, st);
         }
         if (c->periodic) {
           fork(c);
@@ -845,7 +854,10 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           Phase ph(c, SIBFA_PH_UPDATE);
           launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
                         c->q, st);
-          launch_check(c->red, flag, j + 1, zz_stop, zz_replace, st);
+          // the last iteration of a batch is tested here, the others by
+          // the next direction update
+          if (b == kBatch - 1 || it + j + 1 >= c->prm.max_iter)
+            launch_check(c->red, flag, j + 1, zz_stop, zz_replace, st);
         }
         ++j;
       }

@@ -57,8 +57,11 @@ void launch_init_residual(const SysView& s, Reduce& red, const double4* E0,
 void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    double4* x, double4* r, double4* z, const double4* p, const double4* q,
                    hipStream_t st);
+// p = z + beta p; with a flag, first the stop test of iteration `iter`
+// (that of k_check), and no update when it stops.
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
-                      double4* p, float4* p32, hipStream_t st);
+                      double4* p, float4* p32, int* flag, int iter, double zz_stop,
+                      double zz_replace, hipStream_t st);
 void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
 // Totals of up to 8 reduction slots (one block each, fixed order) into out.
 struct SlotList {

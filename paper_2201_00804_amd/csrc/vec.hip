@@ -62,10 +62,30 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
   block_partial(zz, red, S_ZZ);
 }
 
-// p = z + beta p with beta = scalars[num] / scalars[den] (no grid to spread)
+// Stop test of the previous iteration (see k_check), made by every block
+// on the same partial sums, so all agree; block 0 raises the flag.
+__device__ __forceinline__ bool check_stop(const Reduce& red, int* flag, int iter, double zz_stop,
+                                           double zz_replace) {
+  const double pq = slot_total(red, S_PQ);
+  const double zz = slot_total(red, S_ZZ);
+  int reason = 0;
+  if (!(pq > 0.0)) reason = 2;
+  else if (zz <= zz_stop) reason = 1;
+  else if (zz <= zz_replace) reason = 3;
+  if (reason && blockIdx.x == 0 && threadIdx.x == 0) {
+    flag[1] = reason; flag[2] = iter; flag[0] = 1;
+  }
+  return reason != 0;
+}
+
+// p = z + beta p with beta = scalars[num] / scalars[den] (no grid to spread),
+// after the stop test of the previous iteration when flag is given.
 __global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int num, int den,
-                                                      const double4* z, double4* p, float4* p32) {
+                                                      const double4* z, double4* p, float4* p32,
+                                                      int* flag, int iter, double zz_stop,
+                                                      double zz_replace) {
   if (stopped(red.stop)) return;
+  if (flag && check_stop(red, flag, iter, zz_stop, zz_replace)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = slot_total(red, num) / slot_total(red, den);
   if (i >= s.npol) return;
@@ -115,17 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
 __global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int iter, double zz_stop,
                                                   double zz_replace) {
   if (flag[0]) return;
-  const double pq = slot_total(red, S_PQ);
-  const double zz = slot_total(red, S_ZZ);
-  if (threadIdx.x == 0) {
-    if (!(pq > 0.0)) {
-      flag[1] = 2; flag[2] = iter; flag[0] = 1;
-    } else if (zz <= zz_stop) {
-      flag[1] = 1; flag[2] = iter; flag[0] = 1;
-    } else if (zz <= zz_replace) {
-      flag[1] = 3; flag[2] = iter; flag[0] = 1;
-    }
-  }
+  (void)check_stop(red, flag, iter, zz_stop, zz_replace);
 }
 
 __global__ void k_copy4(const double4* in, double4* out, float4* out32, int n) {
@@ -198,8 +208,10 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
   red.nparts[rz_next_slot] = red.nparts[S_ZZ] = (int)grid_for(s.npol).x;
 }
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
-                      double4* p, float4* p32, hipStream_t st) {
-  hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32);
+                      double4* p, float4* p32, int* flag, int iter, double zz_stop,
+                      double zz_replace, hipStream_t st) {
+  hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32,
+                     flag, iter, zz_stop, zz_replace);
 }
 // One block per slot: the slot's partials summed in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_slot_totals(Reduce red, SlotList sl, double* out) {
