@@ -196,7 +196,7 @@ def copy_probe(mib, reps):
                       "reps": reps}), flush=True)
 
 
-def cpu_baseline(sysd, prm, iters, sample=160):
+def cpu_baseline(sysd, prm, iters, sample=360):
     """The FP64 oracle on a bounded sample of the same box, scaled to one
     evaluation: the oracle's real-space pair sums for `sample` sites
     (polarizable ones for E and T p, arbitrary ones for forces and the MM

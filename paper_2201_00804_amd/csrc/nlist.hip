@@ -336,15 +336,18 @@ void launch_rec_polsites(const RecArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_rec_polsites, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
 }
 
-// One block: extremes over the polarizable sites (fixed reduction order).
-__global__ __launch_bounds__(kBlock) void k_pol_extents(RecArgs a, double* out) {
+// Extremes over the polarizable sites: block maxima / minima combined with
+// atomics on the IEEE bit patterns (order-preserving for non-negative
+// doubles), so the result does not depend on block order.  out must hold
+// 0 and +inf beforehand.
+__global__ __launch_bounds__(kBlock) void k_pol_extents(RecArgs a, unsigned long long* out) {
   __shared__ double smax[kBlock], smin[kBlock];
   double amax = 0.0, tmin = INFINITY;
-  for (int i = threadIdx.x; i < a.n; i += kBlock) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
     if (!a.is_pol[i]) continue;
     const double s = a.sd[i].w;   // 1 / sqrt(mean polarizability)
     amax = fmax(amax, 1.0 / (s * s));
-    tmin = fmin(tmin, a.sa[i]);
+    tmin = fmin(tmin, fmax(a.sa[i], 0.0));
   }
   smax[threadIdx.x] = amax;
   smin[threadIdx.x] = tmin;
@@ -357,13 +360,19 @@ __global__ __launch_bounds__(kBlock) void k_pol_extents(RecArgs a, double* out) 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = smax[0];
-    out[1] = smin[0];
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(smax[0]));
+    atomicMin(&out[1], (unsigned long long)__double_as_longlong(smin[0]));
   }
 }
 
 void launch_pol_extents(const RecArgs& a, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_pol_extents, dim3(1), dim3(kBlock), 0, s, a, out);
+  unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
+  // 0.0 and +inf
+  launch_fill_int(reinterpret_cast<int*>(o), 0, 3, s);
+  launch_fill_int(reinterpret_cast<int*>(o) + 3, 0x7ff00000, 1, s);
+  int blocks = (a.n + kBlock - 1) / kBlock;
+  blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
+  hipLaunchKernelGGL(k_pol_extents, dim3(blocks), dim3(kBlock), 0, s, a, o);
 }
 
 // ------------------------------------------------------------ neighbour lists
