@@ -183,6 +183,38 @@ def test_mixed_precision_bounds(name):
     assert mu_rms <= 1e-5
 
 
+def test_mixed_tight_tolerance():
+    """A tolerance far below what FP32 iterations alone reach: the mixed
+    solve gets there by replacing the recurrence residual with the FP64 true
+    residual and continuing the same sequence.  Checked independently: the
+    FP64 operator of a second context, applied to the mixed dipoles, leaves
+    a residual against the mixed context's own field within the tolerance."""
+    from tests.gpu_util import pol_rows
+    d, prm = config_system("box1024")
+    kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"], tol=1e-11, max_iter=400)
+    e32 = engine_for(d, gpu_params(d, precision="mixed", **kw))
+    mu, it, rms = e32.solve()
+    st = e32.stats()
+    E0 = e32.permanent_field().cpu().numpy()
+    e32.close()
+    e64 = engine_for(d, gpu_params(d, precision="fp64", **kw))
+    it64 = e64.solve()[1]
+    Tmu = e64.apply_T(mu).cpu().numpy()
+    e64.close()
+    rows = pol_rows(d)
+    r = (E0 - Tmu)[rows]
+    a = d["alpha"][rows]
+    A = np.stack([np.stack([a[:, 0], a[:, 1], a[:, 2]], 1), np.stack([a[:, 1], a[:, 3], a[:, 4]], 1),
+                  np.stack([a[:, 2], a[:, 4], a[:, 5]], 1)], 1)
+    z = np.einsum("nij,nj->ni", A, r)
+    rho = DEBYE * np.sqrt(np.mean(np.sum(z * z, 1)))
+    say(f"  tol 1e-11: mixed {it} iterations ({st['restarts']} replacements; fp64 {it64}), "
+        f"reported rms {rms:.2e} D, recomputed {rho:.2e} D")
+    assert rms <= 1e-11 and st["restarts"] >= 1
+    assert rho <= 2e-11
+    assert it <= it64 + 4
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_bitwise_reproducible(precision):
     """Cell sort, brick lists, spreading, FFT, solver reductions and forces

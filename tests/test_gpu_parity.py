@@ -108,6 +108,18 @@ def test_multipass_fft_matches_plane_fft(monkeypatch):
     _compare_full(d, kw, "box27-multipass")
 
 
+@pytest.mark.parametrize("scale", [0.05, 3.0])
+def test_damping_split_extremes(scale):
+    """The all-pairs rows are split at the radius beyond which no
+    polarizable pair is Thole-damped (x >= 50), set from the largest mean
+    polarizability.  Small polarizabilities put that radius below most pair
+    distances (nearly every pair far), large ones beyond the cutoff (every
+    pair near); both must still meet the oracle."""
+    d = water_box(27, 9.5, 11)
+    d = dict(d, alpha=d["alpha"] * scale)
+    _compare_full(d, dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-10), f"box27-alpha*{scale}")
+
+
 @pytest.mark.slow
 def test_box216_parity():
     d, prm = config_system("box216")
