@@ -7,7 +7,8 @@
 //   k_cl_solve : block-Jacobi PCG for T mu = E (Eq. 18) held entirely in
 //                the workgroup -- the direction vector lives in LDS, dot
 //                products are LDS reductions, and the FP64 true residual
-//                with restarts is evaluated in the same launch -- then
+//                (replacing the recurrence residual, as in the context
+//                solver) is evaluated in the same launch -- then
 //                E_pol = -1/2 mu.E (Eq. 19);
 //   k_cl_force : forces at the converged mu through the combined-density
 //                identity of the periodic force kernel with the bare kernel.
@@ -355,9 +356,24 @@ __global__ __launch_bounds__(kClBlock) void k_cl_solve(ClusterArgs a) {
     const double zz_stop = (tol / kDebye) * (tol / kDebye) * np;
     int it = 0, restarts = 0, status = 0;
     double rho = 0.0;
-    double zr[kClOwn][3];
+    double rz_run = 0.0;            // r.z of the running sequence
+    double zz_replace = -1.0;       // see the context solver: one early
+    bool fresh = true;              // residual replacement in mixed mode
+    double zr[kClOwn][3], ps[kClOwn][3];
     for (;;) {
-      // true residual r = E - T x in FP64; z = alpha r; p = z
+      // true residual r = E - T x in FP64, z = alpha r; the running search
+      // directions of this slot's sites are kept while lv holds x
+      if (!fresh) {
+#pragma unroll
+        for (int kk = 0; kk < kClOwn; ++kk) {
+          const int k = slot + kk * nslot;
+          if (k < np && lane == 0) {
+            const double4 pv = lv[k];
+            ps[kk][0] = pv.x; ps[kk][1] = pv.y; ps[kk][2] = pv.z;
+          }
+        }
+      }
+      __syncthreads();
       for (int k = t; k < np; k += kClBlock) lv[k] = a.X[base + k];
       __syncthreads();
       double zz = 0.0, rz = 0.0, d = 0.0;
@@ -392,12 +408,26 @@ __global__ __launch_bounds__(kClBlock) void k_cl_solve(ClusterArgs a) {
         status = (int)SIBFA_E_NOT_CONVERGED;
         break;
       }
-      if (it > 0) ++restarts;
+      // a new sequence (p = z) at the start; afterwards the true residual
+      // replaces the recurrence one and the sequence goes on (p = z + beta p)
+      const double beta0 = fresh ? 0.0 : rz / rz_run;
+      if (fresh) {
+        if (sizeof(R) == 4) zz_replace = 1e-8 * zz;
+      } else {
+        ++restarts;
+      }
 #pragma unroll
       for (int kk = 0; kk < kClOwn; ++kk) {
         const int k = slot + kk * nslot;
-        if (k < np && lane == 0) lv[k] = make_double4(zr[kk][0], zr[kk][1], zr[kk][2], 0.0);
+        if (k < np && lane == 0) {
+          const double b0 = fresh ? 0.0 : beta0;
+          const double q0 = fresh ? 0.0 : ps[kk][0], q1 = fresh ? 0.0 : ps[kk][1],
+                       q2 = fresh ? 0.0 : ps[kk][2];
+          lv[k] = make_double4(zr[kk][0] + b0 * q0, zr[kk][1] + b0 * q1, zr[kk][2] + b0 * q2, 0.0);
+        }
       }
+      fresh = false;
+      rz_run = rz;
       __syncthreads();
       while (it < a.max_iter) {
         double pq = 0.0, d1 = 0.0, d2 = 0.0;
@@ -424,7 +454,7 @@ __global__ __launch_bounds__(kClBlock) void k_cl_solve(ClusterArgs a) {
           status = (int)SIBFA_E_NOT_SPD;
           break;
         }
-        const double gamma = rz / pq;
+        const double gamma = rz_run / pq;
         double zz2 = 0.0, rz2 = 0.0, d3 = 0.0;
 #pragma unroll
         for (int kk = 0; kk < kClOwn; ++kk) {
@@ -455,8 +485,12 @@ __global__ __launch_bounds__(kClBlock) void k_cl_solve(ClusterArgs a) {
         bsum(zz2, rz2, d3);
         ++it;
         if (zz2 <= zz_stop) break;
-        const double beta = rz2 / rz;
-        rz = rz2;
+        if (zz2 <= zz_replace) {
+          zz_replace = -1.0;
+          break;
+        }
+        const double beta = rz2 / rz_run;
+        rz_run = rz2;
 #pragma unroll
         for (int kk = 0; kk < kClOwn; ++kk) {
           const int k = slot + kk * nslot;
