@@ -688,7 +688,8 @@ sibfa_status ensure_coef(sibfa_ctx c) {
 }
 
 // t = T v.  mix: FP32 pair/PME arithmetic (cached FP32 coefficients);
-// otherwise FP64 (cached FP64 coefficients, kept in both modes).
+// otherwise FP64 (cached FP64 coefficients, kept in both modes).  Callers
+// run ensure_coef first.
 void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
   SysView s = make_view(c);
   if (c->periodic) {
@@ -700,10 +701,9 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     Phase ph(c, SIBFA_PH_FFT, c->aux);
     conv(c, mix, c->aux);
   }
-  const bool coef = c->coef_valid;
   {
     Phase ph2(c, SIBFA_PH_MATVEC);
-    launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, coef, c->stream);
+    launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->stream);
   }
   if (c->periodic) join(c);
   Phase ph3(c, SIBFA_PH_MATVEC_RECIP);
@@ -843,7 +843,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         }
         {
           Phase ph(c, SIBFA_PH_MATVEC);
-          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->coef_valid, st);
+          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
         }
         if (c->periodic) join(c);
         {

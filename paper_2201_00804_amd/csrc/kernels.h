@@ -6,11 +6,11 @@ namespace sibfa {
 
 // pair.hip
 void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStream_t st);
-// T p in two kernels: real space (coef: read the cached pair coefficients)
-// and, for periodic systems, the PME field gather with p.Tp.  The dot
-// product's partials come from the last of the two.
+// T p in two kernels: real space (reads the cached pair coefficients, which
+// must be current) and, for periodic systems, the PME field gather with
+// p.Tp.  The dot product's partials come from the last of the two.
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
-                        double4* out, int dot_slot, bool mixed, bool coef, hipStream_t st);
+                        double4* out, int dot_slot, bool mixed, hipStream_t st);
 void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
                          double4* out, int dot_slot, bool mixed, hipStream_t st);
 // cache the pol-list pair coefficients: FP64 into out, or FP32 into out32

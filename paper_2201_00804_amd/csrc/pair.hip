@@ -308,27 +308,18 @@ __device__ __forceinline__ void load_coef<float>(const SysView& s, size_t e, flo
   c1 = c.x; c2 = c.y;
 }
 
-// One intermolecular pol pair of the matvec: field at i of the dipole p_j.
-template <typename R, bool COEF>
+// One intermolecular pol pair of the matvec: field at i of the dipole p_j,
+// with the cached coefficients of the entry.
+template <typename R>
 __device__ __forceinline__ void matvec_pair(const SysView& s, const double4* p, const float4* p32,
-                                            int pi, size_t e, const R xr[3], R sr, double f[3]) {
+                                            size_t e, const R xr[3], double f[3]) {
   const int j = __builtin_nontemporal_load(&s.nb_pol[e]);
   R xj[3], sj, Rv[3], pj[3];
   load_pp<R>(s, j, xj, sj);
   load_p<R>(p, p32, j, pj);
   R c1, c2;
-  if (COEF) load_coef<R>(s, e, c1, c2);
+  load_coef<R>(s, e, c1, c2);
   displacement<R>(s, xr, xj, Rv);
-  if (!COEF) {
-    const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-    const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-    R Eb[3], c0[3], tp[5];
-    base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
-    bare_coeffs<R, 2>(rinv, rinv2, c0);
-    thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
-    c1 = Eb[1] - tp[1] * c0[1];
-    c2 = Eb[2] - tp[2] * c0[2];
-  }
   R E[3];
   dip_field<R>(c1, c2, pj, Rv, E);
   f[0] += (double)E[0]; f[1] += (double)E[1]; f[2] += (double)E[2];
@@ -336,8 +327,9 @@ __device__ __forceinline__ void matvec_pair(const SysView& s, const double4* p, 
 
 // Real-space part of (T p)_i = alpha_i^-1 p_i - [real field + self field]
 // (minus the reciprocal field, subtracted by k_matvec_recip when periodic;
-// clusters finish here, with p.Tp).
-template <typename R, int G, bool COEF>
+// clusters finish here, with p.Tp).  Needs the cached coefficients of the
+// current positions (k_pol_coef).
+template <typename R, int G>
 __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const double4* p,
                                                    const float4* p32, double4* out,
                                                    int dot_slot) {
@@ -357,20 +349,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const 
       load_pp<double>(s, j, xj, sj);
       load_p<double>(p, p32, j, pj);
       displacement<double>(s, xi, xj, Rv);
-      double c1, c2;
-      if (COEF) {
-        const double2 cc = s.cipol[e];
-        c1 = cc.x; c2 = cc.y;
-      } else {
-        const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-        const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-        double Eb[3], c0[3], tp[5];
-        base_coeffs<double, 2>(s, r, rinv, rinv2, Eb);
-        bare_coeffs<double, 2>(rinv, rinv2, c0);
-        thole_tp<double>(thole_a_polpair(s, pi, j) * r2 * r * si * sj, tp);
-        c1 = Eb[1] - tp[1] * c0[1];
-        c2 = Eb[2] - tp[2] * c0[2];
-      }
+      const double2 cc = s.cipol[e];
+      const double c1 = cc.x, c2 = cc.y;
       double E[3];
       dip_field<double>(c1, c2, pj, Rv, E);
       f[0] += E[0]; f[1] += E[1]; f[2] += E[2];
@@ -383,12 +363,12 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const 
     const size_t row = (size_t)pi * s.cap_pol;
     int k = sub;
     for (; k + 3 * G < cnt; k += 4 * G) {
-      matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
-      matvec_pair<R, COEF>(s, p, p32, pi, row + k + G, xr, sr, f);
-      matvec_pair<R, COEF>(s, p, p32, pi, row + k + 2 * G, xr, sr, f);
-      matvec_pair<R, COEF>(s, p, p32, pi, row + k + 3 * G, xr, sr, f);
+      matvec_pair<R>(s, p, p32, row + k, xr, f);
+      matvec_pair<R>(s, p, p32, row + k + G, xr, f);
+      matvec_pair<R>(s, p, p32, row + k + 2 * G, xr, f);
+      matvec_pair<R>(s, p, p32, row + k + 3 * G, xr, f);
     }
-    for (; k < cnt; k += G) matvec_pair<R, COEF>(s, p, p32, pi, row + k, xr, sr, f);
+    for (; k < cnt; k += G) matvec_pair<R>(s, p, p32, row + k, xr, f);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
@@ -645,16 +625,11 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
 }
 
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
-                        double4* out, int dot_slot, bool mixed, bool coef, hipStream_t st) {
+                        double4* out, int dot_slot, bool mixed, hipStream_t st) {
   if (s.npol <= 0) return;
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (mixed) {
-    if (coef) hipLaunchKernelGGL((k_matvec<float, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-    else hipLaunchKernelGGL((k_matvec<float, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-  } else {
-    if (coef) hipLaunchKernelGGL((k_matvec<double, kG, true>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-    else hipLaunchKernelGGL((k_matvec<double, kG, false>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-  }
+  if (mixed) hipLaunchKernelGGL((k_matvec<float, kG>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+  else hipLaunchKernelGGL((k_matvec<double, kG>), g, b, 0, st, s, red, p, p32, out, dot_slot);
   if (!s.periodic && dot_slot >= 0) red.nparts[dot_slot] = (int)g.x;
 }
 

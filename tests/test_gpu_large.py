@@ -91,6 +91,13 @@ def test_box32000_sampled():
     _sampled_parity("box32000", 16)
 
 
+@pytest.mark.slow
+def test_box96000_sampled():
+    """The largest workload: 480,000 sites, a 144^3 grid (the five-pass FFT
+    path: its planes do not fit a workgroup's LDS)."""
+    _sampled_parity("box96000", 8)
+
+
 def test_fd_forces_on_gpu_energy():
     """-(E(x+h) - E(x-h))/2h of the GPU's total energy against its forces,
     at a few sites of a 1,024-water box (cold solve to 1e-11 D each time)."""
@@ -153,7 +160,8 @@ def test_warm_start_and_position_update_match_fresh():
     fresh.close()
 
 
-@pytest.mark.parametrize("name", ["box216", "box4096"])
+@pytest.mark.parametrize("name", ["box216", "box4096",
+                                  pytest.param("box96000", marks=pytest.mark.slow)])
 def test_mixed_precision_bounds(name):
     """FP32 pair/PME arithmetic with FP64 accumulation, reductions and true
     residual: the solve still meets the FP64 tolerance against the FP64
