@@ -98,8 +98,9 @@ struct sibfa_ctx_s {
   DevBuf nbbuf[4];
   // [0..3] list maxima, [4] binning errors (bits 2, 8), [5] list errors
   // (bit 1), [6] finiteness flag, [7] polarizability errors (bit 4),
-  // [8..11] solver stop flag, [16..31] eight slot totals (doubles),
-  // [32..35] polarizability extents (doubles)
+  // [8..11] solver stop flag, [12..13] z.z of the last test (double),
+  // [16..31] eight slot totals (doubles), [32..35] polarizability extents
+  // (doubles)
   int* dints = nullptr;
   // solver vectors (pol order)
   double4 *E0 = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
@@ -779,9 +780,18 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   int it = 0, restarts = 0;
   int kk = 0;            // iterations of the running sequence (slot parity)
   bool fresh = true;     // no sequence yet: the first true residual sets p = z
+  bool read_res = true;  // read the new true residual back (not after the
+                         // early replacement, which is far from converged)
   double zz_replace = -1.0;
   double rho_true = 0.0;
+  // Batch sizing: z.z of the last update read back with the stop flag and
+  // its decay per iteration, to size the next batch so that it ends about
+  // where the run will stop (fewer launches that return at once, fewer
+  // host round trips).
+  double zz_last = -1.0, rate = -1.0;
   sibfa_status result = SIBFA_OK;
+  int* flag = c->dints + 8;                                    // [0..3]
+  double* zz_dev = reinterpret_cast<double*>(c->dints + 12);  // after flag
   for (;;) {
     // residual from scratch: FP64 operator, except the very first residual
     // of a cold start in mixed mode (FP32 operator; the early replacement
@@ -793,35 +803,45 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     else
       launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, nullptr, nullptr,
                            S_RZ0 + (kk & 1), st);
-    double zz0 = 0.0;
-    sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
-    if (e != SIBFA_OK) return e;
-    rho_true = rms_debye(c, zz0);
-    if (rho_true <= tol) {
-      if (!fp32_res) break;
-      fresh = false;   // confirm with the FP64 operator
-      continue;
+    if (read_res) {
+      double zz0 = 0.0;
+      sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
+      if (e != SIBFA_OK) return e;
+      rho_true = rms_debye(c, zz0);
+      zz_last = zz0;
+      if (rho_true <= tol) {
+        if (!fp32_res) break;
+        fresh = false;   // confirm with the FP64 operator
+        continue;
+      }
     }
+    read_res = true;
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
     if (fresh) {
-      if (mix) zz_replace = kReplace * zz0;
+      if (mix) zz_replace = kReplace * zz_last;
     } else {
       ++restarts;
     }
     fresh = false;
-    // Iterations are enqueued in batches; after each update a one-block
-    // kernel tests z.z and p.Tp on the device and raises a stop flag that
-    // makes the remaining enqueued kernels return at once, so the host reads
-    // the flag once per batch instead of synchronising every iteration.
-    int* flag = c->dints + 8;
+    // Iterations are enqueued in batches; a stop test after each update
+    // (folded into the next direction update, or a one-block kernel at the
+    // end of a batch) raises a flag in device memory that makes the
+    // remaining enqueued kernels return at once, so the host reads the flag
+    // once per batch instead of synchronising every iteration.
     launch_fill_int(flag, 0, 4, st);
     c->red.stop = flag;
     c->pm.stop = flag;
-    const int kBatch = 4;
     int j = 0, j_done = 0, reason = 0;   // iterations of this run
     for (;;) {
       if (c->prof && c->marks.size() > 4096) fold_marks(c);
-      for (int b = 0; b < kBatch && it + j < c->prm.max_iter; ++b) {
+      int nb = 4;
+      if (rate > 0.0 && rate < 1.0 && zz_last > 0.0) {
+        const double target = zz_replace > zz_stop ? zz_replace : zz_stop;
+        const double est = std::ceil(std::log(target / zz_last) / std::log(rate));
+        nb = est < 1.0 ? 1 : (est > 8.0 ? 8 : (int)est);
+      }
+      const int j0 = j;
+      for (int b = 0; b < nb && it + j < c->prm.max_iter; ++b) {
         const int k = kk + j;
         c->cur_tag = j;
         if (k > 0) {
@@ -832,20 +852,24 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           launch_direction(s, c->red, num, den, c->z, c->p, c->p32, b > 0 ? flag : nullptr, j,
                            zz_stop, zz_replace, st);
         }
-        if (c->periodic) {
-          fork(c);
-          {
-            Phase ph(c, SIBFA_PH_SPREAD, c->aux);
-            launch_spread_dip(s, c->pm, c->p, mix, c->aux);
-          }
-          Phase ph(c, SIBFA_PH_FFT, c->aux);
-          conv(c, mix, c->aux);
-        }
+        // the real-space matvec is enqueued first (at the start of a batch
+        // the host is behind the device), the reciprocal chain beside it
+        if (c->periodic) fork(c);
         {
           Phase ph(c, SIBFA_PH_MATVEC);
           launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
         }
-        if (c->periodic) join(c);
+        if (c->periodic) {
+          {
+            Phase ph(c, SIBFA_PH_SPREAD, c->aux);
+            launch_spread_dip(s, c->pm, c->p, mix, c->aux);
+          }
+          {
+            Phase ph(c, SIBFA_PH_FFT, c->aux);
+            conv(c, mix, c->aux);
+          }
+          join(c);
+        }
         {
           Phase ph(c, SIBFA_PH_MATVEC_RECIP);
           launch_matvec_recip(s, c->pm, c->red, c->p, c->q, S_PQ, mix, st);
@@ -856,20 +880,27 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
                         c->q, st);
           // the last iteration of a batch is tested here, the others by
           // the next direction update
-          if (b == kBatch - 1 || it + j + 1 >= c->prm.max_iter)
-            launch_check(c->red, flag, j + 1, zz_stop, zz_replace, st);
+          if (b == nb - 1 || it + j + 1 >= c->prm.max_iter)
+            launch_check(c->red, flag, zz_dev, j + 1, zz_stop, zz_replace, st);
         }
         ++j;
       }
       c->cur_tag = -1;
-      HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-      e = sync_read(c);
+      HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int) + sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+      sibfa_status e = sync_read(c);
       if (e != SIBFA_OK) {
         c->red.stop = nullptr;
         c->pm.stop = nullptr;
         return e;
       }
-      if (c->h_ints[8]) {
+      const int stop = c->h_ints[8];
+      const int ran = stop ? c->h_ints[10] - j0 : j - j0;   // iterations this batch
+      double zz_now;
+      std::memcpy(&zz_now, c->h_ints + 12, sizeof(double));
+      if (ran > 0 && zz_last > 0.0 && zz_now > 0.0) rate = std::pow(zz_now / zz_last, 1.0 / ran);
+      zz_last = zz_now;
+      if (stop) {
         j_done = c->h_ints[10];
         reason = c->h_ints[9];
         for (auto& m : c->marks)
@@ -887,7 +918,10 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     c->pm.stop = nullptr;
     it += j_done;
     kk += j_done;
-    if (reason == 3) zz_replace = -1.0;
+    if (reason == 3) {
+      zz_replace = -1.0;
+      read_res = false;
+    }
     if (reason == 2) result = SIBFA_E_NOT_SPD;
     if (result == SIBFA_E_NOT_SPD) break;
     launch_copy4(c->x, c->x, c->x32, c->npol, st);

@@ -71,8 +71,8 @@ struct SlotList {
 };
 void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipStream_t st);
 // device-side convergence test (see k_check)
-void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, double zz_replace,
-                  hipStream_t st);
+void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
+                  double zz_replace, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st);

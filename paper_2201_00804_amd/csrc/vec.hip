@@ -132,8 +132,12 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
 // one; a negative value never triggers).
 // flag: [0] stop, [1] reason (1 converged, 2 not SPD, 3 replace),
 // [2] iterations done.
-__global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, int iter, double zz_stop,
-                                                  double zz_replace) {
+__global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, double* zz_out, int iter,
+                                                  double zz_stop, double zz_replace) {
+  // z.z of the last update that ran (kernels after a stop leave the
+  // partials alone), for the host's batch sizing
+  const double zz = slot_total(red, S_ZZ);
+  if (threadIdx.x == 0) *zz_out = zz;
   if (flag[0]) return;
   (void)check_stop(red, flag, iter, zz_stop, zz_replace);
 }
@@ -252,9 +256,9 @@ void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(kBlock), 0, st, v, n, flag);
 }
 
-void launch_check(const Reduce& red, int* flag, int iter, double zz_stop, double zz_replace,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, iter, zz_stop,
+void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
+                  double zz_replace, hipStream_t st) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, zz_out, iter, zz_stop,
                      zz_replace);
 }
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
