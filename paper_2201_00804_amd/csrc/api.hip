@@ -694,19 +694,26 @@ sibfa_status ensure_coef(sibfa_ctx c) {
 void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
   SysView s = make_view(c);
   if (c->periodic) {
+    // as in the solver loop: reciprocal chain on the main stream, the
+    // real-space part beside it
     fork(c);
     {
-      Phase ph(c, SIBFA_PH_SPREAD, c->aux);
-      launch_spread_dip(s, c->pm, v, mix, c->aux);
+      Phase ph2(c, SIBFA_PH_MATVEC, c->aux);
+      launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->aux);
     }
-    Phase ph(c, SIBFA_PH_FFT, c->aux);
-    conv(c, mix, c->aux);
-  }
-  {
+    {
+      Phase ph(c, SIBFA_PH_SPREAD);
+      launch_spread_dip(s, c->pm, v, mix, c->stream);
+    }
+    {
+      Phase ph(c, SIBFA_PH_FFT);
+      conv(c, mix, c->stream);
+    }
+    join(c);
+  } else {
     Phase ph2(c, SIBFA_PH_MATVEC);
     launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->stream);
   }
-  if (c->periodic) join(c);
   Phase ph3(c, SIBFA_PH_MATVEC_RECIP);
   launch_matvec_recip(s, c->pm, c->red, v, out, dot_slot, mix, c->stream);
 }
@@ -852,23 +859,27 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           launch_direction(s, c->red, num, den, c->z, c->p, c->p32, b > 0 ? flag : nullptr, j,
                            zz_stop, zz_replace, st);
         }
-        // the real-space matvec is enqueued first (at the start of a batch
-        // the host is behind the device), the reciprocal chain beside it
-        if (c->periodic) fork(c);
-        {
-          Phase ph(c, SIBFA_PH_MATVEC);
-          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
-        }
+        // the reciprocal chain (the critical path) on the main stream, the
+        // real-space matvec beside it on the auxiliary stream: both stream
+        // events then fall off the critical path
         if (c->periodic) {
+          fork(c);
           {
-            Phase ph(c, SIBFA_PH_SPREAD, c->aux);
-            launch_spread_dip(s, c->pm, c->p, mix, c->aux);
+            Phase ph(c, SIBFA_PH_MATVEC, c->aux);
+            launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->aux);
           }
           {
-            Phase ph(c, SIBFA_PH_FFT, c->aux);
-            conv(c, mix, c->aux);
+            Phase ph(c, SIBFA_PH_SPREAD);
+            launch_spread_dip(s, c->pm, c->p, mix, st);
+          }
+          {
+            Phase ph(c, SIBFA_PH_FFT);
+            conv(c, mix, st);
           }
           join(c);
+        } else {
+          Phase ph(c, SIBFA_PH_MATVEC);
+          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
         }
         {
           Phase ph(c, SIBFA_PH_MATVEC_RECIP);
@@ -1113,8 +1124,13 @@ sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream, sibfa_al
   if (ov && std::atoi(ov) == 0) {
     c->aux = c->stream;
   } else if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+             // the events order the two streams of one device only: no
+             // system-scope fence (kernel boundaries already make device
+             // memory coherent across the device)
+             hipEventCreateWithFlags(&c->ev_fork,
+                                     hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_join,
+                                     hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
     sibfa_destroy(c);
     return SIBFA_E_DEVICE;
   }
