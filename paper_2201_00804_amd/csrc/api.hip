@@ -431,7 +431,11 @@ sibfa_status binning_errors(sibfa_ctx c) {
 sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
   for (int k = 0; k < 4; ++k) {
     const int rows = (k < 2) ? c->n : std::max(c->npol, 1);
-    if (c->nb[k] && c->cap[k] >= want[k]) continue;
+    // the row count of lists 2 and 3 follows the number of polarizable
+    // sites, which a change of polarizabilities may raise: check the bytes
+    if (c->nb[k] && c->cap[k] >= want[k] &&
+        c->nbbuf[k].bytes >= (size_t)rows * c->cap[k] * sizeof(int))
+      continue;
     dev_free(c, c->nbbuf[k].p);
     const size_t bytes = (size_t)rows * want[k] * sizeof(int);
     void* ptr = dev_alloc(c, bytes);

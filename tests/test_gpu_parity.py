@@ -148,3 +148,31 @@ def test_neighbor_counts_exact(name):
     ref = _kdtree_counts(d, prm["cutoff"])
     assert np.array_equal(got, ref)
     eng.close()
+
+
+def test_polarizable_count_changes_on_a_live_context():
+    """set_polarizabilities may change which sites are polarizable: the
+    polarizable-pair lists (whose row counts follow that number) are
+    re-sized, and the results equal those of a fresh context."""
+    d = water_box(27, 9.5, 13)
+    kw = dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-10)
+    few = d["alpha"].copy()
+    few[np.arange(len(few)) % 5 != 0] = 0.0      # only the O sites
+    iso = np.zeros_like(d["alpha"])
+    iso[:, [0, 3, 5]] = 0.6                        # every site, isotropic
+    eng = engine_for(dict(d, alpha=few), gpu_params(d, **kw))
+    eng.solve()
+    for alpha in (iso, few, iso):
+        eng.set_polarizabilities(torch.as_tensor(alpha, device="cuda"))
+        mu, it, _ = eng.solve()
+        ep, ee, F = eng.energy_forces()
+        ref = engine_for(dict(d, alpha=alpha), gpu_params(d, **kw))
+        mu_r, it_r, _ = ref.solve()
+        ep_r, ee_r, F_r = ref.energy_forces()
+        say(f"  npol {int(np.count_nonzero(alpha.any(1)))}: iters {it}/{it_r}")
+        assert it == it_r
+        assert torch.equal(mu, mu_r)
+        assert ep == ep_r and ee == ee_r
+        assert torch.equal(F, F_r)
+        ref.close()
+    eng.close()
