@@ -199,6 +199,28 @@ __device__ __forceinline__ int xcd_block() {
   const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
   return x * per + (x < extra ? x : extra) + b / kXcd;
 }
+// For every active lane, adds 1 to base[key], with one atomic per distinct
+// key of the wavefront (sorted or clustered keys make that a few atomics
+// instead of one per lane on the same address); returns the lane's slot,
+// the counter's old value plus the number of lower active lanes with the
+// same key.  Every lane of the wavefront must call it.
+__device__ __forceinline__ int wave_atomic_inc(int* base, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long todo = __ballot(active);
+  int slot = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int k = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(active && key == k);
+    int old = 0;
+    if (lane == leader) old = atomicAdd(&base[k], __popcll(same));
+    old = __shfl(old, leader, 64);
+    if (active && key == k) slot = old + __popcll(same & below);
+    todo &= ~same;
+  }
+  return slot;
+}
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

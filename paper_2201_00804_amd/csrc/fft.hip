@@ -393,13 +393,16 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r(PmeView pm, int nl) {
 // as X + iY into one complex line, inverse, real and imaginary parts ->
 // rows y and y + 1 of phi.  The imaginary parts of the kx = 0 and kx = K0/2
 // entries are dropped, as a real inverse does.
-constexpr int kPlaneThreads = 1024;
+// 512 threads (two waves per SIMD): small enough that a plane workgroup
+// finds room on a CU beside the waves of the real-space matvec, which runs
+// on the other stream at the same time (1024-thread planes waited for the
+// matvec to drain; 256 threads leave the plane itself too slow).
+constexpr int kPlaneThreads = 512;
 
-template <typename T>
-__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_fwd(PmeView pm) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fft_plane_fwd(PmeView pm) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  constexpr int NT = kPlaneThreads;
   const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
   const int rs = K0 + 1, cs = K1 + 1;           // row and column strides
   const int bufsz = max((K1 / 2) * rs, h * cs);
@@ -434,11 +437,10 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_fwd(PmeView pm) {
   for2d<NT>(K1, h, [&](int y, int k) { C[y * h + k] = res[k * cs + y]; });
 }
 
-template <typename T>
-__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_inv(PmeView pm) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fft_plane_inv(PmeView pm) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
-  constexpr int NT = kPlaneThreads;
   const int K0 = pm.K[0], K1 = pm.K[1], h = pm.kxh, z = blockIdx.x;
   const int rs = K0 + 1, cs = K1 + 1;
   const int bufsz = max((K1 / 2) * rs, h * cs);
@@ -521,17 +523,17 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
   if (lds) {
     static bool attr = false;   // raise the dynamic LDS limit once per kernel
     if (!attr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<T>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<T, kPlaneThreads>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<T>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<T, kPlaneThreads>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);
       attr = true;
     }
     launch_spread_fold(pm, mixed, st);
-    hipLaunchKernelGGL(k_fft_plane_fwd<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
+    hipLaunchKernelGGL((k_fft_plane_fwd<T, kPlaneThreads>), dim3(K2), dim3(kPlaneThreads), lds, st, pm);
     red.nparts[pm.erec_slot] = K1 * nkbz;
     hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
-    hipLaunchKernelGGL(k_fft_plane_inv<T>, dim3(K2), dim3(kPlaneThreads), lds, st, pm);
+    hipLaunchKernelGGL((k_fft_plane_inv<T, kPlaneThreads>), dim3(K2), dim3(kPlaneThreads), lds, st, pm);
     return;
   }
   launch_spread_fold(pm, mixed, st);

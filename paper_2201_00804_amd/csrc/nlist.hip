@@ -109,35 +109,42 @@ __device__ __forceinline__ double wrap(double x, double L, double iL) {
   return (w >= L) ? w - L : w;
 }
 
+// Neighbouring caller indices are usually neighbouring sites (a molecule's
+// sites, molecules laid out in space order), so the counters are
+// incremented per wavefront run of equal keys.
 __global__ void k_bin(BinArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n) return;
-  int cell = 0;
-  const double x0 = a.xyz[3 * c], x1 = a.xyz[3 * c + 1], x2 = a.xyz[3 * c + 2];
-  if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(a.err, 8);
-  if (a.periodic) {
-    int ci[3];
-    for (int d = 0; d < 3; ++d) {
-      double w = wrap(a.xyz[3 * c + d], a.box[d], a.ibox[d]);
-      int k = (int)(w * a.nc[d] * a.ibox[d]);
-      ci[d] = k >= a.nc[d] ? a.nc[d] - 1 : (k < 0 ? 0 : k);
+  const bool act = c < a.n;
+  int cell = 0, m = -1;
+  if (act) {
+    const double x0 = a.xyz[3 * c], x1 = a.xyz[3 * c + 1], x2 = a.xyz[3 * c + 2];
+    if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(a.err, 8);
+    if (a.periodic) {
+      int ci[3];
+      for (int d = 0; d < 3; ++d) {
+        double w = wrap(a.xyz[3 * c + d], a.box[d], a.ibox[d]);
+        int k = (int)(w * a.nc[d] * a.ibox[d]);
+        ci[d] = k >= a.nc[d] ? a.nc[d] - 1 : (k < 0 ? 0 : k);
+      }
+      cell = ci[0] + a.nc[0] * (ci[1] + a.nc[1] * ci[2]);
     }
-    cell = ci[0] + a.nc[0] * (ci[1] + a.nc[1] * ci[2]);
+    a.cell_of[c] = cell;
+    m = a.mol[c];
+    if (!(m >= 0 && m < a.n)) atomicOr(a.err, 2);
   }
-  a.cell_of[c] = cell;
-  atomicAdd(&a.cell_count[cell], 1);
-  const int m = a.mol[c];
-  if (m >= 0 && m < a.n) atomicAdd(&a.mol_count[m], 1);
-  else atomicOr(a.err, 2);
+  wave_atomic_inc(a.cell_count, cell, act);
+  wave_atomic_inc(a.mol_count, m, act && m >= 0 && m < a.n);
 }
 
+// Slots within a key come from wavefront runs and one atomic per run; their
+// order across wavefronts is fixed afterwards by k_sort_cells.
 __global__ void k_scatter(const int* cell_of, const int* cell_start, int* cursor,
                           int* perm, int n) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int cell = cell_of[c];
-  const int slot = atomicAdd(&cursor[cell], 1);
-  perm[cell_start[cell] + slot] = c;
+  const bool act = c < n;
+  const int cell = act ? cell_of[c] : 0;
+  const int slot = wave_atomic_inc(cursor, cell, act);
+  if (act) perm[cell_start[cell] + slot] = c;
 }
 
 // One thread per cell: insertion sort of the cell's segment by caller index.

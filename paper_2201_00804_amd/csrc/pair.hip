@@ -281,11 +281,18 @@ __global__ __launch_bounds__(kBlock) void k_pol_coef(SysView s, double2* out, fl
     displacement<R>(s, xr, xj, Rv);
     const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
     const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-    R Eb[3], c0[3], tp[5];
+    R Eb[3];
     base_coeffs<R, 2>(s, r, rinv, rinv2, Eb);
-    bare_coeffs<R, 2>(rinv, rinv2, c0);
-    thole_tp<R>(R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj, tp);
-    const R c1 = Eb[1] - tp[1] * c0[1], c2 = Eb[2] - tp[2] * c0[2];
+    R c1 = Eb[1], c2 = Eb[2];
+    // damping only where it is not negligible (x < 50, as in k_perm)
+    const R x = R(thole_a_polpair(s, pi, j)) * r2 * r * sr * sj;
+    if (x < R(50)) {
+      R c0[3], tp[5];
+      bare_coeffs<R, 2>(rinv, rinv2, c0);
+      thole_tp<R>(x, tp);
+      c1 -= tp[1] * c0[1];
+      c2 -= tp[2] * c0[2];
+    }
     if (out) out[e] = make_double2((double)c1, (double)c2);
     if (out32) out32[e] = make_float2((float)c1, (float)c2);
   }

@@ -54,22 +54,27 @@ __device__ __forceinline__ void site_splines(const PmeView& pm, double x, double
 //                  k_spread_fold writes the real grid Q the convolution
 //                  starts from.
 
+// Sites come in cell-sorted order, so a wavefront's sites fall in a few
+// bricks: one counter atomic per run of equal bricks.
 __global__ void k_brick_bin(SysView s, PmeView pm, int pol, int* brick_of, int* counts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = pol ? s.npol : s.n;
-  if (i >= n) return;
-  double x[3];
-  if (pol) { const double4 p = s.pp[i]; x[0] = p.x; x[1] = p.y; x[2] = p.z; }
-  else { const double4 p = s.sp[i]; x[0] = p.x; x[1] = p.y; x[2] = p.z; }
-  int h[3];
+  const bool act = i < n;
+  int b = 0;
+  if (act) {
+    double x[3];
+    if (pol) { const double4 p = s.pp[i]; x[0] = p.x; x[1] = p.y; x[2] = p.z; }
+    else { const double4 p = s.sp[i]; x[0] = p.x; x[1] = p.y; x[2] = p.z; }
+    int h[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double fr;
-    h[a] = grid_base(x[a], pm.scale[a], pm.K[a], &fr) / pm.Bb[a];
+    for (int a = 0; a < 3; ++a) {
+      double fr;
+      h[a] = grid_base(x[a], pm.scale[a], pm.K[a], &fr) / pm.Bb[a];
+    }
+    b = h[0] + pm.nb[0] * (h[1] + pm.nb[1] * h[2]);
+    brick_of[i] = b;
   }
-  const int b = h[0] + pm.nb[0] * (h[1] + pm.nb[1] * h[2]);
-  brick_of[i] = b;
-  atomicAdd(&counts[b], 1);
+  wave_atomic_inc(counts, b, act);
 }
 
 void launch_brick_bin(const SysView& s, const PmeView& pm, int pol, int* brick_of, int* counts,
