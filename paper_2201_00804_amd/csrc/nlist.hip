@@ -539,6 +539,12 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
 //    64 at a time (a lane finds its run by binary search over the run
 //    offsets), so chunks are full;
 //  * polarizable-pair masks come from one ballot per chunk.
+// base + the number of set bits of mask below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)base));
+}
+
 __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
   __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
   __shared__ int moli[kNlIB], poli[kNlIB];
@@ -614,7 +620,10 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
         polj = a.polidx[j];
       }
       const bool pj = valid && polj >= 0;
-      const unsigned long long pjmask = __ballot(pj);
+      const unsigned long long pjmask = __builtin_amdgcn_ballot_w64(pj);
+      // Site t's counts live in lane t: read with readlane (a wave-uniform
+      // base) and updated by lane t; a lane's slot is the base plus
+      // the lower lanes of the ballot (mbcnt).
       for (int t = 0; t < ni; ++t) {
         const double dx = xi[t] - xj, dy = yi[t] - yj, dz = zi[t] - zj;
         const double r2 = dx * dx + dy * dy + dz * dz;
@@ -622,42 +631,48 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
         const int mi = moli[t], pi_ = poli[t];
         const bool same = valid && (molj == mi) && (j != i);
         const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
-        const bool near = r2 < a.rsplit2;
-        const unsigned long long b0 = __ballot(inter);
-        const unsigned long long b1 = __ballot(same);
+        const unsigned long long b0 = __builtin_amdgcn_ballot_w64(inter);
+        const unsigned long long b1 = __builtin_amdgcn_ballot_w64(same);
         if ((b0 | b1) == 0ull) continue;   // no neighbour of site t in this chunk
-        const unsigned long long bn = __ballot(inter && near), bf = b0 & ~bn;
-        const int basen = __shfl(cnt0, t, 64), basef = __shfl(cntf, t, 64);
-        const int base1 = __shfl(cnt1, t, 64);
-        if (inter) {
-          const int k = near ? basen + __popcll(bn & below) : basef + __popcll(bf & below);
-          const int e = near ? k : a.cap_all - 1 - k;
-          if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + e] = j;
+        if (b0) {
+          const bool near = r2 < a.rsplit2;
+          const unsigned long long bn = __builtin_amdgcn_ballot_w64(inter && near), bf = b0 & ~bn;
+          const int basen = __builtin_amdgcn_readlane(cnt0, t);
+          const int basef = __builtin_amdgcn_readlane(cntf, t);
+          if (inter) {
+            const int k = near ? lanes_below(bn, basen) : lanes_below(bf, basef);
+            const int e = near ? k : a.cap_all - 1 - k;
+            if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + e] = j;
+          }
+          if (lane == t) cnt0 = basen + __popcll(bn);
+          if (lane == t) cntf = basef + __popcll(bf);
         }
-        if (same) {
-          const int k = base1 + __popcll(b1 & below);
-          if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
+        if (b1) {
+          const int base1 = __builtin_amdgcn_readlane(cnt1, t);
+          if (same) {
+            const int k = lanes_below(b1, base1);
+            if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
+          }
+          if (lane == t) cnt1 = base1 + __popcll(b1);
         }
         if (pi_ >= 0) {
           const unsigned long long b2 = b0 & pjmask, b3 = b1 & pjmask;
-          const int base2 = __shfl(cnt2, t, 64), base3 = __shfl(cnt3, t, 64);
-          if (inter && pj) {
-            const int k = base2 + __popcll(b2 & below);
-            if (k < a.cap_pol) a.nb_pol[(size_t)pi_ * a.cap_pol + k] = polj;
+          if (b2) {
+            const int base2 = __builtin_amdgcn_readlane(cnt2, t);
+            if (inter && pj) {
+              const int k = lanes_below(b2, base2);
+              if (k < a.cap_pol) a.nb_pol[(size_t)pi_ * a.cap_pol + k] = polj;
+            }
+            if (lane == t) cnt2 = base2 + __popcll(b2);
           }
-          if (same && pj) {
-            const int k = base3 + __popcll(b3 & below);
-            if (k < a.cap_ipol) a.nb_ipol[(size_t)pi_ * a.cap_ipol + k] = polj;
+          if (b3) {
+            const int base3 = __builtin_amdgcn_readlane(cnt3, t);
+            if (same && pj) {
+              const int k = lanes_below(b3, base3);
+              if (k < a.cap_ipol) a.nb_ipol[(size_t)pi_ * a.cap_ipol + k] = polj;
+            }
+            if (lane == t) cnt3 = base3 + __popcll(b3);
           }
-          if (lane == t) {
-            cnt2 += __popcll(b2);
-            cnt3 += __popcll(b3);
-          }
-        }
-        if (lane == t) {
-          cnt0 += __popcll(bn);
-          cntf += __popcll(bf);
-          cnt1 += __popcll(b1);
         }
       }
     }
