@@ -32,7 +32,9 @@
  *    into its own cell-sorted device buffers.  Scalars (energies, iteration
  *    counts, residuals) are HOST pointers.
  *  - Calls that return host scalars synchronize the context's stream;
- *    the others only enqueue work on it.
+ *    the others only enqueue work on it.  sibfa_solve_induced reads its
+ *    scalars at the solver's last stop test and returns with the copy of
+ *    mu_out still enqueued (ordered before later work on the stream).
  *  - Exclusions: a molecule's own sites do not interact through E or
  *    E_elec; induced dipoles of one molecule do couple (Thole-damped).
  *  - Thole damping: lambda_3 = 1 - exp(-a u^3), u = r/(abar_i abar_j)^(1/6),

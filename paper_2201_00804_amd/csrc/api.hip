@@ -1386,8 +1386,12 @@ sibfa_status sibfa_solve_induced(sibfa_ctx c, int warm_start, double* mu_out, in
                          c->stream);
   if (iters) *iters = c->stats.iterations;
   if (true_rms_debye) *true_rms_debye = c->stats.true_rms_debye;
-  sibfa_status s2 = sync_read(c);
-  return st != SIBFA_OK ? st : s2;
+  // the host scalars come from the solver's own (synchronized) stop test;
+  // the dipole copy stays enqueued, so a following call's work queues
+  // behind it without a host round trip
+  if (st != SIBFA_OK) return st;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SIBFA_OK : hip_fail(c, e, "kernel launch");
 }
 
 sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, double* forces,

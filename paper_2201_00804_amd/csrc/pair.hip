@@ -191,8 +191,16 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
     const int* row = s.nb_all + (size_t)i * s.cap_all;
     const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
     for (int k = sub; k < nn; k += G) perm_pair<R, true>(s, i, row[k], pi, Mi, xi, si, U, acc);
-    for (int k = sub; k < nf; k += G)
-      perm_pair<R, false>(s, i, row[s.cap_all - 1 - k], pi, Mi, xi, si, U, acc);
+    // far entries two per step (same summation order): the second pair's
+    // gathers are issued while the first is evaluated
+    const int* far = row + s.cap_all - 1;
+    int k = sub;
+    for (; k + G < nf; k += 2 * G) {
+      const int j0 = far[-k], j1 = far[-(k + G)];
+      perm_pair<R, false>(s, i, j0, pi, Mi, xi, si, U, acc);
+      perm_pair<R, false>(s, i, j1, pi, Mi, xi, si, U, acc);
+    }
+    if (k < nf) perm_pair<R, false>(s, i, far[-k], pi, Mi, xi, si, U, acc);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) acc[a] = group_sum<G>(acc[a]);
@@ -600,8 +608,14 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
     const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
     for (int k = sub; k < nn; k += G)
       force_pair<R, true>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F);
-    for (int k = sub; k < nf; k += G)
-      force_pair<R, false>(s, i, row[s.cap_all - 1 - k], Mi, Pi, xi, si, mu, mu32, F);
+    const int* far = row + s.cap_all - 1;
+    int k = sub;
+    for (; k + G < nf; k += 2 * G) {
+      const int j0 = far[-k], j1 = far[-(k + G)];
+      force_pair<R, false>(s, i, j0, Mi, Pi, xi, si, mu, mu32, F);
+      force_pair<R, false>(s, i, j1, Mi, Pi, xi, si, mu, mu32, F);
+    }
+    if (k < nf) force_pair<R, false>(s, i, far[-k], Mi, Pi, xi, si, mu, mu32, F);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
