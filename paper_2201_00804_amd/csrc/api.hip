@@ -490,8 +490,7 @@ sibfa_status build_lists(sibfa_ctx c) {
     for (int k = 0; k < 4; ++k) want[k] = std::max(want[k], c->cap[k]);
     sibfa_status st = alloc_lists(c, want);
     if (st != SIBFA_OK) return st;
-    launch_fill_int(c->dints, 0, 4, c->stream);
-    launch_fill_int(c->dints + 5, 0, 1, c->stream);
+    launch_fill_ints({{c->dints, 4}, {c->dints + 5, 1}}, 0, c->stream);
     NlistArgs a{};
     a.periodic = c->periodic;
     for (int d = 0; d < 3; ++d) {
@@ -563,10 +562,8 @@ sibfa_status prepare(sibfa_ctx c) {
   if (c->dirty_sort || c->dirty_mult || c->dirty_pol || c->dirty_lists) join(c);
 
   if (c->dirty_sort) {
-    launch_fill_int(c->cell_count, 0, c->ncell + 1, s);
-    launch_fill_int(c->cursor, 0, c->ncell, s);
-    launch_fill_int(c->mol_count, 0, c->n, s);
-    launch_fill_int(c->dints + 4, 0, 1, s);
+    launch_fill_ints({{c->cell_count, (size_t)c->ncell + 1}, {c->cursor, (size_t)c->ncell},
+                      {c->mol_count, (size_t)c->n}, {c->dints + 4, 1}}, 0, s);
     BinArgs b{};
     b.n = c->n;
     b.periodic = c->periodic;
@@ -644,8 +641,8 @@ sibfa_status prepare(sibfa_ctx c) {
           int* start = pol ? c->bstart_pol : c->bstart_all;
           int* order = pol ? c->border_pol : c->border_all;
           const int cnt = pol ? c->npol : c->n;
-          launch_fill_int(c->bcount, 0, c->nbricks + 1, s);
-          launch_fill_int(c->bcursor, 0, c->nbricks, s);
+          launch_fill_ints({{c->bcount, (size_t)c->nbricks + 1}, {c->bcursor, (size_t)c->nbricks}},
+                           0, s);
           launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, s);
           launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, s);
           if (cnt > 0) {

@@ -2,6 +2,8 @@
 // views of the cell-sorted system, small device helpers (wave and block
 // reductions, minimum image, B-spline weights) and kernel launchers.
 #pragma once
+#include <initializer_list>
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -329,6 +331,15 @@ __device__ __forceinline__ void bspline_weights(R w, R th[ND + 1][P]) {
 // ---------------------------------------------------------------- launchers
 // nlist.hip
 void launch_fill_int(int* p, int v, size_t n, hipStream_t s);
+constexpr int kFillMax = 8;
+struct FillList {
+  int n;
+  int* p[kFillMax];
+  size_t cnt[kFillMax];
+  int v;
+};
+// every (buffer, count) set to v, in one launch per eight buffers
+void launch_fill_ints(std::initializer_list<std::pair<int*, size_t>> bufs, int v, hipStream_t s);
 void launch_fill_double(double* p, double v, size_t n, hipStream_t s);
 void launch_fill_float(float* p, float v, size_t n, hipStream_t s);
 size_t scan_temp_ints(int n);

@@ -12,6 +12,10 @@
 //   in    same-molecule site pairs (excluded or damped, always present)
 //   pol   intermolecular polarizable pairs within the cutoff (T)
 //   ipol  same-molecule polarizable pairs (T, Thole-damped)
+#include <algorithm>
+#include <initializer_list>
+#include <utility>
+
 #include "common.h"
 #include "nlist.h"
 
@@ -40,6 +44,32 @@ void launch_fill_double(double* p, double v, size_t n, hipStream_t s) {
 }
 void launch_fill_float(float* p, float v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill<float>, dim3(fill_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+}
+
+// Several int buffers set to one value in a single launch.
+__global__ void k_fill_ints(FillList f) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < f.n; ++k)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.cnt[k]; i += stride)
+      f.p[k][i] = f.v;
+}
+
+void launch_fill_ints(std::initializer_list<std::pair<int*, size_t>> bufs, int v, hipStream_t s) {
+  FillList f{};
+  size_t mx = 0;
+  for (const auto& b : bufs) {
+    if (f.n == kFillMax) {   // more than one launch's worth
+      hipLaunchKernelGGL(k_fill_ints, dim3(fill_blocks(mx)), dim3(kBlock), 0, s, f);
+      f.n = 0;
+      mx = 0;
+    }
+    f.p[f.n] = b.first;
+    f.cnt[f.n] = b.second;
+    ++f.n;
+    mx = std::max(mx, b.second);
+  }
+  f.v = v;
+  if (f.n && mx) hipLaunchKernelGGL(k_fill_ints, dim3(fill_blocks(mx)), dim3(kBlock), 0, s, f);
 }
 
 constexpr int kScanTile = 4 * kBlock;   // elements per block
@@ -87,6 +117,48 @@ __global__ void k_scan_add(int* out, int n, const int* tile_offsets) {
     if (base + k < n) out[base + k] += add;
 }
 
+// Exclusive scan of up to kScanSingleMax values by one 1,024-thread
+// workgroup: tiles of 4,096 values in order, each scanned in registers and
+// across the wavefronts, with the running total carried to the next tile.
+// One launch instead of the three of the multi-block form.
+constexpr int kScanBig = 1024;
+constexpr int kScanSingleMax = 64 * 4 * kScanBig;
+__global__ __launch_bounds__(kScanBig) void k_scan_single(const int* in, int* out, int n) {
+  __shared__ int wsum[kScanBig / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int carry = 0;
+  for (int t0 = 0; t0 < n; t0 += 4 * kScanBig) {
+    const int base = t0 + threadIdx.x * 4;
+    int v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (base + k < n) ? in[base + k] : 0;
+      sum += v[k];
+    }
+    int x = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int wbase = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBig / 64; ++w) {
+      if (w < wid) wbase += wsum[w];
+      tot += wsum[w];
+    }
+    __syncthreads();   // wsum is rewritten by the next tile
+    int ex = carry + wbase + x - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (base + k < n) out[base + k] = ex;
+      ex += v[k];
+    }
+    carry += tot;
+  }
+}
+
 size_t scan_temp_ints(int n) {
   const size_t tiles = (size_t)(n + kScanTile - 1) / kScanTile;
   if (tiles <= 1) return 1;
@@ -96,6 +168,10 @@ size_t scan_temp_ints(int n) {
 void launch_exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s) {
   if (n <= 0) return;
   const int tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles > 1 && n <= kScanSingleMax) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanBig), 0, s, in, out, n);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, in, out, n, tmp);
   if (tiles == 1) return;
   launch_exclusive_scan(tmp, tmp + tiles, tiles, tmp + 2 * tiles, s);
