@@ -67,7 +67,6 @@ void launch_bin(const BinArgs& a, hipStream_t s);
 void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int* perm,
                     int n, hipStream_t s);
 void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s);
-void launch_max_int(const int* v, int n, int* out, hipStream_t s);
 void launch_sum_ints(const int* v, int n, unsigned long long* out, hipStream_t s);
 void launch_rec_pos(const RecArgs& a, hipStream_t s);
 // out[0] = largest mean polarizability, out[1] = smallest Thole factor over

@@ -257,14 +257,6 @@ __global__ __launch_bounds__(64) void k_sort_cells(const int* cell_start, int nc
   }
 }
 
-__global__ void k_max_int(const int* v, int n, int* out) {
-  int m = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    m = max(m, v[i]);
-  for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
-}
-
 __global__ void k_sum_ints(const int* v, int n, unsigned long long* out) {
   unsigned long long m = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -291,13 +283,6 @@ void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int*
 void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_cells, dim3(ncell), dim3(64), 0, s, cell_start, ncell, perm);
 }
-void launch_max_int(const int* v, int n, int* out, hipStream_t s) {
-  int blocks = (n + kBlock - 1) / kBlock;
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_max_int, dim3(blocks), dim3(kBlock), 0, s, v, n, out);
-}
-
 // ------------------------------------------------------------ records
 // Positions (wrapped when periodic) and molecule ids in sorted order; the
 // inverse permutation.  A non-finite coordinate (flagged by the binning, the
