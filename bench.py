@@ -324,7 +324,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is built for a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built); use --gpus 1",
+              "(sharding over several GPUs is designed, not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
