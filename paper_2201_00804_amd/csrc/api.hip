@@ -852,22 +852,28 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       for (int b = 0; b < nb && it + j < c->prm.max_iter; ++b) {
         const int k = kk + j;
         c->cur_tag = j;
+        // with two streams, the direction kernel's own completion records
+        // the fork event (a separate marker cost the main stream ~5 us)
+        const bool fork_by_dir = k > 0 && c->periodic && c->aux != c->stream;
         if (k > 0) {
           // p = z + beta p, after the stop test of the previous iteration
           // when that was enqueued in this batch
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
           Phase ph(c, SIBFA_PH_UPDATE);
           launch_direction(s, c->red, num, den, c->z, c->p, c->p32, b > 0 ? flag : nullptr, j,
-                           zz_stop, zz_replace, st);
+                           zz_stop, zz_replace, st, fork_by_dir ? c->ev_fork : nullptr);
         }
         // the reciprocal chain (the critical path) on the main stream, the
         // real-space matvec beside it on the auxiliary stream: both stream
         // events then fall off the critical path
         if (c->periodic) {
-          fork(c);
+          if (fork_by_dir) (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+          else fork(c);
           {
             Phase ph(c, SIBFA_PH_MATVEC, c->aux);
-            launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->aux);
+            // the matvec's completion records the join event itself
+            launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->aux,
+                               c->aux != c->stream ? c->ev_join : nullptr);
           }
           {
             Phase ph(c, SIBFA_PH_SPREAD);
@@ -877,7 +883,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
             Phase ph(c, SIBFA_PH_FFT);
             conv(c, mix, st);
           }
-          join(c);
+          if (c->aux != c->stream) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
         } else {
           Phase ph(c, SIBFA_PH_MATVEC);
           launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);

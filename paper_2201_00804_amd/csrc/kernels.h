@@ -10,7 +10,8 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
 // must be current) and, for periodic systems, the PME field gather with
 // p.Tp.  The dot product's partials come from the last of the two.
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
-                        double4* out, int dot_slot, bool mixed, hipStream_t st);
+                        double4* out, int dot_slot, bool mixed, hipStream_t st,
+                        hipEvent_t done = nullptr);
 void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
                          double4* out, int dot_slot, bool mixed, hipStream_t st);
 // cache the pol-list pair coefficients: FP64 into out, or FP32 into out32
@@ -58,10 +59,11 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    double4* x, double4* r, double4* z, const double4* p, const double4* q,
                    hipStream_t st);
 // p = z + beta p; with a flag, first the stop test of iteration `iter`
-// (that of k_check), and no update when it stops.
+// (that of k_check), and no update when it stops.  done (may be NULL):
+// recorded by the kernel's completion.
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, int* flag, int iter, double zz_stop,
-                      double zz_replace, hipStream_t st);
+                      double zz_replace, hipStream_t st, hipEvent_t done = nullptr);
 void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
 // Totals of up to 8 reduction slots (one block each, fixed order) into out.
 struct SlotList {

@@ -14,6 +14,8 @@
 //              field of p + PME field of p + self]; k_matvec_recip gathers
 //              the PME field from the potential grid and forms p.Tp.
 //  k_force   : real-space forces of MM, Mmu and mumu classes at fixed mu.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "pairmath.h"
 #include "kernels.h"
@@ -646,11 +648,19 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
 }
 
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
-                        double4* out, int dot_slot, bool mixed, hipStream_t st) {
-  if (s.npol <= 0) return;
+                        double4* out, int dot_slot, bool mixed, hipStream_t st, hipEvent_t done) {
+  if (s.npol <= 0) {
+    if (done) (void)hipEventRecord(done, st);
+    return;
+  }
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  if (mixed) hipLaunchKernelGGL((k_matvec<float, kG>), g, b, 0, st, s, red, p, p32, out, dot_slot);
-  else hipLaunchKernelGGL((k_matvec<double, kG>), g, b, 0, st, s, red, p, p32, out, dot_slot);
+  // done: recorded by the kernel's own completion (no marker packet)
+  if (mixed)
+    hipExtLaunchKernelGGL((k_matvec<float, kG>), g, b, 0, st, nullptr, done, 0, s, red, p, p32, out,
+                          dot_slot);
+  else
+    hipExtLaunchKernelGGL((k_matvec<double, kG>), g, b, 0, st, nullptr, done, 0, s, red, p, p32, out,
+                          dot_slot);
   if (!s.periodic && dot_slot >= 0) red.nparts[dot_slot] = (int)g.x;
 }
 

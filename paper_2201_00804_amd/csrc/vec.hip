@@ -5,6 +5,8 @@
 // preconditioner is z = alpha r with the 3x3 site polarizability
 // (the inverse of T's diagonal blocks).  Dot products are reduced per block
 // and finalised deterministically by the last block (block_reduce_to_slot).
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -213,9 +215,13 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
 }
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, int* flag, int iter, double zz_stop,
-                      double zz_replace, hipStream_t st) {
-  hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p, p32,
-                     flag, iter, zz_stop, zz_replace);
+                      double zz_replace, hipStream_t st, hipEvent_t done) {
+  if (done)   // the kernel's own completion records the event: no marker packet
+    hipExtLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, nullptr, done, 0, s,
+                          red, num, den, z, p, p32, flag, iter, zz_stop, zz_replace);
+  else
+    hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p,
+                       p32, flag, iter, zz_stop, zz_replace);
 }
 // One block per slot: the slot's partials summed in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_slot_totals(Reduce red, SlotList sl, double* out) {
