@@ -700,7 +700,8 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
     fork(c);
     {
       Phase ph2(c, SIBFA_PH_MATVEC, c->aux);
-      launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->aux);
+      launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->aux,
+                         c->aux != c->stream ? c->ev_join : nullptr);
     }
     {
       Phase ph(c, SIBFA_PH_SPREAD);
@@ -710,7 +711,7 @@ void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bo
       Phase ph(c, SIBFA_PH_FFT);
       conv(c, mix, c->stream);
     }
-    join(c);
+    if (c->aux != c->stream) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
   } else {
     Phase ph2(c, SIBFA_PH_MATVEC);
     launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->stream);
