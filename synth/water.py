@@ -173,6 +173,25 @@ def water_box(n_waters, box_len, seed_index=0):
     return _pack(sites, n_waters, box_len, rng)
 
 
+def water_box_ortho(counts, spacing, seed_index=0):
+    """Orthorhombic periodic box: a full jittered lattice of counts[a]
+    waters along axis a with lattice spacing[a] (box sides counts * spacing,
+    positions wrapped into the box)."""
+    rng = np.random.Generator(np.random.PCG64(_SEED_BASE + 2000 + seed_index))
+    counts = np.asarray(counts, dtype=int)
+    spacing = np.asarray(spacing, dtype=float)
+    box = counts * spacing
+    grid = np.stack(np.meshgrid(*[np.arange(c) for c in counts], indexing="ij"), axis=-1)
+    centres = (grid.reshape(-1, 3) + 0.5) * spacing
+    centres = centres + rng.uniform(-0.1, 0.1, size=centres.shape)
+    n_waters = len(centres)
+    sites = _orient(rng, centres, box)
+    sites = np.mod(sites, box)
+    d = _pack(sites, n_waters, None, rng)
+    d["box"] = box.copy()
+    return d
+
+
 def water_cluster(n_waters, seed_index=0):
     """Random compact gas-phase water cluster (O-O >= 2.5 A)."""
     rng = np.random.Generator(np.random.PCG64(_SEED_BASE + 1000 + seed_index))

@@ -12,7 +12,7 @@ from scipy.spatial import cKDTree
 
 import oracle
 from oracle.model import System, Context, permanent_field, apply_T
-from synth import water_box, water_cluster, config_system
+from synth import water_box, water_box_ortho, water_cluster, config_system
 from tests.gpu_util import (say, oracle_params, gpu_params, engine_for, rel_err, rms_rel,
                             pol_rows)
 
@@ -77,6 +77,14 @@ def test_small_box_parity():
     # 27 waters, 9.5 A box: every site sees most of the box; ragged PME grid 24
     _compare_full(water_box(27, 9.5, 3), dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-10),
                   "box27")
+
+
+def test_orthorhombic_box_parity():
+    # 120 waters in an 18.6 x 15.5 x 12.4 A box: unequal sides, a different
+    # grid size per axis (non-square FFT planes), and cell counts 8 x 6 x 5
+    # (the shifted-stencil list builder)
+    d = water_box_ortho((6, 5, 4), (3.1, 3.1, 3.1), 1)
+    _compare_full(d, dict(beta=0.45, cutoff=4.5, grid=(36, 30, 24), tol=1e-10), "ortho120")
 
 
 def test_small_box_other_orders():

@@ -24,7 +24,7 @@ import pytest
 import oracle
 from oracle.model import System, Params, Context, permanent_field, apply_T
 from oracle.units import COULOMB
-from synth import water_cluster, water_box
+from synth import water_cluster, water_box, water_box_ortho
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -93,6 +93,27 @@ def test_p2_beta_invariance():
     for beta in (0.45, 0.6, 0.75):
         p = Params(method="ewald", beta=beta, realspace="images",
                    rmax=6.2 / beta, tol=1e-11)
+        c = Context(s, p)
+        E0 = permanent_field(s, p, ctx=c)
+        Tp = apply_T(s, p, pvec, ctx=c)
+        out = oracle.evaluate(s, p, forces=False)
+        res.append((E0, Tp, out["E_pol"], out["E_elec"]))
+    for r in res[1:]:
+        assert np.abs(r[0] - res[0][0]).max() <= 1e-10 * np.abs(res[0][0]).max()
+        assert np.abs(r[1] - res[0][1]).max() <= 1e-10 * np.abs(res[0][1]).max()
+        assert r[2] == pytest.approx(res[0][2], rel=1e-10)
+        assert r[3] == pytest.approx(res[0][3], rel=1e-10)
+
+
+def test_p2_beta_invariance_orthorhombic():
+    """The same invariance with three different box sides (pins the
+    per-axis reciprocal vectors and images)."""
+    s = System.from_dict(water_box_ortho((3, 2, 2), (3.1, 3.4, 2.9), 4))
+    rng = np.random.default_rng(1)
+    pvec = rng.normal(size=(len(s.pol), 3)) * 0.1
+    res = []
+    for beta in (0.5, 0.65, 0.8):
+        p = Params(method="ewald", beta=beta, realspace="images", rmax=6.2 / beta, tol=1e-11)
         c = Context(s, p)
         E0 = permanent_field(s, p, ctx=c)
         Tp = apply_T(s, p, pvec, ctx=c)
@@ -174,6 +195,22 @@ def test_p5_spme_converges_to_ewald():
                                       **base), forces=False)
         eo.append(abs(o["E_elec"] - ref["E_elec"]))
     assert eo[0] > eo[1] > eo[2]
+
+
+def test_p5_spme_converges_orthorhombic():
+    """SPME with a different grid size per axis converges to Ewald in a box
+    with unequal sides."""
+    s = System.from_dict(water_box_ortho((4, 3, 3), (3.1, 3.1, 3.1), 5))   # 12.4 x 9.3 x 9.3
+    base = dict(beta=0.45, cutoff=4.5, tol=1e-11)
+    ref = oracle.evaluate(s, Params(method="ewald", realspace="minimage", **base))
+    errs = []
+    for g in ((16, 12, 12), (24, 18, 18), (32, 24, 24)):
+        o = oracle.evaluate(s, Params(method="spme", grid=g, order=5, **base))
+        errs.append((abs(o["E_pol"] - ref["E_pol"]), abs(o["E_elec"] - ref["E_elec"]),
+                     np.abs(o["forces"] - ref["forces"]).max()))
+    for k in range(3):
+        assert errs[0][k] > errs[1][k] > errs[2][k]
+    assert errs[2][0] < 1e-3 * abs(ref["E_pol"])
 
 
 # ---------------------------------------------------------------- P6 / P7
