@@ -95,6 +95,9 @@ struct sibfa_ctx_s {
   // all-list split radius squared: every polarizable pair beyond it has a
   // Thole exponent x = a r^3 s_i s_j >= 50 (no damping)
   double rsplit2 = 0.0;
+  // z.z decay per iteration seen in the first run of the last solve: sizes
+  // the first batch of the next one (-1: none yet)
+  double rate_hint = -1.0;
   DevBuf nbbuf[4];
   // [0..3] list maxima, [4] binning errors (bits 2, 8), [5] list errors
   // (bit 1), [6] finiteness flag, [7] polarizability errors (bit 4),
@@ -299,6 +302,7 @@ sibfa_status check_params(sibfa_ctx c, const sibfa_params* p, const double* box)
 }
 
 void release_system(sibfa_ctx c) {
+  c->rate_hint = -1.0;
   free_list(c, c->bufs);
   free_list(c, c->pmebufs);
   for (int k = 0; k < 4; ++k) {
@@ -797,7 +801,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   // its decay per iteration, to size the next batch so that it ends about
   // where the run will stop (fewer launches that return at once, fewer
   // host round trips).
-  double zz_last = -1.0, rate = -1.0;
+  // The first batch of a solve uses the decay rate of the previous solve
+  // (positions move little between evaluations), so that it usually ends
+  // where the first run stops instead of after a default four iterations.
+  double zz_last = -1.0, rate = c->rate_hint;
+  bool first_run = true;
   sibfa_status result = SIBFA_OK;
   int* flag = c->dints + 8;                                    // [0..3]
   double* zz_dev = reinterpret_cast<double*>(c->dints + 12);  // after flag
@@ -847,7 +855,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
       if (rate > 0.0 && rate < 1.0 && zz_last > 0.0) {
         const double target = zz_replace > zz_stop ? zz_replace : zz_stop;
         const double est = std::ceil(std::log(target / zz_last) / std::log(rate));
-        nb = est < 1.0 ? 1 : (est > 8.0 ? 8 : (int)est);
+        nb = est < 1.0 ? 1 : (est > 12.0 ? 12 : (int)est);
       }
       const int j0 = j;
       for (int b = 0; b < nb && it + j < c->prm.max_iter; ++b) {
@@ -935,6 +943,8 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     }
     c->red.stop = nullptr;
     c->pm.stop = nullptr;
+    if (first_run && rate > 0.0 && rate < 1.0) c->rate_hint = rate;
+    first_run = false;
     it += j_done;
     kk += j_done;
     if (reason == 3) {
