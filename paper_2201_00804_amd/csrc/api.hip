@@ -809,6 +809,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   sibfa_status result = SIBFA_OK;
   int* flag = c->dints + 8;                                    // [0..3]
   double* zz_dev = reinterpret_cast<double*>(c->dints + 12);  // after flag
+  // z.z of a cold mixed start's first residual, left on the device: the
+  // stop tests scale the replacement factor by it there, and the host reads
+  // it with the first batch's flag (one host round trip fewer)
+  double* zz0_dev = reinterpret_cast<double*>(c->dints + 36);
+  const double* zz_ref = nullptr;
   for (;;) {
     // residual from scratch: FP64 operator, except the very first residual
     // of a cold start in mixed mode (FP32 operator; the early replacement
@@ -820,7 +825,16 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     else
       launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, nullptr, nullptr,
                            S_RZ0 + (kk & 1), st);
-    if (read_res) {
+    if (read_res && fp32_res) {
+      // far from the tolerance (FP32 operator, cold start): no read back
+      SlotList sl{};
+      sl.n = 1;
+      sl.slot[0] = S_ZZ;
+      sl.nparts[0] = c->red.nparts[S_ZZ];
+      launch_slot_totals(c->red, sl, zz0_dev, st);
+      zz_ref = zz0_dev;
+      zz_last = -1.0;
+    } else if (read_res) {
       double zz0 = 0.0;
       sibfa_status e = read_totals(c, {S_ZZ}, &zz0);
       if (e != SIBFA_OK) return e;
@@ -835,7 +849,8 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     read_res = true;
     if (it >= c->prm.max_iter || restarts > 8) { result = SIBFA_E_NOT_CONVERGED; break; }
     if (fresh) {
-      if (mix) zz_replace = kReplace * zz_last;
+      // with zz_ref the kernels take kReplace as a factor of *zz_ref
+      if (mix) zz_replace = zz_ref ? kReplace : kReplace * zz_last;
     } else {
       ++restarts;
     }
@@ -852,9 +867,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     for (;;) {
       if (c->prof && c->marks.size() > 4096) fold_marks(c);
       int nb = 4;
-      if (rate > 0.0 && rate < 1.0 && zz_last > 0.0) {
-        const double target = zz_replace > zz_stop ? zz_replace : zz_stop;
-        const double est = std::ceil(std::log(target / zz_last) / std::log(rate));
+      if (rate > 0.0 && rate < 1.0 && (zz_last > 0.0 || zz_ref)) {
+        // deferred start: the first run ends at z.z = kReplace z.z0
+        const double ratio = zz_ref ? zz_replace
+                                    : (zz_replace > zz_stop ? zz_replace : zz_stop) / zz_last;
+        const double est = std::ceil(std::log(ratio) / std::log(rate));
         nb = est < 1.0 ? 1 : (est > 12.0 ? 12 : (int)est);
       }
       const int j0 = j;
@@ -870,7 +887,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           const int num = S_RZ0 + (k & 1), den = S_RZ0 + ((k - 1) & 1);
           Phase ph(c, SIBFA_PH_UPDATE);
           launch_direction(s, c->red, num, den, c->z, c->p, c->p32, b > 0 ? flag : nullptr, j,
-                           zz_stop, zz_replace, st, fork_by_dir ? c->ev_fork : nullptr);
+                           zz_stop, zz_replace, zz_ref, st, fork_by_dir ? c->ev_fork : nullptr);
         }
         // the reciprocal chain (the critical path) on the main stream, the
         // real-space matvec beside it on the auxiliary stream: both stream
@@ -908,18 +925,25 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           // the last iteration of a batch is tested here, the others by
           // the next direction update
           if (b == nb - 1 || it + j + 1 >= c->prm.max_iter)
-            launch_check(c->red, flag, zz_dev, j + 1, zz_stop, zz_replace, st);
+            launch_check(c->red, flag, zz_dev, j + 1, zz_stop, zz_replace, zz_ref, st);
         }
         ++j;
       }
       c->cur_tag = -1;
       HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int) + sizeof(double),
                              hipMemcpyDeviceToHost, st));
+      if (zz_ref)
+        HIP_TRY(hipMemcpyAsync(c->h_pinned + 60, zz0_dev, sizeof(double), hipMemcpyDeviceToHost, st));
       sibfa_status e = sync_read(c);
       if (e != SIBFA_OK) {
         c->red.stop = nullptr;
         c->pm.stop = nullptr;
         return e;
+      }
+      if (zz_ref) {   // the deferred z.z0: host values from here on
+        zz_last = c->h_pinned[60];
+        zz_replace = kReplace * zz_last;
+        zz_ref = nullptr;
       }
       const int stop = c->h_ints[8];
       const int ran = stop ? c->h_ints[10] - j0 : j - j0;   // iterations this batch

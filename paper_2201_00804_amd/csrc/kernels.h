@@ -59,11 +59,13 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
                    double4* x, double4* r, double4* z, const double4* p, const double4* q,
                    hipStream_t st);
 // p = z + beta p; with a flag, first the stop test of iteration `iter`
-// (that of k_check), and no update when it stops.  done (may be NULL):
+// (that of k_check), and no update when it stops.  zz_ref (may be NULL):
+// the replacement threshold is zz_replace * *zz_ref.  done (may be NULL):
 // recorded by the kernel's completion.
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, int* flag, int iter, double zz_stop,
-                      double zz_replace, hipStream_t st, hipEvent_t done = nullptr);
+                      double zz_replace, const double* zz_ref, hipStream_t st,
+                      hipEvent_t done = nullptr);
 void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st);
 // Totals of up to 8 reduction slots (one block each, fixed order) into out.
 struct SlotList {
@@ -74,7 +76,7 @@ struct SlotList {
 void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipStream_t st);
 // device-side convergence test (see k_check)
 void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
-                  double zz_replace, hipStream_t st);
+                  double zz_replace, const double* zz_ref, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st);

@@ -47,7 +47,9 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
   if (stopped(red.stop)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0, zz = 0.0;
-  const double gamma = slot_total(red, rz_slot) / slot_total(red, S_PQ);
+  // r.z = 0 only for a zero residual (alpha is SPD): nothing to update
+  const double rzt = slot_total(red, rz_slot);
+  const double gamma = rzt == 0.0 ? 0.0 : rzt / slot_total(red, S_PQ);
   if (i < s.npol) {
     const double4 pv = p[i], qv = q[i];
     double4 xv = x[i], rv = r[i];
@@ -65,15 +67,19 @@ __global__ __launch_bounds__(kBlock) void k_update(SysView s, Reduce red, int rz
 }
 
 // Stop test of the previous iteration (see k_check), made by every block
-// on the same partial sums, so all agree; block 0 raises the flag.
+// on the same partial sums, so all agree; block 0 raises the flag.  With
+// zz_ref (a device total the host has not read), the replacement threshold
+// is zz_replace * *zz_ref.
 __device__ __forceinline__ bool check_stop(const Reduce& red, int* flag, int iter, double zz_stop,
-                                           double zz_replace) {
+                                           double zz_replace, const double* zz_ref) {
   const double pq = slot_total(red, S_PQ);
   const double zz = slot_total(red, S_ZZ);
+  const double zr = zz_ref ? zz_replace * *zz_ref : zz_replace;
+  // a converged residual stops first (a zero residual also has p.Tp = 0)
   int reason = 0;
-  if (!(pq > 0.0)) reason = 2;
-  else if (zz <= zz_stop) reason = 1;
-  else if (zz <= zz_replace) reason = 3;
+  if (zz <= zz_stop) reason = 1;
+  else if (!(pq > 0.0)) reason = 2;
+  else if (zz <= zr) reason = 3;
   if (reason && blockIdx.x == 0 && threadIdx.x == 0) {
     flag[1] = reason; flag[2] = iter; flag[0] = 1;
   }
@@ -85,9 +91,9 @@ __device__ __forceinline__ bool check_stop(const Reduce& red, int* flag, int ite
 __global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int num, int den,
                                                       const double4* z, double4* p, float4* p32,
                                                       int* flag, int iter, double zz_stop,
-                                                      double zz_replace) {
+                                                      double zz_replace, const double* zz_ref) {
   if (stopped(red.stop)) return;
-  if (flag && check_stop(red, flag, iter, zz_stop, zz_replace)) return;
+  if (flag && check_stop(red, flag, iter, zz_stop, zz_replace, zz_ref)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = slot_total(red, num) / slot_total(red, den);
   if (i >= s.npol) return;
@@ -135,13 +141,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red,
 // flag: [0] stop, [1] reason (1 converged, 2 not SPD, 3 replace),
 // [2] iterations done.
 __global__ __launch_bounds__(kBlock) void k_check(Reduce red, int* flag, double* zz_out, int iter,
-                                                  double zz_stop, double zz_replace) {
+                                                  double zz_stop, double zz_replace,
+                                                  const double* zz_ref) {
   // z.z of the last update that ran (kernels after a stop leave the
   // partials alone), for the host's batch sizing
   const double zz = slot_total(red, S_ZZ);
   if (threadIdx.x == 0) *zz_out = zz;
   if (flag[0]) return;
-  (void)check_stop(red, flag, iter, zz_stop, zz_replace);
+  (void)check_stop(red, flag, iter, zz_stop, zz_replace, zz_ref);
 }
 
 __global__ void k_copy4(const double4* in, double4* out, float4* out32, int n) {
@@ -215,13 +222,13 @@ void launch_update(const SysView& s, Reduce& red, int rz_slot, int rz_next_slot,
 }
 void launch_direction(const SysView& s, const Reduce& red, int num, int den, const double4* z,
                       double4* p, float4* p32, int* flag, int iter, double zz_stop,
-                      double zz_replace, hipStream_t st, hipEvent_t done) {
+                      double zz_replace, const double* zz_ref, hipStream_t st, hipEvent_t done) {
   if (done)   // the kernel's own completion records the event: no marker packet
     hipExtLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, nullptr, done, 0, s,
-                          red, num, den, z, p, p32, flag, iter, zz_stop, zz_replace);
+                          red, num, den, z, p, p32, flag, iter, zz_stop, zz_replace, zz_ref);
   else
     hipLaunchKernelGGL(k_direction, grid_for(s.npol), dim3(kBlock), 0, st, s, red, num, den, z, p,
-                       p32, flag, iter, zz_stop, zz_replace);
+                       p32, flag, iter, zz_stop, zz_replace, zz_ref);
 }
 // One block per slot: the slot's partials summed in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_slot_totals(Reduce red, SlotList sl, double* out) {
@@ -263,9 +270,9 @@ void launch_nonfinite(const double* v, size_t n, int* flag, hipStream_t st) {
 }
 
 void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
-                  double zz_replace, hipStream_t st) {
+                  double zz_replace, const double* zz_ref, hipStream_t st) {
   hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, zz_out, iter, zz_stop,
-                     zz_replace);
+                     zz_replace, zz_ref);
 }
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);

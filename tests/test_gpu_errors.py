@@ -177,6 +177,25 @@ def test_no_polarizable_sites():
     eng.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_permanent_field(precision):
+    """No permanent multipoles: E = 0, so the cold start is already the
+    solution (mu = 0).  The solve must end converged (a zero residual also
+    has p.Tp = 0, which must not read as an indefinite T) with zero
+    energies and forces."""
+    d = water_box(27, 9.5, 3)
+    d = dict(d, q=np.zeros_like(d["q"]), dip=np.zeros_like(d["dip"]),
+             quad=np.zeros_like(d["quad"]))
+    eng = engine_for(d, gpu_params(d, beta=0.45, cutoff=4.5, grid=24, precision=precision))
+    mu, it, rms = eng.solve()
+    say(f"  {precision}: iterations {it}, rms {rms}")
+    assert float(mu.abs().max()) == 0.0 and rms == 0.0
+    e_pol, e_elec, F = eng.energy_forces()
+    assert e_pol == 0.0 and e_elec == 0.0
+    assert float(F.abs().max()) == 0.0
+    eng.close()
+
+
 def test_per_site_thole_factors():
     """Per-site Thole factors with a_ij = min(a_i, a_j) against the oracle."""
     d = water_cluster(7, 8)
