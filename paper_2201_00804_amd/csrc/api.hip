@@ -977,7 +977,8 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     }
     if (reason == 2) result = SIBFA_E_NOT_SPD;
     if (result == SIBFA_E_NOT_SPD) break;
-    launch_copy4(c->x, c->x, c->x32, c->npol, st);
+    // the next residual is an FP64 one (only a cold start's first is FP32),
+    // so x32 needs no refresh here
   }
   c->stats.iterations = it;
   c->stats.restarts = restarts;
@@ -1445,12 +1446,11 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   hipStream_t sm = c->stream;
   const bool mix = mixed(c);
   if (c->npol > 0) {
-    // mu came from the last solve, which ended on the FP64 true residual
-    // r = E - T x of exactly these dipoles: x.T x = x.E - x.r gives the
-    // variational energy (Eq. 17) without another matvec
-    launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, sm);
-    launch_dot(s, c->red, c->x, c->E0, S_MUE, sm);
-    launch_dot(s, c->red, c->x, c->r, S_MUTMU, sm);
+    // mu came from the last solve (mu_valid), whose x (polarizable order)
+    // it is, and which ended on the FP64 true residual r = E - T x of
+    // exactly these dipoles: x.T x = x.E - x.r gives the variational energy
+    // (Eq. 17) without another matvec
+    launch_dot(s, c->red, c->x, c->E0, S_MUE, sm, c->r, S_MUTMU);
   } else {
     launch_fill_double(reinterpret_cast<double*>(c->x), 0.0, 4, sm);
   }

@@ -110,15 +110,22 @@ __global__ __launch_bounds__(kBlock) void k_precond(SysView s, const double4* in
   out[i] = make_double4(v.x, v.y, v.z, 0.0);
 }
 
+// a.b into slot and, when b2 is given, a.b2 into slot2 (one launch)
 __global__ __launch_bounds__(kBlock) void k_dot(SysView s, Reduce red, const double4* a,
-                                                const double4* b, int slot) {
+                                                const double4* b, int slot, const double4* b2,
+                                                int slot2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double d = 0.0;
+  double d = 0.0, d2 = 0.0;
   if (i < s.npol) {
     const double4 u = a[i], v = b[i];
     d = u.x * v.x + u.y * v.y + u.z * v.z;
+    if (b2) {
+      const double4 w = b2[i];
+      d2 = u.x * w.x + u.y * w.y + u.z * w.z;
+    }
   }
   block_partial(d, red, slot);
+  if (b2) block_partial(d2, red, slot2);
 }
 
 __global__ __launch_bounds__(kBlock) void k_residual_norm(SysView s, Reduce red, const double4* E0,
@@ -278,9 +285,10 @@ void launch_precond(const SysView& s, const double4* in, double4* out, hipStream
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
 }
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
-                hipStream_t st) {
+                hipStream_t st, const double4* b2, int slot2) {
   red.nparts[slot] = (int)grid_for(s.npol).x;
-  hipLaunchKernelGGL(k_dot, grid_for(s.npol), dim3(kBlock), 0, st, s, red, a, b, slot);
+  if (b2) red.nparts[slot2] = (int)grid_for(s.npol).x;
+  hipLaunchKernelGGL(k_dot, grid_for(s.npol), dim3(kBlock), 0, st, s, red, a, b, slot, b2, slot2);
 }
 void launch_residual_norm(const SysView& s, Reduce& red, const double4* E0, const double4* t,
                           hipStream_t st) {
