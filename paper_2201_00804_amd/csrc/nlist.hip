@@ -117,12 +117,12 @@ __global__ void k_scan_add(int* out, int n, const int* tile_offsets) {
     if (base + k < n) out[base + k] += add;
 }
 
-// Exclusive scan of up to kScanSingleMax values by one 1,024-thread
+// Exclusive scan of up to kScanSingleMax (16,384) values by one 1,024-thread
 // workgroup: tiles of 4,096 values in order, each scanned in registers and
 // across the wavefronts, with the running total carried to the next tile.
 // One launch instead of the three of the multi-block form.
 constexpr int kScanBig = 1024;
-constexpr int kScanSingleMax = 64 * 4 * kScanBig;
+constexpr int kScanSingleMax = 4 * 4 * kScanBig;   // larger scans: the multi-block form is faster
 __global__ __launch_bounds__(kScanBig) void k_scan_single(const int* in, int* out, int n) {
   __shared__ int wsum[kScanBig / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
