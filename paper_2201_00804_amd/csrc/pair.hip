@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(SysView s, Reduce red, const 
       dip_field<double>(c1, c2, pj, Rv, E);
       f[0] += E[0]; f[1] += E[1]; f[2] += E[2];
     }
-    // intermolecular polarizable pairs within the cutoff, precision R; two
+    // intermolecular polarizable pairs within the cutoff, precision R; four
     // entries per lane and step so that their gathers overlap
     R xr[3], sr;
     load_pp<R>(s, pi, xr, sr);
