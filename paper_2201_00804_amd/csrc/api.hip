@@ -565,6 +565,8 @@ sibfa_status prepare(sibfa_ctx c) {
   // failed reads the records rewritten below
   if (c->dirty_sort || c->dirty_mult || c->dirty_pol || c->dirty_lists) join(c);
 
+  // a re-sort rewrites all per-site records in one pass
+  const bool resort = c->dirty_sort;
   if (c->dirty_sort) {
     launch_fill_ints({{c->cell_count, (size_t)c->ncell + 1}, {c->cursor, (size_t)c->ncell},
                       {c->mol_count, (size_t)c->n}, {c->dints + 4, 1}}, 0, s);
@@ -584,7 +586,7 @@ sibfa_status prepare(sibfa_ctx c) {
       launch_exclusive_scan(c->cell_count, c->cell_start, c->ncell + 1, c->scan_tmp, s);
       launch_scatter(c->cell_of, c->cell_start, c->cursor, c->perm, c->n, s);
       launch_sort_cells(c->cell_start, c->ncell, c->perm, s);
-      launch_rec_pos(ra, s);
+      launch_rec_all(ra, s);
     }
     if (!c->ids_ok) {
       HIP_TRY(hipMemcpyAsync(c->h_ints + 4, c->dints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -598,13 +600,13 @@ sibfa_status prepare(sibfa_ctx c) {
     c->e0_valid = false;
   }
   if (c->dirty_mult) {
-    launch_rec_mult(ra, s);
+    if (!resort) launch_rec_mult(ra, s);
     c->dirty_mult = false;
     c->e0_valid = false;
   }
   if (c->dirty_pol) {
     launch_fill_int(c->dints + 7, 0, 1, s);
-    launch_rec_pol(ra, s);
+    if (!resort) launch_rec_pol(ra, s);
     launch_exclusive_scan(c->is_pol, c->pol_scan, c->n + 1, c->scan_tmp, s);
     launch_rec_polsites(ra, s);
     // a re-sort permutes the same polarizabilities: count, definiteness

@@ -68,9 +68,12 @@ void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int*
                     int n, hipStream_t s);
 void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s);
 void launch_sum_ints(const int* v, int n, unsigned long long* out, hipStream_t s);
-void launch_rec_pos(const RecArgs& a, hipStream_t s);
+// positions, multipoles and polarizability records in one pass (after a
+// re-sort, when all three change)
+void launch_rec_all(const RecArgs& a, hipStream_t s);
 // out[0] = largest mean polarizability, out[1] = smallest Thole factor over
-// the polarizable sites (after launch_rec_pol); 0 and +inf when none.
+// the polarizable sites (after the polarizability records); 0 and +inf
+// when none.
 void launch_pol_extents(const RecArgs& a, double* out, hipStream_t s);
 void launch_rec_mult(const RecArgs& a, hipStream_t s);
 void launch_rec_pol(const RecArgs& a, hipStream_t s);

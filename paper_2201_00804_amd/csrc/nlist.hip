@@ -288,38 +288,49 @@ void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t 
 // inverse permutation.  A non-finite coordinate (flagged by the binning, the
 // call then fails) is stored as 0 and an out-of-range molecule id as 0, so
 // that every kernel queued before the error is read back indexes in bounds.
-__global__ void k_rec_pos(RecArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int c = a.perm[i];
-  double x = a.xyz[3 * c], y = a.xyz[3 * c + 1], z = a.xyz[3 * c + 2];
-  if (!isfinite(x)) x = 0.0;
-  if (!isfinite(y)) y = 0.0;
-  if (!isfinite(z)) z = 0.0;
-  if (a.periodic) {
-    x = wrap(x, a.box[0], a.ibox[0]);
-    y = wrap(y, a.box[1], a.ibox[1]);
-    z = wrap(z, a.box[2], a.ibox[2]);
+__device__ __forceinline__ void rec_pos_of(const RecArgs& a, int i, int c, double xyz[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v = a.xyz[3 * c + k];
+    if (!isfinite(v)) v = 0.0;
+    if (a.periodic) v = wrap(v, a.box[k], a.ibox[k]);
+    xyz[k] = v;
   }
-  double4 p = a.sp[i];
-  p.x = x; p.y = y; p.z = z;
-  a.sp[i] = p;
-  float4 p32 = a.sp32[i];
-  p32.x = (float)x; p32.y = (float)y; p32.z = (float)z;
-  a.sp32[i] = p32;
   const int m = a.mol[c];
   a.mol_s[i] = (m >= 0 && m < a.n) ? m : 0;
   a.inv_perm[c] = i;
+}
+// Multipoles of caller site c: q, d, Theta (zero where not given).
+__device__ __forceinline__ void rec_mult_of(const RecArgs& a, int c, double& q, double d[3],
+                                            double t[6]) {
+  q = a.q ? a.q[c] : 0.0;
+  for (int k = 0; k < 3; ++k) d[k] = a.dip ? a.dip[3 * c + k] : 0.0;
+  for (int k = 0; k < 6; ++k) t[k] = a.quad ? a.quad[6 * c + k] : 0.0;
+}
+__device__ __forceinline__ void rec_mult_store(const RecArgs& a, int i, const double d[3],
+                                               const double t[6]) {
+  a.sth[i] = make_double4(t[0], t[1], t[2], t[3]);
+  a.sth2[i] = make_double2(t[4], t[5]);
+  a.sth32[i] = make_float4((float)t[0], (float)t[1], (float)t[2], (float)t[3]);
+  a.sth232[i] = make_float2((float)t[4], (float)t[5]);
+}
+// Polarizability of caller site c: s = abar^-1/2 (0 when not polarizable);
+// writes the Thole factor and the polarizable flag of sorted site i.
+__device__ __forceinline__ double rec_pol_of(const RecArgs& a, int i, int c) {
+  const double* al = a.alpha + 6 * c;
+  bool pol = false;
+  for (int k = 0; k < 6; ++k) pol = pol || (al[k] != 0.0);
+  const double abar = (al[0] + al[3] + al[5]) / 3.0;
+  a.sa[i] = a.thole ? a.thole[c] : a.thole_default;
+  a.is_pol[i] = pol ? 1 : 0;
+  return pol && abar > 0.0 ? 1.0 / sqrt(abar) : 0.0;
 }
 
 __global__ void k_rec_mult(RecArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const int c = a.perm[i];
-  const double q = a.q ? a.q[c] : 0.0;
-  double d[3] = {0, 0, 0}, t[6] = {0, 0, 0, 0, 0, 0};
-  if (a.dip) for (int k = 0; k < 3; ++k) d[k] = a.dip[3 * c + k];
-  if (a.quad) for (int k = 0; k < 6; ++k) t[k] = a.quad[6 * c + k];
+  double q, d[3], t[6];
+  rec_mult_of(a, a.perm[i], q, d, t);
   double4 p = a.sp[i];
   p.w = q;
   a.sp[i] = p;
@@ -332,10 +343,7 @@ __global__ void k_rec_mult(RecArgs a) {
   float4 dd32 = a.sd32[i];
   dd32.x = (float)d[0]; dd32.y = (float)d[1]; dd32.z = (float)d[2];
   a.sd32[i] = dd32;
-  a.sth[i] = make_double4(t[0], t[1], t[2], t[3]);
-  a.sth2[i] = make_double2(t[4], t[5]);
-  a.sth32[i] = make_float4((float)t[0], (float)t[1], (float)t[2], (float)t[3]);
-  a.sth232[i] = make_float2((float)t[4], (float)t[5]);
+  rec_mult_store(a, i, d, t);
 }
 
 // Polarizability records: s = abar^-1/2 (0 when not polarizable), Thole
@@ -343,20 +351,29 @@ __global__ void k_rec_mult(RecArgs a) {
 __global__ void k_rec_pol(RecArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const int c = a.perm[i];
-  const double* al = a.alpha + 6 * c;
-  bool pol = false;
-  for (int k = 0; k < 6; ++k) pol = pol || (al[k] != 0.0);
-  const double abar = (al[0] + al[3] + al[5]) / 3.0;
-  const double s = pol && abar > 0.0 ? 1.0 / sqrt(abar) : 0.0;
+  const double s = rec_pol_of(a, i, a.perm[i]);
   double4 dd = a.sd[i];
   dd.w = s;
   a.sd[i] = dd;
   float4 dd32 = a.sd32[i];
   dd32.w = (float)s;
   a.sd32[i] = dd32;
-  a.sa[i] = a.thole ? a.thole[c] : a.thole_default;
-  a.is_pol[i] = pol ? 1 : 0;
+}
+
+// After a re-sort all three records change: one pass writes them whole.
+__global__ void k_rec_all(RecArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int c = a.perm[i];
+  double x[3], q, d[3], t[6];
+  rec_pos_of(a, i, c, x);
+  rec_mult_of(a, c, q, d, t);
+  const double s = rec_pol_of(a, i, c);
+  a.sp[i] = make_double4(x[0], x[1], x[2], q);
+  a.sp32[i] = make_float4((float)x[0], (float)x[1], (float)x[2], (float)q);
+  a.sd[i] = make_double4(d[0], d[1], d[2], s);
+  a.sd32[i] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)s);
+  rec_mult_store(a, i, d, t);
 }
 
 // After the scan of is_pol: polarizable index maps and polarizable records,
@@ -391,8 +408,8 @@ __global__ void k_rec_polsites(RecArgs a) {
   a.ainv_s[6 * pi + 5] = (xx * yy - xy * xy) * id;
 }
 
-void launch_rec_pos(const RecArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rec_pos, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+void launch_rec_all(const RecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_all, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
 }
 void launch_rec_mult(const RecArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_rec_mult, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
