@@ -11,7 +11,8 @@ Many-Body Polarizable Force Field", technical appendix, Polarization):
   * the polarization matrix T (inverse polarizabilities on the diagonal
     blocks, minus the dipole-dipole field tensors off the diagonal),
   * the induced dipoles mu solving T mu = E (Eq. 18) by preconditioned
-    conjugate gradient or by a dense solve,
+    conjugate gradient or by a dense solve, and the fixed-cost truncated
+    conjugate gradient (TCG-n) the paper names as the alternative,
   * E_pol = -1/2 mu.E (Eq. 19) and the variational form
     1/2 mu.T mu - mu.E (Eq. 17),
   * the multipolar electrostatic energy (Eq. 2, without the penetration
@@ -24,11 +25,11 @@ quadrupole convention, Nyquist handling of the B-spline moduli, units of the
 solver tolerance) are listed in the module docstrings that use them.
 """
 from .model import Params, System, evaluate, permanent_field, apply_T, \
-    dense_T_columns, dense_T_blocks, energy_forces, electrostatic_energy
+    dense_T_columns, dense_T_blocks, energy_forces, electrostatic_energy, tcg
 from .solver import pcg, plain_cg, jacobi
 from . import radial, tensors, realspace, recip, units
 
 __all__ = ["Params", "System", "evaluate", "permanent_field", "apply_T",
            "dense_T_columns", "dense_T_blocks", "energy_forces",
-           "electrostatic_energy", "pcg", "plain_cg", "jacobi", "radial",
+           "electrostatic_energy", "tcg", "pcg", "plain_cg", "jacobi", "radial",
            "tensors", "realspace", "recip", "units"]

@@ -36,6 +36,7 @@ import numpy as np
 
 from . import realspace as rs
 from . import recip
+from . import solver as sv
 from .solver import pcg
 from .units import COULOMB
 
@@ -323,6 +324,17 @@ def solve(sysm, prm, E0, ctx=None, x0=None):
     if x0 is None:
         x0 = pc(E0)
     return pcg(mv, pc, E0, x0, prm.tol, prm.max_iter)
+
+
+def tcg(sysm, prm, E0, order, omega=0.0, ctx=None):
+    """TCG-n dipoles from the direct-field guess x0 = alpha E0 (with the
+    optional peek step, see solver.tcg) and E_pol at them in the form of
+    Eq. 19.  Returns (mu, E_pol)."""
+    c = _ctx(sysm, prm, ctx)
+    mv = lambda v: apply_T(sysm, prm, v, ctx=c)
+    pc = lambda r: precond(sysm, r)
+    mu = sv.tcg(mv, pc, E0, pc(E0), order, omega)
+    return mu, -0.5 * COULOMB * float(np.sum(mu * E0))
 
 
 def evaluate(sysm, prm, forces=True):

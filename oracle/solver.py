@@ -64,6 +64,43 @@ def pcg(matvec, precond, rhs, x0, tol, max_iter=200, max_restarts=5):
     return x, iters, rho
 
 
+def tcg(matvec, precond, rhs, x0, order, omega=0.0):
+    """Truncated conjugate gradient (TCG-n): a fixed cost instead of a
+    convergence test.
+
+    The paper names TCG as the fixed-cost way to converge the dipoles
+    (Many-Body Polarization) and leaves its definition to the cited work.
+    Reading: TCG-n is the n-th iterate of the PCG above (same guess, same
+    preconditioner M^-1 = alpha, no stop test; the closed forms of the cited
+    work are this iterate written out), optionally followed by one "peek"
+    step x <- x + omega M^-1 r_n with the residual r_n of that iterate.  A
+    zero residual ends the steps early (the iterate is then exact).
+    Returns x.
+    """
+    x = x0.copy()
+    r = rhs - matvec(x)
+    z = precond(r)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    for _ in range(order):
+        if rz == 0.0:
+            break
+        q = matvec(p)
+        pq = float(np.sum(p * q))
+        if pq <= 0.0:
+            raise NotSPD("p.Tp <= 0: T is not positive definite")
+        gamma = rz / pq
+        x = x + gamma * p
+        r = r - gamma * q
+        z = precond(r)
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    if omega != 0.0:
+        x = x + omega * z
+    return x
+
+
 def plain_cg(matvec, rhs, x0, tol_abs, max_iter=1000):
     """Unpreconditioned CG to |r|_inf <= tol_abs."""
     x = x0.copy()

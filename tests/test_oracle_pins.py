@@ -14,6 +14,10 @@ P9  Closed forms: charge + polarizable site; two sites on an axis
     (Applequist 2x2); alpha -> 0 limit.
 P10 PCG, plain CG and block-Jacobi reach the same mu.
 P11 Rotation invariance (cluster); translation invariance (Ewald).
+P12 TCG-n: the Galerkin solution on the preconditioned Krylov space of
+    dimension n (built from a dense T); exact after as many steps as
+    unknowns; the peek step from a dense residual; the energy functional
+    of Eq. 17 falls with n.
 """
 import math
 import os
@@ -382,3 +386,69 @@ def test_p11_translation_invariance_ewald():
                          p, forces=False)
     assert o2["E_pol"] == pytest.approx(o1["E_pol"], rel=1e-10)
     assert o2["E_elec"] == pytest.approx(o1["E_elec"], rel=1e-10)
+
+
+# ---------------------------------------------------------------- P12
+def _dense_tcg_system(nw, seed):
+    s = _cluster(nw, seed)
+    p = Params(method="direct", tol=1e-12)
+    c = Context(s, p)
+    T = oracle.dense_T_blocks(s, p, ctx=c)
+    E = permanent_field(s, p, ctx=c)
+    a3 = s.alpha3[s.pol]
+    npol = len(a3)
+    M = np.zeros((3 * npol, 3 * npol))
+    for k in range(npol):
+        M[3 * k:3 * k + 3, 3 * k:3 * k + 3] = a3[k]
+    return s, p, c, T, E, M
+
+
+@pytest.mark.parametrize("nw,seed", [(3, 21), (4, 22)])
+def test_p12_tcg_is_the_krylov_galerkin_solution(nw, seed):
+    """PCG's n-th iterate minimises the T-norm error over x0 + K_n(M T, M r0);
+    solved here as a projected dense system instead of by the recurrence."""
+    s, p, c, T, E, M = _dense_tcg_system(nw, seed)
+    e = E.ravel()
+    x0 = M @ e
+    z0 = M @ (e - T @ x0)
+    prev = None
+    for order in range(1, 6):
+        K = [z0]
+        for _ in range(order - 1):
+            K.append(M @ (T @ K[-1]))
+        Q, _ = np.linalg.qr(np.stack(K, 1))
+        y = np.linalg.solve(Q.T @ T @ Q, Q.T @ (e - T @ x0))
+        x_gal = x0 + Q @ y
+        mu, e_pol = oracle.tcg(s, p, E, order, ctx=c)
+        assert np.abs(mu.ravel() - x_gal).max() <= 1e-10 * np.abs(x_gal).max(), order
+        assert e_pol == pytest.approx(-0.5 * COULOMB * float(x_gal @ e), rel=1e-10)
+        f = 0.5 * x_gal @ T @ x_gal - x_gal @ e
+        if prev is not None:
+            assert f <= prev + 1e-12 * abs(prev)
+        prev = f
+
+
+def test_p12_tcg_exact_after_as_many_steps_as_unknowns():
+    s, p, c, T, E, M = _dense_tcg_system(2, 23)
+    n = T.shape[0]
+    mu, _ = oracle.tcg(s, p, E, n, ctx=c)
+    exact = np.linalg.solve(T, E.ravel())
+    assert np.abs(mu.ravel() - exact).max() <= 1e-10 * np.abs(exact).max()
+    mu1, _ = oracle.tcg(s, p, E, 1, ctx=c)
+    assert np.abs(mu1.ravel() - exact).max() > 1e-4 * np.abs(exact).max()
+
+
+def test_p12_tcg_peek_step():
+    s, p, c, T, E, M = _dense_tcg_system(3, 24)
+    e = E.ravel()
+    for order, omega in ((1, 1.0), (2, 0.8)):
+        mu, _ = oracle.tcg(s, p, E, order, ctx=c)
+        pk, _ = oracle.tcg(s, p, E, order, omega, ctx=c)
+        want = mu.ravel() + omega * (M @ (e - T @ mu.ravel()))
+        assert np.abs(pk.ravel() - want).max() <= 1e-11 * np.abs(want).max()
+
+
+def test_p12_tcg_zero_field():
+    s, p, c, T, E, M = _dense_tcg_system(2, 25)
+    mu, e_pol = oracle.tcg(s, p, np.zeros_like(E), 3, 1.0, ctx=c)
+    assert not mu.any() and e_pol == 0.0
