@@ -995,6 +995,54 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   return SIBFA_OK;
 }
 
+// Truncated conjugate gradient (TCG-n): `order` steps of the solver above
+// from the direct-field guess, with no convergence test, host round trip
+// or residual replacement, then the optional peek step x += omega alpha r.
+// The same matvec, update and direction kernels; a check kernel after each
+// update still raises the device flag on p.Tp <= 0 (a zero residual raises
+// it first, harmlessly), read back with the energy.
+sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, double* mu_out, double* e_pol) {
+  SysView s = make_view(c);
+  hipStream_t st = c->stream;
+  const bool mix = mixed(c);
+  // the solver vectors (x, r) are overwritten: the last solve's dipoles
+  // stay in mu_c for warm starts, and the next energy call solves again
+  c->mu_valid = false;
+  if (c->npol == 0) {
+    if (mu_out) launch_fill_double(mu_out, 0.0, 3 * (size_t)c->n, st);
+    if (e_pol) *e_pol = 0.0;
+    return sync_read(c);
+  }
+  ensure_coef(c);
+  launch_precond(s, c->E0, c->x, st);
+  launch_copy4(c->x, c->x, c->x32, c->npol, st);
+  matvec(c, c->x, c->x32, c->t, -1, mix);
+  launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
+  int* flag = c->dints + 8;
+  double* zz_dev = reinterpret_cast<double*>(c->dints + 12);
+  launch_fill_int(flag, 0, 4, st);
+  for (int k = 0; k < order; ++k) {
+    if (k > 0)
+      launch_direction(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k - 1) & 1), c->z, c->p, c->p32,
+                       nullptr, k, 0.0, -1.0, nullptr, st);
+    matvec(c, c->p, c->p32, c->q, S_PQ, mix);
+    launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p, c->q,
+                  st);
+    launch_check(c->red, flag, zz_dev, k + 1, 0.0, -1.0, nullptr, st);
+  }
+  if (omega != 0.0) launch_axpy4(s, c->x, c->z, omega, st);
+  launch_dot(s, c->red, c->x, c->E0, S_MUE, st);
+  if (mu_out) launch_pol_to_caller(s, c->perm, c->x, mu_out, st);
+  HIP_TRY(hipMemcpyAsync(c->h_ints + 8, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  double mue = 0.0;
+  sibfa_status e = read_totals(c, {S_MUE}, &mue);
+  if (e != SIBFA_OK) return e;
+  if (c->h_ints[8] && c->h_ints[9] == 2)
+    return fail(c, SIBFA_E_NOT_SPD, "p.Tp <= 0: the polarization matrix is not positive definite");
+  if (e_pol) *e_pol = -0.5 * kCoulomb * mue;
+  return SIBFA_OK;
+}
+
 // Spreading brick edge along an axis of K points: the largest size <=
 // kBrick whose last (partial) brick still spans order - 1 points, so that
 // every grid point lies in the tiles of at most two bricks per axis; 0 if
@@ -1433,6 +1481,19 @@ sibfa_status sibfa_solve_induced(sibfa_ctx c, int warm_start, double* mu_out, in
   if (st != SIBFA_OK) return st;
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SIBFA_OK : hip_fail(c, e, "kernel launch");
+}
+
+sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, double* mu_out,
+                             double* e_pol) {
+  if (!c) return SIBFA_E_ARG;
+  if (order < 1 || order > SIBFA_TCG_MAX_ORDER)
+    return fail(c, SIBFA_E_ARG, "order must lie in 1.." + std::to_string(SIBFA_TCG_MAX_ORDER));
+  if (!std::isfinite(omega)) return fail(c, SIBFA_E_ARG, "omega must be finite");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
+  return solve_tcg(c, order, omega, mu_out, e_pol);
 }
 
 sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, double* forces,

@@ -78,6 +78,8 @@ void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipS
 void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
                   double zz_replace, const double* zz_ref, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
+// x += w z over the polarizable sites
+void launch_axpy4(const SysView& s, double4* x, const double4* z, double w, hipStream_t st);
 // a.b into slot (and a.b2 into slot2 when b2 is given)
 void launch_dot(const SysView& s, Reduce& red, const double4* a, const double4* b, int slot,
                 hipStream_t st, const double4* b2 = nullptr, int slot2 = -1);

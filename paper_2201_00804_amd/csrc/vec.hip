@@ -95,12 +95,25 @@ __global__ __launch_bounds__(kBlock) void k_direction(SysView s, Reduce red, int
   if (stopped(red.stop)) return;
   if (flag && check_stop(red, flag, iter, zz_stop, zz_replace, zz_ref)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double beta = slot_total(red, num) / slot_total(red, den);
+  // r.z = 0 only for a zero residual (then z = 0 and p = 0 as well)
+  const double rz_old = slot_total(red, den);
+  const double beta = rz_old == 0.0 ? 0.0 : slot_total(red, num) / rz_old;
   if (i >= s.npol) return;
   const double4 zv = z[i], pv = p[i];
   const double4 o = make_double4(zv.x + beta * pv.x, zv.y + beta * pv.y, zv.z + beta * pv.z, 0.0);
   p[i] = o;
   p32[i] = make_float4((float)o.x, (float)o.y, (float)o.z, 0.f);
+}
+
+// x += w z (the peek step of the truncated solver)
+__global__ __launch_bounds__(kBlock) void k_axpy4(SysView s, double4* x, const double4* z,
+                                                  double w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.npol) return;
+  const double4 zv = z[i];
+  double4 xv = x[i];
+  xv.x += w * zv.x; xv.y += w * zv.y; xv.z += w * zv.z;
+  x[i] = xv;
 }
 
 __global__ __launch_bounds__(kBlock) void k_precond(SysView s, const double4* in, double4* out) {
@@ -280,6 +293,9 @@ void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double
                   double zz_replace, const double* zz_ref, hipStream_t st) {
   hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, st, red, flag, zz_out, iter, zz_stop,
                      zz_replace, zz_ref);
+}
+void launch_axpy4(const SysView& s, double4* x, const double4* z, double w, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy4, grid_for(s.npol), dim3(kBlock), 0, st, s, x, z, w);
 }
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st) {
   hipLaunchKernelGGL(k_precond, grid_for(s.npol), dim3(kBlock), 0, st, s, in, out);
