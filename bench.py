@@ -142,6 +142,48 @@ def run_gpu(sysd, prm, precision, steps, warmup):
     return out
 
 
+def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
+    """Fixed-cost truncated CG (with the peek step) against the converged
+    solve, both without forces (TCG forces are not provided): ms per
+    evaluation (positions update, lists, field, solve, E_pol) and E_pol."""
+    import torch
+    from paper_2201_00804_amd import Engine, default_params
+
+    params = default_params(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"],
+                            order=prm["order"], tol=prm["tol"], precision=precision,
+                            max_iter=400)
+    eng = Engine(0)
+    eng.load(sysd, params)
+    pos = torch.as_tensor(sysd["pos"], dtype=torch.float64, device=eng.device).contiguous()
+
+    def pcg():
+        eng.update_positions(pos)
+        eng.solve(warm_start=False)
+        return eng.energy_forces(forces=False)[0]
+
+    def tcg(n):
+        eng.update_positions(pos)
+        return eng.solve_tcg(n, omega, mu_out=False)[1]
+
+    variants = [("pcg", pcg)] + [(f"tcg{n}_peek", (lambda n=n: tcg(n))) for n in orders]
+    out = {}
+    for name, fn in variants:
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e = fn()
+        torch.cuda.synchronize()
+        out[name] = dict(ms=round(1e3 * (time.perf_counter() - t0) / steps, 3), e_pol=e)
+    eng.close()
+    ref = out["pcg"]["e_pol"]
+    for name in out:
+        out[name]["e_pol_rel_err"] = abs(out[name]["e_pol"] - ref) / abs(ref)
+    out["omega"] = omega
+    return out
+
+
 def roofline(res, precision):
     """Roofline point of the kernel with the largest share of the timed
     region.  The real-space matvec streams its list and coefficient arrays
@@ -319,6 +361,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=300)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tcg", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -390,6 +433,16 @@ def main():
                                            np.mean(a["forces"] ** 2))),
             "mu_rms_debye": float(4.803204 * np.sqrt(np.mean(np.sum((b["mu"] - a["mu"]) ** 2, 1)))),
         }
+    if not args.no_tcg:
+        out["tcg"] = {}
+        for prec in precisions:
+            print(f"[bench] tcg {prec}: converged solve vs TCG-1/TCG-2 with peek, no forces",
+                  file=sys.stderr, flush=True)
+            t = run_tcg(sysd, prm, prec, args.steps, args.warmup)
+            out["tcg"][prec] = t
+            print("[bench] tcg " + prec + ": " + ", ".join(
+                f"{k} {v['ms']} ms (E_pol rel err {v['e_pol_rel_err']:.2e})"
+                for k, v in t.items() if isinstance(v, dict)), file=sys.stderr, flush=True)
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_warmup} warm-up + {args.serve_requests} requests",
               file=sys.stderr, flush=True)
