@@ -14,7 +14,8 @@ import torch
 
 import oracle
 from oracle.model import System, Context, permanent_field
-from synth import water_box, water_box_ortho, water_cluster
+from oracle.units import COULOMB
+from synth import water_box, water_box_ortho, water_cluster, config_system
 from tests.gpu_util import say, oracle_params, gpu_params, engine_for, rel_err, pol_rows
 
 pytestmark = pytest.mark.gpu
@@ -120,4 +121,38 @@ def test_tcg_bad_arguments():
         assert ei.value.status == -1, (order, omega)
     mu, e = eng.solve_tcg(64, 0.0)   # the largest order is accepted
     assert np.isfinite(e)
+    eng.close()
+
+
+@pytest.mark.parametrize("name", ["box4096", "box32000"])
+def test_tcg_is_the_truncated_pcg_at_full_size(name):
+    """At the benchmark sizes, where the oracle cannot run the solve:
+    TCG-n without the peek step is the PCG stopped after n iterations (the
+    same kernels in the same order, FP64), bit for bit; the peek step adds
+    omega alpha (E - T mu) computed from the library's own field and
+    operator; E_pol is -1/2 f mu.E0 of the returned dipoles and field."""
+    from paper_2201_00804_amd import SibfaError
+    d, prm = config_system(name)
+    kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"])
+    n_it = 3
+    eng = engine_for(d, gpu_params(d, tol=1e-14, max_iter=n_it, **kw))
+    say(f"[tcg] {name}: n_sites={len(d['pos'])}, {n_it} iterations")
+    with pytest.raises(SibfaError) as ei:
+        eng.solve()
+    assert ei.value.status == -5          # not converged: mu is the 3rd iterate
+    mu_pcg = eng.get_dipoles()
+    mu, e = eng.solve_tcg(n_it, 0.0)
+    assert torch.equal(mu, mu_pcg)
+    E0 = eng.permanent_field()
+    e_ref = -0.5 * COULOMB * float((mu * E0).sum())
+    assert abs(e - e_ref) <= 1e-12 * abs(e_ref), (e, e_ref)
+    omega = 0.85
+    mu_pk, _ = eng.solve_tcg(n_it, omega)
+    r = (E0 - eng.apply_T(mu)).cpu().numpy()
+    a3 = np.asarray(d["alpha"])[:, [0, 1, 2, 1, 3, 4, 2, 4, 5]].reshape(-1, 3, 3)
+    want = mu.cpu().numpy() + omega * np.einsum("nab,nb->na", a3, r)
+    got = mu_pk.cpu().numpy()
+    err = rel_err(got - mu.cpu().numpy(), want - mu.cpu().numpy())
+    say(f"  peek step vs omega alpha (E - T mu): {err:.2e} of its largest entry")
+    assert err < 1e-8
     eng.close()
