@@ -164,9 +164,11 @@ sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
 /* Truncated conjugate gradient (TCG-n), the fixed-cost alternative to an
  * iterated solve that the paper names (Many-Body Polarization; defined in
  * the work it cites).  The dipoles are the `order`-th iterate of the PCG
- * above from the direct-field guess alpha E, with no convergence test,
- * then, when omega != 0, one peek step mu += omega alpha r with that
- * iterate's residual r.  order: 1..SIBFA_TCG_MAX_ORDER.  mu_out [n][3]
+ * above, with no convergence test, then, when omega != 0, one peek step
+ * mu += omega alpha r with that iterate's residual r.  The guess is the
+ * direct field alpha E, or with warm_start the dipoles kept from the last
+ * solve_induced or given to sibfa_set_dipoles (an extrapolated guess;
+ * SIBFA_E_STATE if there are none).  order: 1..SIBFA_TCG_MAX_ORDER.  mu_out [n][3]
  * (device, zero rows at non-polarizable sites) or NULL; e_pol (HOST,
  * kcal/mol) = -1/2 mu.E (the form of Eq. 19) or NULL.  Runs in the
  * context's precision and returns after a stream synchronisation.  The
@@ -176,8 +178,8 @@ sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
  * Returns SIBFA_E_ARG for a bad order or a non-finite omega, SIBFA_E_NOT_SPD
  * if p.Tp <= 0 in a step. */
 #define SIBFA_TCG_MAX_ORDER 64
-sibfa_status sibfa_solve_tcg(sibfa_ctx ctx, int order, double omega, double* mu_out,
-                             double* e_pol);
+sibfa_status sibfa_solve_tcg(sibfa_ctx ctx, int order, double omega, int warm_start,
+                             double* mu_out, double* e_pol);
 
 /* Energies (HOST, kcal/mol) and forces [n][3] (device, kcal/mol/A, or
  * NULL) at the current dipoles; solves first if they are stale.  virial

@@ -326,14 +326,14 @@ def solve(sysm, prm, E0, ctx=None, x0=None):
     return pcg(mv, pc, E0, x0, prm.tol, prm.max_iter)
 
 
-def tcg(sysm, prm, E0, order, omega=0.0, ctx=None):
-    """TCG-n dipoles from the direct-field guess x0 = alpha E0 (with the
-    optional peek step, see solver.tcg) and E_pol at them in the form of
-    Eq. 19.  Returns (mu, E_pol)."""
+def tcg(sysm, prm, E0, order, omega=0.0, ctx=None, x0=None):
+    """TCG-n dipoles from the guess x0 (default the direct field alpha E0),
+    with the optional peek step (see solver.tcg), and E_pol at them in the
+    form of Eq. 19.  Returns (mu, E_pol)."""
     c = _ctx(sysm, prm, ctx)
     mv = lambda v: apply_T(sysm, prm, v, ctx=c)
     pc = lambda r: precond(sysm, r)
-    mu = sv.tcg(mv, pc, E0, pc(E0), order, omega)
+    mu = sv.tcg(mv, pc, E0, pc(E0) if x0 is None else x0, order, omega)
     return mu, -0.5 * COULOMB * float(np.sum(mu * E0))
 
 

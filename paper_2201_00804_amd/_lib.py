@@ -59,7 +59,7 @@ SIGNATURES = [
     ("sibfa_permanent_field", ctypes.c_int, [_P, _P]),
     ("sibfa_apply_T", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_solve_induced", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), _D]),
-    ("sibfa_solve_tcg", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _P, _D]),
+    ("sibfa_solve_tcg", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _D]),
     ("sibfa_energy_forces", ctypes.c_int, [_P, _D, _D, _P, _P]),
     ("sibfa_get_dipoles", ctypes.c_int, [_P, _P]),
     ("sibfa_set_dipoles", ctypes.c_int, [_P, _P]),

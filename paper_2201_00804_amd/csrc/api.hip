@@ -996,12 +996,14 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
 }
 
 // Truncated conjugate gradient (TCG-n): `order` steps of the solver above
-// from the direct-field guess, with no convergence test, host round trip
+// from the direct-field guess (or the kept dipoles when warm), with no
+// convergence test, host round trip
 // or residual replacement, then the optional peek step x += omega alpha r.
 // The same matvec, update and direction kernels; a check kernel after each
 // update still raises the device flag on p.Tp <= 0 (a zero residual raises
 // it first, harmlessly), read back with the energy.
-sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, double* mu_out, double* e_pol) {
+sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, bool warm, double* mu_out,
+                       double* e_pol) {
   SysView s = make_view(c);
   hipStream_t st = c->stream;
   const bool mix = mixed(c);
@@ -1014,7 +1016,8 @@ sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, double* mu_out, dou
     return sync_read(c);
   }
   ensure_coef(c);
-  launch_precond(s, c->E0, c->x, st);
+  if (warm) launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
+  else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
   matvec(c, c->x, c->x32, c->t, -1, mix);
   launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
@@ -1483,8 +1486,8 @@ sibfa_status sibfa_solve_induced(sibfa_ctx c, int warm_start, double* mu_out, in
   return e == hipSuccess ? SIBFA_OK : hip_fail(c, e, "kernel launch");
 }
 
-sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, double* mu_out,
-                             double* e_pol) {
+sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, int warm_start,
+                             double* mu_out, double* e_pol) {
   if (!c) return SIBFA_E_ARG;
   if (order < 1 || order > SIBFA_TCG_MAX_ORDER)
     return fail(c, SIBFA_E_ARG, "order must lie in 1.." + std::to_string(SIBFA_TCG_MAX_ORDER));
@@ -1492,8 +1495,10 @@ sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, double* mu_ou
   HIP_TRY(hipSetDevice(c->device));
   sibfa_status st = prepare(c);
   if (st != SIBFA_OK) return st;
+  if (warm_start && !c->mu_have)
+    return fail(c, SIBFA_E_STATE, "warm start without dipoles (solve or set_dipoles first)");
   if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
-  return solve_tcg(c, order, omega, mu_out, e_pol);
+  return solve_tcg(c, order, omega, warm_start != 0, mu_out, e_pol);
 }
 
 sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, double* forces,

@@ -141,14 +141,14 @@ class Engine:
                                                  ctypes.byref(it), ctypes.byref(rms)))
         return mu, it.value, rms.value
 
-    def solve_tcg(self, order, omega=0.0, mu_out=True):
+    def solve_tcg(self, order, omega=0.0, warm_start=False, mu_out=True):
         """TCG-n dipoles (or None) and E_pol at them (kcal/mol)."""
         mu = None
         if mu_out:
             mu = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
         e = ctypes.c_double(0.0)
-        self._check(self.lib.sibfa_solve_tcg(self.h, int(order), float(omega), _ptr(mu),
-                                             ctypes.byref(e)))
+        self._check(self.lib.sibfa_solve_tcg(self.h, int(order), float(omega),
+                                             int(bool(warm_start)), _ptr(mu), ctypes.byref(e)))
         return mu, e.value
 
     def energy_forces(self, forces=True, out=None):
