@@ -5,6 +5,9 @@
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
         --copy-bytes N --command CMD
 
+    python -m paper_2201_00804_amd.profsum valu --counters C.csv --trace TRACE_CSV \
+        --command CMD [--command CMD2]
+
 `stats` lists the per-kernel totals of `--kernel-trace --stats` and, for
 each kernel, the mean over its working launches: the solver enqueues its
 iterations in batches of four and launches queued after the device-side stop
@@ -120,6 +123,56 @@ def traffic(args):
     print("\n".join(out))
 
 
+# gfx950: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 VALU instruction occupies
+# its SIMD for 4 cycles (16 lanes per cycle, FP32 unpacked and FP64 alike)
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def valu(args):
+    """VALU (and SALU) instructions per working dispatch from SQ_INSTS_VALU /
+    SQ_INSTS_SALU, over each kernel's working mean duration in a kernel
+    trace, against the issue peak."""
+    inst = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(args.counters)):
+        inst[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = collections.defaultdict(list)
+    for r in csv.DictReader(open(args.trace)):
+        dur[short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) -
+                                             int(r["Start_Timestamp"])) / 1e3)
+
+    def working_mean(v):
+        med = sorted(v)[len(v) // 2]
+        w = [x for x in v if x >= IDLE_FRACTION * med]
+        return sum(w) / len(w)
+
+    rows = []
+    for k, d in dur.items():
+        if k not in inst or "SQ_INSTS_VALU" not in inst[k]:
+            continue
+        t = working_mean(d)
+        nv = working_mean(inst[k]["SQ_INSTS_VALU"])
+        ns = working_mean(inst[k]["SQ_INSTS_SALU"]) if "SQ_INSTS_SALU" in inst[k] else 0.0
+        rows.append((t * len(d), k, t, nv, ns))
+    rows.sort(reverse=True)
+    out = ["# VALU issue of the kernels, 32,000-water box", "", "Commands:", "", "```"]
+    out += args.command
+    out += ["```", "",
+            "Instructions are wavefront instructions per working dispatch (counter run); "
+            "durations are working means from the kernel trace (a separate run, the same "
+            "workload).  Issue peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU "
+            f"instruction = {VALU_PEAK / 1e9:.1f} G/s.  Transcendental and FP64 "
+            "transcendental-helper instructions take longer than 4 cycles, so a kernel "
+            "bound by them reads below 1.", "",
+            "| kernel | working avg us | VALU instr (M) | VALU G/s | fraction of issue peak | "
+            "SALU instr (M) |",
+            "|---|---|---|---|---|---|"]
+    for _, k, t, nv, ns in rows[:args.top]:
+        rate = nv / (t * 1e-6)
+        out.append(f"| `{k}` | {t:.2f} | {nv / 1e6:.2f} | {rate / 1e9:.1f} | "
+                   f"{rate / VALU_PEAK:.3f} | {ns / 1e6:.2f} |")
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -138,8 +191,13 @@ def main(argv=None):
     b.add_argument("--copy-write", required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--command", action="append", required=True)
+    c = sub.add_parser("valu")
+    c.add_argument("--counters", required=True)
+    c.add_argument("--trace", required=True)
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--top", type=int, default=24)
     args = ap.parse_args(argv)
-    (stats if args.cmd == "stats" else traffic)(args)
+    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
 
 
 if __name__ == "__main__":
