@@ -6,7 +6,9 @@ P2  Ewald beta-invariance of E0, T p, E_pol, E_elec (self terms, exclusion
     corrections and Thole composition).
 P3  NaCl / CsCl Madelung constants (charge Ewald).
 P4  Cluster in a growing box: Ewald plus the surface term -> direct sum.
-P5  SPME -> brute-force Ewald as the grid is refined / order raised.
+P5  SPME -> brute-force Ewald as the grid is refined / order raised, and
+    agreement to 1e-8 at order 8 on a fine grid (with planted 1% errors in
+    the dipole and quadrupole spread shown to break that bar).
 P6  Zero net force (direct, Ewald).
 P7  Finite-difference forces (direct, Ewald, SPME).
 P8  E_pol of Eq. 19 equals the variational Eq. 17 at convergence.
@@ -199,6 +201,47 @@ def test_p5_spme_converges_to_ewald():
                                       **base), forces=False)
         eo.append(abs(o["E_elec"] - ref["E_elec"]))
     assert eo[0] > eo[1] > eo[2]
+
+
+def _p5_fine_errors(s, base):
+    ref = oracle.evaluate(s, Params(method="ewald", realspace="minimage", **base))
+    o = oracle.evaluate(s, Params(method="spme", grid=(48, 48, 48), order=8, **base))
+    F = ref["forces"]
+    return (abs(o["E_pol"] / ref["E_pol"] - 1.0), abs(o["E_elec"] / ref["E_elec"] - 1.0),
+            np.abs(o["forces"] - F).max() / np.abs(F).max())
+
+
+# measured on this machine: 9e-11, 4e-10 and 6e-9
+P5_FINE_BARS = (1e-8, 1e-8, 5e-8)
+
+
+def test_p5_spme_matches_ewald_at_fine_grid():
+    """At order 8 on a 48^3 grid (0.2 A spacing) SPME reproduces the
+    brute-force Ewald energies and forces to 1e-8, so every spread and gather
+    term (charge, dipole, quadrupole; field to third derivatives) is pinned
+    by value, not only by the direction of convergence."""
+    s = System.from_dict(water_box(27, 9.5, 3))
+    errs = _p5_fine_errors(s, dict(beta=0.45, cutoff=4.5, tol=1e-12))
+    assert all(e <= b for e, b in zip(errs, P5_FINE_BARS)), errs
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_p5_fine_grid_bar_sees_a_wrong_spread_factor(which, monkeypatch):
+    """A 1% error planted in the dipole (1) or quadrupole (2) amplitude of
+    the oracle's SPME spread breaks the fine-grid bar."""
+    from oracle import recip
+    orig = recip.spme_spread
+
+    def planted(pos, box, K, order, mult):
+        m = list(mult)
+        if m[which] is not None:
+            m[which] = 1.01 * m[which]
+        return orig(pos, box, K, order, tuple(m))
+
+    monkeypatch.setattr(recip, "spme_spread", planted)
+    s = System.from_dict(water_box(27, 9.5, 3))
+    errs = _p5_fine_errors(s, dict(beta=0.45, cutoff=4.5, tol=1e-12))
+    assert any(e > 10 * b for e, b in zip(errs, P5_FINE_BARS)), errs
 
 
 def test_p5_spme_converges_orthorhombic():
