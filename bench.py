@@ -29,16 +29,25 @@ if ROOT not in sys.path:
 METRIC = "pol+elec energy/force evals/s @32k waters, FP32-mixed vs FP64; p50/p99 latency"
 WORKLOAD = "box32000"
 
-# MI355X published peaks.  The pair kernels run on the vector ALUs without
-# packed FP32 (disabled at compile time), so FP32 and FP64 share the
-# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s rate.
-PEAK_ALU_TFLOPS = 78.6
+# MI355X published peaks: vector FP64 78.6 TFLOP/s, vector FP32 157.3
+# TFLOP/s (the FP32 figure counts packed two-wide FP32 instructions, which
+# this build leaves disabled: its FP32 kernels can issue at most half of
+# it), HBM 8 TB/s.
+PEAK_VALU_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic flop counts (FMA = 2, each erfc/exp/rsqrt = 1) of one pair of
 # the real-space force and permanent-field kernels.
 FLOPS_FORCE_PAIR = 560
 FLOPS_FIELD_PAIR = 190
+# Algorithmic flops of one unordered polarizable pair of the matvec T p,
+# counted for the pair evaluated from scratch (the method's work, whatever
+# the kernel caches): separation and r^2 (8), rsqrt and r (2), the Ewald
+# B1, B2 with exp(-beta^2 r^2) and erfc (32), the Thole lambda_3,
+# lambda_5 and bare coefficients (20), the two screened coefficients (6),
+# and the dipole field of each site at the other, R.p and c2 R (R.p) -
+# c1 p accumulated (2 x 13).
+FLOPS_MATVEC_HALF_PAIR = 95
 
 # Algorithmic bytes of the real-space matvec kernel k_matvec, streamed once
 # per launch (operands gathered for neighbour j are shared by every row that
@@ -186,9 +195,11 @@ def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
 
 def roofline(res, precision):
     """Roofline point of the kernel with the largest share of the timed
-    region.  The real-space matvec streams its list and coefficient arrays
-    (HBM-bound); the force and field pair kernels are priced in flops
-    against the vector-ALU peak."""
+    region, the real-space matvec.  It is priced as vector-ALU work (the
+    method's flops per unordered pair times the pairs of one launch, over
+    the launch time, against the vector peak of the kernel's precision); the
+    HBM rate of the bytes it streams is given beside it.  The force and field
+    pair kernels, if they dominate, are priced in flops the same way."""
     prof = res["profile"]
     ms, calls, pairs = prof["ms"], prof["calls"], prof["pairs"]
     npol = res["stats"]["n_polarizable"]
@@ -206,22 +217,60 @@ def roofline(res, precision):
                 phase_share=share,
                 timing="HIP events around each launch on the library stream, over the "
                        "timed steps repeated with only that phase instrumented")
+    peak = PEAK_VALU_TFLOPS[precision]
     if dom == "matvec":
+        half_pairs = (pairs["pol"] + pairs["pol_same_molecule"]) / 2.0
+        fl = half_pairs * FLOPS_MATVEC_HALF_PAIR
+        tf = fl / (avg_ms * 1e-3) / 1e12
         b = matvec_bytes(pairs, npol, precision)
         gbs = b / (avg_ms * 1e-3) / 1e9
-        return dict(kernel="k_matvec", bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS,
-                    unit="GB/s", frac=round(gbs / PEAK_HBM_GBS, 4),
-                    traffic=measured_traffic(precision), bytes_per_launch=int(b), **base)
+        return dict(kernel="k_matvec", bound="alu", achieved=round(tf, 3), peak=peak,
+                    unit="TFLOP/s", frac=round(tf / peak, 4),
+                    traffic=measured_traffic(precision), flops_per_launch=int(fl),
+                    half_pairs_per_launch=int(half_pairs),
+                    hbm=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                             frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_launch=int(b)),
+                    **base)
     if dom in ("force_real", "field_real"):
         fl = (pairs["all"] + pairs["same_molecule"]) * \
             (FLOPS_FORCE_PAIR if dom == "force_real" else FLOPS_FIELD_PAIR)
         tf = fl / (avg_ms * 1e-3) / 1e12
         return dict(kernel="k_force" if dom == "force_real" else "k_perm", bound="alu",
-                    achieved=round(tf, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                    frac=round(tf / PEAK_ALU_TFLOPS, 4), traffic=None,
+                    achieved=round(tf, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(tf / peak, 4), traffic=None,
                     flops_per_launch=int(fl), **base)
     return dict(kernel=dom, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=None, traffic=None, **base)
+
+
+def recip_chain(res, precision, K):
+    """HBM rate of the solver's reciprocal chain against its algorithmic
+    bytes per iteration (grid of K^3 values of w bytes; w = 4 in mixed
+    precision, 8 in FP64; N_pol polarizable sites):
+      spread (tile + fold)   K^3 w written + position and p read (6 w per site)
+      FFT pair (fwd + inv)   two transforms of three read+write passes: 12 K^3 w
+      gather (+ p.Tp)        K^3 w read + position (3 w), p (24 B) read and
+                             T p read and written (2 x 24 B) per site
+    Phase times are the HIP-event means per launch group of the profiled
+    steps (the chain runs beside the real-space matvec)."""
+    prof = res["profile"]
+    npol = res["stats"]["n_polarizable"]
+    w = 4 if precision == "mixed" else 8
+    grid = K ** 3 * w
+    parts = {"spread": grid + 6 * w * npol, "fft": 12 * grid,
+             "matvec_recip": grid + (3 * w + 72) * npol}
+    out, tb, tt = {}, 0.0, 0.0
+    for ph, b in parts.items():
+        calls = max(prof["calls"][ph], 1)
+        ms = prof["ms"][ph] / calls
+        gbs = b / (ms * 1e-3) / 1e9
+        out[ph] = dict(avg_ms=round(ms, 5), bytes=int(b), achieved_gbs=round(gbs, 1),
+                       frac=round(gbs / PEAK_HBM_GBS, 4))
+        tb += b
+        tt += ms
+    out["chain"] = dict(ms=round(tt, 5), bytes=int(tb), achieved_gbs=round(tb / (tt * 1e-3) / 1e9, 1),
+                        frac=round(tb / (tt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4))
+    return out
 
 
 def copy_probe(mib, reps):
@@ -238,13 +287,82 @@ def copy_probe(mib, reps):
                       "reps": reps}), flush=True)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+# State shared with the forked real-space workers of the CPU baseline.
+_MP = {}
+
+
+def _rs_rows_worker(rows):
+    """One worker's share of the oracle's real-space pair sums: rows
+    (pol_rows, all_rows) of the sample.  Returns the time of each part."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import realspace as rs
+    from oracle.model import Context
+
+    s, p, pf = _MP["s"], _MP["p"], _MP["pf"]
+    rp, ra = rows
+    t = {}
+    with threadpool_limits(limits=1):
+        # the neighbour search's cost per row: a one-row search measures the
+        # fixed part (tree and same-molecule pairs over the whole box)
+        t0 = time.perf_counter()
+        Context(s, p, subset=np.union1d(rp, ra)[:1])
+        t1 = time.perf_counter()
+        ctx = Context(s, p, subset=np.union1d(rp, ra))
+        t["pairs"] = max((time.perf_counter() - t1) - (t1 - t0), 0.0)
+        mult = (s.q, s.dip, s.th)
+        none3 = (None, None, None)
+        I = ctx.pairs.i
+        m_pol = np.isin(I, rp)
+        m_all = np.isin(I, ra)
+        t0 = time.perf_counter()
+        rs.pair_sum(ctx.pairs, "Mmu", ctx.kernel, p.beta, ctx.thole, none3, mult, "field", s.n,
+                    pair_mask=m_pol)
+        t["real_field"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rs.pair_sum(ctx.pairs, ctx.mumu_cls, ctx.kernel, p.beta, ctx.thole, none3,
+                    (None, pf, None), "field", s.n, pair_mask=m_pol & ctx.is_pol[ctx.pairs.j])
+        t["real_matvec"] = time.perf_counter() - t0
+        mud = (None, pf, None)
+        t0 = time.perf_counter()
+        for cls, a, b in (("MM", mult, mult), ("Mmu", mud, mult), ("Mmu", mult, mud),
+                          (ctx.mumu_cls, mud, mud)):
+            rs.pair_sum(ctx.pairs, cls, ctx.kernel, p.beta, ctx.thole, a, b, "force", s.n,
+                        pair_mask=m_all)
+        t["real_force"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rs.pair_sum(ctx.pairs, "MM", ctx.kernel, p.beta, ctx.thole, mult, mult, "energy", s.n,
+                    pair_mask=m_all)
+        t["real_energy"] = time.perf_counter() - t0
+    return t
+
+
 def cpu_baseline(sysd, prm, iters, sample=360):
     """The FP64 oracle on a bounded sample of the same box, scaled to one
     evaluation: the oracle's real-space pair sums for `sample` sites
     (polarizable ones for E and T p, arbitrary ones for forces and the MM
     energy) and its neighbour search for them, each scaled by N/sample, plus
     one full-size SPME pass of each kind (permanent field; dipoles, once per
-    matvec; combined density for forces)."""
+    matvec; combined density for forces).
+
+    Two timings: one process on one thread, and the real-space rows split
+    over every host core the process may use (forked worker processes, one
+    thread each; each part timed by its slowest worker) with the SPME passes
+    (one process, one thread) added unchanged."""
+    import multiprocessing
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -287,8 +405,8 @@ def cpu_baseline(sysd, prm, iters, sample=360):
         mask_t = m_pol & ctx.is_pol[ctx.pairs.j]
         _, dt = timed(lambda: rs.pair_sum(ctx.pairs, ctx.mumu_cls, ctx.kernel, p.beta, ctx.thole,
                                           none3, (None, pf, None), "field", s.n, pair_mask=mask_t))
-        _, t_spme_t = timed(lambda: ctx.recip_derivs((None, pf, None), s.pos[samp_pol], 1))
-        t["matvec_per_iter"] = dt * len(pol) / sample + t_spme_t
+        t["real_matvec"] = dt * len(pol) / sample
+        _, t["spme_matvec"] = timed(lambda: ctx.recip_derivs((None, pf, None), s.pos[samp_pol], 1))
         mud = (None, pf, None)
 
         def forces():
@@ -304,16 +422,45 @@ def cpu_baseline(sysd, prm, iters, sample=360):
         _, dt = timed(lambda: rs.pair_sum(ctx.pairs, "MM", ctx.kernel, p.beta, ctx.thole, mult,
                                           mult, "energy", s.n, pair_mask=m_all))
         t["real_energy"] = dt * s.n / sample
-        t_eval = (t["pairs"] + t["real_field"] + t["spme_field"] + (iters + 1) *
-                  t["matvec_per_iter"] + t["real_force"] + t["spme_force"] + t["real_energy"])
-    return dict(value=1.0 / t_eval, unit="evals/s", cores=1, kind="oracle",
+
+    def per_eval(tt):
+        return (tt["pairs"] + tt["real_field"] + t["spme_field"] +
+                (iters + 1) * (tt["real_matvec"] + t["spme_matvec"]) + tt["real_force"] +
+                t["spme_force"] + tt["real_energy"])
+
+    t_eval1 = per_eval(t)
+    # the real-space rows over every usable core
+    cores = max(1, len(os.sched_getaffinity(0)))
+    _MP.update(s=s, p=p, pf=pf)
+    chunks = [(samp_pol[k::cores], samp_all[k::cores]) for k in range(cores)]
+    mp = multiprocessing.get_context("fork")
+    t0 = time.perf_counter()
+    with mp.Pool(cores) as pool:
+        parts = pool.map(_rs_rows_worker, chunks, chunksize=1)
+    t_map = time.perf_counter() - t0
+    _MP.clear()
+    tm = {}
+    for k in ("pairs", "real_field", "real_matvec", "real_force", "real_energy"):
+        slowest = max(w[k] for w in parts)
+        rows = len(pol) if k in ("real_field", "real_matvec") else s.n
+        tm[k] = slowest * rows / sample
+    tm["pairs"] = t_fixed + max(w["pairs"] for w in parts) * s.n / len(both)
+    t_eval_mc = per_eval(tm)
+    return dict(value=1.0 / t_eval_mc, unit="evals/s", cores=cores, kind="oracle",
+                cpu_model=_cpu_model(),
                 sample=(f"{sample} polarizable + {sample} arbitrary sites of the 32,000-water "
-                        f"box (real-space rows and neighbour search scaled by N/sample) plus "
-                        f"full-size SPME passes (permanent; dipole, once per matvec; combined "
-                        f"for forces); {iters + 1} matvecs per solve; {wall:.1f} s of "
-                        f"measured single-thread CPU work"),
-                seconds_per_eval=round(t_eval, 1),
-                parts_s={k: round(v, 2) for k, v in t.items()})
+                        f"box (real-space rows and neighbour search scaled by N/sample; rows "
+                        f"split over {cores} worker processes, one thread each) plus "
+                        f"full-size SPME passes on one thread (permanent; dipole, once per "
+                        f"matvec; combined for forces); {iters + 1} matvecs per solve; "
+                        f"{wall:.1f} s of single-thread and {t_map:.1f} s of parallel "
+                        f"measured CPU work"),
+                seconds_per_eval=round(t_eval_mc, 1),
+                parts_s={**{k: round(v, 2) for k, v in tm.items()},
+                         **{k: round(t[k], 2) for k in ("spme_field", "spme_matvec",
+                                                        "spme_force")}},
+                single_thread=dict(value=1.0 / t_eval1, cores=1, seconds_per_eval=round(t_eval1, 1),
+                                   parts_s={k: round(v, 2) for k, v in t.items()}))
 
 
 def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0):
@@ -422,13 +569,20 @@ def main():
     }
     for k, r in results.items():
         out[k] = summary(r)
+        out[k]["recip_chain"] = recip_chain(r, k, prm["grid"])
+        if k != head:
+            out[k]["roofline"] = roofline(r, k)
     if "fp64" in results and "mixed" in results:
         a, b = results["fp64"], results["mixed"]
         rel = lambda x, y: abs(x - y) / max(abs(y), 1e-300)
         out["mixed_vs_fp64"] = {
             "speedup": round(a["total_s"] / b["total_s"], 3),
+            "speedup_target": 2.0,
             "e_pol_rel": rel(b["e_pol"], a["e_pol"]),
             "e_elec_rel": rel(b["e_elec"], a["e_elec"]),
+            "e_elec_real_rel": rel(b["stats"]["e_elec_real"], a["stats"]["e_elec_real"]),
+            "e_elec_recip_rel": rel(b["stats"]["e_elec_recip"], a["stats"]["e_elec_recip"]),
+            "iterations": {"fp64": a["iters"], "mixed": b["iters"]},
             "force_rms_rel": float(np.sqrt(np.mean((b["forces"] - a["forces"]) ** 2) /
                                            np.mean(a["forces"] ** 2))),
             "mu_rms_debye": float(4.803204 * np.sqrt(np.mean(np.sum((b["mu"] - a["mu"]) ** 2, 1)))),

@@ -29,11 +29,23 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def _sampled_parity(name, n_sample, seed=3):
+# Bars of the sampled parity.  FP64: both sides FP64, only summation order
+# differs.  Mixed: the GPU's pair and PME arithmetic is FP32 (about 1e-7
+# relative per term), so fields and T rows carry ~1e-6 of their largest
+# entry; the residual against the oracle's field is then set by the FP32
+# field (|alpha dE| ~ 1e-7 e A ~ 5e-7 D), not by the solver tolerance.
+SAMPLED_BARS = {
+    "fp64": dict(field=1e-8, rows=1e-8, resid=None, force=1e-5, erec=1e-9, eself=1e-12),
+    "mixed": dict(field=1e-5, rows=1e-5, resid=1e-5, force=1e-4, erec=1e-6, eself=1e-12),
+}
+
+
+def _sampled_parity(name, n_sample, seed=3, precision="fp64"):
+    bars = SAMPLED_BARS[precision]
     d, prm = config_system(name)
     kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"], tol=prm["tol"])
-    say(f"[large] {name}: {len(d['pos'])} sites, sample {n_sample}")
-    eng = engine_for(d, gpu_params(d, **kw))
+    say(f"[large] {name} {precision}: {len(d['pos'])} sites, sample {n_sample}")
+    eng = engine_for(d, gpu_params(d, precision=precision, max_iter=400, **kw))
     E0_g = eng.permanent_field().cpu().numpy()
     mu_g, it, rms = eng.solve()
     mu_g = mu_g.cpu().numpy()
@@ -53,16 +65,22 @@ def _sampled_parity(name, n_sample, seed=3):
     ctx = Context(s, op, subset=np.union1d(samp_pol, samp_all))
     # permanent field at sampled polarizable sites
     E0_o = permanent_field(s, op, ctx=ctx, sites=samp_pol)
-    assert rel_err(E0_g[samp_pol], E0_o) < 1e-8, rel_err(E0_g[samp_pol], E0_o)
+    e_field = rel_err(E0_g[samp_pol], E0_o)
     # rows of T applied to the GPU dipoles, and the residual at those rows
     Tmu_o = apply_T(s, op, mu_g[pol], ctx=ctx, sites=samp_pol)
-    assert rel_err(Tmu_g[samp_pol], Tmu_o) < 1e-8, rel_err(Tmu_g[samp_pol], Tmu_o)
+    e_rows = rel_err(Tmu_g[samp_pol], Tmu_o)
     a3 = s.alpha3[samp_pol]
     z = np.einsum("nab,nb->na", a3, E0_o - Tmu_o)
-    assert DEBYE * np.sqrt(np.mean(np.sum(z * z, 1))) < 20 * prm["tol"]
+    resid = DEBYE * np.sqrt(np.mean(np.sum(z * z, 1)))
     # forces at fixed mu at sampled sites
     _, _, _, F_o = energy_forces(s, op, mu_g[pol], None, ctx=ctx, sites=samp_all)
-    assert rms_rel(F_g[samp_all], F_o) < 1e-5, rms_rel(F_g[samp_all], F_o)
+    e_force = rms_rel(F_g[samp_all], F_o)
+    say(f"  field {e_field:.2e}, T rows {e_rows:.2e}, residual vs oracle field {resid:.2e} D, "
+        f"forces {e_force:.2e}")
+    assert e_field < bars["field"]
+    assert e_rows < bars["rows"]
+    assert resid < (bars["resid"] or 20 * prm["tol"])
+    assert e_force < bars["force"]
     # E_pol from the returned arrays (Eq. 19) and the variational form (Eq. 17)
     e19 = -0.5 * COULOMB * float(np.sum(mu_g[pol] * E0_g[pol]))
     assert e_pol == pytest.approx(e19, rel=1e-12)
@@ -76,8 +94,10 @@ def _sampled_parity(name, n_sample, seed=3):
     eself = -np.sum(b / np.sqrt(np.pi) * s.q ** 2
                     + 2 * b ** 3 / (3 * np.sqrt(np.pi)) * np.sum(s.dip ** 2, 1)
                     + 8 * b ** 5 / (45 * np.sqrt(np.pi)) * np.sum(s.th * s.th, (1, 2)))
-    assert st["e_elec_recip"] == pytest.approx(COULOMB * erec, rel=1e-9)
-    assert st["e_elec_self"] == pytest.approx(COULOMB * eself, rel=1e-12)
+    say(f"  E_rec rel {abs(st['e_elec_recip'] / (COULOMB * erec) - 1):.2e}, "
+        f"E_self rel {abs(st['e_elec_self'] / (COULOMB * eself) - 1):.2e}")
+    assert st["e_elec_recip"] == pytest.approx(COULOMB * erec, rel=bars["erec"])
+    assert st["e_elec_self"] == pytest.approx(COULOMB * eself, rel=bars["eself"])
     say(f"  iters {it}, E_pol {e_pol:.6f}, E_elec {e_elec:.6f}")
 
 
@@ -89,6 +109,13 @@ def test_box4096_sampled():
 @pytest.mark.slow
 def test_box32000_sampled():
     _sampled_parity("box32000", 16)
+
+
+@pytest.mark.slow
+def test_box32000_sampled_mixed():
+    """The benchmark workload in the benchmarked precision: sampled field,
+    T rows and forces of the FP32-mixed path against the FP64 oracle."""
+    _sampled_parity("box32000", 16, precision="mixed")
 
 
 @pytest.mark.slow
@@ -160,14 +187,31 @@ def test_warm_start_and_position_update_match_fresh():
     fresh.close()
 
 
+# Bounds of the FP32-mixed path against the FP64 path, per result.
+#  E_pol          1e-5 relative
+#  E_elec         1e-6 of |E_rec|.  E_elec is a sum of terms of both signs
+#                 (random orientations): -24 kcal/mol at 32,000 waters, while
+#                 its parts are ~2e6 (real space, self) and ~8e4
+#                 (reciprocal).  Its FP32 parts are the reciprocal energy and
+#                 the intermolecular real-space pairs (the same-molecule
+#                 corrections and the self term are FP64); the reciprocal one
+#                 is the larger, ~10x the other, and FP32 spreading and FFT
+#                 leave ~1e-7 of it.
+#  E_elec parts   real 1e-7, reciprocal 5e-7 relative
+#  forces         1e-4 relative RMS
+#  mu             1e-5 D RMS
+MIXED_BOUNDS = dict(e_pol=1e-5, e_elec_of_recip=1e-6, real=1e-7, recip=5e-7, force=1e-4,
+                    mu=1e-5)
+
+
 @pytest.mark.parametrize("name", ["box216", "box4096",
+                                  pytest.param("box32000", marks=pytest.mark.slow),
                                   pytest.param("box96000", marks=pytest.mark.slow)])
 def test_mixed_precision_bounds(name):
     """FP32 pair/PME arithmetic with FP64 accumulation, reductions and true
     residual: the solve still meets the FP64 tolerance against the FP64
-    operator, and each result stays within the stated bounds of the FP64
-    path (E_pol 1e-5 relative; E_elec 1e-5 of the summed magnitude of its
-    terms; forces 1e-4 relative RMS; mu 1e-5 D RMS)."""
+    operator, and each result stays within the bounds above of the FP64
+    path."""
     d, prm = config_system(name)
     kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"], tol=prm["tol"])
     res = {}
@@ -179,16 +223,19 @@ def test_mixed_precision_bounds(name):
         eng.close()
     mu64, it64, rms64, ep64, ee64, F64, st64 = res["fp64"]
     mu32, it32, rms32, ep32, ee32, F32, st32 = res["mixed"]
-    scale = abs(st64["e_elec_real"]) + abs(st64["e_elec_recip"]) + abs(st64["e_elec_self"])
+    b = MIXED_BOUNDS
     mu_rms = DEBYE * np.sqrt(np.mean(np.sum((mu32 - mu64) ** 2, 1)))
+    parts = {k: abs(st32[k] - st64[k]) / abs(st64[k]) for k in ("e_elec_real", "e_elec_recip")}
     say(f"  {name} mixed: iters {it32} (fp64 {it64}), E_pol rel {abs(ep32 - ep64) / abs(ep64):.2e}, "
-        f"E_elec {abs(ee32 - ee64):.2e} of {scale:.3g}, F rms rel {rms_rel(F32, F64):.2e}, "
+        f"E_elec rel {abs(ee32 - ee64) / abs(ee64):.2e} (real {parts['e_elec_real']:.2e}, "
+        f"recip {parts['e_elec_recip']:.2e}), F rms rel {rms_rel(F32, F64):.2e}, "
         f"mu rms {mu_rms:.2e} D")
     assert rms32 <= prm["tol"]
-    assert abs(ep32 - ep64) <= 1e-5 * abs(ep64)
-    assert abs(ee32 - ee64) <= 1e-5 * scale
-    assert rms_rel(F32, F64) <= 1e-4
-    assert mu_rms <= 1e-5
+    assert abs(ep32 - ep64) <= b["e_pol"] * abs(ep64)
+    assert parts["e_elec_real"] <= b["real"] and parts["e_elec_recip"] <= b["recip"]
+    assert abs(ee32 - ee64) <= b["e_elec_of_recip"] * abs(st64["e_elec_recip"])
+    assert rms_rel(F32, F64) <= b["force"]
+    assert mu_rms <= b["mu"]
 
 
 def test_mixed_tight_tolerance():

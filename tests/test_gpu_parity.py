@@ -136,18 +136,44 @@ def test_box216_parity():
 
 
 def _kdtree_counts(sysd, cutoff):
-    pos = np.mod(sysd["pos"], sysd["box"])
-    tree = cKDTree(pos, boxsize=sysd["box"])
-    pairs = tree.query_pairs(cutoff, output_type="ndarray")
-    mol = sysd["mol"]
+    """Intermolecular sites within the cutoff of each site (minimum image),
+    from a periodic k-d tree: every site within the cutoff (the site itself
+    included) less the sites of its own molecule, all of which lie within
+    the cutoff (checked)."""
+    box = np.asarray(sysd["box"], float)
+    pos = np.mod(sysd["pos"], box)
+    mol = np.asarray(sysd["mol"])
+    order = np.argsort(mol, kind="stable")
+    ms = mol[order]
+    starts = np.flatnonzero(np.r_[True, ms[1:] != ms[:-1]])
+    sizes = np.diff(np.r_[starts, len(ms)])
+    for size in np.unique(sizes):
+        grp = order[starts[sizes == size][:, None] + np.arange(size)[None, :]]
+        d = pos[grp][:, :, None, :] - pos[grp][:, None, :, :]
+        d -= box * np.round(d / box)
+        assert np.linalg.norm(d, axis=-1).max() < cutoff
+    tree = cKDTree(pos, boxsize=box)
+    within = tree.query_ball_point(pos, cutoff, return_length=True)
+    own = np.bincount(mol, minlength=mol.max() + 1)[mol]
+    return within.astype(np.int64) - own
+
+
+def test_kdtree_counts_match_pair_enumeration():
+    """The count helper against an explicit pair enumeration (small box)."""
+    d = water_box(27, 9.5, 3)
+    pos = np.mod(d["pos"], d["box"])
+    tree = cKDTree(pos, boxsize=d["box"])
+    pairs = tree.query_pairs(4.5, output_type="ndarray")
+    mol = d["mol"]
     inter = pairs[mol[pairs[:, 0]] != mol[pairs[:, 1]]]
     cnt = np.zeros(len(pos), np.int64)
     np.add.at(cnt, inter[:, 0], 1)
     np.add.at(cnt, inter[:, 1], 1)
-    return cnt
+    assert np.array_equal(_kdtree_counts(d, 4.5), cnt)
 
 
-@pytest.mark.parametrize("name", ["box216", "box4096"])
+@pytest.mark.parametrize("name", ["box216", "box4096",
+                                  pytest.param("box32000", marks=pytest.mark.slow)])
 def test_neighbor_counts_exact(name):
     say(f"[nlist] {name}")
     d, prm = config_system(name)
