@@ -247,7 +247,7 @@ def dense_T_blocks(sysm, prm, ctx=None):
         if prm.method != "ewald":
             raise ValueError("block assembly needs brute-force Ewald")
         box = s.box
-        V = float(np.prod(box))
+        V = recip.cell_volume(box)
         m, m2 = recip.kvectors(box, prm.beta)
         w = np.exp(-np.pi ** 2 * m2 / prm.beta ** 2) / m2
         P = s.pos[pol]
@@ -317,6 +317,36 @@ def energy_forces(sysm, prm, mu_pol, E0, ctx=None, sites=None):
     return e_pol, e_var, e_elec, F
 
 
+def virial(sysm, prm, mu_pol, ctx=None):
+    """Virial W (3,3, kcal/mol): W_ab = -dE_tot/d eps_ab for the homogeneous
+    strain r -> (1 + eps) r of every site (and of the cell when periodic),
+    with the multipoles, polarizabilities and mu fixed in the global frame.
+    mu is stationary, so at the solution this is the full strain derivative,
+    as the forces are the full gradient.  Real space: the pair energies of
+    the MM, Mmu and mumu classes (the alpha^-1 and self terms do not depend
+    on the geometry); reciprocal: the reciprocal energy of the combined
+    density (q, d + mu, Theta).  Cutoff pairs are taken as in the energy
+    (a pair crossing the cutoff under strain is not followed)."""
+    c = _ctx(sysm, prm, ctx)
+    s = c.s
+    mult = (s.q, s.dip, s.th)
+    mud = (None, c.full(mu_pol), None)
+    W = rs.pair_sum(c.pairs, "MM", c.kernel, prm.beta, c.thole, mult, mult, "virial", s.n)
+    W += rs.pair_sum(c.pairs, "Mmu", c.kernel, prm.beta, c.thole, mud, mult, "virial", s.n)
+    W += rs.pair_sum(c.pairs, "Mmu", c.kernel, prm.beta, c.thole, mult, mud, "virial", s.n)
+    W += rs.pair_sum(c.pairs, c.mumu_cls, c.kernel, prm.beta, c.thole, mud, mud, "virial",
+                     s.n)
+    if prm.periodic:
+        comb = (s.q, s.dip + mud[1], s.th)
+        if prm.method == "ewald":
+            _, Wr = recip.ewald_recip_virial(s.pos, s.box, prm.beta, comb)
+        else:
+            K = np.broadcast_to(np.asarray(prm.grid, int), (3,))
+            _, Wr = recip.spme_virial(s.pos, s.box, K, prm.order, prm.beta, comb)
+        W = W + Wr
+    return COULOMB * W
+
+
 def solve(sysm, prm, E0, ctx=None, x0=None):
     c = _ctx(sysm, prm, ctx)
     mv = lambda v: apply_T(sysm, prm, v, ctx=c)
@@ -337,12 +367,15 @@ def tcg(sysm, prm, E0, order, omega=0.0, ctx=None, x0=None):
     return mu, -0.5 * COULOMB * float(np.sum(mu * E0))
 
 
-def evaluate(sysm, prm, forces=True):
-    """Full evaluation: E0 -> PCG -> energies -> forces (fixed mu)."""
+def evaluate(sysm, prm, forces=True, with_virial=False):
+    """Full evaluation: E0 -> PCG -> energies -> forces (fixed mu), and the
+    virial when asked."""
     c = Context(sysm, prm)
     E0 = permanent_field(sysm, prm, ctx=c)
     mu, iters, rho = solve(sysm, prm, E0, ctx=c)
     out = dict(E0=E0, mu=mu, iters=iters, rho=rho)
+    if with_virial:
+        out["virial"] = virial(sysm, prm, mu, ctx=c)
     if forces:
         e_pol, e_var, e_elec, F = energy_forces(sysm, prm, mu, E0, ctx=c)
         out.update(E_pol=e_pol, E_pol_var=e_var, E_elec=e_elec, forces=F)

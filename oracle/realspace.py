@@ -103,9 +103,16 @@ def pairs_min_image(pos, mol, box, cutoff, subset=None):
 
 def pairs_images(pos, mol, box, rmax):
     """Every ordered (i, j, image) with |R| < rmax, except i == j unshifted.
-    For brute-force Ewald on tiny systems."""
+    For brute-force Ewald on tiny systems.  box: (3,) edge lengths of an
+    orthorhombic cell, or (3,3) lattice vectors as rows (any cell)."""
     box = np.asarray(box, float)
-    nimg = np.ceil(rmax / box).astype(int) + 1
+    if box.ndim == 2:
+        # image n along a_k moves every point by n / |b_k| across the planes
+        # of a_k, with b_k the reciprocal vectors (rows of inv(H)^T)
+        recip_len = np.linalg.norm(np.linalg.inv(box).T, axis=1)
+        nimg = np.ceil(rmax * recip_len).astype(int) + 1
+    else:
+        nimg = np.ceil(rmax / box).astype(int) + 1
     I, J, RR, S = [], [], [], []
     n = len(pos)
     base = pos[:, None, :] - pos[None, :, :]
@@ -113,7 +120,8 @@ def pairs_images(pos, mol, box, rmax):
     for a in range(-nimg[0], nimg[0] + 1):
         for b in range(-nimg[1], nimg[1] + 1):
             for c in range(-nimg[2], nimg[2] + 1):
-                shift = np.array([a, b, c]) * box
+                shift = (np.array([a, b, c]) @ box if box.ndim == 2
+                         else np.array([a, b, c]) * box)
                 d = base - shift
                 r = np.linalg.norm(d, axis=2)
                 zero = (a == 0 and b == 0 and c == 0)
@@ -176,6 +184,10 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     what: 'energy' -> 1/2 sum of U over ordered pairs
           'force'  -> per-site force -dU/dr_i summed over pairs at i (n,3)
           'field'  -> per-site field of the j-side multipoles at i (n,3)
+          'virial' -> W_ab = -dE/d eps_ab of the pair energy (3,3) under the
+                      homogeneous strain R -> (1 + eps) R of every pair
+                      separation with the multipoles fixed in the global
+                      frame: -1/2 sum over ordered pairs of (dU/dR)_a R_b
     """
     abar, athole = thole
     maxrank_i = max([k for k, v in enumerate(Mi) if v is not None], default=0)
@@ -184,6 +196,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     nmax = maxrank_i + maxrank_j + extra
     if what == "energy":
         acc = 0.0
+    elif what == "virial":
+        acc = np.zeros((3, 3))
     else:
         acc = np.zeros((n_sites, 3))
     sel = np.arange(len(pairs)) if pair_mask is None else np.flatnonzero(pair_mask)
@@ -202,6 +216,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
         val = _interaction(D, mi, mj, extra)
         if what == "energy":
             acc += 0.5 * float(np.sum(val))
+        elif what == "virial":
+            acc -= 0.5 * np.einsum("pa,pb->ab", val, R)
         else:
             np.add.at(acc, i, -val)
     return acc

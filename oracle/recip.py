@@ -32,15 +32,25 @@ from scipy.special import comb, factorial
 
 
 # ---------------------------------------------------------------- k-sum
+def cell_volume(box):
+    box = np.asarray(box, float)
+    return float(abs(np.linalg.det(box))) if box.ndim == 2 else float(np.prod(box))
+
+
 def kvectors(box, beta, tol=1e-18):
+    """Reciprocal vectors m != 0 with exp(-pi^2 m^2/beta^2) >= tol.  box:
+    (3,) edges of an orthorhombic cell (m = n / L), or (3,3) lattice vectors
+    as rows H (m = n inv(H)^T, so that m.a_k = n_k)."""
     box = np.asarray(box, float)
     # exp(-pi^2 m^2/beta^2) < tol  =>  |m| > beta sqrt(-ln tol)/pi
     mmax = beta * math.sqrt(-math.log(tol)) / math.pi
-    na = np.ceil(mmax * box).astype(int)
+    # |n_k| = |m.a_k| <= |m| |a_k|
+    lengths = np.linalg.norm(box, axis=1) if box.ndim == 2 else box
+    na = np.ceil(mmax * lengths).astype(int)
     rng = [np.arange(-n, n + 1) for n in na]
     g = np.stack(np.meshgrid(*rng, indexing="ij"), axis=-1).reshape(-1, 3)
     g = g[np.any(g != 0, axis=1)]
-    m = g / box
+    m = g @ np.linalg.inv(box).T if box.ndim == 2 else g / box
     m2 = np.sum(m * m, axis=1)
     keep = m2 <= mmax * mmax
     return m[keep], m2[keep]
@@ -64,8 +74,7 @@ def ewald_recip(pos, box, beta, mult, at, nderiv, chunk=2000):
     mult = (q, d, th) source multipoles (any may be None); at = evaluation
     positions (k, 3).  Returns (E_rec, [phi, grad phi (k,3), grad^2 (k,3,3),
     grad^3 (k,3,3,3)][:nderiv+1])."""
-    box = np.asarray(box, float)
-    V = float(np.prod(box))
+    V = cell_volume(box)
     m, m2 = kvectors(box, beta)
     q, d, th = mult
     energy = 0.0
@@ -225,3 +234,71 @@ def spme_gather(pos, box, K, order, phi, nderiv):
             v = np.einsum("nxyz,nx,ny,nz->n", local, wx, wy, wz)
             out[k][(slice(None),) + axes] = v
     return out
+
+
+# ---------------------------------------------------------------- virial
+# W_ab = -dE_rec/d eps_ab under the homogeneous strain r -> (1 + eps) r of
+# every site and of the cell, with the multipoles fixed in the global
+# frame.  Fractional coordinates are unchanged, reciprocal vectors go to
+# (1 + eps)^-T m (dm_c/d eps_ab = -delta_cb m_a), V to (1 + tr eps) V, and
+# the amplitude 2 pi i m.d - (4 pi^2/3) m.Theta.m of each site follows m.
+# Differentiating E_rec = 1/(2 pi V) sum_m f(m^2) |S(m)|^2,
+# f = exp(-pi^2 m^2/beta^2)/m^2, term by term:
+#   volume      -delta_ab E_rec
+#   f(m^2)      sum_m C(m) (pi^2/beta^2 + 1/m^2) m_a m_b |S(m)|^2,
+#               C = f/(pi V) (twice the energy weight)
+#   amplitudes  -sum_j [d_jb d_a phi(r_j) + 2/3 Theta_jbc d_a d_c phi(r_j)]
+# so W_ab = delta_ab E_rec - (m-space sum) + sum_j [d_jb d_a phi_j
+#           + 2/3 Theta_jbc d_a d_c phi_j].
+# For SPME the same steps hold exactly for the interpolated energy: the
+# B-spline weights depend only on fractional coordinates, and the dipole
+# and quadrupole spread terms carry the Cartesian gradient, which strains
+# as the amplitudes above; C(m) becomes G(m) = B(m) C(m) on the grid.
+def _site_virial(mult, derivs):
+    q, d, th = mult
+    W = np.zeros((3, 3))
+    if d is not None:
+        W += np.einsum("jb,ja->ab", d, derivs[1])
+    if th is not None:
+        W += (2.0 / 3.0) * np.einsum("jbc,jac->ab", th, derivs[2])
+    return W
+
+
+def ewald_recip_virial(pos, box, beta, mult, chunk=2000):
+    """Brute-force reciprocal energy and its virial (3,3) (e^2/A units)."""
+    V = cell_volume(box)
+    m, m2 = kvectors(box, beta)
+    q, d, th = mult
+    nd = 2 if th is not None else 1
+    energy, derivs = ewald_recip(pos, box, beta, mult, pos, nd, chunk)
+    W = energy * np.eye(3) + _site_virial(mult, derivs)
+    for s in range(0, len(m), chunk):
+        mm = m[s:s + chunk]
+        mm2 = m2[s:s + chunk]
+        C = np.exp(-np.pi ** 2 * mm2 / beta ** 2) / mm2 / (np.pi * V)
+        S = structure_factor(mm, pos, q, d, th)
+        wgt = C * (np.pi ** 2 / beta ** 2 + 1.0 / mm2) * np.abs(S) ** 2
+        W -= np.einsum("m,ma,mb->ab", wgt, mm, mm)
+    return energy, W
+
+
+def spme_virial(pos, box, K, order, beta, mult):
+    """SPME reciprocal energy and its virial (3,3), orthorhombic cell."""
+    box = np.asarray(box, float)
+    K = np.asarray(K, int)
+    q, d, th = mult
+    grid = spme_spread(pos, box, K, order, mult)
+    G = spme_influence(box, K, order, beta)
+    energy, phi = spme_potential(grid, G)
+    nd = 2 if th is not None else 1
+    derivs = spme_gather(pos, box, K, order, phi, nd)
+    F = np.fft.fftn(grid)
+    freqs = [np.fft.fftfreq(K[a], d=1.0 / K[a]) / box[a] for a in range(3)]
+    m = np.stack(np.meshgrid(*freqs, indexing="ij"), axis=-1)
+    m2 = np.sum(m * m, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        wgt = G * (np.pi ** 2 / beta ** 2 + 1.0 / m2) * np.abs(F) ** 2
+    wgt[0, 0, 0] = 0.0
+    W = energy * np.eye(3) + _site_virial(mult, derivs)
+    W -= np.einsum("xyz,xyza,xyzb->ab", wgt, m, m)
+    return energy, W
