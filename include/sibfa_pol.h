@@ -290,6 +290,49 @@ sibfa_status sibfa_batch_clusters(sibfa_batch b, int n_clusters,
                                   double* e_elec, int* iterations,
                                   double* rms_debye, int* status);
 
+/* ------------------------------------------------------------------------
+ * Batched clusters without allocation.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation and kernels as sibfa_batch_clusters, with no executor: the
+ * scratch arrays live in a fixed device array of the library (about 8 MB,
+ * for at most SIBFA_BATCH_NOALLOC_MAX_SITES sites and
+ * SIBFA_BATCH_NOALLOC_MAX_CLUSTERS clusters per call), which each device
+ * holds until the process ends.  The call allocates nothing, enqueues three
+ * kernels on hip_stream (a hipStream_t; NULL = null stream) on `device` and
+ * returns; it neither synchronises nor copies from the host.
+ *
+ * Differences from sibfa_batch_clusters:
+ *  - site_offsets [n_clusters + 1] and warm_start [n_clusters] (or NULL)
+ *    are DEVICE arrays; n_sites is the number of sites in the caller
+ *    arrays.  The offsets are checked on the device: a cluster whose range
+ *    is not 1..SIBFA_BATCH_MAX_SITES sites inside [0, n_sites) gets status
+ *    SIBFA_E_ARG and NaN e_pol and e_elec, and its mu and forces rows are
+ *    not written.
+ *  - Errors are return codes only: SIBFA_E_ARG (n_clusters or n_sites out
+ *    of range, a required pointer NULL, bad params), SIBFA_E_DEVICE (HIP
+ *    error).
+ *  - Every call on one device uses the same scratch array, and each call
+ *    rewrites every scratch value it reads, so nothing carries over between
+ *    calls.  Calls that overlap in time on one device (other streams, other
+ *    threads, or enqueued before an earlier call's kernels have finished
+ *    while on another stream) race on it: order them on one stream.
+ * Inputs and outputs as for sibfa_batch_clusters, all DEVICE pointers.
+ * ------------------------------------------------------------------------ */
+#define SIBFA_BATCH_NOALLOC_MAX_SITES 32768
+#define SIBFA_BATCH_NOALLOC_MAX_CLUSTERS 4096
+
+sibfa_status sibfa_batch_clusters_noalloc(int device, void* hip_stream, int n_clusters,
+                                          int n_sites, const int* site_offsets,
+                                          const int* warm_start, const double* xyz,
+                                          const int32_t* mol, const double* q,
+                                          const double* dip, const double* quad,
+                                          const double* alpha, const double* thole,
+                                          const sibfa_params* params, double* mu,
+                                          double* forces, double* e_pol, double* e_elec,
+                                          int* iterations, double* rms_debye, int* status);
+
 #ifdef __cplusplus
 }
 #endif

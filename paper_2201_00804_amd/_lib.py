@@ -73,10 +73,15 @@ SIGNATURES = [
     ("sibfa_batch_last_error", ctypes.c_char_p, [_P]),
     ("sibfa_batch_clusters", ctypes.c_int, [_P, ctypes.c_int, _P, _P] + [_P] * 7 +
      [ctypes.POINTER(Params)] + [_P] * 7),
+    ("sibfa_batch_clusters_noalloc", ctypes.c_int,
+     [ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, _P, _P] + [_P] * 7 +
+     [ctypes.POINTER(Params)] + [_P] * 7),
 ]
 
 BATCH_MAX_SITES = 1024
 BATCH_MAX_POLARIZABLE = 640
+BATCH_NOALLOC_MAX_SITES = 32768
+BATCH_NOALLOC_MAX_CLUSTERS = 4096
 
 _lib = None
 

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/sibfa_pol.h"
@@ -41,6 +42,7 @@ constexpr int kClOwn = (kClMaxPol + kClBlock - 1) / kClBlock;   // sites per slo
 
 struct ClusterArgs {
   int nclusters;
+  int nsites;           // sites in the caller arrays (and scratch capacity)
   const int* off;       // [nclusters + 1] site offsets into the caller arrays
   const int* warm;      // [nclusters] 1: start from mu, or nullptr
   const double* xyz;    // caller arrays, concatenated clusters
@@ -83,6 +85,18 @@ __device__ __forceinline__ int lanes_for(int count) {
   int G = 1;
   while (G < 16 && 2 * G * count <= kClBlock) G *= 2;
   return G;
+}
+
+// Cluster c's site range [base, base + n) from the offsets, and whether it
+// is a valid one: 1..kClMaxSites sites inside the nsites of the arrays.
+// Offsets validated on the host always pass; offsets that the caller
+// keeps on the device are checked here, and a cluster whose range fails
+// is reported (E_ARG) without touching its rows.
+__device__ __forceinline__ bool cluster_range(const ClusterArgs& a, int c, int& base, int& n) {
+  base = a.off[c];
+  const int end = a.off[c + 1];
+  n = end - base;
+  return base >= 0 && n >= 1 && n <= kClMaxSites && end <= a.nsites;
 }
 
 __device__ __forceinline__ double group_sum_rt(double v, int G) {
@@ -164,7 +178,15 @@ __global__ __launch_bounds__(kClBlock) void k_cl_prep(ClusterArgs a) {
   const BlockSum bsum{sh};
   const int t = threadIdx.x, lane64 = t & 63, w = t >> 6;
   for (int c = blockIdx.x; c < a.nclusters; c += gridDim.x) {
-    const int base = a.off[c], n = a.off[c + 1] - base;
+    int base, n;
+    if (!cluster_range(a, c, base, n)) {
+      if (t == 0) {
+        a.npol[c] = 0;
+        a.status[c] = (int)SIBFA_E_ARG;
+        a.e_elec[c] = __longlong_as_double(0x7ff8000000000000ll);
+      }
+      continue;
+    }
     __syncthreads();
     if (t == 0) bad = 0;
     // order-preserving compaction of the polarizable sites, 256 at a time
@@ -319,7 +341,15 @@ __global__ __launch_bounds__(kClBlock) void k_cl_solve(ClusterArgs a) {
   const BlockSum bsum{sh};
   const int t = threadIdx.x;
   for (int c = blockIdx.x; c < a.nclusters; c += gridDim.x) {
-    const int base = a.off[c], n = a.off[c + 1] - base;
+    int base, n;
+    if (!cluster_range(a, c, base, n)) {
+      if (t == 0) {
+        a.e_pol[c] = __longlong_as_double(0x7ff8000000000000ll);
+        a.iters[c] = 0;
+        a.rms[c] = 0.0;
+      }
+      continue;
+    }
     const int np = a.npol[c];
     const int st0 = a.status[c];
     if (st0 != 0 || np == 0) {
@@ -536,7 +566,8 @@ template <typename R>
 __global__ __launch_bounds__(kClBlock) void k_cl_force(ClusterArgs a) {
   const int t = threadIdx.x;
   for (int c = blockIdx.x; c < a.nclusters; c += gridDim.x) {
-    const int base = a.off[c], n = a.off[c + 1] - base;
+    int base, n;
+    if (!cluster_range(a, c, base, n)) continue;
     if (a.status[c] == (int)SIBFA_E_ARG) {
       for (int i = t; i < n; i += kClBlock)
         for (int k = 0; k < 3; ++k) a.forces[3 * (size_t)(base + i) + k] = 0.0;
@@ -638,6 +669,24 @@ __global__ __launch_bounds__(kClBlock) void k_cl_force(ClusterArgs a) {
 }  // namespace sibfa
 
 using namespace sibfa;
+
+// Device memory of sibfa_batch_clusters_noalloc: the batch scratch arrays
+// for SIBFA_BATCH_NOALLOC_MAX_SITES sites and SIBFA_BATCH_NOALLOC_MAX_CLUSTERS
+// clusters, carved as by carve() below (every region rounded up to 256
+// bytes).  Each device the library runs on holds its own copy for the life
+// of the process; calls on one device share it.
+namespace {
+constexpr size_t kNaSites = SIBFA_BATCH_NOALLOC_MAX_SITES;
+constexpr size_t kNaClusters = SIBFA_BATCH_NOALLOC_MAX_CLUSTERS;
+constexpr size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaBytes =
+    a256((kNaClusters + 1) * sizeof(int)) + 2 * a256(kNaClusters * sizeof(int)) +
+    2 * a256(kNaSites * sizeof(int)) + 2 * a256(kNaSites * sizeof(double)) +
+    a256(kNaSites * sizeof(double4)) + 2 * a256(kNaSites * 6 * sizeof(double)) +
+    3 * a256(kNaSites * sizeof(double4));
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
 struct sibfa_batch_s {
   int device = 0;
@@ -832,6 +881,7 @@ sibfa_status sibfa_batch_clusters(sibfa_batch b, int n_clusters, const int* site
   BHIP(hipEventRecord(b->staged, b->stream));
   b->staged_pending = true;
   a.nclusters = n_clusters;
+  a.nsites = (int)n;
   a.xyz = xyz;
   a.mol = mol;
   a.q = q;
@@ -856,3 +906,75 @@ sibfa_status sibfa_batch_clusters(sibfa_batch b, int n_clusters, const int* site
 }
 
 }  // extern "C"
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+void* g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked
+// up once per device.  In host code the array's name is only a stand-in
+// for the symbol: kernels get this address.
+sibfa_status noalloc_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  if (!g_na_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SIBFA_E_DEVICE;
+    g_na_ptr[device] = p;
+  }
+  *out = g_na_ptr[device];
+  return SIBFA_OK;
+}
+
+}  // namespace
+
+extern "C" sibfa_status sibfa_batch_clusters_noalloc(
+    int device, void* hip_stream, int n_clusters, int n_sites, const int* site_offsets,
+    const int* warm_start, const double* xyz, const int32_t* mol, const double* q,
+    const double* dip, const double* quad, const double* alpha, const double* thole,
+    const sibfa_params* params, double* mu, double* forces, double* e_pol, double* e_elec,
+    int* iterations, double* rms_debye, int* status) {
+  if (n_clusters < 1 || n_clusters > SIBFA_BATCH_NOALLOC_MAX_CLUSTERS || n_sites < 1 ||
+      n_sites > SIBFA_BATCH_NOALLOC_MAX_SITES)
+    return SIBFA_E_ARG;
+  if (!site_offsets || !xyz || !mol || !q || !dip || !quad || !alpha || !params || !mu ||
+      !e_pol || !e_elec || !iterations || !rms_debye || !status)
+    return SIBFA_E_ARG;
+  if (!(params->tol_debye > 0.0) || params->max_iter < 1 || !(params->thole_a > 0.0) ||
+      (params->precision != SIBFA_FP64 && params->precision != SIBFA_MIXED))
+    return SIBFA_E_ARG;
+  if (device < 0 || device >= kNaMaxDevices) return SIBFA_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return SIBFA_E_DEVICE;
+  // the layout of carve() must fit the static array
+  if (carve(nullptr, kNaSites, kNaClusters, nullptr) > kNaBytes) return SIBFA_E_DEVICE;
+  void* base = nullptr;
+  if (noalloc_scratch(device, &base) != SIBFA_OK) return SIBFA_E_DEVICE;
+  ClusterArgs a{};
+  carve(static_cast<char*>(base), kNaSites, kNaClusters, &a);
+  a.off = site_offsets;   // the caller's device arrays, checked per cluster
+  a.warm = warm_start;
+  a.nclusters = n_clusters;
+  a.nsites = n_sites;
+  a.xyz = xyz;
+  a.mol = mol;
+  a.q = q;
+  a.dip = dip;
+  a.quad = quad;
+  a.alpha = alpha;
+  a.thole = thole;
+  a.thole_a = params->thole_a;
+  a.tol = params->tol_debye;
+  a.max_iter = params->max_iter;
+  a.mu = mu;
+  a.forces = forces;
+  a.e_pol = e_pol;
+  a.e_elec = e_elec;
+  a.iters = iterations;
+  a.rms = rms_debye;
+  a.status = status;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (params->precision == SIBFA_MIXED) launch_batch<float>(a, st);
+  else launch_batch<double>(a, st);
+  return hipGetLastError() == hipSuccess ? SIBFA_OK : SIBFA_E_DEVICE;
+}
