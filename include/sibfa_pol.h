@@ -116,32 +116,46 @@ void sibfa_default_params(sibfa_params* p);
 
 /* Device bytes a context will hold for a system of n_sites sites of which
  * n_polarizable are polarizable (box NULL = cluster); for admission
- * control.  Returns 0 on invalid arguments. */
+ * control.  The polarizable count is an argument because the
+ * polarization-pair lists and their cached coefficients (rows and density
+ * both follow it) dominate the footprint, and a caller admitting a request
+ * knows it from its polarizabilities before any context exists.  Returns 0
+ * on invalid arguments. */
 size_t sibfa_footprint_bytes(int n_sites, int n_polarizable,
                              const double* box, const sibfa_params* p);
 
 /* Define the system: n_sites sites at xyz [n][3] (device), molecule ids
  * mol [n] (device int32, each in [0, n)), box [3] (HOST, orthorhombic edge
  * lengths) or NULL for a non-periodic cluster, and the parameters (HOST).
- * Periodic systems need every molecule's sites within the cutoff of each
- * other (checked when lists are built: SIBFA_E_ARG). */
+ * The sites are the paper's multipole centres (Multipolar Electrostatics:
+ * atoms and bond barycentres of each molecule); molecule ids carry the
+ * exclusion rule above (the permanent field and E_elec are intermolecular
+ * terms).  The Ewald/SPME parameters are those of the Computational
+ * Details' periodic runs.  Periodic systems need every molecule's sites
+ * within the cutoff of each other (checked when lists are built:
+ * SIBFA_E_ARG). */
 sibfa_status sibfa_set_system(sibfa_ctx ctx, int n_sites, const double* xyz,
                               const int32_t* mol, const double* box,
                               const sibfa_params* params);
 
-/* New positions for the same sites; keeps mu for a warm start.  Only
+/* New positions for the same sites (one MD step of the Computational
+ * Details); keeps mu as the guess for the next solve (warm start).  Only
  * enqueues the copy: NaN/Inf coordinates are reported (SIBFA_E_ARG) by the
  * next call that computes. */
 sibfa_status sibfa_update_positions(sibfa_ctx ctx, const double* xyz);
 
-/* Permanent multipoles (device): q [n], dip [n][3], quad [n][6] traceless.
- * dip or quad may be NULL (zero). */
+/* Permanent multipoles (device): q [n], dip [n][3], quad [n][6] traceless,
+ * the distributed multipoles up to quadrupole of Multipolar
+ * Electrostatics (Eq. 2), given in the global frame.  dip or quad may be
+ * NULL (zero). */
 sibfa_status sibfa_set_multipoles(sibfa_ctx ctx, const double* q,
                                   const double* dip, const double* quad);
 
 /* Polarizabilities alpha [n][6] (device; symmetric positive definite, or an
- * all-zero row for a non-polarizable site) and optional per-site Thole
- * factors thole [n] (device; NULL = params.thole_a). */
+ * all-zero row for a non-polarizable site), the 3x3 alpha_i of the
+ * technical appendix (Polarization) whose inverses are T's diagonal blocks,
+ * and optional per-site Thole factors thole [n] (device; NULL =
+ * params.thole_a; the Thole damping of Many-Body Polarization). */
 sibfa_status sibfa_set_polarizabilities(sibfa_ctx ctx, const double* alpha,
                                         const double* thole);
 
@@ -182,12 +196,27 @@ sibfa_status sibfa_solve_tcg(sibfa_ctx ctx, int order, double omega, int warm_st
                              double* mu_out, double* e_pol);
 
 /* Energies (HOST, kcal/mol) and forces [n][3] (device, kcal/mol/A, or
- * NULL) at the current dipoles; solves first if they are stale.  virial
- * must be NULL (not provided). */
+ * NULL) at the current dipoles; solves first if they are stale.
+ * virial [9] (HOST, kcal/mol, row-major) or NULL: W_ab = -dE/d eps_ab,
+ * E = E_elec + E_pol, for the homogeneous strain r -> (1 + eps) r of every
+ * site and of the box, with the multipoles, polarizabilities and induced
+ * dipoles held in the global frame (the dipoles make E_pol stationary, so
+ * this is the full strain derivative, as the forces are the full
+ * gradient; the NPT runs of the Computational Details need it).  Real
+ * space: 1/2 sum over ordered pairs of f_a R_b; reciprocal (Smooth PME of
+ * the combined density q, d + mu, Theta):
+ *   W_ab = delta_ab E_rec - sum_m G(m) (pi^2/beta^2 + 1/m^2) m_a m_b |S(m)|^2
+ *          + sum_j [(d + mu)_jb d_a phi(r_j) + 2/3 Theta_jbc d_a d_c phi(r_j)].
+ * Not symmetric in general (the global-frame multipoles do not rotate with
+ * the strain).  Pairs crossing the cutoff under the strain are not
+ * followed, as for the energy. */
 sibfa_status sibfa_energy_forces(sibfa_ctx ctx, double* e_pol, double* e_elec,
                                  double* forces, double* virial);
 
-/* Copy out / restore the induced dipoles [n][3] (device). */
+/* Copy out / restore the induced dipoles mu of Eq. 18 [n][3] (device):
+ * the next solve starts from the restored ones when warm-started (an
+ * extrapolated guess from earlier steps, as the truncated and predicted
+ * solvers the Many-Body Polarization section cites use). */
 sibfa_status sibfa_get_dipoles(sibfa_ctx ctx, double* mu);
 sibfa_status sibfa_set_dipoles(sibfa_ctx ctx, const double* mu);
 

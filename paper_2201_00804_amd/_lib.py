@@ -46,7 +46,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = [
-    ("sibfa_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, _P]),
+    ("sibfa_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ALLOC_FN, FREE_FN, _P]),
     ("sibfa_destroy", None, [_P]),
     ("sibfa_last_error", ctypes.c_char_p, [_P]),
     ("sibfa_default_params", None, [ctypes.POINTER(Params)]),
@@ -68,7 +68,8 @@ SIGNATURES = [
     ("sibfa_set_profiling", ctypes.c_int, [_P, ctypes.c_int]),
     ("sibfa_set_profiling_phases", ctypes.c_int, [_P, ctypes.c_uint]),
     ("sibfa_get_profile", ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
-    ("sibfa_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, _P]),
+    ("sibfa_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ALLOC_FN, FREE_FN,
+                                          _P]),
     ("sibfa_batch_destroy", None, [_P]),
     ("sibfa_batch_last_error", ctypes.c_char_p, [_P]),
     ("sibfa_batch_clusters", ctypes.c_int, [_P, ctypes.c_int, _P, _P] + [_P] * 7 +

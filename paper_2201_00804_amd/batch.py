@@ -7,7 +7,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .engine import SibfaError, _dev, _ptr
+from .engine import SibfaError, TorchAllocator, _callbacks, _dev, _ptr
 
 MAX_SITES = _lib.BATCH_MAX_SITES
 MAX_POLARIZABLE = _lib.BATCH_MAX_POLARIZABLE
@@ -46,13 +46,15 @@ class BatchResult:
 class ClusterBatch:
     """Batch executor bound to one device and stream."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, torch_memory=True):
         self.lib = _lib.load()
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.allocator = TorchAllocator(device, self.stream) if torch_memory else None
+        af, ff = _callbacks(self.allocator)
         h = ctypes.c_void_p()
         st = self.lib.sibfa_batch_create(ctypes.byref(h), int(device),
-                                         ctypes.c_void_p(self.stream.cuda_stream), None, None, None)
+                                         ctypes.c_void_p(self.stream.cuda_stream), af, ff, None)
         if st != 0:
             raise SibfaError(st, "sibfa_batch_create failed")
         self.h = h

@@ -135,6 +135,12 @@ struct sibfa_ctx_s {
   unsigned long long* dsums = nullptr;   // list entry totals
   long long pair_totals[4] = {0, 0, 0, 0};
   bool totals_valid = false;
+  // virial requests: forces scratch when the caller passes no forces, and
+  // the device and host copies of the virial slot totals (allocated on the
+  // first request)
+  double* fvir = nullptr;
+  double* vir_tot = nullptr;
+  double* h_vir = nullptr;
   // profiling: HIP events on the context stream around each phase
   bool prof = false;
   unsigned prof_mask = ~0u;   // phases timed while profiling
@@ -178,8 +184,17 @@ void* dev_alloc(sibfa_ctx c, size_t bytes) {
 
 void dev_free(sibfa_ctx c, void* ptr) {
   if (!ptr) return;
-  if (c->ff) c->ff(ptr, c->user);
-  else (void)hipFree(ptr);
+  if (c->ff) {
+    // a caching allocator hands the block out again at once, ordered only
+    // against its own stream: let the work of both library streams that
+    // may still read it finish first (frees happen on resizes and
+    // teardown, not in the evaluation path)
+    (void)hipStreamSynchronize(c->stream);
+    if (c->aux && c->aux != c->stream) (void)hipStreamSynchronize(c->aux);
+    c->ff(ptr, c->user);
+  } else {
+    (void)hipFree(ptr);
+  }
 }
 
 template <typename T>
@@ -304,6 +319,8 @@ sibfa_status check_params(sibfa_ctx c, const sibfa_params* p, const double* box)
 void release_system(sibfa_ctx c) {
   c->rate_hint = -1.0;
   free_list(c, c->bufs);
+  c->fvir = nullptr;      // both lived in bufs
+  c->vir_tot = nullptr;
   free_list(c, c->pmebufs);
   for (int k = 0; k < 4; ++k) {
     dev_free(c, c->nbbuf[k].p);
@@ -402,10 +419,10 @@ struct Phase {
   }
 };
 
-void conv(sibfa_ctx c, bool mix, hipStream_t st, int erec_slot = S_EREC) {
+void conv(sibfa_ctx c, bool mix, hipStream_t st, int erec_slot = S_EREC, bool virial = false) {
   PmeView pm = c->pm;
   pm.erec_slot = erec_slot;
-  launch_convolution(pm, c->red, mix, st);
+  launch_convolution(pm, c->red, mix, st, virial);
   c->phi_e0 = false;
 }
 
@@ -1077,6 +1094,7 @@ sibfa_status setup_pme(sibfa_ctx c) {
     for (int k = 0; k < pm.nrad[a]; ++k) pm.radcode[a] |= (unsigned)(rad[k] - 2) << (2 * k);
   }
   pm.kxh = pm.K[0] / 2 + 1;
+  pm.beta = c->prm.ewald_beta;
   for (int a = 0; a < 3; ++a) {
     pm.Bb[a] = brick_edge(pm.K[a], order);
     if (pm.Bb[a] == 0) return fail(c, SIBFA_E_ARG, "no spreading brick size fits this grid");
@@ -1246,6 +1264,7 @@ void sibfa_destroy(sibfa_ctx c) {
   if (c->aux && c->aux != c->stream) (void)hipStreamDestroy(c->aux);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
+  if (c->h_vir) (void)hipHostFree(c->h_vir);
   delete c;
 }
 
@@ -1501,15 +1520,52 @@ sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, int warm_star
   return solve_tcg(c, order, omega, warm_start != 0, mu_out, e_pol);
 }
 
+// Totals of the virial slots (33 of them, S_VRI .. S_COUNT - 1) in one
+// device-to-host copy.
+sibfa_status read_virial_totals(sibfa_ctx c, double* out) {
+  constexpr int nv = S_COUNT - S_VRI;
+  if (!c->vir_tot) {
+    if (!alloc_into(c, c->bufs, c->vir_tot, 40))
+      return fail(c, SIBFA_E_NOMEM, "virial totals allocation failed");
+  }
+  if (!c->h_vir && hipHostMalloc((void**)&c->h_vir, 40 * sizeof(double), hipHostMallocDefault) !=
+                       hipSuccess) {
+    c->h_vir = nullptr;
+    return fail(c, SIBFA_E_NOMEM, "virial host staging allocation failed");
+  }
+  for (int k0 = 0; k0 < nv; k0 += 8) {
+    SlotList sl{};
+    for (int k = k0; k < nv && k < k0 + 8; ++k) {
+      sl.slot[sl.n] = S_VRI + k;
+      sl.nparts[sl.n] = c->red.nparts[S_VRI + k];
+      ++sl.n;
+    }
+    launch_slot_totals(c->red, sl, c->vir_tot + k0, c->stream);
+  }
+  HIP_TRY(hipMemcpyAsync(c->h_vir, c->vir_tot, nv * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  sibfa_status st = sync_read(c);
+  if (st != SIBFA_OK) return st;
+  for (int k = 0; k < nv; ++k) out[k] = c->h_vir[k];
+  return SIBFA_OK;
+}
+
 sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, double* forces,
                                  double* virial) {
   if (!c) return SIBFA_E_ARG;
-  if (virial) return fail(c, SIBFA_E_ARG, "the virial is not provided; pass NULL");
   HIP_TRY(hipSetDevice(c->device));
   sibfa_status st = prepare(c);
   if (st != SIBFA_OK) return st;
   if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
   if (!c->mu_valid && (st = solve(c, c->mu_have)) != SIBFA_OK) return st;
+  // the virial comes out of the force kernels: forces into a scratch array
+  // when the caller wants the virial only
+  const bool want_vir = virial != nullptr;
+  if (want_vir && !forces) {
+    if (!c->fvir && !alloc_into(c, c->bufs, c->fvir, 3 * (size_t)c->n))
+      return fail(c, SIBFA_E_NOMEM, "force scratch allocation failed");
+    forces = c->fvir;
+  }
   SysView s = make_view(c);
   hipStream_t sm = c->stream;
   const bool mix = mixed(c);
@@ -1528,19 +1584,41 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
       fork(c);
       Phase ph(c, SIBFA_PH_FORCE_RECIP, c->aux);
       launch_spread_mult(s, c->pm, c->mu_s, mix, c->aux);
-      conv(c, mix, c->aux);
+      conv(c, mix, c->aux, S_EREC, want_vir);
     }
     {
       Phase ph(c, SIBFA_PH_FORCE_REAL);
-      launch_force(s, c->mu_s, c->mu_s32, c->Freal, mix, sm);
+      launch_force(s, c->red, c->mu_s, c->mu_s32, c->Freal, mix, want_vir, sm);
     }
     if (c->periodic) {
       join(c);
       Phase ph(c, SIBFA_PH_FORCE_RECIP);
-      launch_gather_force(s, c->pm, c->mu_s, c->Freal, c->perm, forces, mix, sm);
+      launch_gather_force(s, c->pm, c->red, c->mu_s, c->Freal, c->perm, forces, mix, want_vir,
+                          sm);
     } else {
       launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
     }
+  }
+  if (want_vir) {
+    // W = real-space pair terms + [E_rec of the combined density times the
+    // identity - m-space sum + site terms]
+    double v[S_COUNT - S_VRI];
+    if ((st = read_virial_totals(c, v)) != SIBFA_OK) return st;
+    double erec = 0.0;
+    if (c->periodic && (st = read_totals(c, {S_EREC}, &erec)) != SIBFA_OK) return st;
+    const double* vi = v;
+    const double* vf = v + (S_VRF - S_VRI);
+    const double* vk = v + (S_VRK - S_VRI);
+    const double* vg = v + (S_VRG - S_VRI);
+    // m-space sum, symmetric: xx yy zz xy xz yz
+    const int kidx[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const int k = 3 * a + b;
+        double w = vi[k] + vf[k];
+        if (c->periodic) w += (a == b ? erec : 0.0) - vk[kidx[k]] + vg[k];
+        virial[k] = kCoulomb * w;
+      }
   }
   double tot[6] = {0, 0, 0, 0, 0, 0};
   if (c->npol > 0)

@@ -30,7 +30,13 @@ enum Slot {
   S_MUTMU,       // mu.T mu
   S_AUX,         // real-space energy of same-molecule (excluded) pairs
   S_EREC0,       // reciprocal energy of the permanent multipoles
-  S_COUNT
+  // virial partials (written only when a virial is asked for), row-major
+  // W_ab at slot + 3a + b unless noted
+  S_VRI,                 // same-molecule pairs, 9 slots
+  S_VRF = S_VRI + 9,     // intermolecular pairs, 9 slots
+  S_VRK = S_VRF + 9,     // reciprocal m-space sum, 6 slots: xx yy zz xy xz yz
+  S_VRG = S_VRK + 6,     // reciprocal site (amplitude) terms, 9 slots
+  S_COUNT = S_VRG + 9
 };
 
 // Device view of the system in cell-sorted order.  Site records are AoS so
@@ -113,6 +119,7 @@ struct PmeView {
   const int* border_all;   // sorted-site indices grouped by brick
   const int* stop;         // see Reduce::stop
   int erec_slot;           // reduction slot of the convolution's E_rec partials
+  double beta;             // Ewald parameter (the virial's m-space weights)
 };
 
 constexpr int kBrick = 8;

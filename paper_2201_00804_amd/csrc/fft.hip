@@ -295,7 +295,12 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(PmeView pm, int nb, T sgn) {
 }
 
 // ---- z pass: forward, influence function, inverse.  Block: (y, kx block).
-template <typename T>
+// VIR: also the m-space sum of the reciprocal virial,
+//   sum_m G(m) (pi^2/beta^2 + 1/m^2) m_a m_b |FFT(Q)(m)|^2
+// over the full spectrum (the half spectrum with the same weights as the
+// energy), with m_a = f_a / L_a and f_a the signed frequency of the index
+// (an index at K/2 taken as -K/2).
+template <typename T, bool VIR>
 __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, int nb) {
   if (stopped(pm.stop)) return;
   extern __shared__ char smem[];
@@ -327,12 +332,32 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
   const cplx<T>* tw = stage_twiddles<T, kBlock>(gTw<T>(pm, 2), b + nb * ls, N);
   cplx<T>* res = lds_fft<T, kBlock>(a, b, N, nb, ls, pm.radcode[2], pm.nrad[2], tw, T(-1));
   double e_part = 0.0;
+  double vk[6] = {0, 0, 0, 0, 0, 0};
   if (mact) {
     const int kx = kx0 + cth;
     const double mult = (kx == 0 || 2 * kx == pm.K[0]) ? 1.0 : 2.0;
+    double mx = 0.0, my = 0.0, b2 = 0.0;
+    if (VIR) {
+      const int fx = 2 * kx == pm.K[0] ? -kx : kx;
+      const int fy = 2 * y < pm.K[1] ? y : y - pm.K[1];
+      mx = fx * pm.scale[0] / pm.K[0];
+      my = fy * pm.scale[1] / pm.K[1];
+      b2 = kPi * kPi / (pm.beta * pm.beta);
+    }
     auto apply = [&](int z, T g) {
       cplx<T> v = res[cth * ls + z];
-      e_part += 0.5 * mult * (double)g * ((double)v.x * v.x + (double)v.y * v.y);
+      const double a2 = (double)v.x * v.x + (double)v.y * v.y;
+      e_part += 0.5 * mult * (double)g * a2;
+      if (VIR) {
+        const int fz = 2 * z < N ? z : z - N;
+        const double mz = fz * pm.scale[2] / N;
+        const double m2 = mx * mx + my * my + mz * mz;
+        if (m2 > 0.0) {
+          const double w = mult * (double)g * a2 * (b2 + 1.0 / m2);
+          vk[0] += w * mx * mx; vk[1] += w * my * my; vk[2] += w * mz * mz;
+          vk[3] += w * mx * my; vk[4] += w * mx * mz; vk[5] += w * my * mz;
+        }
+      }
       v.x *= g; v.y *= g;
       res[cth * ls + z] = v;
     };
@@ -349,6 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_conv(PmeView pm, Reduce red, i
     if (c < cols) C[((size_t)z * K1 + y) * h + kx0 + c] = res2[c * ls + z];
   });
   block_partial(e_part, red, pm.erec_slot);
+  if (VIR)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) block_partial(vk[k], red, S_VRK + k);
 }
 
 // ---- x pass, half complex to real.
@@ -499,7 +527,19 @@ static int pick_batch(int h) {
 }
 
 template <typename T>
-static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
+static void z_conv(const PmeView& pm, Reduce& red, int blocks, size_t shz, int nbz, hipStream_t st,
+                   bool vir) {
+  red.nparts[pm.erec_slot] = blocks;
+  if (vir) {
+    hipLaunchKernelGGL((k_fft_z_conv<T, true>), dim3(blocks), dim3(kBlock), shz, st, pm, red, nbz);
+    for (int k = 0; k < 6; ++k) red.nparts[S_VRK + k] = blocks;
+  } else {
+    hipLaunchKernelGGL((k_fft_z_conv<T, false>), dim3(blocks), dim3(kBlock), shz, st, pm, red, nbz);
+  }
+}
+
+template <typename T>
+static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st, bool vir) {
   const int K0 = pm.K[0], K1 = pm.K[1], K2 = pm.K[2], h = pm.kxh;
   const size_t csz = sizeof(cplx<T>);
   const int budget = 48 * 1024;
@@ -531,8 +571,7 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
     }
     launch_spread_fold(pm, mixed, st);
     hipLaunchKernelGGL((k_fft_plane_fwd<T, kPlaneThreads>), dim3(K2), dim3(kPlaneThreads), lds, st, pm);
-    red.nparts[pm.erec_slot] = K1 * nkbz;
-    hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
+    z_conv<T>(pm, red, K1 * nkbz, shz, nbz, st, vir);
     hipLaunchKernelGGL((k_fft_plane_inv<T, kPlaneThreads>), dim3(K2), dim3(kPlaneThreads), lds, st, pm);
     return;
   }
@@ -545,15 +584,14 @@ static void convolution_t(const PmeView& pm, Reduce& red, bool mixed, hipStream_
   const int nkby = (h + nby - 1) / nby;
   const size_t shy = lds_for(nby, K1);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(-1));
-  red.nparts[pm.erec_slot] = K1 * nkbz;
-  hipLaunchKernelGGL(k_fft_z_conv<T>, dim3(K1 * nkbz), dim3(kBlock), shz, st, pm, red, nbz);
+  z_conv<T>(pm, red, K1 * nkbz, shz, nbz, st, vir);
   hipLaunchKernelGGL(k_fft_y<T>, dim3(K2 * nkby), dim3(kBlock), shy, st, pm, nby, T(1));
   hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3((nrows + nlx - 1) / nlx), dim3(kBlock), shx, st, pm, nlx);
 }
 
-void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st) {
-  if (mixed) convolution_t<float>(pm, red, mixed, st);
-  else convolution_t<double>(pm, red, mixed, st);
+void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st, bool virial) {
+  if (mixed) convolution_t<float>(pm, red, mixed, st, virial);
+  else convolution_t<double>(pm, red, mixed, st, virial);
 }
 
 }  // namespace sibfa

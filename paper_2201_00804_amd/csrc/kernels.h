@@ -18,8 +18,9 @@ void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const
 // when out is NULL; the same-molecule pol list always in FP64 into out_in
 void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out_in,
                      hipStream_t st);
-void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
-                  hipStream_t st);
+// virial: also the real-space virial partials (slots S_VRI, S_VRF)
+void launch_force(const SysView& s, Reduce& red, const double4* mu, const float4* mu32, double4* F,
+                  bool mixed, bool virial, hipStream_t st);
 
 // pme.hip
 // Spread of the permanent multipoles (with the induced dipoles added to d
@@ -40,13 +41,17 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
                          hipStream_t st);
 // Reciprocal forces of the combined density added to the real-space forces;
 // scaled by the Coulomb constant and written in caller order.
-void launch_gather_force(const SysView& s, const PmeView& pm, const double4* mu,
+// virial: also the site (amplitude) terms of the reciprocal virial (slots
+// S_VRG).
+void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
-                         hipStream_t st);
+                         bool virial, hipStream_t st);
 
 // fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec partials in
-// the slot pm.erec_slot.
-void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st);
+// the slot pm.erec_slot; virial: also the m-space sum of the reciprocal
+// virial (slots S_VRK).
+void launch_convolution(const PmeView& pm, Reduce& red, bool mixed, hipStream_t st,
+                        bool virial = false);
 
 // vec.hip
 // PCG kernels over polarizable sites (double4 vectors, w unused).

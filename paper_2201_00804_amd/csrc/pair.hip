@@ -491,11 +491,30 @@ __device__ __forceinline__ MP<R> dipole_only(const R d[3]) {
 //  same-molecule pair:  MM and Mmu excluded (E - c0), mumu damped
 //                       = F(M', M'; E - c0) + F(mu, mu; lambda c0)
 //    (the first term is zero for clusters, where E = c0).
+// The virial (VIR) of the pair energies under a homogeneous strain
+// R -> (1 + eps) R with the multipoles fixed, W_ab = -dE/d eps_ab, is
+// 1/2 sum over directed list entries of f_a R_b, f the force on i of the
+// entry's pair; each kernel writes its block partials of the nine
+// components (row-major) to its own nine reduction slots.
+__device__ __forceinline__ void vir_add(double W[9], const double f[3], const double R[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) W[3 * a + b] += 0.5 * f[a] * R[b];
+}
+
+__device__ __forceinline__ void vir_partials(const double W[9], const Reduce& red, int slot0) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) block_partial(W[k], red, slot0 + k);
+}
+
 // Same-molecule pairs (FP64, one thread per site); writes Fout.
-__global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, const double4* mu,
+template <bool VIR>
+__global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, Reduce red, const double4* mu,
                                                         double4* Fout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double F[3] = {0.0, 0.0, 0.0};
+  double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (i < s.n) {
     {
       const int sub = 0, G = 1;
@@ -528,6 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, const double4
           Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
           mp_pair<double, false, true>(c, Pi, Pj, Rv, u, f);
           F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+          if (VIR) vir_add(W, f, Rv);
         }
         const double sj = s.sd[j].w;
         if (si > 0.0 && sj > 0.0) {
@@ -540,19 +560,22 @@ __global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, const double4
           const MP<double> Ui = dipole_only<double>(mui), Uj = dipole_only<double>(muj);
           mp_pair<double, false, true>(c, Ui, Uj, Rv, u, f);
           F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+          if (VIR) vir_add(W, f, Rv);
         }
       }
     }
     Fout[i] = make_double4(F[0], F[1], F[2], 0.0);
   }
+  if (VIR) vir_partials(W, red, S_VRI);
 }
 
 // One intermolecular pair of k_force (see the identity above).  NEAR: the
 // pair may be damped (x < 50); far pairs never are.
-template <typename R, bool NEAR>
+template <typename R, bool NEAR, bool VIR>
 __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const MP<R>& Mi,
                                            const MP<R>& Pi, const R xi[3], R si,
-                                           const double4* mu, const float4* mu32, double F[3]) {
+                                           const double4* mu, const float4* mu32, double F[3],
+                                           double W[9]) {
   MP<R> Mj;
   R xj[3], Rv[3], muj[3];
   load_mp<R>(s, j, Mj, xj);
@@ -583,21 +606,30 @@ __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const
   Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
   R u, f[3];
   mp_pair<R, false, true>(c, Pi, Pj, Rv, u, f);
-  F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+  double fd[3] = {(double)f[0], (double)f[1], (double)f[2]};
+  F[0] += fd[0]; F[1] += fd[1]; F[2] += fd[2];
   if (NEAR && damp) {
     mp_pair<R, false, true>(D, Mi, Mj, Rv, u, f);
     F[0] += (double)f[0]; F[1] += (double)f[1]; F[2] += (double)f[2];
+    if (VIR) {
+      fd[0] += (double)f[0]; fd[1] += (double)f[1]; fd[2] += (double)f[2];
+    }
+  }
+  if (VIR) {
+    const double Rd[3] = {(double)Rv[0], (double)Rv[1], (double)Rv[2]};
+    vir_add(W, fd, Rd);
   }
 }
 
 // Intermolecular pairs within the cutoff (precision R); adds to Fout.
 // Near entries first (the damped ones are among them), then far ones.
-template <typename R, int G>
-__global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, const float4* mu32,
-                                                  double4* Fout) {
+template <typename R, int G, bool VIR>
+__global__ __launch_bounds__(kBlock) void k_force(SysView s, Reduce red, const double4* mu,
+                                                  const float4* mu32, double4* Fout) {
   const int sub = threadIdx.x % G;
   const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   double F[3] = {0.0, 0.0, 0.0};
+  double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (i < s.n) {
     MP<R> Mi;
     R xi[3], mui[3];
@@ -609,15 +641,15 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
     const int* row = s.nb_all + (size_t)i * s.cap_all;
     const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
     for (int k = sub; k < nn; k += G)
-      force_pair<R, true>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F);
+      force_pair<R, true, VIR>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F, W);
     const int* far = row + s.cap_all - 1;
     int k = sub;
     for (; k + G < nf; k += 2 * G) {
       const int j0 = far[-k], j1 = far[-(k + G)];
-      force_pair<R, false>(s, i, j0, Mi, Pi, xi, si, mu, mu32, F);
-      force_pair<R, false>(s, i, j1, Mi, Pi, xi, si, mu, mu32, F);
+      force_pair<R, false, VIR>(s, i, j0, Mi, Pi, xi, si, mu, mu32, F, W);
+      force_pair<R, false, VIR>(s, i, j1, Mi, Pi, xi, si, mu, mu32, F, W);
     }
-    if (k < nf) force_pair<R, false>(s, i, far[-k], Mi, Pi, xi, si, mu, mu32, F);
+    if (k < nf) force_pair<R, false, VIR>(s, i, far[-k], Mi, Pi, xi, si, mu, mu32, F, W);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
@@ -626,6 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, const double4* mu, 
     f.x += F[0]; f.y += F[1]; f.z += F[2];
     Fout[i] = f;
   }
+  if (VIR) vir_partials(W, red, S_VRF);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -691,13 +724,23 @@ void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out
   else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, nullptr, out32, out_in);
 }
 
-void launch_force(const SysView& s, const double4* mu, const float4* mu32, double4* F, bool mixed,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_force_intra, dim3((s.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, mu,
-                     F);
-  const dim3 g(blocks_for(s.n, kG)), b(kBlock);
-  if (mixed) hipLaunchKernelGGL((k_force<float, kG>), g, b, 0, st, s, mu, mu32, F);
-  else hipLaunchKernelGGL((k_force<double, kG>), g, b, 0, st, s, mu, mu32, F);
+void launch_force(const SysView& s, Reduce& red, const double4* mu, const float4* mu32, double4* F,
+                  bool mixed, bool virial, hipStream_t st) {
+  const dim3 gi((s.n + kBlock - 1) / kBlock), b(kBlock);
+  const dim3 g(blocks_for(s.n, kG));
+  if (virial) {
+    hipLaunchKernelGGL(k_force_intra<true>, gi, b, 0, st, s, red, mu, F);
+    if (mixed) hipLaunchKernelGGL((k_force<float, kG, true>), g, b, 0, st, s, red, mu, mu32, F);
+    else hipLaunchKernelGGL((k_force<double, kG, true>), g, b, 0, st, s, red, mu, mu32, F);
+    for (int k = 0; k < 9; ++k) {
+      red.nparts[S_VRI + k] = (int)gi.x;
+      red.nparts[S_VRF + k] = (int)g.x;
+    }
+    return;
+  }
+  hipLaunchKernelGGL(k_force_intra<false>, gi, b, 0, st, s, red, mu, F);
+  if (mixed) hipLaunchKernelGGL((k_force<float, kG, false>), g, b, 0, st, s, red, mu, mu32, F);
+  else hipLaunchKernelGGL((k_force<double, kG, false>), g, b, 0, st, s, red, mu, mu32, F);
 }
 
 }  // namespace sibfa

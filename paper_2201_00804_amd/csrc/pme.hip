@@ -283,68 +283,90 @@ __host__ __device__ constexpr int didx(int kx, int ky, int kz) {
   return kx + 4 * (ky + 4 * kz);
 }
 
-template <typename R, int P>
-__global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, const double4* mu,
-                                                         const double4* Freal, const int* perm,
-                                                         double* out) {
+// Reciprocal forces of the combined density at every site.  VIR: also the
+// site terms of the reciprocal virial, sum_j [d'_jb d_a phi(r_j) +
+// 2/3 Theta_jbc d_a d_c phi(r_j)] with d' = d + mu (block partials, slots
+// S_VRG, row-major).
+template <typename R, int P, bool VIR>
+__global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, Reduce red,
+                                                         const double4* mu, const double4* Freal,
+                                                         const int* perm, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s.n) return;
-  const double4 p = s.sp[i], d4 = s.sd[i], t4 = s.sth[i];
-  const double2 t2 = s.sth2[i];
-  const double4 m = mu[i];
-  int base[3];
-  R th[3][4][P];
-  site_splines<R, P, 3>(pm, p.x, p.y, p.z, base, th);
-  double D[64];
+  double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < s.n) {
+    const double4 p = s.sp[i], d4 = s.sd[i], t4 = s.sth[i];
+    const double2 t2 = s.sth2[i];
+    const double4 m = mu[i];
+    int base[3];
+    R th[3][4][P];
+    site_splines<R, P, 3>(pm, p.x, p.y, p.z, base, th);
+    double D[64];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) D[k] = 0.0;
-  for (int tz = 0; tz < P; ++tz) {
-    int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
-    for (int ty = 0; ty < P; ++ty) {
-      int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
-      const size_t row = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
-      R sx[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 64; ++k) D[k] = 0.0;
+    for (int tz = 0; tz < P; ++tz) {
+      int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
+      for (int ty = 0; ty < P; ++ty) {
+        int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
+        const size_t row = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
+        R sx[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int tx = 0; tx < P; ++tx) {
-        int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
-        const R v = grid_phi<R>(pm, row + ix);
+        for (int tx = 0; tx < P; ++tx) {
+          int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
+          const R v = grid_phi<R>(pm, row + ix);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sx[k] += v * th[0][k][tx];
-      }
-#pragma unroll
-      for (int kz = 0; kz <= 3; ++kz)
-#pragma unroll
-        for (int ky = 0; ky <= 3 - kz; ++ky) {
-          const R yz = th[1][ky][ty] * th[2][kz][tz];
-#pragma unroll
-          for (int kx = 0; kx <= 3 - ky - kz; ++kx) D[didx(kx, ky, kz)] += (double)(sx[kx] * yz);
+          for (int k = 0; k < 4; ++k) sx[k] += v * th[0][k][tx];
         }
-    }
-  }
-  const double sc[3] = {pm.scale[0], pm.scale[1], pm.scale[2]};
-  auto der = [&](int a, int b, int c) -> double {   // b, c = -1 for lower order
-    int k[3] = {0, 0, 0};
-    double f = sc[a];
-    k[a]++;
-    if (b >= 0) { k[b]++; f *= sc[b]; }
-    if (c >= 0) { k[c]++; f *= sc[c]; }
-    return D[didx(k[0], k[1], k[2])] * f;
-  };
-  const double q = p.w;
-  const double dd[3] = {d4.x + m.x, d4.y + m.y, d4.z + m.z};
-  const double T[3][3] = {{t4.x, t4.y, t4.z}, {t4.y, t4.w, t2.x}, {t4.z, t2.x, t2.y}};
-  const double4 fr = Freal[i];
-  const double frr[3] = {fr.x, fr.y, fr.z};
-  const int c = perm[i];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double f = q * der(a, -1, -1);
-    for (int b = 0; b < 3; ++b) {
-      f += dd[b] * der(a, b, -1);
-      for (int cc = 0; cc < 3; ++cc) f += T[b][cc] * der(a, b, cc) * (1.0 / 3.0);
+        for (int kz = 0; kz <= 3; ++kz)
+#pragma unroll
+          for (int ky = 0; ky <= 3 - kz; ++ky) {
+            const R yz = th[1][ky][ty] * th[2][kz][tz];
+#pragma unroll
+            for (int kx = 0; kx <= 3 - ky - kz; ++kx) D[didx(kx, ky, kz)] += (double)(sx[kx] * yz);
+          }
+      }
     }
-    out[3 * (size_t)c + a] = kCoulomb * (frr[a] - f);
+    const double sc[3] = {pm.scale[0], pm.scale[1], pm.scale[2]};
+    auto der = [&](int a, int b, int c) -> double {   // b, c = -1 for lower order
+      int k[3] = {0, 0, 0};
+      double f = sc[a];
+      k[a]++;
+      if (b >= 0) { k[b]++; f *= sc[b]; }
+      if (c >= 0) { k[c]++; f *= sc[c]; }
+      return D[didx(k[0], k[1], k[2])] * f;
+    };
+    const double q = p.w;
+    const double dd[3] = {d4.x + m.x, d4.y + m.y, d4.z + m.z};
+    const double T[3][3] = {{t4.x, t4.y, t4.z}, {t4.y, t4.w, t2.x}, {t4.z, t2.x, t2.y}};
+    const double4 fr = Freal[i];
+    const double frr[3] = {fr.x, fr.y, fr.z};
+    const int c = perm[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double f = q * der(a, -1, -1);
+      for (int b = 0; b < 3; ++b) {
+        f += dd[b] * der(a, b, -1);
+        for (int cc = 0; cc < 3; ++cc) f += T[b][cc] * der(a, b, cc) * (1.0 / 3.0);
+      }
+      out[3 * (size_t)c + a] = kCoulomb * (frr[a] - f);
+    }
+    if (VIR) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double da = der(a, -1, -1);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          double w = dd[b] * da;
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) w += (2.0 / 3.0) * T[b][cc] * der(a, cc, -1);
+          W[3 * a + b] = w;
+        }
+      }
+    }
   }
+  if (VIR)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) block_partial(W[k], red, S_VRG + k);
 }
 
 // ------------------------------------------------------------ launchers
@@ -394,24 +416,36 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
   }
 }
 
-template <int P>
-static void gather_force_p(const SysView& s, const PmeView& pm, const double4* mu,
-                           const double4* Freal, const int* perm, double* out, bool mixed,
-                           hipStream_t st) {
+template <int P, bool VIR>
+static void gather_force_pv(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
+                            const double4* Freal, const int* perm, double* out, bool mixed,
+                            hipStream_t st) {
   const dim3 g((s.n + kBlock - 1) / kBlock), b(kBlock);
   if (mixed)
-    hipLaunchKernelGGL((k_gather_force<float, P>), g, b, 0, st, s, pm, mu, Freal, perm, out);
+    hipLaunchKernelGGL((k_gather_force<float, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
+                       out);
   else
-    hipLaunchKernelGGL((k_gather_force<double, P>), g, b, 0, st, s, pm, mu, Freal, perm, out);
+    hipLaunchKernelGGL((k_gather_force<double, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
+                       out);
+  if (VIR)
+    for (int k = 0; k < 9; ++k) red.nparts[S_VRG + k] = (int)g.x;
 }
 
-void launch_gather_force(const SysView& s, const PmeView& pm, const double4* mu,
+template <int P>
+static void gather_force_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
+                           const double4* Freal, const int* perm, double* out, bool mixed,
+                           bool vir, hipStream_t st) {
+  if (vir) gather_force_pv<P, true>(s, pm, red, mu, Freal, perm, out, mixed, st);
+  else gather_force_pv<P, false>(s, pm, red, mu, Freal, perm, out, mixed, st);
+}
+
+void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
-                         hipStream_t st) {
+                         bool virial, hipStream_t st) {
   switch (pm.order) {
-    case 4: gather_force_p<4>(s, pm, mu, Freal, perm, out, mixed, st); break;
-    case 6: gather_force_p<6>(s, pm, mu, Freal, perm, out, mixed, st); break;
-    default: gather_force_p<5>(s, pm, mu, Freal, perm, out, mixed, st); break;
+    case 4: gather_force_p<4>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
+    case 6: gather_force_p<6>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
+    default: gather_force_p<5>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
   }
 }
 

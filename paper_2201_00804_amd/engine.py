@@ -56,16 +56,52 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-class Engine:
-    """One system (box or cluster) resident on one device."""
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator: the
+    alloc/free callbacks of sibfa_create and sibfa_batch_create.  Blocks
+    are taken on the stream the library enqueues on."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device, stream):
+        self.device = int(device)
+        self.stream = stream
+
+        def _alloc(nbytes, user):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                              self.stream))
+            except RuntimeError:   # out of memory: the library reports E_NOMEM
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        # the ctypes callback objects must outlive the library's use of them
+        self.alloc_fn = _lib.ALLOC_FN(_alloc)
+        self.free_fn = _lib.FREE_FN(_free)
+
+
+def _callbacks(allocator):
+    """The alloc/free arguments of the create calls: the allocator's, or
+    null function pointers (the library then calls hipMalloc)."""
+    if allocator is None:
+        return _lib.ALLOC_FN(), _lib.FREE_FN()
+    return allocator.alloc_fn, allocator.free_fn
+
+
+class Engine:
+    """One system (box or cluster) resident on one device.  Device memory
+    comes from torch's caching allocator (torch_memory=False: the library
+    calls hipMalloc itself)."""
+
+    def __init__(self, device=0, stream=None, torch_memory=True):
         self.lib = _lib.load()
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.allocator = TorchAllocator(device, self.stream) if torch_memory else None
+        af, ff = _callbacks(self.allocator)
         h = ctypes.c_void_p()
         st = self.lib.sibfa_create(ctypes.byref(h), int(device),
-                                   ctypes.c_void_p(self.stream.cuda_stream), None, None, None)
+                                   ctypes.c_void_p(self.stream.cuda_stream), af, ff, None)
         if st != 0:
             raise SibfaError(st, "sibfa_create failed")
         self.h = h
@@ -151,7 +187,9 @@ class Engine:
                                              int(bool(warm_start)), _ptr(mu), ctypes.byref(e)))
         return mu, e.value
 
-    def energy_forces(self, forces=True, out=None):
+    def energy_forces(self, forces=True, out=None, virial=False):
+        """(E_pol, E_elec, forces or None), plus the 3x3 virial (a host
+        list of rows, kcal/mol) as a fourth item when virial is true."""
         e_pol = ctypes.c_double(0.0)
         e_elec = ctypes.c_double(0.0)
         f = None
@@ -159,8 +197,12 @@ class Engine:
             f = out if out is not None else torch.empty((self.n, 3), dtype=torch.float64,
                                                         device=self.device)
             _dev(f, torch.float64, (self.n, 3), self.device, "forces")
+        w = (ctypes.c_double * 9)() if virial else None
         self._check(self.lib.sibfa_energy_forces(self.h, ctypes.byref(e_pol), ctypes.byref(e_elec),
-                                                 _ptr(f), None))
+                                                 _ptr(f), w))
+        if virial:
+            return e_pol.value, e_elec.value, f, [[w[3 * a + b] for b in range(3)]
+                                                  for a in range(3)]
         return e_pol.value, e_elec.value, f
 
     def get_dipoles(self):
