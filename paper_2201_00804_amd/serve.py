@@ -11,14 +11,20 @@ converged induced dipoles.  The server keeps work resident on the device:
     larger than the whole budget is rejected.  A repeat of a resident
     system (new positions, e.g. the next MD step) updates positions and
     warm-starts the solve from its previous dipoles;
+  * several box requests are in flight at once: box_slots worker threads
+    each take the oldest queued box request whose system is not already in
+    flight (requests of one system stay in arrival order), so the solves of
+    different boxes overlap on the device, each on its context's streams;
   * clusters are gathered into batches: every cluster pending when the
     cluster worker becomes free goes into one sibfa_batch_clusters call
     (three launches for the whole batch), warm-started from the dipoles of
-    the system's previous request when there was one.
+    the system's previous request when there was one.  A cluster system's
+    multipoles, polarizabilities and last dipoles stay on the device; a
+    request brings only its positions.
 
-Two worker threads (boxes, clusters) run concurrently on separate streams;
-the request clock starts at the request's arrival and stops when its
-energies and forces are in host memory.
+The box workers and the cluster worker run concurrently on separate
+streams; the request clock starts at the request's arrival and stops when
+its energies and forces are in host memory.
 """
 import collections
 import math
@@ -60,7 +66,7 @@ class Server:
     alpha, box or None) plus, for boxes, 'params' (beta, cutoff, grid)."""
 
     def __init__(self, systems, device=0, precision="mixed", tol=1e-8, hbm_budget=None,
-                 max_batch_sites=1 << 18, max_iter=400):
+                 max_batch_sites=1 << 18, max_iter=400, box_slots=3):
         self.systems = systems
         self.dev = torch.device("cuda", device)
         self.precision = precision
@@ -71,11 +77,16 @@ class Server:
             hbm_budget = int(0.5 * free)
         self.budget = int(hbm_budget)
         self.max_batch_sites = max_batch_sites
+        self.box_slots = max(1, int(box_slots))
         self.resident = collections.OrderedDict()   # name -> _Resident (LRU order)
         self.resident_bytes = 0
         self.evictions = 0
         self.rejections = 0
-        self.cluster_mu = {}                        # name -> host mu of the last request
+        self.inflight = set()                       # box systems being evaluated
+        self.box_spans = []                         # (start, done) of box requests
+        self._admit_lock = threading.Lock()
+        self.cl_static = {}                         # name -> device arrays of a cluster
+        self.cluster_mu = {}                        # name -> device mu of the last request
         self.cl_stream = torch.cuda.Stream(self.dev)
         self.batcher = ClusterBatch(device, stream=self.cl_stream)
         self.cl_params = _engine.default_params(tol=tol, precision=precision, max_iter=max_iter)
@@ -95,8 +106,19 @@ class Server:
                                       precision=self.precision, max_iter=self.max_iter)
 
     def _admit(self, name):
-        """Resident context of a box system, creating it (and evicting LRU
-        contexts) if needed; None if it can never fit."""
+        """Resident context of a box system, creating it (and evicting
+        least-recently-used contexts that are not in flight) if needed; None
+        if it can never fit.  Waits while the contexts in flight hold the
+        memory it needs."""
+        while True:
+            with self._admit_lock:
+                r = self._admit_now(name)
+            if r is not False:
+                return r
+            with self._cv:   # a box in flight finishes and notifies
+                self._cv.wait(timeout=0.01)
+
+    def _admit_now(self, name):
         if name in self.resident:
             self.resident.move_to_end(name)
             return self.resident[name]
@@ -108,8 +130,11 @@ class Server:
         if fp > self.budget:
             self.rejections += 1
             return None
-        while self.resident and self.resident_bytes + fp > self.budget:
-            old, r = self.resident.popitem(last=False)
+        while self.resident_bytes + fp > self.budget:
+            idle = [k for k in self.resident if k not in self.inflight]
+            if not idle:
+                return False          # only contexts in flight: wait for one
+            r = self.resident.pop(idle[0])
             r.stream.synchronize()
             r.engine.close()
             self.resident_bytes -= r.footprint
@@ -146,26 +171,42 @@ class Server:
         r.has_mu = req.status == 0
         req.iterations, req.e_pol, req.e_elec = it, e_pol, e_elec
 
+    def _static(self, name):
+        """Device arrays of a cluster system, uploaded on its first request."""
+        s = self.cl_static.get(name)
+        if s is None:
+            d = self.systems[name]
+            t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=self.dev)
+            s = dict(mol=t(np.asarray(d["mol"]).astype(np.int32), torch.int32), q=t(d["q"]),
+                     dip=t(d["dip"]), quad=t(d["quad"]), alpha=t(d["alpha"]))
+            self.cl_static[name] = s
+        return s
+
     def _run_clusters(self, reqs):
         offsets = [0]
         for q in reqs:
             offsets.append(offsets[-1] + len(q.pos))
-        cat = lambda key: np.concatenate([self.systems[q.system][key] for q in reqs])
         warm = [q.system in self.cluster_mu for q in reqs]
-        mu0 = np.concatenate([self.cluster_mu.get(q.system, np.zeros((len(q.pos), 3)))
-                              for q in reqs])
-        t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=self.dev)
         with torch.cuda.stream(self.cl_stream):
-            xyz = t(np.concatenate([q.pos for q in reqs]))
-            mol = t(cat("mol").astype(np.int32), torch.int32)
-            res = self.batcher.run(offsets, xyz, mol, t(cat("q")), t(cat("dip")), t(cat("quad")),
-                                   t(cat("alpha")), self.cl_params, warm=warm, mu=t(mu0))
-            mu = res.mu.cpu().numpy()
+            # only the positions come from the host; the rest of the batch is
+            # laid out from device-resident arrays
+            st_ = [self._static(q.system) for q in reqs]
+            cat = lambda key: torch.cat([s[key] for s in st_])
+            xyz = torch.as_tensor(np.concatenate([q.pos for q in reqs]), dtype=torch.float64,
+                                  device=self.dev)
+            mu0 = torch.cat([self.cluster_mu[q.system] if w else
+                             torch.zeros((len(q.pos), 3), dtype=torch.float64, device=self.dev)
+                             for q, w in zip(reqs, warm)])
+            res = self.batcher.run(offsets, xyz, cat("mol"), cat("q"), cat("dip"), cat("quad"),
+                                   cat("alpha"), self.cl_params, warm=warm, mu=mu0)
             F = res.forces.cpu().numpy()
             e_pol = res.e_pol.cpu().numpy()
             e_elec = res.e_elec.cpu().numpy()
             its = res.iters.cpu().numpy()
             st = res.status.cpu().numpy()
+            for c, q in enumerate(reqs):
+                if st[c] == 0:   # the dipoles stay on the device for the next request
+                    self.cluster_mu[q.system] = res.mu[offsets[c]:offsets[c + 1]].clone()
         for c, q in enumerate(reqs):
             a, b = offsets[c], offsets[c + 1]
             q.forces = F[a:b]
@@ -173,18 +214,27 @@ class Server:
             q.iterations, q.status = int(its[c]), int(st[c])
             q.warm = warm[c]
             q.batch_size = len(reqs)
-            if st[c] == 0:
-                self.cluster_mu[q.system] = mu[a:b].copy()
         self.batches.append((len(reqs), offsets[-1]))
+
+    def _next_box(self):
+        """The oldest queued box request whose system is not in flight
+        (called with the condition held), or None."""
+        for k, q in enumerate(self._box_q):
+            if q.system not in self.inflight:
+                del self._box_q[k]
+                self.inflight.add(q.system)
+                return q
+        return None
 
     def _box_worker(self):
         while True:
             with self._cv:
-                while not self._box_q and not self._stop:
+                req = self._next_box()
+                while req is None and not (self._stop and not self._box_q):
                     self._cv.wait()
-                if not self._box_q:
+                    req = self._next_box()
+                if req is None:
                     return
-                req = self._box_q.popleft()
             t0 = time.perf_counter()
             req.start = t0
             try:
@@ -193,7 +243,11 @@ class Server:
                 self.errors.append(repr(e))
                 req.status = "error"
             req.done = time.perf_counter()
-            self.busy["box"] += req.done - t0
+            with self._cv:
+                self.inflight.discard(req.system)
+                self.busy["box"] += req.done - t0
+                self.box_spans.append((t0, req.done))
+                self._cv.notify_all()
 
     def _cluster_worker(self):
         while True:
@@ -230,8 +284,9 @@ class Server:
             if q.kind == "cluster" and len(q.pos) > MAX_SITES:
                 raise ValueError("cluster larger than the batch limit; serve it as a box-less context")
         self._stop = False
-        workers = [threading.Thread(target=self._box_worker, daemon=True),
-                   threading.Thread(target=self._cluster_worker, daemon=True)]
+        workers = [threading.Thread(target=self._box_worker, daemon=True)
+                   for _ in range(self.box_slots)]
+        workers.append(threading.Thread(target=self._cluster_worker, daemon=True))
         for w in workers:
             w.start()
         t0 = time.perf_counter()
@@ -303,6 +358,25 @@ def request_stream(systems, n_requests, rate, seed=0, cluster_share=0.7, step=0.
     return out
 
 
+def box_overlap(spans):
+    """How much box evaluations overlapped in time: the share of box
+    requests that ran while another box request was running, and the
+    largest number in flight at once."""
+    if not spans:
+        return dict(box_overlap_share=0.0, max_boxes_in_flight=0)
+    ev = sorted([(s, 1) for s, _ in spans] + [(d, -1) for _, d in spans])
+    cur = best = 0
+    for _, k in ev:
+        cur += k
+        best = max(best, cur)
+    s = np.array(sorted(spans))
+    overl = 0
+    for i, (a, b) in enumerate(s):
+        if np.any((s[:, 0] < b) & (s[:, 1] > a) & (np.arange(len(s)) != i)):
+            overl += 1
+    return dict(box_overlap_share=round(overl / len(s), 3), max_boxes_in_flight=int(best))
+
+
 def summarize(requests, wall, server=None, skip=0):
     """Latency percentiles (ms) and throughput over requests[skip:]."""
     rs = [q for q in requests[skip:] if q.done is not None]
@@ -323,6 +397,8 @@ def summarize(requests, wall, server=None, skip=0):
                                   and q.iterations is not None])), 2))
     if server is not None:
         out["utilisation"] = {k: round(v / wall, 3) for k, v in server.busy.items()}
+        out["box_slots"] = server.box_slots
+        out.update(box_overlap(server.box_spans))
         out["evictions"] = server.evictions
         out["rejections"] = server.rejections
         if server.batches:
