@@ -184,6 +184,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     what: 'energy' -> 1/2 sum of U over ordered pairs
           'force'  -> per-site force -dU/dr_i summed over pairs at i (n,3)
           'field'  -> per-site field of the j-side multipoles at i (n,3)
+          'fieldgrad' -> per-site field gradient dE_b/dr_a of the j-side
+                      multipoles at i (n,3,3), E = -grad phi
           'virial' -> W_ab = -dE/d eps_ab of the pair energy (3,3) under the
                       homogeneous strain R -> (1 + eps) R of every pair
                       separation with the multipoles fixed in the global
@@ -192,12 +194,14 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     abar, athole = thole
     maxrank_i = max([k for k, v in enumerate(Mi) if v is not None], default=0)
     maxrank_j = max([k for k, v in enumerate(Mj) if v is not None], default=0)
-    extra = 0 if what == "energy" else 1
+    extra = {"energy": 0, "fieldgrad": 2}.get(what, 1)
     nmax = maxrank_i + maxrank_j + extra
     if what == "energy":
         acc = 0.0
     elif what == "virial":
         acc = np.zeros((3, 3))
+    elif what == "fieldgrad":
+        acc = np.zeros((n_sites, 3, 3))
     else:
         acc = np.zeros((n_sites, 3))
     sel = np.arange(len(pairs)) if pair_mask is None else np.flatnonzero(pair_mask)
@@ -211,7 +215,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
         c = class_coefficients(cls, r, pairs.same[idx], kernel, beta,
                                abar[i], abar[j], a_ij, nmax)
         D = [deriv_tensor(n, R, c) for n in range(nmax + 1)]
-        mi = _mlist(*Mi, i) if what != "field" else [(0, np.ones(len(i)))]
+        mi = (_mlist(*Mi, i) if what not in ("field", "fieldgrad")
+              else [(0, np.ones(len(i)))])
         mj = _mlist(*Mj, j)
         val = _interaction(D, mi, mj, extra)
         if what == "energy":

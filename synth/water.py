@@ -221,3 +221,15 @@ def config_system(name):
     params = dict(beta=c["beta"], cutoff=c["cutoff"], grid=c["grid"],
                   order=c["order"], tol=c["tol"])
     return sysd, params
+
+
+def water_frames(sysd):
+    """Frame sites of every site for local-frame multipoles: each water's
+    five sites (O, H1, H2, B1, B2, consecutive) use the frame of its O, H1
+    and H2.  Returns int32 [n, 3] site indices (caller order).  The random
+    dipoles, quadrupoles and polarizabilities of the system dicts serve as
+    the local-frame values (their distributions do not depend on the
+    frame)."""
+    n = len(sysd["pos"])
+    first = (np.arange(n) // WATER_SITES) * WATER_SITES
+    return np.stack([first, first + 1, first + 2], axis=1).astype(np.int32)
