@@ -159,6 +159,33 @@ sibfa_status sibfa_set_multipoles(sibfa_ctx ctx, const double* q,
 sibfa_status sibfa_set_polarizabilities(sibfa_ctx ctx, const double* alpha,
                                         const double* thole);
 
+/* Molecular local frames (Multipolar Electrostatics: the distributed
+ * multipoles, and SIBFA's anisotropic polarizabilities, are given in a
+ * frame attached to the molecule and rotated to the global frame at each
+ * geometry).  frames [n][3] (device, int32): for every site the indices
+ * (o, a, b) of three distinct sites of its own molecule that span its
+ * frame (e_z along the bisector of r_a - r_o and r_b - r_o, e_x in their
+ * plane towards a, e_y = e_z x e_x), or -1 -1 -1 for a site whose local
+ * values are already global.  dip_local [n][3], quad_local [n][6]
+ * (device; NULL = zero) replace the dipoles and quadrupoles of
+ * sibfa_set_multipoles (q stays); alpha_local [n][6] (device; NULL = the
+ * polarizabilities of sibfa_set_polarizabilities are not rotated)
+ * replaces them.  The library copies all arrays.  From then on every
+ * computation rotates them at the current positions, and the forces of
+ * sibfa_energy_forces include the derivative of the rotation (the torques
+ * as forces on the frame sites), as does its virial.  Call after
+ * sibfa_set_multipoles and sibfa_set_polarizabilities (SIBFA_E_STATE
+ * otherwise); a later call of either of them switches the frames off, as
+ * does frames = NULL (the global multipoles then stay those of the last
+ * rotation).  A frame that does not meet the rules above: SIBFA_E_ARG,
+ * nothing changed.  Synchronizes the context's streams.  Device memory:
+ * about 300 bytes per site more while frames are set (the local copies
+ * and the buffers of the rotation forces). */
+sibfa_status sibfa_set_local_frames(sibfa_ctx ctx, const int32_t* frames,
+                                    const double* dip_local,
+                                    const double* quad_local,
+                                    const double* alpha_local);
+
 /* Permanent field E (Eq. 18's right-hand side, e/A^2) at every site, [n][3]
  * (device), zero rows at non-polarizable sites. */
 sibfa_status sibfa_permanent_field(sibfa_ctx ctx, double* field_out);

@@ -108,9 +108,14 @@ def _mat_to_sym6(m):
 
 
 def site_rotations(pos, frames):
-    """R of every site's molecule (n, 3, 3); frames (n, 3) site indices."""
+    """R of every site's molecule (n, 3, 3); frames (n, 3) site indices, a
+    row of -1 for a site without a frame (R = identity: its local values
+    are global)."""
     f = np.asarray(frames, int)
-    return frame(pos[f[:, 0]], pos[f[:, 1]], pos[f[:, 2]])
+    R = np.broadcast_to(np.eye(3), (len(f), 3, 3)).copy()
+    on = f[:, 0] >= 0
+    R[on] = frame(pos[f[on, 0]], pos[f[on, 1]], pos[f[on, 2]])
+    return R
 
 
 def to_global(sys_local, frames):
@@ -158,9 +163,9 @@ def multipole_gradients(sysm, prm, mu_pol, ctx=None):
     return COULOMB * Gd, COULOMB * GT, COULOMB * Ga
 
 
-def frame_forces(sys_local, frames, prm, mu_pol, ctx=None):
-    """The forces (n,3) from the rotation of the local multipoles and
-    polarizabilities: -sum_pq (dE/dR)_pq dR_pq/dr_k on each frame site k."""
+def _frame_terms(sys_local, frames, prm, mu_pol, ctx=None):
+    """Per site n and frame site k = o, a, b of n's frame: the force
+    -sum_pq C_n,pq dR_pq/dr_k (n, 3, 3), C_n the site's term of dE/dR."""
     s_loc = sys_local
     f = np.asarray(frames, int)
     glob = to_global(s_loc, f)
@@ -169,13 +174,54 @@ def frame_forces(sys_local, frames, prm, mu_pol, ctx=None):
     C = np.einsum("na,nb->nab", Gd, s_loc.dip)
     C += 2.0 * np.einsum("nab,nbc,ncd->nad", GT, R, _sym6_to_mat(s_loc.quad))
     C += 2.0 * np.einsum("nab,nbc,ncd->nad", Ga, R, _sym6_to_mat(s_loc.alpha))
-    dR = frame_derivatives(s_loc.pos[f[:, 0]], s_loc.pos[f[:, 1]], s_loc.pos[f[:, 2]])
-    F = np.zeros((s_loc.n, 3))
+    on = f[:, 0] >= 0
+    per = np.zeros((s_loc.n, 3, 3))
+    dR = frame_derivatives(s_loc.pos[f[on, 0]], s_loc.pos[f[on, 1]], s_loc.pos[f[on, 2]])
+    per[on] = -np.einsum("npq,nkcpq->nkc", C[on], dR)
+    return per
+
+
+def frame_forces(sys_local, frames, prm, mu_pol, ctx=None):
+    """The forces (n,3) from the rotation of the local multipoles and
+    polarizabilities: -sum_pq (dE/dR)_pq dR_pq/dr_k on each frame site k."""
+    f = np.asarray(frames, int)
+    per = _frame_terms(sys_local, f, prm, mu_pol, ctx)
+    F = np.zeros((sys_local.n, 3))
     # each site's contribution, through its own frame sites
-    per = -np.einsum("npq,nkcpq->nkc", C, dR)
+    on = f[:, 0] >= 0
     for k in range(3):
-        np.add.at(F, f[:, k], per[:, k, :])
+        np.add.at(F, f[on, k], per[on, k, :])
     return F
+
+
+def _min_image(d, box):
+    if box is None:
+        return d
+    b = np.asarray(box, float)
+    H = np.diag(b) if b.ndim == 1 else b      # rows: lattice vectors
+    frac = d @ np.linalg.inv(H)
+    return d - np.round(frac) @ H
+
+
+def virial(sys_local, frames, prm, mu_pol, ctx=None):
+    """Virial (3,3, kcal/mol) with local frames: W_ab = -dE/d eps_ab when the
+    strain r -> (1 + eps) r moves the sites and the cell and the local
+    multipoles follow their strained frames.  It is the virial at fixed
+    global multipoles (model.virial) plus the frame term: for every site's
+    frame, sum over its sites k of F_k (r_k - r_o)^T, F_k the forces of
+    the rotation (they sum to zero over the frame, so the origin o is
+    free; minimum-image separations in a periodic cell)."""
+    from .model import virial as fixed_virial
+    f = np.asarray(frames, int)
+    glob = to_global(sys_local, f)
+    c = ctx if ctx is not None else Context(glob, prm)
+    W = fixed_virial(glob, prm, mu_pol, ctx=c)
+    per = _frame_terms(sys_local, f, prm, mu_pol, ctx=c)
+    pos = sys_local.pos
+    on = f[:, 0] >= 0
+    rel = np.stack([_min_image(pos[f[on, k]] - pos[f[on, 0]], sys_local.box) for k in range(3)],
+                   1)
+    return W + np.einsum("nkc,nkd->cd", per[on], rel)
 
 
 def evaluate(sys_local, frames, prm):

@@ -56,6 +56,7 @@ SIGNATURES = [
     ("sibfa_update_positions", ctypes.c_int, [_P, _P]),
     ("sibfa_set_multipoles", ctypes.c_int, [_P, _P, _P, _P]),
     ("sibfa_set_polarizabilities", ctypes.c_int, [_P, _P, _P]),
+    ("sibfa_set_local_frames", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sibfa_permanent_field", ctypes.c_int, [_P, _P]),
     ("sibfa_apply_T", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_solve_induced", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), _D]),

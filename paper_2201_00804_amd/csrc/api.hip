@@ -15,11 +15,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -141,6 +143,17 @@ struct sibfa_ctx_s {
   double* fvir = nullptr;
   double* vir_tot = nullptr;
   double* h_vir = nullptr;
+  // local frames: device copies of the frames and local quantities, the
+  // frame groups and site references, and the force-path buffers (all in
+  // framebufs, replaced by every sibfa_set_local_frames)
+  bool have_frames = false, dirty_rot = false, rot_alpha = false;
+  int ngroups = 0;
+  std::vector<DevBuf> framebufs;
+  int* frames_d = nullptr;
+  double *dloc = nullptr, *qloc = nullptr, *aloc = nullptr;
+  int *gframe = nullptr, *gstart = nullptr, *gsites = nullptr, *sstart = nullptr, *sref = nullptr;
+  double *Cs = nullptr, *Fg = nullptr, *GS = nullptr;
+  double4* FS = nullptr;
   // profiling: HIP events on the context stream around each phase
   bool prof = false;
   unsigned prof_mask = ~0u;   // phases timed while profiling
@@ -288,6 +301,28 @@ SysView make_view(sibfa_ctx c) {
   return s;
 }
 
+FrameArgs make_frames(sibfa_ctx c) {
+  FrameArgs f{};
+  f.n = c->n;
+  f.ngroups = c->ngroups;
+  f.periodic = c->periodic;
+  for (int a = 0; a < 3; ++a) {
+    f.box[a] = c->periodic ? c->box[a] : 1.0;
+    f.ibox[a] = c->periodic ? 1.0 / c->box[a] : 1.0;
+  }
+  f.xyz = c->xyz_c;
+  f.frames = c->frames_d;
+  f.dloc = c->dloc; f.qloc = c->qloc; f.aloc = c->rot_alpha ? c->aloc : nullptr;
+  f.dip = c->dip_c; f.quad = c->quad_c; f.alpha = c->alpha_c;
+  f.inv_perm = c->inv_perm;
+  f.FS = c->FS; f.GS = c->GS; f.mu_s = c->mu_s;
+  f.C = c->Cs;
+  f.gframe = c->gframe; f.gstart = c->gstart; f.gsites = c->gsites;
+  f.Fg = c->Fg;
+  f.sstart = c->sstart; f.sref = c->sref;
+  return f;
+}
+
 bool mixed(sibfa_ctx c) { return c->prm.precision == SIBFA_MIXED; }
 
 sibfa_status check_params(sibfa_ctx c, const sibfa_params* p, const double* box) {
@@ -321,6 +356,9 @@ void release_system(sibfa_ctx c) {
   free_list(c, c->bufs);
   c->fvir = nullptr;      // both lived in bufs
   c->vir_tot = nullptr;
+  free_list(c, c->framebufs);
+  c->have_frames = c->dirty_rot = c->rot_alpha = false;
+  c->ngroups = 0;
   free_list(c, c->pmebufs);
   for (int k = 0; k < 4; ++k) {
     dev_free(c, c->nbbuf[k].p);
@@ -578,6 +616,14 @@ sibfa_status prepare(sibfa_ctx c) {
   ra.pol_scan = c->pol_scan; ra.polidx = c->polidx; ra.polsite = c->polsite;
   ra.pp = c->pp; ra.pp32 = c->pp32; ra.pa = c->pa; ra.alpha_s = c->alpha_s; ra.ainv_s = c->ainv_s;
   ra.err = c->dints + 7;
+  // local frames: global d, Theta (alpha) at the current positions, then
+  // the records are rebuilt from them as after new multipoles
+  if (c->have_frames && c->dirty_rot) {
+    launch_rotate(make_frames(c), s);
+    c->dirty_rot = false;
+    c->dirty_mult = true;
+    if (c->rot_alpha) c->dirty_pol = true;
+  }
   // work still queued on the auxiliary stream by an earlier call that
   // failed reads the records rewritten below
   if (c->dirty_sort || c->dirty_mult || c->dirty_pol || c->dirty_lists) join(c);
@@ -1410,6 +1456,7 @@ sibfa_status sibfa_update_positions(sibfa_ctx c, const double* xyz) {
   // non-finite coordinates are caught by the cell binning of the next call
   // that computes (reported there as SIBFA_E_ARG)
   c->dirty_sort = true;
+  c->dirty_rot = c->have_frames;
   c->e0_valid = false;
   c->mu_valid = false;
   return SIBFA_OK;
@@ -1432,6 +1479,7 @@ sibfa_status sibfa_set_multipoles(sibfa_ctx c, const double* q, const double* di
   if (st == SIBFA_OK) st = finite_check(c, c->quad_c, 6 * n, "quad");
   if (st != SIBFA_OK) return st;
   c->have_mult = true;
+  c->have_frames = false;   // global multipoles given: local frames off
   c->dirty_mult = true;
   c->e0_valid = false;
   c->mu_valid = false;
@@ -1451,11 +1499,124 @@ sibfa_status sibfa_set_polarizabilities(sibfa_ctx c, const double* alpha, const 
   if (st == SIBFA_OK && thole) st = finite_check(c, c->thole_c, n, "thole");
   if (st != SIBFA_OK) return st;
   c->have_pol = true;
+  c->have_frames = false;   // new polarizabilities: local frames off
   c->dirty_pol = true;
   c->pol_ok = false;
   c->e0_valid = false;
   c->mu_valid = false;
   c->mu_have = false;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_set_local_frames(sibfa_ctx c, const int32_t* frames, const double* dip_local,
+                                   const double* quad_local, const double* alpha_local) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!c->have_mult) return fail(c, SIBFA_E_STATE, "sibfa_set_multipoles has not been called");
+  if (!c->have_pol) return fail(c, SIBFA_E_STATE, "sibfa_set_polarizabilities has not been called");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->aux && c->aux != c->stream) HIP_TRY(hipStreamSynchronize(c->aux));
+  if (!frames) {
+    // off: the global multipoles stay those of the last rotation
+    c->have_frames = false;
+    return SIBFA_OK;
+  }
+  const int n = c->n;
+  std::vector<int> hf(3 * (size_t)n), hm(n);
+  HIP_TRY(hipMemcpy(hf.data(), frames, 3 * (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hm.data(), c->mol_c, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+  // distinct frames in order of first use; every site's frame is three
+  // distinct sites of its own molecule, or (-1, -1, -1)
+  std::vector<int> group_of(n, -1), gf, gcount;
+  {
+    std::map<std::array<int, 3>, int> gid;   // frame -> group, numbered by first use
+    for (int i = 0; i < n; ++i) {
+      const int o = hf[3 * i], a = hf[3 * i + 1], b = hf[3 * i + 2];
+      if (o < 0 && a < 0 && b < 0) continue;
+      if (o < 0 || a < 0 || b < 0 || o >= n || a >= n || b >= n || o == a || o == b || a == b)
+        return fail(c, SIBFA_E_ARG, "frame of site " + std::to_string(i) +
+                                        ": three distinct site indices in [0, n_sites) or -1 -1 -1");
+      if (hm[o] != hm[i] || hm[a] != hm[i] || hm[b] != hm[i])
+        return fail(c, SIBFA_E_ARG, "frame of site " + std::to_string(i) +
+                                        ": the frame sites must belong to the site's molecule");
+      const std::array<int, 3> key{o, a, b};
+      auto it = gid.find(key);
+      int g;
+      if (it == gid.end()) {
+        g = (int)gcount.size();
+        gid.emplace(key, g);
+        gf.insert(gf.end(), {o, a, b});
+        gcount.push_back(0);
+      } else {
+        g = it->second;
+      }
+      group_of[i] = g;
+      gcount[g]++;
+    }
+  }
+  const int G = (int)gcount.size();
+  std::vector<int> gstart(G + 1, 0), gsites;
+  for (int g = 0; g < G; ++g) gstart[g + 1] = gstart[g] + gcount[g];
+  gsites.resize(std::max(gstart[G], 1));
+  {
+    std::vector<int> cur(gstart.begin(), gstart.end() - 1);
+    for (int i = 0; i < n; ++i)
+      if (group_of[i] >= 0) gsites[cur[group_of[i]]++] = i;   // increasing site index
+  }
+  std::vector<int> sstart(n + 1, 0), sref(std::max(3 * G, 1));
+  for (int g = 0; g < G; ++g)
+    for (int k = 0; k < 3; ++k) sstart[gf[3 * g + k] + 1]++;
+  for (int i = 0; i < n; ++i) sstart[i + 1] += sstart[i];
+  {
+    std::vector<int> cur(sstart.begin(), sstart.end() - 1);
+    for (int g = 0; g < G; ++g)
+      for (int k = 0; k < 3; ++k) sref[cur[gf[3 * g + k]]++] = 3 * g + k;   // increasing g
+  }
+  free_list(c, c->framebufs);
+  c->have_frames = false;
+  auto& L = c->framebufs;
+  const size_t nn = n;
+  const bool ok = alloc_into(c, L, c->frames_d, 3 * nn) && alloc_into(c, L, c->dloc, 3 * nn) &&
+                  alloc_into(c, L, c->qloc, 6 * nn) &&
+                  (!alpha_local || alloc_into(c, L, c->aloc, 6 * nn)) &&
+                  alloc_into(c, L, c->gframe, std::max<size_t>(3 * (size_t)G, 1)) &&
+                  alloc_into(c, L, c->gstart, (size_t)G + 1) &&
+                  alloc_into(c, L, c->gsites, gsites.size()) &&
+                  alloc_into(c, L, c->sstart, nn + 1) && alloc_into(c, L, c->sref, sref.size()) &&
+                  alloc_into(c, L, c->Cs, 9 * nn) &&
+                  alloc_into(c, L, c->Fg, std::max<size_t>(9 * (size_t)G, 1)) &&
+                  alloc_into(c, L, c->FS, nn) && alloc_into(c, L, c->GS, 6 * nn);
+  if (!ok) {
+    free_list(c, c->framebufs);
+    return fail(c, SIBFA_E_NOMEM, "local frame allocation failed");
+  }
+  hipStream_t st = c->stream;
+  HIP_TRY(hipMemcpyAsync(c->frames_d, frames, 3 * nn * sizeof(int), hipMemcpyDeviceToDevice, st));
+  if (dip_local) HIP_TRY(hipMemcpyAsync(c->dloc, dip_local, 3 * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else launch_fill_double(c->dloc, 0.0, 3 * nn, st);
+  if (quad_local) HIP_TRY(hipMemcpyAsync(c->qloc, quad_local, 6 * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else launch_fill_double(c->qloc, 0.0, 6 * nn, st);
+  if (alpha_local) HIP_TRY(hipMemcpyAsync(c->aloc, alpha_local, 6 * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (G > 0) HIP_TRY(hipMemcpyAsync(c->gframe, gf.data(), 3 * (size_t)G * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->gstart, gstart.data(), gstart.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->gsites, gsites.data(), gsites.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->sstart, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->sref, sref.data(), sref.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  sibfa_status r = finite_check(c, c->dloc, 3 * nn, "dip_local");
+  if (r == SIBFA_OK) r = finite_check(c, c->qloc, 6 * nn, "quad_local");
+  if (r == SIBFA_OK && alpha_local) r = finite_check(c, c->aloc, 6 * nn, "alpha_local");
+  if (r != SIBFA_OK) {
+    free_list(c, c->framebufs);
+    return r;
+  }
+  c->ngroups = G;
+  c->have_frames = true;
+  c->rot_alpha = alpha_local != nullptr;
+  c->dirty_rot = true;
+  if (c->rot_alpha) c->pol_ok = false;   // the rotated tensors are validated again
+  c->e0_valid = false;
+  c->mu_valid = false;
   return SIBFA_OK;
 }
 
@@ -1525,10 +1686,10 @@ sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, int warm_star
 sibfa_status read_virial_totals(sibfa_ctx c, double* out) {
   constexpr int nv = S_COUNT - S_VRI;
   if (!c->vir_tot) {
-    if (!alloc_into(c, c->bufs, c->vir_tot, 40))
+    if (!alloc_into(c, c->bufs, c->vir_tot, 48))
       return fail(c, SIBFA_E_NOMEM, "virial totals allocation failed");
   }
-  if (!c->h_vir && hipHostMalloc((void**)&c->h_vir, 40 * sizeof(double), hipHostMallocDefault) !=
+  if (!c->h_vir && hipHostMalloc((void**)&c->h_vir, 48 * sizeof(double), hipHostMallocDefault) !=
                        hipSuccess) {
     c->h_vir = nullptr;
     return fail(c, SIBFA_E_NOMEM, "virial host staging allocation failed");
@@ -1561,6 +1722,7 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   // the virial comes out of the force kernels: forces into a scratch array
   // when the caller wants the virial only
   const bool want_vir = virial != nullptr;
+  const bool frames_on = c->have_frames;
   if (want_vir && !forces) {
     if (!c->fvir && !alloc_into(c, c->bufs, c->fvir, 3 * (size_t)c->n))
       return fail(c, SIBFA_E_NOMEM, "force scratch allocation failed");
@@ -1588,15 +1750,20 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
     }
     {
       Phase ph(c, SIBFA_PH_FORCE_REAL);
-      launch_force(s, c->red, c->mu_s, c->mu_s32, c->Freal, mix, want_vir, sm);
+      launch_force(s, c->red, c->mu_s, c->mu_s32, c->Freal, mix, want_vir, sm,
+                   frames_on ? c->FS : nullptr, frames_on ? c->GS : nullptr);
     }
     if (c->periodic) {
       join(c);
       Phase ph(c, SIBFA_PH_FORCE_RECIP);
       launch_gather_force(s, c->pm, c->red, c->mu_s, c->Freal, c->perm, forces, mix, want_vir,
-                          sm);
+                          sm, frames_on ? c->FS : nullptr, frames_on ? c->GS : nullptr);
     } else {
       launch_forces_out(c->n, c->perm, c->Freal, forces, sm);
+    }
+    if (frames_on) {
+      Phase ph(c, SIBFA_PH_FORCE_REAL);
+      launch_frame_forces(make_frames(c), c->red, forces, want_vir, sm);
     }
   }
   if (want_vir) {
@@ -1610,6 +1777,7 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
     const double* vf = v + (S_VRF - S_VRI);
     const double* vk = v + (S_VRK - S_VRI);
     const double* vg = v + (S_VRG - S_VRI);
+    const double* vr = v + (S_VRR - S_VRI);
     // m-space sum, symmetric: xx yy zz xy xz yz
     const int kidx[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
     for (int a = 0; a < 3; ++a)
@@ -1617,7 +1785,8 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
         const int k = 3 * a + b;
         double w = vi[k] + vf[k];
         if (c->periodic) w += (a == b ? erec : 0.0) - vk[kidx[k]] + vg[k];
-        virial[k] = kCoulomb * w;
+        // the frame term is in kcal/mol already
+        virial[k] = kCoulomb * w + (frames_on ? vr[k] : 0.0);
       }
   }
   double tot[6] = {0, 0, 0, 0, 0, 0};

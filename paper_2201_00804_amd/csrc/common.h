@@ -36,7 +36,8 @@ enum Slot {
   S_VRF = S_VRI + 9,     // intermolecular pairs, 9 slots
   S_VRK = S_VRF + 9,     // reciprocal m-space sum, 6 slots: xx yy zz xy xz yz
   S_VRG = S_VRK + 6,     // reciprocal site (amplitude) terms, 9 slots
-  S_COUNT = S_VRG + 9
+  S_VRR = S_VRG + 9,     // rotation of local frames, 9 slots
+  S_COUNT = S_VRR + 9
 };
 
 // Device view of the system in cell-sorted order.  Site records are AoS so

@@ -18,9 +18,15 @@ void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const
 // when out is NULL; the same-molecule pol list always in FP64 into out_in
 void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out_in,
                      hipStream_t st);
-// virial: also the real-space virial partials (slots S_VRI, S_VRF)
+// virial: also the real-space virial partials (slots S_VRI, S_VRF).
+// FS, GS (may be NULL; local frames): also the field and field gradient
+// (xx xy xz yy yz zz) at every site (sorted order) from the real-space
+// pairs its permanent multipoles take part in -- the other molecules'
+// multipoles, the induced dipoles (damped where the pair is) and, for
+// periodic systems, the excluded same-molecule part.  Overwrites FS, GS.
 void launch_force(const SysView& s, Reduce& red, const double4* mu, const float4* mu32, double4* F,
-                  bool mixed, bool virial, hipStream_t st);
+                  bool mixed, bool virial, hipStream_t st, double4* FS = nullptr,
+                  double* GS = nullptr);
 
 // pme.hip
 // Spread of the permanent multipoles (with the induced dipoles added to d
@@ -43,9 +49,12 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
 // scaled by the Coulomb constant and written in caller order.
 // virial: also the site (amplitude) terms of the reciprocal virial (slots
 // S_VRG).
+// FS, GS (may be NULL): the reciprocal field and field gradient at every
+// site plus the Ewald self terms of d + mu and Theta are added to them.
 void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
-                         bool virial, hipStream_t st);
+                         bool virial, hipStream_t st, double4* FS = nullptr,
+                         double* GS = nullptr);
 
 // fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec partials in
 // the slot pm.erec_slot; virial: also the m-space sum of the reciprocal
@@ -102,5 +111,38 @@ void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, d
 void launch_forces_out(int n, const int* perm, const double4* F, double* out, hipStream_t st);
 // neighbour counts to caller order
 void launch_counts_out(int n, const int* perm, const int* counts, int* out, hipStream_t st);
+
+// frames.hip: molecular local frames (caller order throughout, except FS,
+// GS and mu_s, which are in sorted order).
+struct FrameArgs {
+  int n, ngroups;
+  int periodic;
+  double box[3], ibox[3];
+  const double* xyz;     // [n][3]
+  const int* frames;     // [n][3] frame sites (o, a, b); o < 0: no frame
+  const double* dloc;    // [n][3] local dipoles
+  const double* qloc;    // [n][6] local quadrupoles
+  const double* aloc;    // [n][6] local polarizabilities (NULL: not rotated)
+  double* dip;           // global outputs (the context's caller-order copies)
+  double* quad;
+  double* alpha;
+  const int* inv_perm;   // caller -> sorted
+  const double4* FS;     // site field (sorted)
+  const double* GS;      // site field gradient (sorted, 6 per site)
+  const double4* mu_s;   // induced dipoles (sorted)
+  double* C;             // [n][9] per-site dE/dR
+  const int* gframe;     // [ngroups][3] distinct frames
+  const int* gstart;     // [ngroups + 1] sites of each frame in gsites
+  const int* gsites;
+  double* Fg;            // [ngroups][3][3] forces on (o, a, b)
+  const int* sstart;     // [n + 1] entries of sref per site
+  const int* sref;       // 3 g + slot of every frame force acting on the site
+};
+// global d, Theta (and alpha when aloc is set) from the local ones
+void launch_rotate(const FrameArgs& f, hipStream_t st);
+// forces of the rotation added to forces (caller order); virial: also the
+// frame virial partials (slots S_VRR)
+void launch_frame_forces(const FrameArgs& f, Reduce& red, double* forces, bool virial,
+                         hipStream_t st);
 
 }  // namespace sibfa

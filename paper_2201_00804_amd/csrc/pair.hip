@@ -569,13 +569,52 @@ __global__ __launch_bounds__(kBlock) void k_force_intra(SysView s, Reduce red, c
   if (VIR) vir_partials(W, red, S_VRI);
 }
 
+// ------------------------------------------------------------------ site fields
+// Field E and field gradient dE_b/dr_a at every site of the multipoles that
+// its own permanent multipoles interact with (local frames: the energy's
+// derivative with respect to a site's dipole is -E, with respect to its
+// quadrupole -1/3 grad E): the permanent multipoles of the other sites
+// (MM class) and the induced dipoles (Mmu class, Thole-damped).  With
+// M' = (q, d + mu, Theta) the two classes combine as in the force kernel:
+// M' with the damped coefficients, plus M with B - cT where the damping
+// matters; same-molecule pairs (periodic only) take M' with E - c0.
+// Field and gradient of a source (q, d, Theta) at R = r_i - r_j:
+//   E_b       = R_b rad - d_b c1 - 2/3 (Theta R)_b c2,
+//   rad       = q c1 + (d.R) c2 + 1/3 (R Theta R) c3,
+//   dE_b/dR_a = delta_ab rad - R_a R_b S + c2 (R_b d_a + R_a d_b)
+//               + 2/3 c3 (R_b (Theta R)_a + R_a (Theta R)_b) - 2/3 c2 Theta_ab,
+//   S         = q c2 + (d.R) c3 + 1/3 (R Theta R) c4
+// (from dc_n/dR_a = -R_a c_{n+1}).  Gradients are stored xx xy xz yy yz zz.
+template <typename R>
+__device__ __forceinline__ void mp_field_grad(const R c[6], const MP<R>& B, const R Rv[3],
+                                              double E[3], double G[6]) {
+  const R dr = B.d[0] * Rv[0] + B.d[1] * Rv[1] + B.d[2] * Rv[2];
+  R tr[3];
+  tvec(B.t, Rv, tr);
+  const R rtr = tr[0] * Rv[0] + tr[1] * Rv[1] + tr[2] * Rv[2];
+  const R third = R(1.0 / 3.0), two3 = R(2.0 / 3.0);
+  const R rad = B.q * c[1] + dr * c[2] + third * rtr * c[3];
+  const R S = B.q * c[2] + dr * c[3] + third * rtr * c[4];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) E[b] += (double)(Rv[b] * rad - B.d[b] * c[1] - two3 * tr[b] * c[2]);
+  const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int a = ia[k], b = ib[k];
+    R g = -Rv[a] * Rv[b] * S + c[2] * (Rv[b] * B.d[a] + Rv[a] * B.d[b]) +
+          two3 * c[3] * (Rv[b] * tr[a] + Rv[a] * tr[b]) - two3 * c[2] * B.t[k];
+    if (a == b) g += rad;
+    G[k] += (double)g;
+  }
+}
+
 // One intermolecular pair of k_force (see the identity above).  NEAR: the
 // pair may be damped (x < 50); far pairs never are.
-template <typename R, bool NEAR, bool VIR>
+template <typename R, bool NEAR, bool VIR, bool FG>
 __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const MP<R>& Mi,
                                            const MP<R>& Pi, const R xi[3], R si,
                                            const double4* mu, const float4* mu32, double F[3],
-                                           double W[9]) {
+                                           double W[9], double E[3], double Gg[6]) {
   MP<R> Mj;
   R xj[3], Rv[3], muj[3];
   load_mp<R>(s, j, Mj, xj);
@@ -604,6 +643,11 @@ __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const
   }
   MP<R> Pj = Mj;
   Pj.d[0] += muj[0]; Pj.d[1] += muj[1]; Pj.d[2] += muj[2];
+  if (FG) {
+    // site field and gradient of the same pair (see mp_field_grad)
+    mp_field_grad<R>(c, Pj, Rv, E, Gg);
+    if (NEAR && damp) mp_field_grad<R>(D, Mj, Rv, E, Gg);
+  }
   R u, f[3];
   mp_pair<R, false, true>(c, Pi, Pj, Rv, u, f);
   double fd[3] = {(double)f[0], (double)f[1], (double)f[2]};
@@ -623,13 +667,15 @@ __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const
 
 // Intermolecular pairs within the cutoff (precision R); adds to Fout.
 // Near entries first (the damped ones are among them), then far ones.
-template <typename R, int G, bool VIR>
+template <typename R, int G, bool VIR, bool FG>
 __global__ __launch_bounds__(kBlock) void k_force(SysView s, Reduce red, const double4* mu,
-                                                  const float4* mu32, double4* Fout) {
+                                                  const float4* mu32, double4* Fout, double4* FS,
+                                                  double* GS) {
   const int sub = threadIdx.x % G;
   const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   double F[3] = {0.0, 0.0, 0.0};
   double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double E[3] = {0.0, 0.0, 0.0}, Gg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (i < s.n) {
     MP<R> Mi;
     R xi[3], mui[3];
@@ -641,15 +687,16 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, Reduce red, const d
     const int* row = s.nb_all + (size_t)i * s.cap_all;
     const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
     for (int k = sub; k < nn; k += G)
-      force_pair<R, true, VIR>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F, W);
+      force_pair<R, true, VIR, FG>(s, i, row[k], Mi, Pi, xi, si, mu, mu32, F, W, E, Gg);
     const int* far = row + s.cap_all - 1;
     int k = sub;
     for (; k + G < nf; k += 2 * G) {
       const int j0 = far[-k], j1 = far[-(k + G)];
-      force_pair<R, false, VIR>(s, i, j0, Mi, Pi, xi, si, mu, mu32, F, W);
-      force_pair<R, false, VIR>(s, i, j1, Mi, Pi, xi, si, mu, mu32, F, W);
+      force_pair<R, false, VIR, FG>(s, i, j0, Mi, Pi, xi, si, mu, mu32, F, W, E, Gg);
+      force_pair<R, false, VIR, FG>(s, i, j1, Mi, Pi, xi, si, mu, mu32, F, W, E, Gg);
     }
-    if (k < nf) force_pair<R, false, VIR>(s, i, far[-k], Mi, Pi, xi, si, mu, mu32, F, W);
+    if (k < nf)
+      force_pair<R, false, VIR, FG>(s, i, far[-k], Mi, Pi, xi, si, mu, mu32, F, W, E, Gg);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) F[a] = group_sum<G>(F[a]);
@@ -658,7 +705,55 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, Reduce red, const d
     f.x += F[0]; f.y += F[1]; f.z += F[2];
     Fout[i] = f;
   }
+  if (FG) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) E[a] = group_sum<G>(E[a]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Gg[k] = group_sum<G>(Gg[k]);
+    if (sub == 0 && i < s.n) {
+      double4 e = FS[i];
+      e.x += E[0]; e.y += E[1]; e.z += E[2];
+      FS[i] = e;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) GS[6 * (size_t)i + k] += Gg[k];
+    }
+  }
   if (VIR) vir_partials(W, red, S_VRF);
+}
+
+// Same-molecule pairs (FP64, one thread per site): writes FS and GS.
+__global__ __launch_bounds__(kBlock) void k_site_fg_intra(SysView s, const double4* mu,
+                                                          double4* FS, double* GS) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  double E[3] = {0.0, 0.0, 0.0}, G[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (s.periodic) {
+    MP<double> Mi;
+    double xi[3];
+    load_mp<double>(s, i, Mi, xi);
+    const int cnt = s.nc_in[i];
+    for (int k = 0; k < cnt; ++k) {
+      const int j = s.nb_in[(size_t)i * s.cap_in + k];
+      MP<double> Mj;
+      double xj[3], Rv[3];
+      load_mp<double>(s, j, Mj, xj);
+      const double4 m = mu[j];
+      Mj.d[0] += m.x; Mj.d[1] += m.y; Mj.d[2] += m.z;
+      displacement<double>(s, xi, xj, Rv);
+      const double r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double Eb[5], c0[5], c[6];
+      ewald_coeffs<double, 4>(r, rinv, rinv2, s.beta, Eb);
+      bare_coeffs<double, 4>(rinv, rinv2, c0);
+#pragma unroll
+      for (int n = 0; n < 5; ++n) c[n] = Eb[n] - c0[n];
+      c[5] = 0.0;
+      mp_field_grad<double>(c, Mj, Rv, E, G);
+    }
+  }
+  FS[i] = make_double4(E[0], E[1], E[2], 0.0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) GS[6 * (size_t)i + k] = G[k];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -716,6 +811,7 @@ void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const
   }
 }
 
+
 void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out_in,
                      hipStream_t st) {
   if (s.npol <= 0) return;
@@ -724,23 +820,35 @@ void launch_pol_coef(const SysView& s, double2* out, float2* out32, double2* out
   else hipLaunchKernelGGL((k_pol_coef<float, kG>), g, b, 0, st, s, nullptr, out32, out_in);
 }
 
-void launch_force(const SysView& s, Reduce& red, const double4* mu, const float4* mu32, double4* F,
-                  bool mixed, bool virial, hipStream_t st) {
+template <bool VIR, bool FG>
+static void force_kernels(const SysView& s, Reduce& red, const double4* mu, const float4* mu32,
+                          double4* F, bool mixed, hipStream_t st, double4* FS, double* GS) {
   const dim3 gi((s.n + kBlock - 1) / kBlock), b(kBlock);
   const dim3 g(blocks_for(s.n, kG));
-  if (virial) {
-    hipLaunchKernelGGL(k_force_intra<true>, gi, b, 0, st, s, red, mu, F);
-    if (mixed) hipLaunchKernelGGL((k_force<float, kG, true>), g, b, 0, st, s, red, mu, mu32, F);
-    else hipLaunchKernelGGL((k_force<double, kG, true>), g, b, 0, st, s, red, mu, mu32, F);
+  if (FG)   // same-molecule part of the site fields first: it overwrites FS and GS
+    hipLaunchKernelGGL(k_site_fg_intra, gi, b, 0, st, s, mu, FS, GS);
+  hipLaunchKernelGGL(k_force_intra<VIR>, gi, b, 0, st, s, red, mu, F);
+  if (mixed)
+    hipLaunchKernelGGL((k_force<float, kG, VIR, FG>), g, b, 0, st, s, red, mu, mu32, F, FS, GS);
+  else
+    hipLaunchKernelGGL((k_force<double, kG, VIR, FG>), g, b, 0, st, s, red, mu, mu32, F, FS, GS);
+  if (VIR)
     for (int k = 0; k < 9; ++k) {
       red.nparts[S_VRI + k] = (int)gi.x;
       red.nparts[S_VRF + k] = (int)g.x;
     }
-    return;
+}
+
+void launch_force(const SysView& s, Reduce& red, const double4* mu, const float4* mu32, double4* F,
+                  bool mixed, bool virial, hipStream_t st, double4* FS, double* GS) {
+  const bool fg = FS != nullptr;
+  if (virial) {
+    if (fg) force_kernels<true, true>(s, red, mu, mu32, F, mixed, st, FS, GS);
+    else force_kernels<true, false>(s, red, mu, mu32, F, mixed, st, FS, GS);
+  } else {
+    if (fg) force_kernels<false, true>(s, red, mu, mu32, F, mixed, st, FS, GS);
+    else force_kernels<false, false>(s, red, mu, mu32, F, mixed, st, FS, GS);
   }
-  hipLaunchKernelGGL(k_force_intra<false>, gi, b, 0, st, s, red, mu, F);
-  if (mixed) hipLaunchKernelGGL((k_force<float, kG, false>), g, b, 0, st, s, red, mu, mu32, F);
-  else hipLaunchKernelGGL((k_force<double, kG, false>), g, b, 0, st, s, red, mu, mu32, F);
 }
 
 }  // namespace sibfa

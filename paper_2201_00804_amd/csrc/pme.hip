@@ -290,7 +290,8 @@ __host__ __device__ constexpr int didx(int kx, int ky, int kz) {
 template <typename R, int P, bool VIR>
 __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, Reduce red,
                                                          const double4* mu, const double4* Freal,
-                                                         const int* perm, double* out) {
+                                                         const int* perm, double* out,
+                                                         double4* FS, double* GS) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (i < s.n) {
@@ -349,6 +350,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, 
         for (int cc = 0; cc < 3; ++cc) f += T[b][cc] * der(a, b, cc) * (1.0 / 3.0);
       }
       out[3 * (size_t)c + a] = kCoulomb * (frr[a] - f);
+    }
+    if (FS) {
+      // site field E = -grad phi and gradient -grad grad phi, plus the self
+      // terms: 4 b^3/(3 sqrt pi) (d + mu) and 16 b^5/(15 sqrt pi) Theta
+      // (the latter 3x the quadrupole self derivative, as the field
+      // gradient enters the quadrupole energy with 1/3)
+      const double b = pm.beta, b3 = b * b * b;
+      const double sf = 4.0 * b3 / (3.0 * kSqrtPi), st = 16.0 * b3 * b * b / (15.0 * kSqrtPi);
+      double4 e = FS[i];
+      e.x += sf * dd[0] - der(0, -1, -1);
+      e.y += sf * dd[1] - der(1, -1, -1);
+      e.z += sf * dd[2] - der(2, -1, -1);
+      FS[i] = e;
+      const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        GS[6 * (size_t)i + k] += st * T[ia[k]][ib[k]] - der(ia[k], ib[k], -1);
     }
     if (VIR) {
 #pragma unroll
@@ -419,14 +437,14 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
 template <int P, bool VIR>
 static void gather_force_pv(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                             const double4* Freal, const int* perm, double* out, bool mixed,
-                            hipStream_t st) {
+                            hipStream_t st, double4* FS, double* GS) {
   const dim3 g((s.n + kBlock - 1) / kBlock), b(kBlock);
   if (mixed)
     hipLaunchKernelGGL((k_gather_force<float, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
-                       out);
+                       out, FS, GS);
   else
     hipLaunchKernelGGL((k_gather_force<double, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
-                       out);
+                       out, FS, GS);
   if (VIR)
     for (int k = 0; k < 9; ++k) red.nparts[S_VRG + k] = (int)g.x;
 }
@@ -434,18 +452,18 @@ static void gather_force_pv(const SysView& s, const PmeView& pm, Reduce& red, co
 template <int P>
 static void gather_force_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                            const double4* Freal, const int* perm, double* out, bool mixed,
-                           bool vir, hipStream_t st) {
-  if (vir) gather_force_pv<P, true>(s, pm, red, mu, Freal, perm, out, mixed, st);
-  else gather_force_pv<P, false>(s, pm, red, mu, Freal, perm, out, mixed, st);
+                           bool vir, hipStream_t st, double4* FS, double* GS) {
+  if (vir) gather_force_pv<P, true>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS);
+  else gather_force_pv<P, false>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS);
 }
 
 void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
-                         bool virial, hipStream_t st) {
+                         bool virial, hipStream_t st, double4* FS, double* GS) {
   switch (pm.order) {
-    case 4: gather_force_p<4>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
-    case 6: gather_force_p<6>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
-    default: gather_force_p<5>(s, pm, red, mu, Freal, perm, out, mixed, virial, st); break;
+    case 4: gather_force_p<4>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
+    case 6: gather_force_p<6>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
+    default: gather_force_p<5>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
   }
 }
 

@@ -148,6 +148,20 @@ class Engine:
         _dev(thole, torch.float64, (self.n,), self.device, "thole")
         self._check(self.lib.sibfa_set_polarizabilities(self.h, _ptr(alpha), _ptr(thole)))
 
+    def set_local_frames(self, frames, dip_local=None, quad_local=None, alpha_local=None):
+        """Frames [n][3] (int32 site indices, -1 rows: none) and the local
+        dipoles, quadrupoles and polarizabilities they carry; frames=None
+        switches local frames off."""
+        if frames is None:
+            self._check(self.lib.sibfa_set_local_frames(self.h, None, None, None, None))
+            return
+        _dev(frames, torch.int32, (self.n, 3), self.device, "frames")
+        _dev(dip_local, torch.float64, (self.n, 3), self.device, "dip_local")
+        _dev(quad_local, torch.float64, (self.n, 6), self.device, "quad_local")
+        _dev(alpha_local, torch.float64, (self.n, 6), self.device, "alpha_local")
+        self._check(self.lib.sibfa_set_local_frames(self.h, _ptr(frames), _ptr(dip_local),
+                                                    _ptr(quad_local), _ptr(alpha_local)))
+
     def load(self, sysd, params):
         """Convenience: system dict (numpy arrays as produced by synth)."""
         dev = self.device

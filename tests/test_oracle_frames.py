@@ -12,6 +12,10 @@ L3  The total forces with frames equal central differences of the energy
     displacement): cluster, brute-force Ewald box, SPME box.
 L4  With frames a free cluster is isotropic: the forces sum to zero and so
     do the torques sum r x F; a rigid rotation leaves the energy unchanged.
+L5  The virial with frames equals central differences of the re-solved
+    energy under a homogeneous strain of sites and cell, the local
+    multipoles following their strained frames (cluster: all components;
+    brute-force Ewald: diagonal and off-diagonal; SPME: diagonal).
 """
 import numpy as np
 import pytest
@@ -172,3 +176,95 @@ def test_frame_pins_see_a_dropped_term(drop, monkeypatch):
     with pytest.raises(AssertionError):
         _fd_frames(water_cluster(3, 2), Params(method="direct", tol=1e-12),
                    [(0, 0), (1, 1), (2, 2), (0, 2), (1, 0)])
+
+
+def _strain(d, eps):
+    F = np.eye(3) + eps
+    out = dict(d, pos=d["pos"] @ F.T)
+    if d.get("box") is not None:
+        H2 = np.diag(np.asarray(d["box"], float)) @ F.T
+        off = H2 - np.diag(np.diag(H2))
+        out["box"] = np.diag(H2).copy() if np.all(off == 0.0) else H2
+    return out
+
+
+def _fd_virial(d, prm, comps, h=1e-5, rtol=1e-6):
+    """W_ab = -dE/d eps_ab of the re-solved energy with the local multipoles
+    re-rotated in the strained frames, against frames.virial."""
+    s, f = _local(d)
+    o = fr.evaluate(s, f, prm)
+    W = fr.virial(s, f, prm, o["mu"])
+    scale = np.abs(W).max()
+
+    def etot(dd):
+        r = fr.evaluate(System.from_dict(dd), f, prm)
+        return r["E_pol"] + r["E_elec"]
+
+    for a, b in comps:
+        e = np.zeros((3, 3))
+        e[a, b] = h
+        fd = -(etot(_strain(d, e)) - etot(_strain(d, -e))) / (2 * h)
+        assert abs(fd - W[a, b]) <= rtol * scale, (a, b, fd, W[a, b])
+    return W
+
+
+def test_l5_virial_cluster():
+    """Every component for a cluster; without the frame term the check
+    fails (the frame term is not small)."""
+    d = water_cluster(3, 2)
+    prm = Params(method="direct", tol=1e-12)
+    W = _fd_virial(d, prm, [(a, b) for a in range(3) for b in range(3)])
+    s, f = _local(d)
+    o = fr.evaluate(s, f, prm)
+    W0 = oracle.model.virial(fr.to_global(s, f), prm, o["mu"])
+    assert np.abs(W - W0).max() > 1e-3 * np.abs(W).max()
+
+
+def test_l5_virial_ewald():
+    d = water_box(4, 6.5, 11)
+    prm = Params(method="ewald", beta=0.55, realspace="images", rmax=11.0, tol=1e-12)
+    _fd_virial(d, prm, [(0, 0), (2, 2), (0, 1), (2, 1)])
+
+
+def test_l5_virial_spme():
+    d = water_box(8, 8.0, 12)
+    prm = Params(method="spme", beta=0.5, cutoff=3.7, grid=(12, 12, 12), order=5, tol=1e-12)
+    _fd_virial(d, prm, [(0, 0), (1, 1)])
+
+
+def test_l5_virial_sees_a_wrong_frame_term(monkeypatch):
+    """The frame term with its sign flipped (planted in the oracle) fails
+    the strain-difference check."""
+    orig = fr._frame_terms
+    monkeypatch.setattr(fr, "_frame_terms", lambda *a, **k: -orig(*a, **k))
+    d = water_cluster(3, 2)
+    prm = Params(method="direct", tol=1e-12)
+    with pytest.raises(AssertionError):
+        _fd_virial(d, prm, [(0, 0), (1, 2), (2, 1)])
+
+
+def test_sites_without_frame_keep_global_values():
+    """Rows of -1 (no frame): those sites' values are used as given and add
+    no rotation forces; the forces still match differences of the energy."""
+    d = water_cluster(3, 2)
+    s, f = _local(d)
+    f = f.copy()
+    f[5:10] = -1                      # water 1 without a frame
+    prm = Params(method="direct", tol=1e-12)
+    g = fr.to_global(s, f)
+    assert np.array_equal(g.dip[5:10], s.dip[5:10]) and np.array_equal(g.alpha[5:10],
+                                                                       s.alpha[5:10])
+    o = fr.evaluate(s, f, prm)
+
+    def etot(pos):
+        return _energy_global(fr.to_global(System(**{**s.__dict__, "pos": pos}), f), prm)
+
+    F = o["forces"]
+    h = 1e-4
+    for (i, a) in ((0, 0), (6, 1), (11, 2)):
+        p = s.pos.copy()
+        p[i, a] += h
+        ep = etot(p)
+        p[i, a] -= 2 * h
+        fd = -(ep - etot(p)) / (2 * h)
+        assert abs(fd - F[i, a]) <= 1e-6 * np.abs(F).max()
