@@ -193,6 +193,47 @@ def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
     return out
 
 
+def run_md(name, precision, relax_steps, steps, dt=1.0, predictor=3):
+    """Beeman dynamics demo: the synthetic start relaxed with damped steps
+    (0.2 fs, friction 0.3), then `steps` plain Beeman steps of dt fs with
+    thermal velocities, warm-started solves with the extrapolating
+    predictor; steps/s of the timed part, solver iterations per step and
+    the total-energy drift over it."""
+    import numpy as np
+    import torch
+    from synth import config_system, water_md
+    from paper_2201_00804_amd import Engine, default_params
+
+    d, cfg = config_system(name)
+    m = water_md(d, 3)
+    t = lambda a, dt_=torch.float64: torch.as_tensor(np.asarray(a), dtype=dt_,
+                                                     device="cuda").contiguous()
+    eng = Engine(0)
+    eng.load(d, default_params(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"],
+                               order=cfg["order"], tol=cfg["tol"], precision=precision,
+                               max_iter=400))
+    eng.set_predictor(predictor)
+    args = (t(m["masses"]), t(m["vsites"], torch.int32), t(m["bonds"], torch.int32),
+            t(m["bond_k"]), t(m["bond_r0"]), t(m["rep_radius"]), m["rep_eps"])
+    eng.md_init(*args)
+    eng.md_run(relax_steps, 0.2, 0.3)
+    eng.md_init(*args, vel=t(m["vel"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = np.array(eng.md_run(steps, dt))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    eng.close()
+    et = st[:, :5].sum(1)
+    return dict(workload=name, n_waters=len(d["pos"]) // 5, dt_fs=dt, steps=steps,
+                relax_steps=relax_steps, predictor=predictor,
+                steps_per_s=round(steps / el, 2), ms_per_step=round(1e3 * el / steps, 3),
+                iterations_mean=round(float(st[:, 5].mean()), 2),
+                e_tot_drift=round(float(et[-1] - et[0]), 4),
+                e_tot_spread=round(float(et.max() - et.min()), 4),
+                e_kin_mean=round(float(st[:, 4].mean()), 2))
+
+
 def roofline(res, precision):
     """Roofline point of the kernel with the largest share of the timed
     region, the real-space matvec.  It is priced as vector-ALU work (the
@@ -509,6 +550,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=300)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tcg", action="store_true")
+    ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -597,6 +639,18 @@ def main():
             print("[bench] tcg " + prec + ": " + ", ".join(
                 f"{k} {v['ms']} ms (E_pol rel err {v['e_pol_rel_err']:.2e})"
                 for k, v in t.items() if isinstance(v, dict)), file=sys.stderr, flush=True)
+    if not args.no_md:
+        out["md"] = []
+        for name, relax, nsteps in (("box216", 300, 300), ("box32000", 100, 20)):
+            for prec in precisions:
+                print(f"[bench] md {name} {prec}: {relax} relaxation + {nsteps} Beeman steps",
+                      file=sys.stderr, flush=True)
+                r = run_md(name, prec, relax, nsteps)
+                r["precision"] = prec
+                out["md"].append(r)
+                print(f"[bench] md {name} {prec}: {r['steps_per_s']} steps/s, "
+                      f"{r['iterations_mean']} iterations per step, E_tot drift "
+                      f"{r['e_tot_drift']} kcal/mol", file=sys.stderr, flush=True)
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_warmup} warm-up + {args.serve_requests} requests",
               file=sys.stderr, flush=True)

@@ -196,7 +196,8 @@ sibfa_status sibfa_apply_T(sibfa_ctx ctx, const double* p, double* tp_out);
 
 /* Solve T mu = E by PCG (block-diagonal preconditioner alpha).
  * warm_start: start from the dipoles kept from the previous solve (or set
- * by sibfa_set_dipoles) instead of alpha E.  mu_out [n][3] (device) or
+ * by sibfa_set_dipoles), or the predictor's extrapolation of them (see
+ * sibfa_set_predictor), instead of alpha E.  mu_out [n][3] (device) or
  * NULL; iters and true_rms_debye (HOST) may be NULL.  Returns
  * SIBFA_E_NOT_CONVERGED (mu still returned) or SIBFA_E_NOT_SPD. */
 sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
@@ -208,8 +209,8 @@ sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
  * above, with no convergence test, then, when omega != 0, one peek step
  * mu += omega alpha r with that iterate's residual r.  The guess is the
  * direct field alpha E, or with warm_start the dipoles kept from the last
- * solve_induced or given to sibfa_set_dipoles (an extrapolated guess;
- * SIBFA_E_STATE if there are none).  order: 1..SIBFA_TCG_MAX_ORDER.  mu_out [n][3]
+ * solve_induced or given to sibfa_set_dipoles, or the predictor's
+ * extrapolation of them (SIBFA_E_STATE if there are none).  order: 1..SIBFA_TCG_MAX_ORDER.  mu_out [n][3]
  * (device, zero rows at non-polarizable sites) or NULL; e_pol (HOST,
  * kcal/mol) = -1/2 mu.E (the form of Eq. 19) or NULL.  Runs in the
  * context's precision and returns after a stream synchronisation.  The
@@ -246,6 +247,67 @@ sibfa_status sibfa_energy_forces(sibfa_ctx ctx, double* e_pol, double* e_elec,
  * solvers the Many-Body Polarization section cites use). */
 sibfa_status sibfa_get_dipoles(sibfa_ctx ctx, double* mu);
 sibfa_status sibfa_set_dipoles(sibfa_ctx ctx, const double* mu);
+
+/* Predictor of the warm-start guess (the extrapolated guesses that the
+ * truncated and iterated solvers cited under Many-Body Polarization start
+ * from along a trajectory).  The context keeps the last
+ * SIBFA_PREDICT_MAX_ORDER dipole sets: every converged sibfa_solve_induced
+ * (also the one inside sibfa_energy_forces) and every sibfa_set_dipoles
+ * adds one.  With order k >= 2 a warm start (solve or TCG) begins at the
+ * value for the next step of the polynomial of degree k' - 1 through the
+ * k' = min(k, kept) newest sets, taken as equally spaced in time:
+ * mu_guess = sum_{j=1..k'} (-1)^(j+1) C(k', j) mu_(newest - j + 1)
+ * (k' = 2: 2 mu_1 - mu_2).  Order 0 or 1, or fewer than two sets kept: the
+ * newest set (the plain warm start).  Setting the order clears the history;
+ * so do new polarizabilities and sibfa_set_system.  The history takes
+ * SIBFA_PREDICT_MAX_ORDER * 24 bytes per site of device memory, allocated
+ * with the first set it keeps.  SIBFA_E_ARG for an order outside
+ * 0..SIBFA_PREDICT_MAX_ORDER. */
+#define SIBFA_PREDICT_MAX_ORDER 6
+sibfa_status sibfa_set_predictor(sibfa_ctx ctx, int order);
+
+/* Molecular dynamics (Computational Details: Beeman integrator, 1 fs
+ * steps, the polarization solved at every step).  The paper's other terms
+ * (repulsion, dispersion, charge transfer, bonded terms) are outside this
+ * library, so the driver takes harmonic bonds as a stand-in that holds the
+ * molecules together; a trajectory exercises and times the polarization
+ * path, it is not the paper's model.
+ * sibfa_md_init: masses [n] (device, g/mol; 0 marks a virtual site),
+ * vsites [n][2] (device int32 or NULL: none): the two atoms whose midpoint
+ * (minimum image) a virtual site is, -1 -1 for an atom; n_bonds harmonic
+ * bonds [n_bonds][2] between atoms (device int32) with bond_k (kcal/mol/A^2)
+ * and bond_r0 (A) (device); a stand-in short-range repulsion
+ * rep_eps ((rho_i + rho_j)/r)^12 (kcal/mol) between sites of different
+ * molecules within the cutoff whose radii are both positive (virtual sites
+ * included; their forces go to the parents), rep_radius [n] (device, A,
+ * >= 0; NULL with rep_eps = 0: none); vel [n][3] (device, A/fs, or NULL:
+ * zero).
+ * Places the virtual sites, evaluates the forces at the current positions
+ * and starts the integrator (a(-dt) = a(0)).  Needs the system, multipoles
+ * and polarizabilities (local frames and the predictor are used when set).
+ * Sites of a molecule must stay within the cutoff of each other, as for
+ * every call.  Synchronizes.
+ * sibfa_md_run: n_steps Beeman steps of dt_fs: new positions, a warm-
+ * started solve (with the predictor if one is set), forces, new velocities,
+ * then scaled by 1 - friction (friction in [0, 1]; 0 is plain Beeman, a
+ * positive value a damped relaxation, e.g. to remove the close contacts of
+ * a synthetic start before a run).
+ * stats [n_steps] (HOST or NULL): per step E_pol, E_elec, bond, repulsion
+ * and kinetic energy (kcal/mol) and the solver iterations.  An error stops the run
+ * with the positions of that step already moved.
+ * sibfa_md_get_state: positions and velocities [n][3] (device; either may
+ * be NULL).  A later sibfa_set_system ends the dynamics. */
+typedef struct {
+  double e_pol, e_elec, e_bond, e_rep, e_kin;
+  int iterations;
+} sibfa_md_stats;
+sibfa_status sibfa_md_init(sibfa_ctx ctx, const double* masses, const int32_t* vsites,
+                           int n_bonds, const int32_t* bonds, const double* bond_k,
+                           const double* bond_r0, const double* rep_radius, double rep_eps,
+                           const double* vel);
+sibfa_status sibfa_md_run(sibfa_ctx ctx, int n_steps, double dt_fs, double friction,
+                          sibfa_md_stats* stats);
+sibfa_status sibfa_md_get_state(sibfa_ctx ctx, double* xyz, double* vel);
 
 /* Real-space neighbour counts per site [n] (device int32): intermolecular
  * sites within the cutoff (all sites within reach for clusters). */

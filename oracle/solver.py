@@ -129,3 +129,25 @@ def jacobi(matvec, precond, rhs, x0, tol_abs, max_iter=5000, omega=0.7):
             return x, k
         x = x + omega * precond(r)
     return x, max_iter
+
+
+def extrapolate(history, k):
+    """Guess for the next step from dipole sets taken at equally spaced
+    times: the value at t = 0 of the polynomial of degree k' - 1 through
+    the k' = min(k, len(history)) newest sets, placed at t = -1, -2, ...
+    (history[0] newest).  Written as Lagrange interpolation evaluated at
+    t = 0; k' <= 1 returns the newest set.  (The extrapolated guesses of
+    the truncated and iterated solvers that Many-Body Polarization cites;
+    the polynomial form is this implementation's reading.)"""
+    kk = min(int(k), len(history))
+    if kk <= 1:
+        return np.array(history[0], dtype=float)
+    ts = -np.arange(1, kk + 1, dtype=float)
+    out = np.zeros_like(np.asarray(history[0], dtype=float))
+    for j in range(kk):
+        w = 1.0
+        for m in range(kk):
+            if m != j:
+                w *= (0.0 - ts[m]) / (ts[j] - ts[m])
+        out += w * np.asarray(history[j], dtype=float)
+    return out

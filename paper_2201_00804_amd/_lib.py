@@ -42,6 +42,13 @@ PHASES = ["lists", "field_real", "field_recip", "spread", "fft", "matvec", "upda
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
+class MdStats(ctypes.Structure):
+    _fields_ = [("e_pol", ctypes.c_double), ("e_elec", ctypes.c_double),
+                ("e_bond", ctypes.c_double), ("e_rep", ctypes.c_double),
+                ("e_kin", ctypes.c_double),
+                ("iterations", ctypes.c_int)]
+
+
 # (name, restype, argtypes)
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -57,6 +64,11 @@ SIGNATURES = [
     ("sibfa_set_multipoles", ctypes.c_int, [_P, _P, _P, _P]),
     ("sibfa_set_polarizabilities", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_set_local_frames", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sibfa_set_predictor", ctypes.c_int, [_P, ctypes.c_int]),
+    ("sibfa_md_init", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_double,
+                                     _P]),
+    ("sibfa_md_run", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P]),
+    ("sibfa_md_get_state", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_permanent_field", ctypes.c_int, [_P, _P]),
     ("sibfa_apply_T", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_solve_induced", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), _D]),

@@ -143,6 +143,17 @@ struct sibfa_ctx_s {
   double* fvir = nullptr;
   double* vir_tot = nullptr;
   double* h_vir = nullptr;
+  // predictor of the warm-start guess: order (<= 1: the last dipoles) and a
+  // ring of the last kPredMax dipole sets (caller order; in bufs)
+  int pred_order = 0;
+  double* hist = nullptr;
+  int hist_head = 0, hist_count = 0;
+  // molecular dynamics: masses, virtual sites, bonds, velocities and
+  // accelerations (mdbufs, replaced by every sibfa_md_init)
+  bool md_on = false;
+  std::vector<DevBuf> mdbufs;
+  MdArgs md{};
+  double* md_force = nullptr;
   // local frames: device copies of the frames and local quantities, the
   // frame groups and site references, and the force-path buffers (all in
   // framebufs, replaced by every sibfa_set_local_frames)
@@ -356,6 +367,10 @@ void release_system(sibfa_ctx c) {
   free_list(c, c->bufs);
   c->fvir = nullptr;      // both lived in bufs
   c->vir_tot = nullptr;
+  free_list(c, c->mdbufs);
+  c->md_on = false;
+  c->hist = nullptr;       // lived in bufs
+  c->hist_head = c->hist_count = 0;
   free_list(c, c->framebufs);
   c->have_frames = c->dirty_rot = c->rot_alpha = false;
   c->ngroups = 0;
@@ -483,7 +498,9 @@ void join(sibfa_ctx c) {
 // Errors of the last binning (h_ints[4] holds the device word).
 sibfa_status binning_errors(sibfa_ctx c) {
   if (c->h_ints[4] & 2) return fail(c, SIBFA_E_ARG, "molecule ids must lie in [0, n_sites)");
-  if (c->h_ints[4] & 8) return fail(c, SIBFA_E_ARG, "xyz contains NaN or Inf");
+  if (c->h_ints[4] & 8)
+    return fail(c, SIBFA_E_ARG, "xyz contains NaN or Inf, or (periodic) a coordinate beyond "
+                                "1e6 box edges");
   return SIBFA_OK;
 }
 
@@ -828,6 +845,42 @@ double rms_debye(sibfa_ctx c, double zz) {
   return c->npol > 0 ? kDebye * std::sqrt(zz / c->npol) : 0.0;
 }
 
+// The newest dipoles (mu_c) join the predictor's history.
+void push_history(sibfa_ctx c, hipStream_t st) {
+  if (c->pred_order < 2) return;
+  const size_t len = 3 * (size_t)c->n;
+  if (!c->hist && !alloc_into(c, c->bufs, c->hist, (size_t)kPredMax * len)) {
+    c->pred_order = 0;   // no memory for the history: plain warm starts
+    return;
+  }
+  (void)hipMemcpyAsync(c->hist + (size_t)c->hist_head * len, c->mu_c, len * sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  c->hist_head = (c->hist_head + 1) % kPredMax;
+  c->hist_count = std::min(c->hist_count + 1, kPredMax);
+}
+
+// Warm-start guess into x (and x32): the kept dipoles, or with a predictor
+// of order k and at least two history entries, the value at the next step
+// of the polynomial of degree k' - 1 through the k' = min(k, entries)
+// newest ones (equally spaced): coefficients (-1)^(j+1) C(k', j), j = 1..k'
+// from the newest back.
+void warm_guess(sibfa_ctx c, const SysView& s, hipStream_t st) {
+  const int k = std::min(c->pred_order, c->hist_count);
+  if (k < 2) {
+    launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
+    return;
+  }
+  PredArgs pa{};
+  pa.k = k;
+  double binom = 1.0;   // C(k, j)
+  for (int j = 1; j <= k; ++j) {
+    binom = binom * (k - j + 1) / j;
+    pa.slot[j - 1] = (c->hist_head - j + 2 * kPredMax) % kPredMax;
+    pa.coef[j - 1] = (j % 2 == 1 ? 1.0 : -1.0) * binom;
+  }
+  launch_predict(s, c->perm, c->hist, 3 * (size_t)c->n, pa, c->x, c->x32, st);
+}
+
 sibfa_status solve(sibfa_ctx c, bool warm) {
   SysView s = make_view(c);
   hipStream_t st = c->stream;
@@ -841,7 +894,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     return SIBFA_OK;
   }
   ensure_coef(c);
-  if (warm && c->mu_have) launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
+  if (warm && c->mu_have) warm_guess(c, s, st);
   else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
   const double tol = c->prm.tol_debye;
@@ -1051,6 +1104,7 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
   launch_pol_to_caller(s, c->perm, c->x, c->mu_c, st);
   c->mu_have = true;
   c->mu_valid = (result == SIBFA_OK);
+  if (result == SIBFA_OK) push_history(c, st);
   if (result == SIBFA_E_NOT_SPD)
     return fail(c, result, "p.Tp <= 0: the polarization matrix is not positive definite");
   if (result == SIBFA_E_NOT_CONVERGED)
@@ -1079,7 +1133,7 @@ sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, bool warm, double* 
     return sync_read(c);
   }
   ensure_coef(c);
-  if (warm) launch_caller_to_pol(s, c->perm, c->mu_c, c->x, c->x32, st);
+  if (warm) warm_guess(c, s, st);
   else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
   matvec(c, c->x, c->x32, c->t, -1, mix);
@@ -1505,6 +1559,7 @@ sibfa_status sibfa_set_polarizabilities(sibfa_ctx c, const double* alpha, const 
   c->e0_valid = false;
   c->mu_valid = false;
   c->mu_have = false;
+  c->hist_count = 0;
   return SIBFA_OK;
 }
 
@@ -1814,6 +1869,187 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   return SIBFA_OK;
 }
 
+// ------------------------------------------------------------ dynamics
+// Forces of the step on md_force: electrostatics and polarization, then
+// the stand-in repulsion (over the lists the evaluation just built).
+static sibfa_status md_forces(sibfa_ctx c, double* ep, double* ee) {
+  sibfa_status r = sibfa_energy_forces(c, ep, ee, c->md_force, nullptr);
+  if (r != SIBFA_OK) return r;
+  if (c->md.rep_eps > 0.0)
+    launch_md_repulsion(make_view(c), c->md, c->red, c->perm, c->stream);
+  else
+    c->red.nparts[S_EREP] = 0;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_md_init(sibfa_ctx c, const double* masses, const int32_t* vsites, int n_bonds,
+                           const int32_t* bonds, const double* bond_k, const double* bond_r0,
+                           const double* rep_radius, double rep_eps, const double* vel) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!masses) return fail(c, SIBFA_E_ARG, "masses is NULL");
+  if (n_bonds < 0 || (n_bonds > 0 && (!bonds || !bond_k || !bond_r0)))
+    return fail(c, SIBFA_E_ARG, "n_bonds >= 0 with bonds, bond_k and bond_r0");
+  if (!(rep_eps >= 0.0) || !std::isfinite(rep_eps) || (rep_eps > 0.0 && !rep_radius))
+    return fail(c, SIBFA_E_ARG, "rep_eps >= 0 finite, with rep_radius when positive");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int n = c->n;
+  const size_t nn = n;
+  std::vector<double> hm(nn), hk(n_bonds), hr(n_bonds), hrho(nn, 0.0);
+  std::vector<int> hv(2 * nn, -1), hb(2 * (size_t)n_bonds);
+  HIP_TRY(hipMemcpy(hm.data(), masses, nn * sizeof(double), hipMemcpyDeviceToHost));
+  if (vsites) HIP_TRY(hipMemcpy(hv.data(), vsites, 2 * nn * sizeof(int), hipMemcpyDeviceToHost));
+  if (n_bonds > 0) {
+    HIP_TRY(hipMemcpy(hb.data(), bonds, hb.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hk.data(), bond_k, n_bonds * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hr.data(), bond_r0, n_bonds * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (rep_radius && rep_eps > 0.0)
+    HIP_TRY(hipMemcpy(hrho.data(), rep_radius, nn * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    if (!(hrho[i] >= 0.0) || !std::isfinite(hrho[i]))
+      return fail(c, SIBFA_E_ARG, "repulsion radii must be finite and >= 0");
+  auto atom = [&](int i) { return i >= 0 && i < n && hm[i] > 0.0; };
+  for (int i = 0; i < n; ++i) {
+    if (!(hm[i] >= 0.0) || !std::isfinite(hm[i]))
+      return fail(c, SIBFA_E_ARG, "masses must be finite and >= 0");
+    const int p = hv[2 * i], q = hv[2 * i + 1];
+    if (p < 0 && q < 0) {
+      if (!(hm[i] > 0.0))
+        return fail(c, SIBFA_E_ARG, "site " + std::to_string(i) + ": a massless site must be a virtual site");
+    } else if (hm[i] != 0.0 || !atom(p) || !atom(q) || p == q) {
+      return fail(c, SIBFA_E_ARG, "site " + std::to_string(i) +
+                                      ": a virtual site is massless with two distinct atoms as parents");
+    }
+  }
+  for (int b = 0; b < n_bonds; ++b) {
+    const int i = hb[2 * b], j = hb[2 * b + 1];
+    if (!atom(i) || !atom(j) || i == j || !(hk[b] >= 0.0) || !std::isfinite(hk[b]) ||
+        !(hr[b] > 0.0) || !std::isfinite(hr[b]))
+      return fail(c, SIBFA_E_ARG, "bond " + std::to_string(b) +
+                                      ": two distinct atoms, k >= 0 and r0 > 0 finite");
+  }
+  // atom -> virtual sites and atom -> bonds, both in increasing order
+  std::vector<int> vstart(nn + 1, 0), bstart(nn + 1, 0);
+  for (int i = 0; i < n; ++i)
+    if (hv[2 * i] >= 0) { vstart[hv[2 * i] + 1]++; vstart[hv[2 * i + 1] + 1]++; }
+  for (int b = 0; b < n_bonds; ++b) { bstart[hb[2 * b] + 1]++; bstart[hb[2 * b + 1] + 1]++; }
+  for (int i = 0; i < n; ++i) { vstart[i + 1] += vstart[i]; bstart[i + 1] += bstart[i]; }
+  std::vector<int> vref(std::max(vstart[n], 1)), bref(std::max(bstart[n], 1));
+  {
+    std::vector<int> cv(vstart.begin(), vstart.end() - 1), cb(bstart.begin(), bstart.end() - 1);
+    for (int i = 0; i < n; ++i)
+      if (hv[2 * i] >= 0) { vref[cv[hv[2 * i]]++] = i; vref[cv[hv[2 * i + 1]]++] = i; }
+    for (int b = 0; b < n_bonds; ++b) { bref[cb[hb[2 * b]]++] = b; bref[cb[hb[2 * b + 1]]++] = b; }
+  }
+  free_list(c, c->mdbufs);
+  c->md_on = false;
+  auto& L = c->mdbufs;
+  const size_t nbk = std::max(n_bonds, 1);
+  double *mass, *bk, *br0, *rho;
+  int *vpar, *vs, *vr, *bd, *bs, *br;
+  const bool ok = alloc_into(c, L, mass, nn) && alloc_into(c, L, vpar, 2 * nn) &&
+                  alloc_into(c, L, rho, nn) &&
+                  alloc_into(c, L, vs, nn + 1) && alloc_into(c, L, vr, vref.size()) &&
+                  alloc_into(c, L, bd, 2 * nbk) && alloc_into(c, L, bk, nbk) &&
+                  alloc_into(c, L, br0, nbk) && alloc_into(c, L, bs, nn + 1) &&
+                  alloc_into(c, L, br, bref.size()) && alloc_into(c, L, c->md.vel, 3 * nn) &&
+                  alloc_into(c, L, c->md.acc, 3 * nn) && alloc_into(c, L, c->md.accp, 3 * nn) &&
+                  alloc_into(c, L, c->md_force, 3 * nn);
+  if (!ok) {
+    free_list(c, c->mdbufs);
+    return fail(c, SIBFA_E_NOMEM, "dynamics allocation failed");
+  }
+  hipStream_t st = c->stream;
+  HIP_TRY(hipMemcpy(mass, hm.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(rho, hrho.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(vpar, hv.data(), 2 * nn * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(vs, vstart.data(), vstart.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(vr, vref.data(), vref.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(bs, bstart.data(), bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(br, bref.data(), bref.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (n_bonds > 0) {
+    HIP_TRY(hipMemcpy(bd, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bk, hk.data(), n_bonds * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(br0, hr.data(), n_bonds * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (vel) HIP_TRY(hipMemcpyAsync(c->md.vel, vel, 3 * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else launch_fill_double(c->md.vel, 0.0, 3 * nn, st);
+  MdArgs& m = c->md;
+  m.n = n;
+  m.periodic = c->periodic;
+  for (int a = 0; a < 3; ++a) {
+    m.box[a] = c->periodic ? c->box[a] : 1.0;
+    m.ibox[a] = c->periodic ? 1.0 / c->box[a] : 1.0;
+  }
+  m.xyz = c->xyz_c;
+  m.force = c->md_force;
+  m.mass = mass; m.vpar = vpar; m.vstart = vs; m.vref = vr;
+  m.bonds = bd; m.bond_k = bk; m.bond_r0 = br0; m.bstart = bs; m.bref = br;
+  m.rep_rho = rho;
+  m.rep_eps = rep_eps;
+  m.rep_force = c->md_force;
+  if (vel) {
+    sibfa_status fs = finite_check(c, c->md.vel, 3 * nn, "vel");
+    if (fs != SIBFA_OK) { free_list(c, c->mdbufs); return fs; }
+  }
+  // virtual sites onto their midpoints, forces and accelerations at t = 0
+  launch_md_vsites(m, st);
+  c->dirty_sort = true;
+  c->dirty_rot = c->have_frames;
+  c->e0_valid = c->mu_valid = false;
+  sibfa_status r = md_forces(c, nullptr, nullptr);
+  if (r != SIBFA_OK) { free_list(c, c->mdbufs); return r; }
+  launch_md_finish(m, c->red, 0.0, 0.0, st);
+  r = sync_read(c);
+  if (r != SIBFA_OK) { free_list(c, c->mdbufs); return r; }
+  c->md_on = true;
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_md_run(sibfa_ctx c, int n_steps, double dt_fs, double friction,
+                          sibfa_md_stats* stats) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->md_on) return fail(c, SIBFA_E_STATE, "sibfa_md_init has not been called");
+  if (n_steps < 0 || !(dt_fs > 0.0) || !std::isfinite(dt_fs))
+    return fail(c, SIBFA_E_ARG, "n_steps >= 0 and a positive finite dt_fs");
+  if (!(friction >= 0.0 && friction <= 1.0))
+    return fail(c, SIBFA_E_ARG, "friction must lie in [0, 1]");
+  HIP_TRY(hipSetDevice(c->device));
+  for (int k = 0; k < n_steps; ++k) {
+    launch_md_positions(c->md, dt_fs, c->stream);
+    c->dirty_sort = true;
+    c->dirty_rot = c->have_frames;
+    c->e0_valid = c->mu_valid = false;
+    double ep = 0.0, ee = 0.0;
+    sibfa_status r = md_forces(c, &ep, &ee);
+    if (r != SIBFA_OK) return r;
+    launch_md_finish(c->md, c->red, dt_fs, friction, c->stream);
+    double kb[3] = {0.0, 0.0, 0.0};
+    if ((r = read_totals(c, {S_EKIN, S_EBOND, S_EREP}, kb)) != SIBFA_OK) return r;
+    if (stats) {
+      stats[k].e_pol = ep;
+      stats[k].e_elec = ee;
+      stats[k].e_kin = kb[0];
+      stats[k].e_bond = kb[1];
+      stats[k].e_rep = kb[2];
+      stats[k].iterations = c->stats.iterations;
+    }
+  }
+  return SIBFA_OK;
+}
+
+sibfa_status sibfa_md_get_state(sibfa_ctx c, double* xyz, double* vel) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->md_on) return fail(c, SIBFA_E_STATE, "sibfa_md_init has not been called");
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t bytes = 3 * (size_t)c->n * sizeof(double);
+  if (xyz) HIP_TRY(hipMemcpyAsync(xyz, c->xyz_c, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (vel) HIP_TRY(hipMemcpyAsync(vel, c->md.vel, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return sync_read(c);
+}
+
 sibfa_status sibfa_get_dipoles(sibfa_ctx c, double* mu) {
   if (!c) return SIBFA_E_ARG;
   if (!mu) return fail(c, SIBFA_E_ARG, "mu is NULL");
@@ -1835,6 +2071,19 @@ sibfa_status sibfa_set_dipoles(sibfa_ctx c, const double* mu) {
   if (st != SIBFA_OK) return st;
   c->mu_have = true;
   c->mu_valid = false;
+  push_history(c, c->stream);
+  return SIBFA_OK;
+}
+
+static_assert(kPredMax == SIBFA_PREDICT_MAX_ORDER, "predictor history length");
+
+sibfa_status sibfa_set_predictor(sibfa_ctx c, int order) {
+  if (!c) return SIBFA_E_ARG;
+  if (order < 0 || order > kPredMax)
+    return fail(c, SIBFA_E_ARG, "order must lie in 0.." + std::to_string(kPredMax));
+  c->pred_order = order;
+  c->hist_count = 0;   // the history starts with the next dipoles
+  c->hist_head = 0;
   return SIBFA_OK;
 }
 

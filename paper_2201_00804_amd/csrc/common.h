@@ -30,6 +30,9 @@ enum Slot {
   S_MUTMU,       // mu.T mu
   S_AUX,         // real-space energy of same-molecule (excluded) pairs
   S_EREC0,       // reciprocal energy of the permanent multipoles
+  S_EKIN,        // kinetic energy (molecular dynamics)
+  S_EBOND,       // bond energy (molecular dynamics)
+  S_EREP,        // stand-in repulsion energy (molecular dynamics)
   // virial partials (written only when a virial is asked for), row-major
   // W_ab at slot + 3a + b unless noted
   S_VRI,                 // same-molecule pairs, 9 slots
@@ -176,9 +179,13 @@ __device__ __forceinline__ T fold_point(const PmeView& pm, int gx, int gy, int g
 __device__ __forceinline__ int grid_base(double x, double scale, int K, double* frac) {
   const double u = x * scale;
   const double fl = floor(u);
-  int k = (int)fl;
-  if (k >= K) k -= K;
-  if (k < 0) k += K;
+  // positions arrive wrapped into the box; the clamp and the modulo keep
+  // any other value in [0, K) as well
+  int k = (int)fmin(fmax(fl, -1073741824.0), 1073741824.0);
+  if (k >= K || k < 0) {
+    k %= K;
+    if (k < 0) k += K;
+  }
   *frac = u - fl;
   return k;
 }

@@ -107,6 +107,16 @@ void launch_pol_to_caller(const SysView& s, const int* perm, const double4* v, d
                           hipStream_t st);
 void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, double4* v,
                           float4* v32, hipStream_t st);
+// Extrapolated initial guess (polarizable order) from k history entries
+// of caller-order dipoles (entry j at hist + slot[j] * stride).
+constexpr int kPredMax = 6;
+struct PredArgs {
+  int k;
+  int slot[kPredMax];
+  double coef[kPredMax];
+};
+void launch_predict(const SysView& s, const int* perm, const double* hist, size_t stride,
+                    const PredArgs& pa, double4* v, float4* v32, hipStream_t st);
 // Coulomb-scaled forces to caller order (no reciprocal part)
 void launch_forces_out(int n, const int* perm, const double4* F, double* out, hipStream_t st);
 // neighbour counts to caller order
@@ -138,6 +148,39 @@ struct FrameArgs {
   const int* sstart;     // [n + 1] entries of sref per site
   const int* sref;       // 3 g + slot of every frame force acting on the site
 };
+// md.hip: Beeman steps (caller order).
+struct MdArgs {
+  int n;
+  int periodic;
+  double box[3], ibox[3];
+  double* xyz;           // the context's positions
+  double* vel;           // [n][3] A/fs
+  double* acc;           // [n][3] a(t), A/fs^2
+  double* accp;          // [n][3] a(t - dt)
+  const double* force;   // [n][3] kcal/mol/A of the electrostatics + polarization
+  const double* mass;    // [n] g/mol, 0 for a virtual site
+  const int* vpar;       // [n][2] parents of a virtual site, -1 -1 otherwise
+  const int* vstart;     // [n + 1] virtual sites parented by each atom (vref)
+  const int* vref;
+  const int* bonds;      // [nb][2]
+  const double* bond_k;  // [nb] kcal/mol/A^2
+  const double* bond_r0; // [nb] A
+  const int* bstart;     // [n + 1] bonds of each atom (bref)
+  const int* bref;
+  const double* rep_rho; // [n] repulsion radii (A)
+  double rep_eps;        // kcal/mol; 0: no repulsion
+  double* rep_force;     // where the repulsion forces are added (= force)
+};
+// stand-in repulsion forces added to m.rep_force, energy partials S_EREP
+void launch_md_repulsion(const SysView& s, const MdArgs& m, Reduce& red, const int* perm,
+                         hipStream_t st);
+void launch_md_positions(const MdArgs& m, double dt, hipStream_t st);
+void launch_md_vsites(const MdArgs& m, hipStream_t st);
+// dt = 0 starts a run (a_prev = a = F/m, no velocity update); velocities
+// are scaled by 1 - friction after each update
+void launch_md_finish(const MdArgs& m, Reduce& red, double dt, double friction,
+                      hipStream_t st);
+
 // global d, Theta (and alpha when aloc is set) from the local ones
 void launch_rotate(const FrameArgs& f, hipStream_t st);
 // forces of the rotation added to forces (caller order); virial: also the

@@ -180,9 +180,14 @@ void launch_exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t
 }
 
 // ------------------------------------------------------------ binning
+// Coordinate wrapped into [0, L).  Coordinates beyond kMaxBoxes box edges
+// (rejected by the binning: the wrap has lost its precision there) map to
+// 0, so that work queued before the error is read back indexes in bounds.
+constexpr double kMaxBoxes = 1e6;
 __device__ __forceinline__ double wrap(double x, double L, double iL) {
   double w = x - L * floor(x * iL);
-  return (w >= L) ? w - L : w;
+  w = (w >= L) ? w - L : w;
+  return (w > -L && w < L) ? w : 0.0;
 }
 
 // Neighbouring caller indices are usually neighbouring sites (a molecule's
@@ -195,6 +200,9 @@ __global__ void k_bin(BinArgs a) {
   if (act) {
     const double x0 = a.xyz[3 * c], x1 = a.xyz[3 * c + 1], x2 = a.xyz[3 * c + 2];
     if (!isfinite(x0) || !isfinite(x1) || !isfinite(x2)) atomicOr(a.err, 8);
+    if (a.periodic && !(fabs(x0) <= kMaxBoxes * a.box[0] && fabs(x1) <= kMaxBoxes * a.box[1] &&
+                        fabs(x2) <= kMaxBoxes * a.box[2]))
+      atomicOr(a.err, 8);
     if (a.periodic) {
       int ci[3];
       for (int d = 0; d < 3; ++d) {

@@ -209,6 +209,23 @@ __global__ void k_caller_to_pol(SysView s, const int* perm, const double* in, do
   if (v32) v32[pi] = make_float4((float)a.x, (float)a.y, (float)a.z, 0.f);
 }
 
+// Extrapolated guess: v = sum_j coef_j h_j over the k newest history
+// entries (caller order, 3 n doubles each).
+__global__ void k_predict(SysView s, const int* perm, const double* hist, size_t stride,
+                          PredArgs pa, double4* v, float4* v32) {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= s.npol) return;
+  const size_t c = perm[s.polsite[pi]];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < pa.k; ++j) {
+    const double* h = hist + (size_t)pa.slot[j] * stride + 3 * c;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a[d] += pa.coef[j] * h[d];
+  }
+  v[pi] = make_double4(a[0], a[1], a[2], 0.0);
+  if (v32) v32[pi] = make_float4((float)a[0], (float)a[1], (float)a[2], 0.f);
+}
+
 __global__ void k_forces_out(int n, const int* perm, const double4* F, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -325,6 +342,12 @@ void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, d
                           float4* v32, hipStream_t st) {
   if (s.npol > 0)
     hipLaunchKernelGGL(k_caller_to_pol, grid_for(s.npol), dim3(kBlock), 0, st, s, perm, in, v, v32);
+}
+void launch_predict(const SysView& s, const int* perm, const double* hist, size_t stride,
+                    const PredArgs& pa, double4* v, float4* v32, hipStream_t st) {
+  if (s.npol > 0)
+    hipLaunchKernelGGL(k_predict, grid_for(s.npol), dim3(kBlock), 0, st, s, perm, hist, stride, pa,
+                       v, v32);
 }
 void launch_forces_out(int n, const int* perm, const double4* F, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_forces_out, grid_for(n), dim3(kBlock), 0, st, n, perm, F, out);

@@ -73,7 +73,10 @@ class TorchAllocator:
                 return None
 
         def _free(ptr, user):
-            torch.cuda.caching_allocator_delete(int(ptr))
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:   # interpreter shutdown: torch is gone already
+                pass
 
         # the ctypes callback objects must outlive the library's use of them
         self.alloc_fn = _lib.ALLOC_FN(_alloc)
@@ -227,6 +230,41 @@ class Engine:
     def set_dipoles(self, mu):
         _dev(mu, torch.float64, (self.n, 3), self.device, "mu")
         self._check(self.lib.sibfa_set_dipoles(self.h, _ptr(mu)))
+
+    def set_predictor(self, order):
+        """Warm starts from the polynomial extrapolation of the last `order`
+        dipole sets (0 or 1: the last set)."""
+        self._check(self.lib.sibfa_set_predictor(self.h, int(order)))
+
+    # -- dynamics (Beeman) ------------------------------------------------
+    def md_init(self, masses, vsites=None, bonds=None, bond_k=None, bond_r0=None,
+                rep_radius=None, rep_eps=0.0, vel=None):
+        _dev(masses, torch.float64, (self.n,), self.device, "masses")
+        _dev(rep_radius, torch.float64, (self.n,), self.device, "rep_radius")
+        _dev(vsites, torch.int32, (self.n, 2), self.device, "vsites")
+        nb = 0 if bonds is None else bonds.shape[0]
+        _dev(bonds, torch.int32, (nb, 2), self.device, "bonds")
+        _dev(bond_k, torch.float64, (nb,), self.device, "bond_k")
+        _dev(bond_r0, torch.float64, (nb,), self.device, "bond_r0")
+        _dev(vel, torch.float64, (self.n, 3), self.device, "vel")
+        self._check(self.lib.sibfa_md_init(self.h, _ptr(masses), _ptr(vsites), nb, _ptr(bonds),
+                                           _ptr(bond_k), _ptr(bond_r0), _ptr(rep_radius),
+                                           float(rep_eps), _ptr(vel)))
+
+    def md_run(self, n_steps, dt_fs=1.0, friction=0.0):
+        """Per-step records (E_pol, E_elec, E_bond, E_rep, E_kin, iterations);
+        friction > 0 damps the velocities (a relaxation)."""
+        st = (_lib.MdStats * max(int(n_steps), 1))()
+        self._check(self.lib.sibfa_md_run(self.h, int(n_steps), float(dt_fs), float(friction),
+                                          st))
+        return [(r.e_pol, r.e_elec, r.e_bond, r.e_rep, r.e_kin, r.iterations)
+                for r in list(st)[:int(n_steps)]]
+
+    def md_state(self):
+        x = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(x)
+        self._check(self.lib.sibfa_md_get_state(self.h, _ptr(x), _ptr(v)))
+        return x, v
 
     def neighbor_counts(self):
         out = torch.empty((self.n,), dtype=torch.int32, device=self.device)

@@ -233,3 +233,47 @@ def water_frames(sysd):
     n = len(sysd["pos"])
     first = (np.arange(n) // WATER_SITES) * WATER_SITES
     return np.stack([first, first + 1, first + 2], axis=1).astype(np.int32)
+
+
+MASSES = {"O": 15.999, "H": 1.008}   # g/mol; the bond barycentres are massless
+
+
+def water_md(sysd, seed_index=0, temperature=300.0, k_oh=500.0, k_hh=150.0, rho_o=1.6,
+             rho_h=0.8, rho_b=0.8, rep_eps=0.5):
+    """Dynamics inputs for a water system: masses (O, H; B1 and B2 massless),
+    the barycentres as midpoint virtual sites of (O, H1) and (O, H2),
+    three harmonic bonds per water (O-H1, O-H2, H1-H2; kcal/mol/A^2) with
+    rest lengths from the current geometry, repulsion radii (O rho_o, H
+    rho_h, B rho_b, A; every site carries random multipoles, so every site
+    needs a wall) with the strength rep_eps (kcal/mol), and Maxwell-Boltzmann
+    velocities (A/fs) at `temperature` from numpy's PCG64 seeded with
+    22010804 + 1000 + seed_index (zero rows at the virtual sites)."""
+    pos = np.asarray(sysd["pos"], float)
+    n = len(pos)
+    nw = n // WATER_SITES
+    base = np.arange(nw) * WATER_SITES
+    masses = np.zeros(n)
+    masses[base] = MASSES["O"]
+    masses[base + 1] = MASSES["H"]
+    masses[base + 2] = MASSES["H"]
+    vsites = -np.ones((n, 2), dtype=np.int32)
+    vsites[base + 3] = np.stack([base, base + 1], 1)
+    vsites[base + 4] = np.stack([base, base + 2], 1)
+    bonds = np.concatenate([np.stack([base, base + 1], 1), np.stack([base, base + 2], 1),
+                            np.stack([base + 1, base + 2], 1)]).astype(np.int32)
+    k = np.concatenate([np.full(nw, k_oh), np.full(nw, k_oh), np.full(nw, k_hh)])
+    r0 = np.linalg.norm(pos[bonds[:, 0]] - pos[bonds[:, 1]], axis=1)
+    rng = np.random.default_rng(_SEED_BASE + 1000 + seed_index)
+    kt = 0.0019872041 * temperature                   # kcal/mol
+    sigma = np.zeros(n)
+    atoms = masses > 0
+    sigma[atoms] = np.sqrt(kt * 4.184e-4 / masses[atoms])
+    vel = rng.standard_normal((n, 3)) * sigma[:, None]
+    rho = np.zeros(n)
+    rho[base] = rho_o
+    rho[base + 1] = rho_h
+    rho[base + 2] = rho_h
+    rho[base + 3] = rho_b
+    rho[base + 4] = rho_b
+    return dict(masses=masses, vsites=vsites, bonds=bonds, bond_k=k, bond_r0=r0, vel=vel,
+                rep_radius=rho, rep_eps=float(rep_eps))

@@ -80,8 +80,9 @@ def test_bad_arguments():
 
 
 def test_nonfinite_positions_after_update():
-    """update_positions only enqueues the copy; a NaN coordinate is reported
-    by the next call that computes, and the context stays usable."""
+    """update_positions only enqueues the copy; a NaN coordinate (or one
+    beyond 1e6 box edges) is reported by the next call that computes, and
+    the context stays usable."""
     from paper_2201_00804_amd import SibfaError
     d = water_box(27, 9.5, 3)
     eng = engine_for(d, gpu_params(d, beta=0.45, cutoff=4.5, grid=24))
@@ -92,6 +93,18 @@ def test_nonfinite_positions_after_update():
     with pytest.raises(SibfaError) as e:
         eng.solve()
     assert _status(e) == -1 and "NaN or Inf" in str(e.value)
+    eng.update_positions(_t(d["pos"]))
+    assert eng.energy_forces()[0] == e0
+    # finite coordinates too far out for the periodic wrap (a run-away atom)
+    # are rejected the same way; the kernels queued before the error is
+    # read back see them wrapped to 0, inside the grid
+    for far in (1e26, -7.1e19):
+        bad = d["pos"].copy()
+        bad[11, 0] = far
+        eng.update_positions(_t(bad))
+        with pytest.raises(SibfaError) as e:
+            eng.energy_forces()
+        assert _status(e) == -1 and "box edges" in str(e.value)
     eng.update_positions(_t(d["pos"]))
     assert eng.energy_forces()[0] == e0
     eng.close()
