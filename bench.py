@@ -234,6 +234,39 @@ def run_md(name, precision, relax_steps, steps, dt=1.0, predictor=3):
                 e_kin_mean=round(float(st[:, 4].mean()), 2))
 
 
+def run_ct(name, steps=10, warmup=2):
+    """Reduced charge transfer on a water box with two lone-pair sites per
+    water: ms per E_ct + forces call (potentials, pair passes, potential
+    forces, the reciprocal passes), FP64."""
+    import numpy as np
+    import torch
+    from synth import config_system, water_lone_pairs, water_ct
+    from paper_2201_00804_amd import Engine, default_params
+
+    d, cfg = config_system(name)
+    d = water_lone_pairs(d)
+    ct = water_ct(d)
+    t = lambda a, dt_=torch.float64: torch.as_tensor(np.asarray(a), dtype=dt_,
+                                                     device="cuda").contiguous()
+    eng = Engine(0)
+    eng.load(d, default_params(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"],
+                               order=cfg["order"], tol=cfg["tol"], max_iter=400))
+    eng.set_charge_transfer(t(ct["lp"], torch.int32), t(ct["lp_par"]), t(ct["acc"], torch.int32),
+                            t(ct["ah"]), t(ct["rvdw"]), ct["eta"], ct["cs"], ct["cp"], ct["t"],
+                            ct["m"])
+    for _ in range(warmup):
+        e, _f = eng.ct_energy_forces()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e, _f = eng.ct_energy_forces()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    eng.close()
+    return dict(workload=name + "+lone_pairs", n_sites=len(d["pos"]), n_lone_pairs=len(ct["lp"]),
+                n_acceptors=len(ct["acc"]), ms_energy_forces=round(ms, 3), e_ct=e)
+
+
 def roofline(res, precision):
     """Roofline point of the kernel with the largest share of the timed
     region, the real-space matvec.  It is priced as vector-ALU work (the
@@ -551,6 +584,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tcg", action="store_true")
     ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--no-ct", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -651,6 +685,14 @@ def main():
                 print(f"[bench] md {name} {prec}: {r['steps_per_s']} steps/s, "
                       f"{r['iterations_mean']} iterations per step, E_tot drift "
                       f"{r['e_tot_drift']} kcal/mol", file=sys.stderr, flush=True)
+    if not args.no_ct:
+        out["ct"] = []
+        for name in ("box216", "box32000"):
+            print(f"[bench] charge transfer {name} + lone pairs", file=sys.stderr, flush=True)
+            r = run_ct(name, args.steps, args.warmup)
+            out["ct"].append(r)
+            print(f"[bench] charge transfer {name}: {r['ms_energy_forces']} ms per E_ct + forces",
+                  file=sys.stderr, flush=True)
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_warmup} warm-up + {args.serve_requests} requests",
               file=sys.stderr, flush=True)

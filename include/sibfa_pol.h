@@ -266,6 +266,42 @@ sibfa_status sibfa_set_dipoles(sibfa_ctx ctx, const double* mu);
 #define SIBFA_PREDICT_MAX_ORDER 6
 sibfa_status sibfa_set_predictor(sibfa_ctx ctx, int order);
 
+/* Reduced many-body charge transfer (Many-Body Charge Transfer/Charge
+ * Delocalization, the reduced expression, Eq. 13-16):
+ *   E_ct = sum_l sum_k -n(l) (e1 - e2)^2 / (ae(l) + V_l - ah(k)),
+ *   e1 = exp(-eta rho1) (V_int(a1) - V_l) (C_s t + C_p m cos alpha),
+ *   e2 = exp(-eta rho2) (V_int(a2) - V_l) (C_s t + C_p m cos beta),
+ * over lone pairs l (a site of the molecule, carried by atom c) and
+ * acceptor bonds k = (a1, a2) (a1 the hydrogen) of other molecules whose
+ * a1 lies within the real-space cutoff of c (every other molecule for a
+ * cluster); rho = |r_c - r_a| / (2 sqrt(rvdw_c rvdw_a)); alpha, beta the
+ * angles at c between r_l - r_c and r_a1 - r_c, r_a2 - r_c.  V_l is the
+ * potential at the lone pair of the other molecules' permanent multipoles
+ * (Smooth PME in a box, own molecule excluded), V_int(a) the bare potential
+ * at atom a of its own molecule's other sites; both enter in kcal/mol per
+ * unit charge.
+ * sibfa_set_charge_transfer: lp [n_lp][2] (device int32: lone-pair site,
+ * carrier atom, one molecule; the lone-pair site carries no multipoles and
+ * no polarizability), lp_par [n_lp][2] (device: occupation n, ionization
+ * energy ae, kcal/mol), acc [n_acc][2] (device int32: a1, a2 of one
+ * molecule), acc_ah [n_acc] (device, kcal/mol), rvdw [n] (device, A,
+ * positive at carriers and acceptor atoms), constants (HOST).  Copied and
+ * checked once (SIBFA_E_ARG); call after the multipoles and
+ * polarizabilities; setting either of them again switches the term off.
+ * Synchronizes.
+ * sibfa_ct_energy_forces: E_ct (HOST, kcal/mol) and, when forces is not
+ * NULL, its forces [n][3] (device, kcal/mol/A, written, not added),
+ * including those through the potentials.  Always FP64; independent of the
+ * induced dipoles (no solve). */
+typedef struct {
+  double eta, cs, cp, t, m;
+} sibfa_ct_params;
+sibfa_status sibfa_set_charge_transfer(sibfa_ctx ctx, int n_lp, const int32_t* lp,
+                                       const double* lp_par, int n_acc, const int32_t* acc,
+                                       const double* acc_ah, const double* rvdw,
+                                       const sibfa_ct_params* params);
+sibfa_status sibfa_ct_energy_forces(sibfa_ctx ctx, double* e_ct, double* forces);
+
 /* Molecular dynamics (Computational Details: Beeman integrator, 1 fs
  * steps, the polarization solved at every step).  The paper's other terms
  * (repulsion, dispersion, charge transfer, bonded terms) are outside this

@@ -27,7 +27,7 @@ solver tolerance) are listed in the module docstrings that use them.
 from .model import Params, System, evaluate, permanent_field, apply_T, \
     dense_T_columns, dense_T_blocks, energy_forces, electrostatic_energy, tcg
 from .solver import pcg, plain_cg, jacobi
-from . import radial, tensors, realspace, recip, units, frames, md
+from . import radial, tensors, realspace, recip, units, frames, md, ct
 
 __all__ = ["Params", "System", "evaluate", "permanent_field", "apply_T",
            "dense_T_columns", "dense_T_blocks", "energy_forces",

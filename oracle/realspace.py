@@ -140,6 +140,9 @@ def pairs_images(pos, mol, box, rmax):
 def class_coefficients(cls, r, same, kernel, beta, abar_i, abar_j, a_ij, nmax):
     """[c_0..c_nmax] for the interaction class on these pairs."""
     c0 = radial.bare(r, nmax)
+    if cls == "intra":   # same-molecule pairs only, bare kernel
+        on = np.where(same, 1.0, 0.0)
+        return [on * c0[n] for n in range(nmax + 1)]
     if cls == "MM":
         lam = [np.ones_like(r)] * (nmax + 1)
     else:
@@ -184,6 +187,7 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     what: 'energy' -> 1/2 sum of U over ordered pairs
           'force'  -> per-site force -dU/dr_i summed over pairs at i (n,3)
           'field'  -> per-site field of the j-side multipoles at i (n,3)
+          'potential' -> per-site potential of the j-side multipoles at i (n,)
           'fieldgrad' -> per-site field gradient dE_b/dr_a of the j-side
                       multipoles at i (n,3,3), E = -grad phi
           'virial' -> W_ab = -dE/d eps_ab of the pair energy (3,3) under the
@@ -194,7 +198,7 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
     abar, athole = thole
     maxrank_i = max([k for k, v in enumerate(Mi) if v is not None], default=0)
     maxrank_j = max([k for k, v in enumerate(Mj) if v is not None], default=0)
-    extra = {"energy": 0, "fieldgrad": 2}.get(what, 1)
+    extra = {"energy": 0, "potential": 0, "fieldgrad": 2}.get(what, 1)
     nmax = maxrank_i + maxrank_j + extra
     if what == "energy":
         acc = 0.0
@@ -202,6 +206,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
         acc = np.zeros((3, 3))
     elif what == "fieldgrad":
         acc = np.zeros((n_sites, 3, 3))
+    elif what == "potential":
+        acc = np.zeros(n_sites)
     else:
         acc = np.zeros((n_sites, 3))
     sel = np.arange(len(pairs)) if pair_mask is None else np.flatnonzero(pair_mask)
@@ -215,7 +221,7 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
         c = class_coefficients(cls, r, pairs.same[idx], kernel, beta,
                                abar[i], abar[j], a_ij, nmax)
         D = [deriv_tensor(n, R, c) for n in range(nmax + 1)]
-        mi = (_mlist(*Mi, i) if what not in ("field", "fieldgrad")
+        mi = (_mlist(*Mi, i) if what not in ("field", "fieldgrad", "potential")
               else [(0, np.ones(len(i)))])
         mj = _mlist(*Mj, j)
         val = _interaction(D, mi, mj, extra)
@@ -223,6 +229,8 @@ def pair_sum(pairs, cls, kernel, beta, thole, Mi, Mj, what, n_sites,
             acc += 0.5 * float(np.sum(val))
         elif what == "virial":
             acc -= 0.5 * np.einsum("pa,pb->ab", val, R)
+        elif what == "potential":
+            np.add.at(acc, i, val)
         else:
             np.add.at(acc, i, -val)
     return acc

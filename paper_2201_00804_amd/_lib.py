@@ -49,6 +49,11 @@ class MdStats(ctypes.Structure):
                 ("iterations", ctypes.c_int)]
 
 
+class CtParams(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("cs", ctypes.c_double), ("cp", ctypes.c_double),
+                ("t", ctypes.c_double), ("m", ctypes.c_double)]
+
+
 # (name, restype, argtypes)
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -65,6 +70,9 @@ SIGNATURES = [
     ("sibfa_set_polarizabilities", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_set_local_frames", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sibfa_set_predictor", ctypes.c_int, [_P, ctypes.c_int]),
+    ("sibfa_set_charge_transfer", ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P,
+                                                 _P, _P]),
+    ("sibfa_ct_energy_forces", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_md_init", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_double,
                                      _P]),
     ("sibfa_md_run", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P]),

@@ -154,6 +154,13 @@ struct sibfa_ctx_s {
   std::vector<DevBuf> mdbufs;
   MdArgs md{};
   double* md_force = nullptr;
+  // reduced charge transfer: inputs, lookup tables and work buffers
+  // (ctbufs, replaced by every sibfa_set_charge_transfer)
+  bool ct_on = false;
+  std::vector<DevBuf> ctbufs;
+  CtArgs ct{};
+  double4 *ct_spw = nullptr, *ct_zero4 = nullptr;
+  double2* ct_zero2 = nullptr;
   // local frames: device copies of the frames and local quantities, the
   // frame groups and site references, and the force-path buffers (all in
   // framebufs, replaced by every sibfa_set_local_frames)
@@ -369,6 +376,8 @@ void release_system(sibfa_ctx c) {
   c->vir_tot = nullptr;
   free_list(c, c->mdbufs);
   c->md_on = false;
+  free_list(c, c->ctbufs);
+  c->ct_on = false;
   c->hist = nullptr;       // lived in bufs
   c->hist_head = c->hist_count = 0;
   free_list(c, c->framebufs);
@@ -1534,6 +1543,7 @@ sibfa_status sibfa_set_multipoles(sibfa_ctx c, const double* q, const double* di
   if (st != SIBFA_OK) return st;
   c->have_mult = true;
   c->have_frames = false;   // global multipoles given: local frames off
+  c->ct_on = false;         // the lone-pair checks were made against the old ones
   c->dirty_mult = true;
   c->e0_valid = false;
   c->mu_valid = false;
@@ -1554,6 +1564,7 @@ sibfa_status sibfa_set_polarizabilities(sibfa_ctx c, const double* alpha, const 
   if (st != SIBFA_OK) return st;
   c->have_pol = true;
   c->have_frames = false;   // new polarizabilities: local frames off
+  c->ct_on = false;
   c->dirty_pol = true;
   c->pol_ok = false;
   c->e0_valid = false;
@@ -1866,6 +1877,181 @@ sibfa_status sibfa_energy_forces(sibfa_ctx c, double* e_pol, double* e_elec, dou
   c->stats.e_elec = c->stats.e_elec_real + c->stats.e_elec_recip + c->stats.e_elec_self;
   if (e_pol) *e_pol = c->stats.e_pol;
   if (e_elec) *e_elec = c->stats.e_elec;
+  return SIBFA_OK;
+}
+
+// ------------------------------------------------------------ charge transfer
+sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
+                                       const double* lp_par, int n_acc, const int32_t* acc,
+                                       const double* acc_ah, const double* rvdw,
+                                       const sibfa_ct_params* prm) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->have_sys) return fail(c, SIBFA_E_STATE, "sibfa_set_system has not been called");
+  if (!c->have_mult || !c->have_pol)
+    return fail(c, SIBFA_E_STATE, "multipoles and polarizabilities must be set first");
+  if (n_lp < 0 || n_acc < 0 || (n_lp > 0 && (!lp || !lp_par)) || (n_acc > 0 && (!acc || !acc_ah)) ||
+      !rvdw || !prm)
+    return fail(c, SIBFA_E_ARG, "charge transfer: missing arrays or negative counts");
+  const double pv[5] = {prm->eta, prm->cs, prm->cp, prm->t, prm->m};
+  for (double v : pv)
+    if (!std::isfinite(v)) return fail(c, SIBFA_E_ARG, "charge transfer: non-finite constants");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->aux && c->aux != c->stream) HIP_TRY(hipStreamSynchronize(c->aux));
+  const int n = c->n;
+  const size_t nn = n;
+  std::vector<int> hl(2 * (size_t)n_lp), ha(2 * (size_t)n_acc), hm(nn);
+  std::vector<double> hlp(2 * (size_t)n_lp), hah(n_acc), hr(nn), hq(nn), hd(3 * nn), ht(6 * nn),
+      hal(6 * nn);
+  if (n_lp > 0) {
+    HIP_TRY(hipMemcpy(hl.data(), lp, hl.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hlp.data(), lp_par, hlp.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (n_acc > 0) {
+    HIP_TRY(hipMemcpy(ha.data(), acc, ha.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hah.data(), acc_ah, hah.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  HIP_TRY(hipMemcpy(hr.data(), rvdw, nn * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hm.data(), c->mol_c, nn * sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hq.data(), c->q_c, nn * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hd.data(), c->dip_c, 3 * nn * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ht.data(), c->quad_c, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hal.data(), c->alpha_c, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
+  auto in = [&](int i) { return i >= 0 && i < n; };
+  std::vector<int> lp_of(nn, -1);
+  for (int p = 0; p < n_lp; ++p) {
+    const int L = hl[2 * p], cr = hl[2 * p + 1];
+    const std::string at = "lone pair " + std::to_string(p);
+    if (!in(L) || !in(cr) || L == cr || hm[L] != hm[cr])
+      return fail(c, SIBFA_E_ARG, at + ": site and carrier distinct, in range, one molecule");
+    if (lp_of[L] >= 0) return fail(c, SIBFA_E_ARG, at + ": site listed twice");
+    lp_of[L] = p;
+    bool zero = hq[L] == 0.0;
+    for (int k = 0; k < 3; ++k) zero = zero && hd[3 * (size_t)L + k] == 0.0;
+    for (int k = 0; k < 6; ++k) zero = zero && ht[6 * (size_t)L + k] == 0.0 && hal[6 * (size_t)L + k] == 0.0;
+    if (!zero) return fail(c, SIBFA_E_ARG, at + ": a lone-pair site carries no multipoles or polarizability");
+    if (!(hr[cr] > 0.0) || !std::isfinite(hr[cr]) || !std::isfinite(hlp[2 * p]) ||
+        !std::isfinite(hlp[2 * p + 1]))
+      return fail(c, SIBFA_E_ARG, at + ": finite parameters and a positive carrier radius");
+  }
+  for (int k = 0; k < n_acc; ++k) {
+    const int a1 = ha[2 * k], a2 = ha[2 * k + 1];
+    const std::string at = "acceptor " + std::to_string(k);
+    if (!in(a1) || !in(a2) || a1 == a2 || hm[a1] != hm[a2])
+      return fail(c, SIBFA_E_ARG, at + ": two distinct atoms of one molecule");
+    if (!(hr[a1] > 0.0) || !(hr[a2] > 0.0) || !std::isfinite(hr[a1]) || !std::isfinite(hr[a2]) ||
+        !std::isfinite(hah[k]))
+      return fail(c, SIBFA_E_ARG, at + ": finite affinity and positive radii");
+  }
+  // site -> acceptors (as a1), lone pairs (as carrier), acceptor slots
+  std::vector<int> a1s(nn + 1, 0), cars(nn + 1, 0), ats(nn + 1, 0);
+  for (int k = 0; k < n_acc; ++k) { a1s[ha[2 * k] + 1]++; ats[ha[2 * k] + 1]++; ats[ha[2 * k + 1] + 1]++; }
+  for (int p = 0; p < n_lp; ++p) cars[hl[2 * p + 1] + 1]++;
+  for (int i = 0; i < n; ++i) { a1s[i + 1] += a1s[i]; cars[i + 1] += cars[i]; ats[i + 1] += ats[i]; }
+  std::vector<int> a1r(std::max(a1s[n], 1)), carr(std::max(cars[n], 1)), atr(std::max(ats[n], 1));
+  std::vector<int> vint;
+  {
+    std::vector<int> ca(a1s.begin(), a1s.end() - 1), cc(cars.begin(), cars.end() - 1),
+        ct(ats.begin(), ats.end() - 1);
+    for (int k = 0; k < n_acc; ++k) {
+      a1r[ca[ha[2 * k]]++] = k;
+      atr[ct[ha[2 * k]]++] = 2 * k;
+      atr[ct[ha[2 * k + 1]]++] = 2 * k + 1;
+    }
+    for (int p = 0; p < n_lp; ++p) carr[cc[hl[2 * p + 1]]++] = p;
+    for (int i = 0; i < n; ++i)
+      if (ats[i + 1] > ats[i]) vint.push_back(i);
+  }
+  free_list(c, c->ctbufs);
+  c->ct_on = false;
+  auto& L = c->ctbufs;
+  CtArgs& a = c->ct;
+  a = CtArgs{};
+  const size_t nl = std::max(n_lp, 1), na = std::max(n_acc, 1);
+  int *dl, *da, *d_a1s, *d_a1r, *d_cs, *d_cr, *d_lpof, *d_ats, *d_atr, *d_vint;
+  double *dlp, *dah, *dr;
+  const bool ok =
+      alloc_into(c, L, dl, 2 * nl) && alloc_into(c, L, dlp, 2 * nl) && alloc_into(c, L, da, 2 * na) &&
+      alloc_into(c, L, dah, na) && alloc_into(c, L, dr, nn) && alloc_into(c, L, d_a1s, nn + 1) &&
+      alloc_into(c, L, d_a1r, a1r.size()) && alloc_into(c, L, d_cs, nn + 1) &&
+      alloc_into(c, L, d_cr, carr.size()) && alloc_into(c, L, d_lpof, nn) &&
+      alloc_into(c, L, d_ats, nn + 1) && alloc_into(c, L, d_atr, atr.size()) &&
+      alloc_into(c, L, d_vint, std::max<size_t>(vint.size(), 1)) &&
+      alloc_into(c, L, a.Vlp, nl) && alloc_into(c, L, a.Gr, 3 * nl) && alloc_into(c, L, a.Vint, nn) &&
+      alloc_into(c, L, a.w, nl) && alloc_into(c, L, a.Fl, 3 * nl) && alloc_into(c, L, a.Fc, 3 * nl) &&
+      alloc_into(c, L, a.Fa, 6 * na) && alloc_into(c, L, a.ua, 2 * na) &&
+      alloc_into(c, L, a.W_s, nn) && alloc_into(c, L, a.U_s, nn) && alloc_into(c, L, a.F_s, nn) &&
+      alloc_into(c, L, c->ct_spw, nn) && alloc_into(c, L, c->ct_zero4, nn) &&
+      alloc_into(c, L, c->ct_zero2, nn);
+  if (!ok) {
+    free_list(c, c->ctbufs);
+    return fail(c, SIBFA_E_NOMEM, "charge-transfer allocation failed");
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  HIP_TRY(up(dl, hl.data(), hl.size() * sizeof(int)));
+  HIP_TRY(up(dlp, hlp.data(), hlp.size() * sizeof(double)));
+  HIP_TRY(up(da, ha.data(), ha.size() * sizeof(int)));
+  HIP_TRY(up(dah, hah.data(), hah.size() * sizeof(double)));
+  HIP_TRY(up(dr, hr.data(), nn * sizeof(double)));
+  HIP_TRY(up(d_a1s, a1s.data(), a1s.size() * sizeof(int)));
+  HIP_TRY(up(d_a1r, a1r.data(), a1r.size() * sizeof(int)));
+  HIP_TRY(up(d_cs, cars.data(), cars.size() * sizeof(int)));
+  HIP_TRY(up(d_cr, carr.data(), carr.size() * sizeof(int)));
+  HIP_TRY(up(d_lpof, lp_of.data(), nn * sizeof(int)));
+  HIP_TRY(up(d_ats, ats.data(), ats.size() * sizeof(int)));
+  HIP_TRY(up(d_atr, atr.data(), atr.size() * sizeof(int)));
+  HIP_TRY(up(d_vint, vint.data(), vint.size() * sizeof(int)));
+  launch_fill_double(reinterpret_cast<double*>(c->ct_zero4), 0.0, 4 * nn, c->stream);
+  launch_fill_double(reinterpret_cast<double*>(c->ct_zero2), 0.0, 2 * nn, c->stream);
+  launch_fill_double(a.Vint, 0.0, nn, c->stream);
+  a.n = n; a.n_lp = n_lp; a.n_acc = n_acc; a.n_vint = (int)vint.size();
+  a.lp = dl; a.lp_par = dlp; a.acc = da; a.ah = dah; a.rvdw = dr;
+  a.eta = prm->eta; a.cs = prm->cs; a.cp = prm->cp; a.t = prm->t; a.m = prm->m;
+  a.a1_start = d_a1s; a.a1_ref = d_a1r; a.car_start = d_cs; a.car_ref = d_cr; a.lp_of = d_lpof;
+  a.at_start = d_ats; a.at_ref = d_atr; a.vint_sites = d_vint;
+  c->ct_on = true;
+  return sync_read(c);
+}
+
+sibfa_status sibfa_ct_energy_forces(sibfa_ctx c, double* e_ct, double* forces) {
+  if (!c) return SIBFA_E_ARG;
+  if (!c->ct_on) return fail(c, SIBFA_E_STATE, "sibfa_set_charge_transfer has not been called");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  join(c);
+  hipStream_t sm = c->stream;
+  SysView s = make_view(c);
+  CtArgs a = c->ct;
+  a.perm = c->perm;
+  a.inv_perm = c->inv_perm;
+  launch_ct_potentials(s, a, sm);
+  if (c->periodic && a.n_lp > 0) {
+    launch_spread_mult(s, c->pm, nullptr, false, sm);
+    conv(c, false, sm, S_CTREC);
+    launch_ct_gather_pot(s, c->pm, a, sm);
+  }
+  launch_ct_pairs(s, a, c->red, sm);
+  if (forces) {
+    launch_ct_wforce(s, a, c->periodic ? c->ct_spw : nullptr, sm);
+    if (c->periodic) {
+      SysView sw = s;
+      sw.sp = c->ct_spw;
+      sw.sd = c->ct_zero4;
+      sw.sth = c->ct_zero4;
+      sw.sth2 = c->ct_zero2;
+      launch_spread_mult(sw, c->pm, nullptr, false, sm);
+      conv(c, false, sm, S_CTREC);
+      launch_gather_force(s, c->pm, c->red, c->ct_zero4, a.F_s, c->perm, forces, false, false, sm);
+    } else {
+      launch_forces_out(c->n, c->perm, a.F_s, forces, sm);
+    }
+  }
+  double e = 0.0;
+  if ((st = read_totals(c, {S_ECT}, &e)) != SIBFA_OK) return st;
+  if (e_ct) *e_ct = e;
   return SIBFA_OK;
 }
 

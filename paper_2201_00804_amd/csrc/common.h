@@ -33,6 +33,8 @@ enum Slot {
   S_EKIN,        // kinetic energy (molecular dynamics)
   S_EBOND,       // bond energy (molecular dynamics)
   S_EREP,        // stand-in repulsion energy (molecular dynamics)
+  S_ECT,         // charge-transfer energy
+  S_CTREC,       // reciprocal energy of the charge-transfer convolutions (unused)
   // virial partials (written only when a virial is asked for), row-major
   // W_ab at slot + 3a + b unless noted
   S_VRI,                 // same-molecule pairs, 9 slots
@@ -340,6 +342,20 @@ __device__ __forceinline__ void bspline_weights(R w, R th[ND + 1][P]) {
       const R d = (t >= 3) ? lev[P - 4][t - 3] : R(0);
       th[ND >= 3 ? 3 : 0][t] = a - R(3) * b + R(3) * c - d;
     }
+  }
+}
+
+// Grid base indices and B-spline weights (derivatives up to ND) of a site
+// along the three axes.
+template <typename R, int P, int ND>
+__device__ __forceinline__ void site_splines(const PmeView& pm, double x, double y, double z,
+                                             int base[3], R th[3][ND + 1][P]) {
+  const double xs[3] = {x, y, z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double fr;
+    base[a] = grid_base(xs[a], pm.scale[a], pm.K[a], &fr);
+    bspline_weights<R, P, ND>((R)fr, th[a]);
   }
 }
 

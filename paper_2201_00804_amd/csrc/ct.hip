@@ -1,0 +1,500 @@
+// Reduced many-body charge transfer (paper: Many-Body Charge
+// Transfer/Charge Delocalization, the reduced expression, Eq. 13-16):
+//   E_ct = sum_l sum_k -n(l) (e1 - e2)^2 / dE,
+//   e1 = exp(-eta rho1) (V_int(a1) - V_l) (C_s t + C_p m cos alpha),
+//   e2 = exp(-eta rho2) (V_int(a2) - V_l) (C_s t + C_p m cos beta),
+//   dE = ae(l) + V_l - ah(k),
+// over lone pairs l (carried by atom c) and acceptor bonds k = (a1, a2) of
+// other molecules with |r_c - r_a1| inside the real-space cutoff; rho the
+// distances c-a over 2 sqrt(rvdw_c rvdw_a), alpha and beta the angles at c
+// between the lone pair and a1, a2.  V_l is the potential of the other
+// molecules' permanent multipoles at the lone pair (Ewald-summed when
+// periodic, own molecule excluded); V_int(a) the bare potential at atom a
+// of its own molecule's other sites.  Potentials enter in kcal/mol per
+// unit charge.  Everything runs in FP64.
+//
+//  k_ct_vlp       : real-space part of V_l (G lanes per lone pair).
+//  k_ct_vint      : V_int at the acceptor atoms.
+//  k_ct_gather_pot: reciprocal V_l and its gradient from the PME grid.
+//  k_ct_pairs_lp  : per lone pair over its carrier's neighbours: the energy,
+//                   w_l = dE/dV_l, the direct forces on l and c.
+//  k_ct_pairs_acc : per acceptor over a1's neighbours (the same pairs): the
+//                   direct forces on a1, a2 and u_a = dE/dV_int(a).
+//  k_ct_collect   : per site, its share of all of these (fixed order).
+//  k_ct_wforce    : -grad of sum_l w_l V_l + sum_a u_a V_int(a) in real
+//                   space: point charges w at the lone pairs (and u at the
+//                   acceptor atoms, own molecule, bare) against the
+//                   permanent multipoles.  The reciprocal part of the w
+//                   charges goes through the ordinary PME force gather.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "pairmath.h"
+#include "kernels.h"
+
+namespace sibfa {
+
+namespace {
+
+constexpr int kCtG = 16;
+
+__device__ __forceinline__ void rec_mp(const SysView& s, int j, MP<double>& M, double x[3]) {
+  const double4 p = s.sp[j], d = s.sd[j], t = s.sth[j];
+  const double2 t2 = s.sth2[j];
+  x[0] = p.x; x[1] = p.y; x[2] = p.z;
+  M.q = p.w;
+  M.d[0] = d.x; M.d[1] = d.y; M.d[2] = d.z;
+  M.t[0] = t.x; M.t[1] = t.y; M.t[2] = t.z; M.t[3] = t.w; M.t[4] = t2.x; M.t[5] = t2.y;
+}
+
+__device__ __forceinline__ void sep(const SysView& s, const double a[3], const double b[3],
+                                    double R[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double d = a[k] - b[k];
+    if (s.periodic) d = min_image<double>(d, s.box[k], s.ibox[k]);
+    R[k] = d;
+  }
+}
+
+// Potential at R (= r - r_j) of multipoles M: q c0 + (d.R) c1 + 1/3 (R Theta R) c2.
+__device__ __forceinline__ double mp_potential(const double c[3], const MP<double>& M,
+                                               const double R[3]) {
+  double tr[3];
+  tvec(M.t, R, tr);
+  const double rtr = tr[0] * R[0] + tr[1] * R[1] + tr[2] * R[2];
+  return M.q * c[0] + (M.d[0] * R[0] + M.d[1] * R[1] + M.d[2] * R[2]) * c[1] +
+         (1.0 / 3.0) * rtr * c[2];
+}
+
+// Entry k of site i's intermolecular list (near entries, then far ones
+// stored from the row's end).
+__device__ __forceinline__ int all_entry(const SysView& s, int i, int k, int nn) {
+  const int* row = s.nb_all + (size_t)i * s.cap_all;
+  return k < nn ? row[k] : row[s.cap_all - 1 - (k - nn)];
+}
+
+// Everything of one (lone pair p, acceptor k) pair.
+struct CtPair {
+  double E, dV, dVi1, dVi2;
+  double gL[3], gC[3], gA1[3], gA2[3];   // dE/dr of l, c, a1, a2
+};
+
+__device__ void ct_pair(const SysView& s, const CtArgs& a, int p, int k, CtPair& o) {
+  const int L = a.lp[2 * p], c = a.lp[2 * p + 1];
+  const int a1 = a.acc[2 * k], a2 = a.acc[2 * k + 1];
+  double xL[3], xc[3], x1[3], x2[3];
+  {
+    const double4 q0 = s.sp[a.inv_perm[L]], q1 = s.sp[a.inv_perm[c]];
+    const double4 q2 = s.sp[a.inv_perm[a1]], q3 = s.sp[a.inv_perm[a2]];
+    xL[0] = q0.x; xL[1] = q0.y; xL[2] = q0.z;
+    xc[0] = q1.x; xc[1] = q1.y; xc[2] = q1.z;
+    x1[0] = q2.x; x1[1] = q2.y; x1[2] = q2.z;
+    x2[0] = q3.x; x2[1] = q3.y; x2[2] = q3.z;
+  }
+  double u[3], d1[3], d2[3];
+  sep(s, xL, xc, u);
+  sep(s, x1, xc, d1);
+  sep(s, x2, xc, d2);
+  const double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const double r1 = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+  const double r2 = sqrt(d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
+  const double s1 = 2.0 * sqrt(a.rvdw[c] * a.rvdw[a1]), s2 = 2.0 * sqrt(a.rvdw[c] * a.rvdw[a2]);
+  const double ud1 = u[0] * d1[0] + u[1] * d1[1] + u[2] * d1[2];
+  const double ud2 = u[0] * d2[0] + u[1] * d2[1] + u[2] * d2[2];
+  const double ca = ud1 / (nu * r1), cb = ud2 / (nu * r2);
+  const double ex1 = exp(-a.eta * r1 / s1), ex2 = exp(-a.eta * r2 / s2);
+  const double VL = kCoulomb * a.Vlp[p];
+  const double X1 = kCoulomb * a.Vint[a1] - VL, X2 = kCoulomb * a.Vint[a2] - VL;
+  const double g1 = a.cs * a.t + a.cp * a.m * ca, g2 = a.cs * a.t + a.cp * a.m * cb;
+  const double e1 = ex1 * X1 * g1, e2 = ex2 * X2 * g2;
+  const double nocc = a.lp_par[2 * p], dE = a.lp_par[2 * p + 1] + VL - a.ah[k];
+  const double diff = e1 - e2;
+  o.E = -nocc * diff * diff / dE;
+  const double G = -2.0 * nocc * diff / dE;   // dE/de1; dE/de2 = -G
+  const double GD = nocc * diff * diff / (dE * dE);
+  o.dV = kCoulomb * (-G * ex1 * g1 + G * ex2 * g2 + GD);
+  o.dVi1 = kCoulomb * G * ex1 * g1;
+  o.dVi2 = -kCoulomb * G * ex2 * g2;
+  const double k1 = G * ex1 * X1 * a.cp * a.m;    // dE/dcos(alpha)
+  const double k2 = -G * ex2 * X2 * a.cp * a.m;   // dE/dcos(beta)
+  const double r1e = G * (-a.eta / s1) * e1;      // dE/dr1
+  const double r2e = -G * (-a.eta / s2) * e2;     // dE/dr2
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double dca_du = d1[q] / (nu * r1) - ca * u[q] / (nu * nu);
+    const double dcb_du = d2[q] / (nu * r2) - cb * u[q] / (nu * nu);
+    const double dca_dd1 = u[q] / (nu * r1) - ca * d1[q] / (r1 * r1);
+    const double dcb_dd2 = u[q] / (nu * r2) - cb * d2[q] / (r2 * r2);
+    o.gL[q] = k1 * dca_du + k2 * dcb_du;
+    o.gA1[q] = r1e * d1[q] / r1 + k1 * dca_dd1;
+    o.gA2[q] = r2e * d2[q] / r2 + k2 * dcb_dd2;
+    o.gC[q] = -(o.gL[q] + o.gA1[q] + o.gA2[q]);
+  }
+}
+
+}  // namespace
+
+// Real-space part of V_l: the other molecules within the cutoff (Ewald or
+// bare kernel) and, periodic, the excluded own-molecule correction.
+__global__ __launch_bounds__(kBlock) void k_ct_vlp(SysView s, CtArgs a) {
+  const int sub = threadIdx.x % kCtG;
+  const int p = blockIdx.x * (kBlock / kCtG) + threadIdx.x / kCtG;
+  double V = 0.0;
+  if (p < a.n_lp) {
+    const int i = a.inv_perm[a.lp[2 * p]];
+    const double4 pi = s.sp[i];
+    const double xi[3] = {pi.x, pi.y, pi.z};
+    const int nn = s.nc_near[i], nt = s.nc_all[i];
+    for (int k = sub; k < nt; k += kCtG) {
+      const int j = all_entry(s, i, k, nn);
+      MP<double> M;
+      double xj[3], R[3];
+      rec_mp(s, j, M, xj);
+      sep(s, xi, xj, R);
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double c[3];
+      if (s.periodic) ewald_coeffs<double, 2>(r, rinv, rinv2, s.beta, c);
+      else bare_coeffs<double, 2>(rinv, rinv2, c);
+      V += mp_potential(c, M, R);
+    }
+    if (s.periodic)
+      for (int k = sub; k < s.nc_in[i]; k += kCtG) {
+        const int j = s.nb_in[(size_t)i * s.cap_in + k];
+        MP<double> M;
+        double xj[3], R[3];
+        rec_mp(s, j, M, xj);
+        sep(s, xi, xj, R);
+        const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+        const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+        double B[3], c0[3], c[3];
+        ewald_coeffs<double, 2>(r, rinv, rinv2, s.beta, B);
+        bare_coeffs<double, 2>(rinv, rinv2, c0);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) c[n] = B[n] - c0[n];
+        V += mp_potential(c, M, R);
+      }
+  }
+  V = group_sum<kCtG>(V);
+  if (sub == 0 && p < a.n_lp) a.Vlp[p] = V;
+}
+
+// V_int at the acceptor atoms: bare potential of the own molecule's other
+// sites.
+__global__ __launch_bounds__(kBlock) void k_ct_vint(SysView s, CtArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_vint) return;
+  const int site = a.vint_sites[t];
+  const int i = a.inv_perm[site];
+  const double4 pi = s.sp[i];
+  const double xi[3] = {pi.x, pi.y, pi.z};
+  double V = 0.0;
+  for (int k = 0; k < s.nc_in[i]; ++k) {
+    const int j = s.nb_in[(size_t)i * s.cap_in + k];
+    MP<double> M;
+    double xj[3], R[3];
+    rec_mp(s, j, M, xj);
+    sep(s, xi, xj, R);
+    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    const double rinv = rsqrt(r2), rinv2 = rinv * rinv;
+    double c[3];
+    bare_coeffs<double, 2>(rinv, rinv2, c);
+    V += mp_potential(c, M, R);
+  }
+  a.Vint[site] = V;
+}
+
+// Reciprocal potential and its gradient at the lone pairs (from the grid of
+// the permanent multipoles).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_ct_gather_pot(SysView s, PmeView pm, CtArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_lp) return;
+  const double4 x = s.sp[a.inv_perm[a.lp[2 * p]]];
+  int base[3];
+  double th[3][2][P];
+  site_splines<double, P, 1>(pm, x.x, x.y, x.z, base, th);
+  double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
+  for (int tz = 0; tz < P; ++tz) {
+    int iz = base[2] - tz; if (iz < 0) iz += pm.K[2];
+    for (int ty = 0; ty < P; ++ty) {
+      int iy = base[1] - ty; if (iy < 0) iy += pm.K[1];
+      const size_t row = ((size_t)iz * pm.K[1] + iy) * pm.K[0];
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int tx = 0; tx < P; ++tx) {
+        int ix = base[0] - tx; if (ix < 0) ix += pm.K[0];
+        const double v = pm.phi[row + ix];
+        s0 += v * th[0][0][tx];
+        s1 += v * th[0][1][tx];
+      }
+      phi += s0 * th[1][0][ty] * th[2][0][tz];
+      g[0] += s1 * th[1][0][ty] * th[2][0][tz];
+      g[1] += s0 * th[1][1][ty] * th[2][0][tz];
+      g[2] += s0 * th[1][0][ty] * th[2][1][tz];
+    }
+  }
+  a.Vlp[p] += phi;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) a.Gr[3 * (size_t)p + q] = g[q] * pm.scale[q];
+}
+
+// Per lone pair: its acceptors among the carrier's neighbours.
+__global__ __launch_bounds__(kBlock) void k_ct_pairs_lp(SysView s, CtArgs a, Reduce red) {
+  const int sub = threadIdx.x % kCtG;
+  const int p = blockIdx.x * (kBlock / kCtG) + threadIdx.x / kCtG;
+  double E = 0.0, w = 0.0, FL[3] = {0.0, 0.0, 0.0}, FC[3] = {0.0, 0.0, 0.0};
+  if (p < a.n_lp) {
+    const int i = a.inv_perm[a.lp[2 * p + 1]];
+    const int nn = s.nc_near[i], nt = s.nc_all[i];
+    for (int e = sub; e < nt; e += kCtG) {
+      const int cj = a.perm[all_entry(s, i, e, nn)];
+      for (int r = a.a1_start[cj]; r < a.a1_start[cj + 1]; ++r) {
+        CtPair o;
+        ct_pair(s, a, p, a.a1_ref[r], o);
+        E += o.E;
+        w += o.dV;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          FL[q] -= o.gL[q];
+          FC[q] -= o.gC[q];
+        }
+      }
+    }
+  }
+  E = group_sum<kCtG>(E);
+  w = group_sum<kCtG>(w);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    FL[q] = group_sum<kCtG>(FL[q]);
+    FC[q] = group_sum<kCtG>(FC[q]);
+  }
+  if (sub == 0 && p < a.n_lp) {
+    a.w[p] = w;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.Fl[3 * (size_t)p + q] = FL[q];
+      a.Fc[3 * (size_t)p + q] = FC[q];
+    }
+  } else {
+    E = 0.0;
+  }
+  block_partial(E, red, S_ECT);
+}
+
+// Per acceptor: the lone pairs carried by a1's neighbours.
+__global__ __launch_bounds__(kBlock) void k_ct_pairs_acc(SysView s, CtArgs a) {
+  const int sub = threadIdx.x % kCtG;
+  const int k = blockIdx.x * (kBlock / kCtG) + threadIdx.x / kCtG;
+  double F1[3] = {0.0, 0.0, 0.0}, F2[3] = {0.0, 0.0, 0.0}, u1 = 0.0, u2 = 0.0;
+  if (k < a.n_acc) {
+    const int i = a.inv_perm[a.acc[2 * k]];
+    const int nn = s.nc_near[i], nt = s.nc_all[i];
+    for (int e = sub; e < nt; e += kCtG) {
+      const int cj = a.perm[all_entry(s, i, e, nn)];
+      for (int r = a.car_start[cj]; r < a.car_start[cj + 1]; ++r) {
+        CtPair o;
+        ct_pair(s, a, a.car_ref[r], k, o);
+        u1 += o.dVi1;
+        u2 += o.dVi2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          F1[q] -= o.gA1[q];
+          F2[q] -= o.gA2[q];
+        }
+      }
+    }
+  }
+  u1 = group_sum<kCtG>(u1);
+  u2 = group_sum<kCtG>(u2);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    F1[q] = group_sum<kCtG>(F1[q]);
+    F2[q] = group_sum<kCtG>(F2[q]);
+  }
+  if (sub == 0 && k < a.n_acc) {
+    a.ua[2 * (size_t)k] = u1;
+    a.ua[2 * (size_t)k + 1] = u2;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.Fa[6 * (size_t)k + q] = F1[q];
+      a.Fa[6 * (size_t)k + 3 + q] = F2[q];
+    }
+  }
+}
+
+// Per site (caller order c): w, u and the direct forces, in sorted order.
+// A lone pair also takes the reciprocal part of -w grad V_l here.
+__global__ __launch_bounds__(kBlock) void k_ct_collect(CtArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  double F[3] = {0.0, 0.0, 0.0}, W = 0.0, U = 0.0;
+  const int p = a.lp_of[c];
+  if (p >= 0) {
+    W = a.w[p];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) F[q] += a.Fl[3 * (size_t)p + q] - W * a.Gr[3 * (size_t)p + q];
+  }
+  for (int r = a.car_start[c]; r < a.car_start[c + 1]; ++r) {
+    const int pl = a.car_ref[r];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) F[q] += a.Fc[3 * (size_t)pl + q];
+  }
+  for (int r = a.at_start[c]; r < a.at_start[c + 1]; ++r) {
+    const int ks = a.at_ref[r];   // 2 k + slot
+    U += a.ua[ks];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) F[q] += a.Fa[3 * (size_t)ks + q];
+  }
+  const int i = a.inv_perm[c];
+  a.W_s[i] = W;
+  a.U_s[i] = U;
+  a.F_s[i] = make_double4(F[0], F[1], F[2], 0.0);
+}
+
+// -grad of sum_l w_l V_l + sum_a u_a V_int(a) in real space, added to F_s;
+// the result leaves divided by the Coulomb constant (the unit of the
+// reciprocal gather, which multiplies by it).
+__global__ __launch_bounds__(kBlock) void k_ct_wforce(SysView s, CtArgs a) {
+  const int sub = threadIdx.x % kCtG;
+  const int i = blockIdx.x * (kBlock / kCtG) + threadIdx.x / kCtG;
+  double F[3] = {0.0, 0.0, 0.0};
+  if (i < s.n) {
+    MP<double> Mi;
+    double xi[3];
+    rec_mp(s, i, Mi, xi);
+    const double Wi = a.W_s[i], Ui = a.U_s[i];
+    MP<double> Qi{};
+    Qi.q = Wi;
+    const int nn = s.nc_near[i], nt = s.nc_all[i];
+    for (int k = sub; k < nt; k += kCtG) {
+      const int j = all_entry(s, i, k, nn);
+      const double Wj = a.W_s[j];
+      if (Wi == 0.0 && Wj == 0.0) continue;
+      MP<double> Mj;
+      double xj[3], R[3];
+      rec_mp(s, j, Mj, xj);
+      sep(s, xi, xj, R);
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double c[6];
+      if (s.periodic) ewald_coeffs<double, 5>(r, rinv, rinv2, s.beta, c);
+      else bare_coeffs<double, 5>(rinv, rinv2, c);
+      double u, f[3];
+      if (Wi != 0.0) {
+        mp_pair<double, false, true>(c, Qi, Mj, R, u, f);
+        F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+      }
+      if (Wj != 0.0) {
+        MP<double> Qj{};
+        Qj.q = Wj;
+        mp_pair<double, false, true>(c, Mi, Qj, R, u, f);
+        F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+      }
+    }
+    for (int k = sub; k < s.nc_in[i]; k += kCtG) {
+      const int j = s.nb_in[(size_t)i * s.cap_in + k];
+      const double Wj = a.W_s[j], Uj = a.U_s[j];
+      const bool wpair = s.periodic && (Wi != 0.0 || Wj != 0.0);
+      if (!wpair && Ui == 0.0 && Uj == 0.0) continue;
+      MP<double> Mj;
+      double xj[3], R[3];
+      rec_mp(s, j, Mj, xj);
+      sep(s, xi, xj, R);
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double c0[6];
+      bare_coeffs<double, 5>(rinv, rinv2, c0);
+      double u, f[3];
+      // own molecule, bare: the u charges of V_int
+      MP<double> A{}, B{};
+      A.q = Ui;
+      B.q = Uj;
+      if (Ui != 0.0) {
+        mp_pair<double, false, true>(c0, A, Mj, R, u, f);
+        F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+      }
+      if (Uj != 0.0) {
+        mp_pair<double, false, true>(c0, Mi, B, R, u, f);
+        F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+      }
+      if (wpair) {
+        // own molecule, periodic: remove the part of the reciprocal sum
+        // that V_l excludes (coefficients B - c0)
+        double Bc[6], c[6];
+        ewald_coeffs<double, 5>(r, rinv, rinv2, s.beta, Bc);
+#pragma unroll
+        for (int n = 0; n < 6; ++n) c[n] = Bc[n] - c0[n];
+        MP<double> Qi2{}, Qj2{};
+        Qi2.q = Wi;
+        Qj2.q = Wj;
+        if (Wi != 0.0) {
+          mp_pair<double, false, true>(c, Qi2, Mj, R, u, f);
+          F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+        }
+        if (Wj != 0.0) {
+          mp_pair<double, false, true>(c, Mi, Qj2, R, u, f);
+          F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) F[q] = group_sum<kCtG>(F[q]);
+  if (sub == 0 && i < s.n) {
+    const double4 d = a.F_s[i];
+    const double sc = 1.0 / kCoulomb;
+    a.F_s[i] = make_double4((d.x + F[0]) * sc, (d.y + F[1]) * sc, (d.z + F[2]) * sc, 0.0);
+  }
+}
+
+// The w charges (divided by the Coulomb constant) as the only amplitude of
+// an alternative record set for the spreading kernel.
+__global__ __launch_bounds__(kBlock) void k_ct_wrecords(SysView s, CtArgs a, double4* sp_w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const double4 p = s.sp[i];
+  sp_w[i] = make_double4(p.x, p.y, p.z, a.W_s[i] * (1.0 / kCoulomb));
+}
+
+void launch_ct_potentials(const SysView& s, const CtArgs& a, hipStream_t st) {
+  const dim3 b(kBlock);
+  if (a.n_lp > 0)
+    hipLaunchKernelGGL(k_ct_vlp, dim3((a.n_lp + kBlock / kCtG - 1) / (kBlock / kCtG)), b, 0, st,
+                       s, a);
+  if (a.n_vint > 0)
+    hipLaunchKernelGGL(k_ct_vint, dim3((a.n_vint + kBlock - 1) / kBlock), b, 0, st, s, a);
+}
+
+void launch_ct_gather_pot(const SysView& s, const PmeView& pm, const CtArgs& a, hipStream_t st) {
+  if (a.n_lp <= 0) return;
+  const dim3 g((a.n_lp + kBlock - 1) / kBlock), b(kBlock);
+  switch (pm.order) {
+    case 4: hipLaunchKernelGGL(k_ct_gather_pot<4>, g, b, 0, st, s, pm, a); break;
+    case 6: hipLaunchKernelGGL(k_ct_gather_pot<6>, g, b, 0, st, s, pm, a); break;
+    default: hipLaunchKernelGGL(k_ct_gather_pot<5>, g, b, 0, st, s, pm, a); break;
+  }
+}
+
+void launch_ct_pairs(const SysView& s, const CtArgs& a, Reduce& red, hipStream_t st) {
+  const dim3 b(kBlock);
+  const dim3 gl((std::max(a.n_lp, 1) + kBlock / kCtG - 1) / (kBlock / kCtG));
+  hipLaunchKernelGGL(k_ct_pairs_lp, gl, b, 0, st, s, a, red);
+  red.nparts[S_ECT] = (int)gl.x;
+  if (a.n_acc > 0)
+    hipLaunchKernelGGL(k_ct_pairs_acc, dim3((a.n_acc + kBlock / kCtG - 1) / (kBlock / kCtG)), b, 0,
+                       st, s, a);
+  hipLaunchKernelGGL(k_ct_collect, dim3((a.n + kBlock - 1) / kBlock), b, 0, st, a);
+}
+
+void launch_ct_wforce(const SysView& s, const CtArgs& a, double4* sp_w, hipStream_t st) {
+  const dim3 b(kBlock);
+  hipLaunchKernelGGL(k_ct_wforce, dim3((s.n + kBlock / kCtG - 1) / (kBlock / kCtG)), b, 0, st, s,
+                     a);
+  if (sp_w) hipLaunchKernelGGL(k_ct_wrecords, dim3((s.n + kBlock - 1) / kBlock), b, 0, st, s, a, sp_w);
+}
+
+}  // namespace sibfa

@@ -181,6 +181,45 @@ void launch_md_vsites(const MdArgs& m, hipStream_t st);
 void launch_md_finish(const MdArgs& m, Reduce& red, double dt, double friction,
                       hipStream_t st);
 
+// ct.hip: reduced charge transfer (caller-order inputs; sorted-order
+// outputs W_s, U_s, F_s).
+struct CtArgs {
+  int n, n_lp, n_acc, n_vint;
+  const int* lp;          // [n_lp][2] lone-pair site, carrier atom
+  const double* lp_par;   // [n_lp][2] occupation, ionization energy (kcal/mol)
+  const int* acc;         // [n_acc][2] a1 (the H), a2 (the heavy atom)
+  const double* ah;       // [n_acc] affinity (kcal/mol)
+  const double* rvdw;     // [n] van der Waals radii (A)
+  double eta, cs, cp, t, m;
+  const int* a1_start;    // [n + 1] acceptors whose a1 is the site (a1_ref)
+  const int* a1_ref;
+  const int* car_start;   // [n + 1] lone pairs the site carries (car_ref)
+  const int* car_ref;
+  const int* lp_of;       // [n] lone pair at the site, or -1
+  const int* at_start;    // [n + 1] 2 k + slot of the acceptors the site is in
+  const int* at_ref;
+  const int* vint_sites;  // [n_vint] distinct acceptor atoms
+  const int* perm;        // sorted -> caller
+  const int* inv_perm;    // caller -> sorted
+  double* Vlp;            // [n_lp] V_l (e/A)
+  double* Gr;             // [n_lp][3] reciprocal grad V_l
+  double* Vint;           // [n] V_int at acceptor atoms (e/A)
+  double* w;              // [n_lp] dE/dV_l
+  double* Fl;             // [n_lp][3] direct force on the lone pair
+  double* Fc;             // [n_lp][3] direct force on its carrier
+  double* Fa;             // [n_acc][2][3] direct forces on a1, a2
+  double* ua;             // [n_acc][2] dE/dV_int(a1), dE/dV_int(a2)
+  double* W_s;            // [n] sorted: w at lone-pair sites
+  double* U_s;            // [n] sorted: u at acceptor atoms
+  double4* F_s;           // [n] sorted: forces (kcal/mol/A, then / Coulomb)
+};
+void launch_ct_potentials(const SysView& s, const CtArgs& a, hipStream_t st);
+void launch_ct_gather_pot(const SysView& s, const PmeView& pm, const CtArgs& a, hipStream_t st);
+// energy partials into S_ECT
+void launch_ct_pairs(const SysView& s, const CtArgs& a, Reduce& red, hipStream_t st);
+// sp_w (may be NULL): records with the w charges for the reciprocal spread
+void launch_ct_wforce(const SysView& s, const CtArgs& a, double4* sp_w, hipStream_t st);
+
 // global d, Theta (and alpha when aloc is set) from the local ones
 void launch_rotate(const FrameArgs& f, hipStream_t st);
 // forces of the rotation added to forces (caller order); virial: also the

@@ -22,22 +22,6 @@ __device__ __forceinline__ double grid_phi<double>(const PmeView& pm, size_t idx
 template <>
 __device__ __forceinline__ float grid_phi<float>(const PmeView& pm, size_t idx) { return pm.phi32[idx]; }
 
-template <typename R, int P, int ND>
-__device__ __forceinline__ void site_splines(const PmeView& pm, double x, double y, double z,
-                                             int base[3], R th[3][ND + 1][P]) {
-  const double xs[3] = {x, y, z};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double u = xs[a] * pm.scale[a];
-    const double fl = floor(u);
-    int k = (int)fl;
-    if (k >= pm.K[a]) k -= pm.K[a];
-    if (k < 0) k += pm.K[a];
-    base[a] = k;
-    bspline_weights<R, P, ND>((R)(u - fl), th[a]);
-  }
-}
-
 // ------------------------------------------------------------ spreading
 // Sites are binned by home brick, the brick of B^3 grid points (B <= 8, per
 // axis; the last brick along an axis never has fewer than p - 1 points)

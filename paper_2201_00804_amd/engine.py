@@ -236,6 +236,30 @@ class Engine:
         dipole sets (0 or 1: the last set)."""
         self._check(self.lib.sibfa_set_predictor(self.h, int(order)))
 
+    # -- reduced charge transfer ------------------------------------------
+    def set_charge_transfer(self, lp, lp_par, acc, acc_ah, rvdw, eta, cs, cp, t, m):
+        """lp [n_lp][2] (lone-pair site, carrier), lp_par [n_lp][2]
+        (occupation, ionization energy), acc [n_acc][2] (a1 = H, a2),
+        acc_ah [n_acc], rvdw [n]: device tensors; the constants as floats."""
+        nl = lp.shape[0]
+        na = acc.shape[0]
+        _dev(lp, torch.int32, (nl, 2), self.device, "lp")
+        _dev(lp_par, torch.float64, (nl, 2), self.device, "lp_par")
+        _dev(acc, torch.int32, (na, 2), self.device, "acc")
+        _dev(acc_ah, torch.float64, (na,), self.device, "acc_ah")
+        _dev(rvdw, torch.float64, (self.n,), self.device, "rvdw")
+        prm = _lib.CtParams(float(eta), float(cs), float(cp), float(t), float(m))
+        self._check(self.lib.sibfa_set_charge_transfer(self.h, nl, _ptr(lp), _ptr(lp_par), na,
+                                                       _ptr(acc), _ptr(acc_ah), _ptr(rvdw),
+                                                       ctypes.byref(prm)))
+
+    def ct_energy_forces(self, forces=True):
+        """(E_ct kcal/mol, forces [n][3] or None)."""
+        e = ctypes.c_double(0.0)
+        f = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if forces else None
+        self._check(self.lib.sibfa_ct_energy_forces(self.h, ctypes.byref(e), _ptr(f)))
+        return e.value, f
+
     # -- dynamics (Beeman) ------------------------------------------------
     def md_init(self, masses, vsites=None, bonds=None, bond_k=None, bond_r0=None,
                 rep_radius=None, rep_eps=0.0, vel=None):

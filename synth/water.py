@@ -277,3 +277,67 @@ def water_md(sysd, seed_index=0, temperature=300.0, k_oh=500.0, k_hh=150.0, rho_
     rho[base + 4] = rho_b
     return dict(masses=masses, vsites=vsites, bonds=bonds, bond_k=k, bond_r0=r0, vel=vel,
                 rep_radius=rho, rep_eps=float(rep_eps))
+
+
+CT_SITES = 7   # O, H1, H2, B1, B2, L1, L2
+
+
+def water_lone_pairs(sysd, length=0.5, half_angle_deg=54.74):
+    """The system with two lone-pair sites appended to every water (order O,
+    H1, H2, B1, B2, L1, L2): at the oxygen plus `length` A along
+    -cos(h) e_z +- sin(h) e_y, e_z the H-O-H bisector (towards the H), e_y
+    the normal of the molecular plane.  Lone pairs carry no multipoles and
+    no polarizability."""
+    pos = np.asarray(sysd["pos"], float)
+    nw = len(pos) // WATER_SITES
+    w = pos.reshape(nw, WATER_SITES, 3)
+    o, h1, h2 = w[:, 0], w[:, 1], w[:, 2]
+    u = (h1 - o) / np.linalg.norm(h1 - o, axis=1, keepdims=True)
+    v = (h2 - o) / np.linalg.norm(h2 - o, axis=1, keepdims=True)
+    ez = (u + v) / np.linalg.norm(u + v, axis=1, keepdims=True)
+    ey = np.cross(u, v)
+    ey /= np.linalg.norm(ey, axis=1, keepdims=True)
+    h = math.radians(half_angle_deg)
+    l1 = o + length * (-math.cos(h) * ez + math.sin(h) * ey)
+    l2 = o + length * (-math.cos(h) * ez - math.sin(h) * ey)
+    out = {}
+    new_pos = np.concatenate([w, l1[:, None], l2[:, None]], axis=1).reshape(-1, 3)
+    out["pos"] = new_pos
+    out["mol"] = np.repeat(np.arange(nw, dtype=np.int32), CT_SITES)
+
+    def widen(a, width):
+        a = np.asarray(a, float).reshape(nw, WATER_SITES, *((width,) if width else ()))
+        z = np.zeros((nw, 2) + ((width,) if width else ()))
+        return np.concatenate([a, z], axis=1).reshape((nw * CT_SITES,) +
+                                                      ((width,) if width else ()))
+
+    out["q"] = widen(sysd["q"], 0)
+    out["dip"] = widen(sysd["dip"], 3)
+    out["quad"] = widen(sysd["quad"], 6)
+    out["alpha"] = widen(sysd["alpha"], 6)
+    out["box"] = sysd.get("box")
+    return out
+
+
+def water_ct(sysd7, n_occ=2.0, ae=250.0, ah=20.0, rvdw_o=1.7, rvdw_h=1.2, eta=3.0, cs=0.5,
+             cp=0.87, t=0.4, m=0.3):
+    """Charge-transfer inputs for a system from water_lone_pairs: each lone
+    pair (L1, L2) carried by its oxygen with occupation n_occ and ionization
+    energy ae (kcal/mol); each O-H bond an acceptor (a1 = H, a2 = O) with
+    affinity ah (kcal/mol); van der Waals radii (O, H; 1 A elsewhere); the
+    constants eta, C_s, C_p, t, m.  All values are synthetic: the paper's
+    parameters are not available."""
+    n = len(sysd7["pos"])
+    nw = n // CT_SITES
+    base = np.arange(nw) * CT_SITES
+    lp = np.concatenate([np.stack([base + 5, base], 1), np.stack([base + 6, base], 1)])
+    lp = lp[np.argsort(lp[:, 0], kind="stable")].astype(np.int32)
+    acc = np.concatenate([np.stack([base + 1, base], 1), np.stack([base + 2, base], 1)])
+    acc = acc[np.argsort(acc[:, 0], kind="stable")].astype(np.int32)
+    rvdw = np.ones(n)
+    rvdw[base] = rvdw_o
+    rvdw[base + 1] = rvdw_h
+    rvdw[base + 2] = rvdw_h
+    lp_par = np.tile([n_occ, ae], (len(lp), 1))
+    return dict(lp=lp, lp_par=lp_par, acc=acc, ah=np.full(len(acc), float(ah)), rvdw=rvdw,
+                eta=eta, cs=cs, cp=cp, t=t, m=m)
