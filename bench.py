@@ -153,8 +153,9 @@ def run_gpu(sysd, prm, precision, steps, warmup):
 
 def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
     """Fixed-cost truncated CG (with the peek step) against the converged
-    solve, both without forces (TCG forces are not provided): ms per
-    evaluation (positions update, lists, field, solve, E_pol) and E_pol."""
+    solve, both without forces: ms per evaluation (positions update, lists,
+    field, solve, E_pol) and E_pol; in FP64 also TCG energies with their
+    forces (the derivative of the truncated iteration)."""
     import torch
     from paper_2201_00804_amd import Engine, default_params
 
@@ -174,7 +175,15 @@ def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
         eng.update_positions(pos)
         return eng.solve_tcg(n, omega, mu_out=False)[1]
 
+    def tcg_forces(n):
+        eng.update_positions(pos)
+        ep, ee, _f, _m = eng.tcg_energy_forces(n, omega)
+        return ep
+
     variants = [("pcg", pcg)] + [(f"tcg{n}_peek", (lambda n=n: tcg(n))) for n in orders]
+    if precision == "fp64":
+        # energies and forces at TCG dipoles (always FP64)
+        variants += [(f"tcg{n}_peek_forces", (lambda n=n: tcg_forces(n))) for n in orders]
     out = {}
     for name, fn in variants:
         for _ in range(warmup):

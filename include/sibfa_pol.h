@@ -223,6 +223,21 @@ sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
 sibfa_status sibfa_solve_tcg(sibfa_ctx ctx, int order, double omega, int warm_start,
                              double* mu_out, double* e_pol);
 
+/* TCG-n energies and forces (Many-Body Polarization names the truncated
+ * solver; its analytic derivative is given in the work it cites, not in
+ * the paper): the dipoles of sibfa_solve_tcg (same order, omega and guess;
+ * a warm guess counts as fixed), E_pol = -1/2 mu.E at them and E_elec
+ * (HOST, kcal/mol), and the forces of E_elec + E_pol [n][3] (device,
+ * kcal/mol/A, or NULL), which include the derivative of every step of the
+ * truncated iteration (at TCG dipoles the fixed-dipole identity of
+ * sibfa_energy_forces does not hold).  Always FP64.  The reverse pass
+ * through the iteration costs n + 1 matvecs and the forces 2n + 4 force
+ * evaluations; every step reads a dot product back to the host.  mu_out
+ * [n][3] (device) or NULL.  Errors as sibfa_solve_tcg. */
+sibfa_status sibfa_tcg_energy_forces(sibfa_ctx ctx, int order, double omega, int warm_start,
+                                     double* e_pol, double* e_elec, double* forces,
+                                     double* mu_out);
+
 /* Energies (HOST, kcal/mol) and forces [n][3] (device, kcal/mol/A, or
  * NULL) at the current dipoles; solves first if they are stale.
  * virial [9] (HOST, kcal/mol, row-major) or NULL: W_ab = -dE/d eps_ab,

@@ -367,6 +367,18 @@ def tcg(sysm, prm, E0, order, omega=0.0, ctx=None, x0=None):
     return mu, -0.5 * COULOMB * float(np.sum(mu * E0))
 
 
+def tcg_energy(sysm, prm, order, omega=0.0, x0=None):
+    """E_elec + E_pol at the TCG-n dipoles (kcal/mol), the guess x0 (the
+    polarizable rows) held fixed, or the direct field alpha E0 of this
+    geometry.  Its derivatives, taken by central differences in the tests,
+    are the oracle's TCG forces (the analytic TCG derivative is given only
+    in the work the paper cites)."""
+    c = Context(sysm, prm)
+    E0 = permanent_field(sysm, prm, ctx=c)
+    _, e_pol = tcg(sysm, prm, E0, order, omega, ctx=c, x0=x0)
+    return electrostatic_energy(sysm, prm, ctx=c) + e_pol
+
+
 def evaluate(sysm, prm, forces=True, with_virial=False):
     """Full evaluation: E0 -> PCG -> energies -> forces (fixed mu), and the
     virial when asked."""

@@ -70,6 +70,8 @@ SIGNATURES = [
     ("sibfa_set_polarizabilities", ctypes.c_int, [_P, _P, _P]),
     ("sibfa_set_local_frames", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sibfa_set_predictor", ctypes.c_int, [_P, ctypes.c_int]),
+    ("sibfa_tcg_energy_forces", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                               _P, _P, _P, _P]),
     ("sibfa_set_charge_transfer", ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P,
                                                  _P, _P]),
     ("sibfa_ct_energy_forces", ctypes.c_int, [_P, _P, _P]),

@@ -154,6 +154,10 @@ struct sibfa_ctx_s {
   std::vector<DevBuf> mdbufs;
   MdArgs md{};
   double* md_force = nullptr;
+  // truncated-CG forces: work vectors (tcgbufs, sized for the last order)
+  std::vector<DevBuf> tcgbufs;
+  int tcg_cap = -1;
+  size_t tcg_np = 0;
   // reduced charge transfer: inputs, lookup tables and work buffers
   // (ctbufs, replaced by every sibfa_set_charge_transfer)
   bool ct_on = false;
@@ -378,6 +382,8 @@ void release_system(sibfa_ctx c) {
   c->md_on = false;
   free_list(c, c->ctbufs);
   c->ct_on = false;
+  free_list(c, c->tcgbufs);
+  c->tcg_cap = -1;
   c->hist = nullptr;       // lived in bufs
   c->hist_head = c->hist_count = 0;
   free_list(c, c->framebufs);
@@ -1172,6 +1178,219 @@ sibfa_status solve_tcg(sibfa_ctx c, int order, double omega, bool warm, double* 
   return SIBFA_OK;
 }
 
+// Forces (caller order, kcal/mol/A) of the combined density of the records
+// in sv and the dipoles v (polarizable order), FP64: the force kernels and,
+// periodic, the PME force pass, all on the main stream.
+void force_eval(sibfa_ctx c, const SysView& sv, const double4* v, double* out) {
+  hipStream_t sm = c->stream;
+  launch_mu_sites(sv, v, c->mu_s, c->mu_s32, sm);
+  if (c->periodic) {
+    launch_spread_mult(sv, c->pm, c->mu_s, false, sm);
+    conv(c, false, sm, S_CTREC);
+  }
+  launch_force(sv, c->red, c->mu_s, c->mu_s32, c->Freal, false, false, sm);
+  if (c->periodic)
+    launch_gather_force(sv, c->pm, c->red, c->mu_s, c->Freal, c->perm, out, false, false, sm);
+  else
+    launch_forces_out(c->n, c->perm, c->Freal, out, sm);
+}
+
+double dot_now(sibfa_ctx c, const SysView& s, const double4* a, const double4* b,
+               sibfa_status* st) {
+  launch_dot(s, c->red, a, b, S_TCGD, c->stream);
+  double v = 0.0;
+  const sibfa_status r = read_totals(c, {S_TCGD}, &v);
+  if (r != SIBFA_OK) *st = r;
+  return v;
+}
+
+// TCG-n energy and forces (FP64).  The forward pass is the iteration of
+// solve_tcg with every vector kept; the reverse pass propagates
+// dE/d(everything) back through it, which leaves
+//   dE = Ebar . dE0 + sum_k abar_k . dT b_k
+// over the (n + 1) products T b_k of the forward pass.  The forces are then
+//   F = F(M, -Ebar) - F(0, Ebar) + 1/2 sum_k [F(0, abar_k + b_k) - F(0, abar_k - b_k)],
+// F(M, v) the force of the combined density (records M, dipoles v) and
+// F(0, v) that of the dipoles alone: F(M, v) = F_MM + F_Mmu(v) + F_mumu(v),
+// F_Mmu linear and F_mumu quadratic in v, and the bilinear T terms follow
+// from the polarization identity.
+sibfa_status tcg_forces(sibfa_ctx c, int n, double omega, bool warm, double* e_pol,
+                        double* e_elec, double* forces, double* mu_out) {
+  SysView s = make_view(c);
+  hipStream_t st = c->stream;
+  const size_t np = std::max(c->npol, 1);
+  const size_t nn = c->n;
+  // work vectors: X, R, Z [n + 1], P, Q, QB [n], then t, MU, EB, XB, RB, ZB,
+  // PB, PBn, QBc, TB, tmp; records without multipoles; force scratch
+  const int nvec = 3 * (n + 1) + 3 * n + 12;
+  if (c->tcg_cap < n || c->tcg_np < np) {
+    free_list(c, c->tcgbufs);
+    c->tcg_cap = -1;
+    double4* base = nullptr;
+    double4 *sp0, *sd0, *sth0;
+    double2* sth20;
+    double *f1, *f2;
+    if (!alloc_into(c, c->tcgbufs, base, (size_t)nvec * np) ||
+        !alloc_into(c, c->tcgbufs, sp0, nn) || !alloc_into(c, c->tcgbufs, sd0, nn) ||
+        !alloc_into(c, c->tcgbufs, sth0, nn) || !alloc_into(c, c->tcgbufs, sth20, nn) ||
+        !alloc_into(c, c->tcgbufs, f1, 3 * nn) || !alloc_into(c, c->tcgbufs, f2, 3 * nn)) {
+      free_list(c, c->tcgbufs);
+      return fail(c, SIBFA_E_NOMEM, "truncated-CG force buffers");
+    }
+    c->tcg_cap = n;
+    c->tcg_np = np;
+  }
+  double4* base = static_cast<double4*>(c->tcgbufs[0].p);
+  double4* sp0 = static_cast<double4*>(c->tcgbufs[1].p);
+  double4* sd0 = static_cast<double4*>(c->tcgbufs[2].p);
+  double4* sth0 = static_cast<double4*>(c->tcgbufs[3].p);
+  double2* sth20 = static_cast<double2*>(c->tcgbufs[4].p);
+  double* f1 = static_cast<double*>(c->tcgbufs[5].p);
+  double* f2 = static_cast<double*>(c->tcgbufs[6].p);
+  auto vec = [&](int k) { return base + (size_t)k * np; };
+  double4** X = new double4*[n + 1];
+  double4** R = new double4*[n + 1];
+  double4** Z = new double4*[n + 1];
+  double4** P = new double4*[std::max(n, 1)];
+  double4** Q = new double4*[std::max(n, 1)];
+  double4** QBk = new double4*[std::max(n, 1)];
+  int at = 0;
+  for (int k = 0; k <= n; ++k) { X[k] = vec(at++); R[k] = vec(at++); Z[k] = vec(at++); }
+  for (int k = 0; k < n; ++k) { P[k] = vec(at++); Q[k] = vec(at++); QBk[k] = vec(at++); }
+  double4 *T0 = vec(at++), *MU = vec(at++), *EB = vec(at++), *XB = vec(at++), *RB = vec(at++),
+          *ZB = vec(at++), *PB = vec(at++), *PBn = vec(at++), *QB = vec(at++), *TB = vec(at++),
+          *TMP = vec(at++), *TMP2 = vec(at++);
+  std::vector<double> rho(n + 1), sig(n), gam(n), bet(n), rhob(n + 1, 0.0);
+  sibfa_status err = SIBFA_OK;
+  float4* v32 = c->p32;
+  auto Tv = [&](double4* v, double4* out) {
+    launch_copy4(v, v, v32, c->npol, st);
+    matvec(c, v, v32, out, -1, false);
+  };
+  ensure_coef(c);
+  // ---- forward
+  if (warm) {
+    warm_guess(c, s, st);
+    launch_copy4(c->x, X[0], nullptr, c->npol, st);
+  } else {
+    launch_precond(s, c->E0, X[0], st);
+  }
+  Tv(X[0], T0);
+  launch_lincomb4(s, R[0], 1.0, c->E0, -1.0, T0, st);
+  launch_precond(s, R[0], Z[0], st);
+  rho[0] = dot_now(c, s, R[0], Z[0], &err);
+  for (int k = 0; k < n; ++k) {
+    if (k == 0) launch_copy4(Z[0], P[0], nullptr, c->npol, st);
+    Tv(P[k], Q[k]);
+    sig[k] = dot_now(c, s, P[k], Q[k], &err);
+    if (!(sig[k] > 0.0) && rho[k] != 0.0) {
+      err = fail(c, SIBFA_E_NOT_SPD, "p.Tp <= 0: the polarization matrix is not positive definite");
+      break;
+    }
+    // a zero residual (the iterate is exact) stays put: gamma = 0
+    gam[k] = sig[k] > 0.0 ? rho[k] / sig[k] : 0.0;
+    launch_lincomb4(s, X[k + 1], 1.0, X[k], gam[k], P[k], st);
+    launch_lincomb4(s, R[k + 1], 1.0, R[k], -gam[k], Q[k], st);
+    launch_precond(s, R[k + 1], Z[k + 1], st);
+    rho[k + 1] = dot_now(c, s, R[k + 1], Z[k + 1], &err);
+    if (k < n - 1) {
+      bet[k] = rho[k] != 0.0 ? rho[k + 1] / rho[k] : 0.0;
+      launch_lincomb4(s, P[k + 1], 1.0, Z[k + 1], bet[k], P[k], st);
+    }
+  }
+  if (err != SIBFA_OK) {
+    delete[] X; delete[] R; delete[] Z; delete[] P; delete[] Q; delete[] QBk;
+    return err;
+  }
+  launch_lincomb4(s, MU, 1.0, X[n], omega, Z[n], st);
+  const double mue = dot_now(c, s, MU, c->E0, &err);
+  // ---- reverse, seeded with d(-1/2 mu.E0) (no Coulomb factor: the force
+  // evaluations below apply it)
+  const double hf = -0.5;
+  launch_lincomb4(s, EB, hf, MU, 0.0, nullptr, st);            // from E0 in -1/2 f mu.E0
+  launch_lincomb4(s, XB, hf, c->E0, 0.0, nullptr, st);         // mubar -> xbar_n
+  launch_lincomb4(s, ZB, omega * hf, c->E0, 0.0, nullptr, st); // zbar_n
+  launch_lincomb4(s, RB, 0.0, c->E0, 0.0, nullptr, st);        // rbar_n = 0
+  for (int k = n - 1; k >= 0; --k) {
+    launch_lincomb4(s, PB, 0.0, c->E0, 0.0, nullptr, st);      // pbar_k = 0
+    if (k < n - 1) {
+      launch_lincomb4(s, ZB, 1.0, ZB, 1.0, PBn, st);
+      const double betab = dot_now(c, s, PBn, P[k], &err);
+      launch_lincomb4(s, PB, 1.0, PB, bet[k], PBn, st);
+      if (rho[k] != 0.0) {
+        rhob[k + 1] += betab / rho[k];
+        rhob[k] -= betab * rho[k + 1] / (rho[k] * rho[k]);
+      }
+    }
+    launch_lincomb4(s, RB, 1.0, RB, rhob[k + 1], Z[k + 1], st);
+    launch_lincomb4(s, ZB, 1.0, ZB, rhob[k + 1], R[k + 1], st);
+    launch_precond(s, ZB, TMP, st);
+    launch_lincomb4(s, RB, 1.0, RB, 1.0, TMP, st);
+    double gammab = -dot_now(c, s, RB, Q[k], &err);
+    launch_lincomb4(s, QB, -gam[k], RB, 0.0, nullptr, st);
+    gammab += dot_now(c, s, XB, P[k], &err);
+    launch_lincomb4(s, PB, 1.0, PB, gam[k], XB, st);
+    double sigb = 0.0;
+    if (sig[k] > 0.0) {
+      rhob[k] += gammab / sig[k];
+      sigb = -gammab * rho[k] / (sig[k] * sig[k]);
+    }
+    launch_lincomb4(s, PB, 1.0, PB, sigb, Q[k], st);
+    launch_lincomb4(s, QB, 1.0, QB, sigb, P[k], st);
+    launch_copy4(QB, QBk[k], nullptr, c->npol, st);
+    Tv(QB, TMP);
+    launch_lincomb4(s, PB, 1.0, PB, 1.0, TMP, st);
+    // level k: rbar_k continues from RB, zbar_k starts at zero
+    launch_lincomb4(s, ZB, 0.0, ZB, 0.0, nullptr, st);
+    launch_copy4(PB, PBn, nullptr, c->npol, st);
+  }
+  // initial steps: p0 = z0, rho0 = r0.z0, z0 = alpha r0, r0 = E0 - T x0
+  launch_lincomb4(s, ZB, 1.0, ZB, 1.0, PBn, st);
+  launch_lincomb4(s, RB, 1.0, RB, rhob[0], Z[0], st);
+  launch_lincomb4(s, ZB, 1.0, ZB, rhob[0], R[0], st);
+  launch_precond(s, ZB, TMP, st);
+  launch_lincomb4(s, RB, 1.0, RB, 1.0, TMP, st);
+  launch_lincomb4(s, EB, 1.0, EB, 1.0, RB, st);
+  launch_lincomb4(s, TB, -1.0, RB, 0.0, nullptr, st);
+  Tv(TB, TMP);
+  launch_lincomb4(s, XB, 1.0, XB, 1.0, TMP, st);
+  if (!warm) {   // x0 = alpha E0
+    launch_precond(s, XB, TMP, st);
+    launch_lincomb4(s, EB, 1.0, EB, 1.0, TMP, st);
+  }
+  // ---- forces
+  if (forces) {
+    launch_zero_records(s, sp0, sd0, sth0, sth20, st);
+    SysView s0 = s;
+    s0.sp = sp0; s0.sd = sd0; s0.sth = sth0; s0.sth2 = sth20;
+    launch_lincomb4(s, TMP, -1.0, EB, 0.0, nullptr, st);
+    force_eval(c, s, TMP, forces);                         // F(M, -Ebar)
+    force_eval(c, s0, EB, f1);                             // F(0, Ebar)
+    launch_axpy_d(3 * nn, -1.0, f1, forces, st);
+    // pairs (QB_k, P_k) and (TB, X0)
+    for (int k = 0; k <= n; ++k) {
+      const double4* a = k < n ? QBk[k] : TB;
+      const double4* b = k < n ? P[k] : X[0];
+      launch_lincomb4(s, TMP, 1.0, a, 1.0, b, st);
+      launch_lincomb4(s, TMP2, 1.0, a, -1.0, b, st);
+      force_eval(c, s0, TMP, f1);
+      force_eval(c, s0, TMP2, f2);
+      launch_axpy_d(3 * nn, 0.5, f1, forces, st);
+      launch_axpy_d(3 * nn, -0.5, f2, forces, st);
+    }
+  }
+  if (mu_out) launch_pol_to_caller(s, c->perm, MU, mu_out, st);
+  delete[] X; delete[] R; delete[] Z; delete[] P; delete[] Q; delete[] QBk;
+  if (err != SIBFA_OK) return err;
+  double tot[4] = {0, 0, 0, 0};
+  sibfa_status r = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC0}, tot)
+                               : read_totals(c, {S_EREAL, S_AUX}, tot);
+  if (r != SIBFA_OK) return r;
+  if (e_pol) *e_pol = -0.5 * kCoulomb * mue;
+  if (e_elec) *e_elec = kCoulomb * (tot[0] + tot[1] + tot[2] + tot[3]);
+  return SIBFA_OK;
+}
+
 // Spreading brick edge along an axis of K points: the largest size <=
 // kBrick whose last (partial) brick still spans order - 1 points, so that
 // every grid point lies in the tiles of at most two bricks per axis; 0 if
@@ -1745,6 +1964,37 @@ sibfa_status sibfa_solve_tcg(sibfa_ctx c, int order, double omega, int warm_star
     return fail(c, SIBFA_E_STATE, "warm start without dipoles (solve or set_dipoles first)");
   if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
   return solve_tcg(c, order, omega, warm_start != 0, mu_out, e_pol);
+}
+
+sibfa_status sibfa_tcg_energy_forces(sibfa_ctx c, int order, double omega, int warm_start,
+                                     double* e_pol, double* e_elec, double* forces,
+                                     double* mu_out) {
+  if (!c) return SIBFA_E_ARG;
+  if (order < 1 || order > SIBFA_TCG_MAX_ORDER)
+    return fail(c, SIBFA_E_ARG, "order must lie in 1.." + std::to_string(SIBFA_TCG_MAX_ORDER));
+  if (!std::isfinite(omega)) return fail(c, SIBFA_E_ARG, "omega must be finite");
+  HIP_TRY(hipSetDevice(c->device));
+  sibfa_status st = prepare(c);
+  if (st != SIBFA_OK) return st;
+  if (warm_start && !c->mu_have)
+    return fail(c, SIBFA_E_STATE, "warm start without dipoles (solve or set_dipoles first)");
+  if (!c->e0_valid && (st = compute_E0(c)) != SIBFA_OK) return st;
+  join(c);
+  // a warm start writes the guess into the solver vectors: the next energy
+  // call solves again (warm from the kept dipoles)
+  c->mu_valid = false;
+  if (c->npol == 0) {
+    if (forces) force_eval(c, make_view(c), c->x, forces);
+    if (mu_out) launch_fill_double(mu_out, 0.0, 3 * (size_t)c->n, c->stream);
+    double tot[4] = {0, 0, 0, 0};
+    st = c->periodic ? read_totals(c, {S_EREAL, S_AUX, S_ESELF, S_EREC0}, tot)
+                     : read_totals(c, {S_EREAL, S_AUX}, tot);
+    if (st != SIBFA_OK) return st;
+    if (e_pol) *e_pol = 0.0;
+    if (e_elec) *e_elec = kCoulomb * (tot[0] + tot[1] + tot[2] + tot[3]);
+    return SIBFA_OK;
+  }
+  return tcg_forces(c, order, omega, warm_start != 0, e_pol, e_elec, forces, mu_out);
 }
 
 // Totals of the virial slots (33 of them, S_VRI .. S_COUNT - 1) in one

@@ -35,6 +35,7 @@ enum Slot {
   S_EREP,        // stand-in repulsion energy (molecular dynamics)
   S_ECT,         // charge-transfer energy
   S_CTREC,       // reciprocal energy of the charge-transfer convolutions (unused)
+  S_TCGD,        // dot products of the truncated-CG force pass
   // virial partials (written only when a virial is asked for), row-major
   // W_ab at slot + 3a + b unless noted
   S_VRI,                 // same-molecule pairs, 9 slots

@@ -107,6 +107,14 @@ void launch_pol_to_caller(const SysView& s, const int* perm, const double4* v, d
                           hipStream_t st);
 void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, double4* v,
                           float4* v32, hipStream_t st);
+// out = a x + b y (polarizable order; y may be NULL)
+void launch_lincomb4(const SysView& s, double4* out, double a, const double4* x, double b,
+                     const double4* y, hipStream_t st);
+// y += a x over count doubles
+void launch_axpy_d(size_t count, double a, const double* x, double* y, hipStream_t st);
+// sorted records without multipoles (positions, Thole widths kept)
+void launch_zero_records(const SysView& s, double4* sp0, double4* sd0, double4* sth0,
+                         double2* sth20, hipStream_t st);
 // Extrapolated initial guess (polarizable order) from k history entries
 // of caller-order dipoles (entry j at hist + slot[j] * stride).
 constexpr int kPredMax = 6;

@@ -209,6 +209,40 @@ __global__ void k_caller_to_pol(SysView s, const int* perm, const double* in, do
   if (v32) v32[pi] = make_float4((float)a.x, (float)a.y, (float)a.z, 0.f);
 }
 
+// out = a x + b y over the polarizable sites (y may be NULL: out = a x).
+__global__ __launch_bounds__(kBlock) void k_lincomb4(SysView s, double4* out, double a,
+                                                     const double4* x, double b,
+                                                     const double4* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.npol) return;
+  const double4 u = x[i];
+  double4 o = make_double4(a * u.x, a * u.y, a * u.z, 0.0);
+  if (y) {
+    const double4 v = y[i];
+    o.x += b * v.x; o.y += b * v.y; o.z += b * v.z;
+  }
+  out[i] = o;
+}
+
+// y += a x over count doubles.
+__global__ __launch_bounds__(kBlock) void k_axpy_d(size_t count, double a, const double* x,
+                                                   double* y) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] += a * x[i];
+}
+
+// Records with the multipoles removed (positions and Thole widths kept).
+__global__ __launch_bounds__(kBlock) void k_zero_records(SysView s, double4* sp0, double4* sd0,
+                                                         double4* sth0, double2* sth20) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const double4 p = s.sp[i];
+  sp0[i] = make_double4(p.x, p.y, p.z, 0.0);
+  sd0[i] = make_double4(0.0, 0.0, 0.0, s.sd[i].w);
+  sth0[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+  sth20[i] = make_double2(0.0, 0.0);
+}
+
 // Extrapolated guess: v = sum_j coef_j h_j over the k newest history
 // entries (caller order, 3 n doubles each).
 __global__ void k_predict(SysView s, const int* perm, const double* hist, size_t stride,
@@ -342,6 +376,20 @@ void launch_caller_to_pol(const SysView& s, const int* perm, const double* in, d
                           float4* v32, hipStream_t st) {
   if (s.npol > 0)
     hipLaunchKernelGGL(k_caller_to_pol, grid_for(s.npol), dim3(kBlock), 0, st, s, perm, in, v, v32);
+}
+void launch_lincomb4(const SysView& s, double4* out, double a, const double4* x, double b,
+                     const double4* y, hipStream_t st) {
+  if (s.npol > 0)
+    hipLaunchKernelGGL(k_lincomb4, grid_for(s.npol), dim3(kBlock), 0, st, s, out, a, x, b, y);
+}
+void launch_axpy_d(size_t count, double a, const double* x, double* y, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_axpy_d, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, count, a, x, y);
+}
+void launch_zero_records(const SysView& s, double4* sp0, double4* sd0, double4* sth0,
+                         double2* sth20, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_records, grid_for(s.n), dim3(kBlock), 0, st, s, sp0, sd0, sth0, sth20);
 }
 void launch_predict(const SysView& s, const int* perm, const double* hist, size_t stride,
                     const PredArgs& pa, double4* v, float4* v32, hipStream_t st) {

@@ -204,6 +204,18 @@ class Engine:
                                              int(bool(warm_start)), _ptr(mu), ctypes.byref(e)))
         return mu, e.value
 
+    def tcg_energy_forces(self, order, omega=0.0, warm_start=False, forces=True, mu_out=False):
+        """(E_pol, E_elec, forces or None, mu or None) at TCG-n dipoles, with
+        the forces of the truncated iteration (FP64)."""
+        e_pol = ctypes.c_double(0.0)
+        e_elec = ctypes.c_double(0.0)
+        f = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if forces else None
+        mu = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if mu_out else None
+        self._check(self.lib.sibfa_tcg_energy_forces(self.h, int(order), float(omega),
+                                                     int(bool(warm_start)), ctypes.byref(e_pol),
+                                                     ctypes.byref(e_elec), _ptr(f), _ptr(mu)))
+        return e_pol.value, e_elec.value, f, mu
+
     def energy_forces(self, forces=True, out=None, virial=False):
         """(E_pol, E_elec, forces or None), plus the 3x3 virial (a host
         list of rows, kcal/mol) as a fourth item when virial is true."""
