@@ -756,10 +756,12 @@ sibfa_status prepare(sibfa_ctx c) {
       // the reciprocal potential of the permanent multipoles needs the
       // brick lists but not the neighbour lists: start it on the auxiliary
       // stream while the lists are built
+      // (FP64 in both modes: it runs beside the list build, and the
+      // reciprocal energy is a large term of E_elec, which is a small sum)
       fork(c);
       Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
-      launch_spread_mult(make_view(c), c->pm, nullptr, mixed(c), c->aux);
-      conv(c, mixed(c), c->aux, S_EREC0);
+      launch_spread_mult(make_view(c), c->pm, nullptr, false, c->aux);
+      conv(c, false, c->aux, S_EREC0);
       c->phi_e0 = true;
     }
     sibfa_status st = build_lists(c);
@@ -832,8 +834,8 @@ sibfa_status compute_E0(sibfa_ctx c) {
     fork(c);
     forked = true;
     Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
-    launch_spread_mult(s, c->pm, nullptr, mix, c->aux);
-    conv(c, mix, c->aux, S_EREC0);
+    launch_spread_mult(s, c->pm, nullptr, false, c->aux);
+    conv(c, false, c->aux, S_EREC0);
   }
   if (!c->coef_valid && c->npol > 0) {
     if (!forked) fork(c);
@@ -848,7 +850,7 @@ sibfa_status compute_E0(sibfa_ctx c) {
   c->phi_e0 = false;
   if (c->periodic) {
     Phase ph(c, SIBFA_PH_FIELD_RECIP);
-    launch_gather_field(s, c->pm, c->E0, mix, c->stream);
+    launch_gather_field(s, c->pm, c->E0, false, c->stream);
   }
   // the energy partials stay in their slots (nothing else writes them)
   // and are read with the polarization energy
