@@ -301,13 +301,15 @@ sibfa_status sibfa_set_predictor(sibfa_ctx ctx, int order);
  * energy ae, kcal/mol), acc [n_acc][2] (device int32: a1, a2 of one
  * molecule), acc_ah [n_acc] (device, kcal/mol), rvdw [n] (device, A,
  * positive at carriers and acceptor atoms), constants (HOST).  Copied and
- * checked once (SIBFA_E_ARG); call after the multipoles and
- * polarizabilities; setting either of them again switches the term off.
- * Synchronizes.
+ * checked once (SIBFA_E_ARG); call after the multipoles, polarizabilities
+ * and local frames (sibfa_set_local_frames); setting any of them again
+ * switches the term off.  With local frames the lone-pair sites carry no
+ * local multipoles or polarizability either.  Synchronizes.
  * sibfa_ct_energy_forces: E_ct (HOST, kcal/mol) and, when forces is not
  * NULL, its forces [n][3] (device, kcal/mol/A, written, not added),
- * including those through the potentials.  Always FP64; independent of the
- * induced dipoles (no solve). */
+ * including those through the potentials and, with local frames, those of
+ * the rotation of the multipoles (E_ct depends on them through V_l and
+ * V_int).  Always FP64; independent of the induced dipoles (no solve). */
 typedef struct {
   double eta, cs, cp, t, m;
 } sibfa_ct_params;

@@ -136,9 +136,9 @@ def _pair_terms(sysm, ct, V, Vint, l, k):
     return E, dV, dVi1, dVi2, g_u, g_c, g_d1, g_d2
 
 
-def energy_forces(sysm, prm, ct, ctx=None):
-    """(E_ct kcal/mol, forces (n, 3) kcal/mol/A)."""
-    c = ctx if ctx is not None else Context(sysm, prm)
+def _charges(sysm, prm, ct, c):
+    """(E_ct, direct forces, W = dE/dV at the lone pairs, U = dE/dV_int at
+    the acceptor atoms), per site."""
     s = c.s
     V, Vint = potentials(s, prm, c)
     lp = np.asarray(ct["lp"], int)
@@ -159,6 +159,15 @@ def energy_forces(sysm, prm, ct, ctx=None):
         F[cr] -= g_c
         F[a1] -= g_d1
         F[a2] -= g_d2
+    return E, F, W, U
+
+
+def energy_forces(sysm, prm, ct, ctx=None):
+    """(E_ct kcal/mol, forces (n, 3) kcal/mol/A), the multipoles fixed in
+    the global frame."""
+    c = ctx if ctx is not None else Context(sysm, prm)
+    s = c.s
+    E, F, W, U = _charges(s, prm, ct, c)
     mult = (s.q, s.dip, s.th)
     wq = (W, None, None)
     uq = (U, None, None)
@@ -173,3 +182,41 @@ def energy_forces(sysm, prm, ct, ctx=None):
         F -= (s.q[:, None] * dw[1] + np.einsum("nb,nab->na", s.dip, dw[2])
               + np.einsum("nbc,nabc->na", s.th, dw[3]) / 3.0)
     return E, F
+
+
+def multipole_gradients(sysm, prm, ct, ctx=None):
+    """(G^d (n,3), G^Theta (n,3,3)): derivatives of E_ct with respect to the
+    global dipoles and quadrupoles.  E_ct depends on the multipoles through
+    V_l and V_int only, so G^d = -(field of the charges W at the lone pairs
+    and U at the acceptor atoms), with the same sums as their potentials
+    (other molecules, Ewald-summed when periodic, for W; own molecule, bare,
+    for U), and G^Theta = -1/3 of the field gradient."""
+    c = ctx if ctx is not None else Context(sysm, prm)
+    s = c.s
+    _, _, W, U = _charges(s, prm, ct, c)
+    none3 = (None, None, None)
+    wq = (W, None, None)
+    uq = (U, None, None)
+    E = rs.pair_sum(c.pairs, "MM", c.kernel, prm.beta, c.thole, none3, wq, "field", s.n)
+    E += rs.pair_sum(c.pairs, "intra", "bare", prm.beta, c.thole, none3, uq, "field", s.n)
+    dE = rs.pair_sum(c.pairs, "MM", c.kernel, prm.beta, c.thole, none3, wq, "fieldgrad", s.n)
+    dE += rs.pair_sum(c.pairs, "intra", "bare", prm.beta, c.thole, none3, uq, "fieldgrad", s.n)
+    Gd = -E
+    GT = -dE / 3.0
+    if prm.periodic:
+        _, der = c.recip_derivs(wq, s.pos, 2)
+        Gd = Gd + der[1]
+        GT = GT + der[2] / 3.0
+    return Gd, GT
+
+
+def energy_forces_frames(sys_local, frames, prm, ct):
+    """(E_ct, forces) with multipoles given in local frames: the energy at
+    the rotated multipoles, the forces with them fixed plus the forces of
+    the rotation."""
+    from .frames import to_global, gradient_forces
+    glob = to_global(sys_local, frames)
+    c = Context(glob, prm)
+    E, F = energy_forces(glob, prm, ct, c)
+    Gd, GT = multipole_gradients(glob, prm, ct, c)
+    return E, F + gradient_forces(sys_local, frames, Gd, GT)

@@ -163,17 +163,18 @@ def multipole_gradients(sysm, prm, mu_pol, ctx=None):
     return COULOMB * Gd, COULOMB * GT, COULOMB * Ga
 
 
-def _frame_terms(sys_local, frames, prm, mu_pol, ctx=None):
+def _terms_from_gradients(sys_local, frames, Gd, GT, Ga=None):
     """Per site n and frame site k = o, a, b of n's frame: the force
-    -sum_pq C_n,pq dR_pq/dr_k (n, 3, 3), C_n the site's term of dE/dR."""
+    -sum_pq C_n,pq dR_pq/dr_k (n, 3, 3), C_n the site's term of dE/dR built
+    from the derivatives of an energy with respect to the global dipoles
+    (Gd), quadrupoles (GT, full symmetric) and polarizabilities (Ga)."""
     s_loc = sys_local
     f = np.asarray(frames, int)
-    glob = to_global(s_loc, f)
-    Gd, GT, Ga = multipole_gradients(glob, prm, mu_pol, ctx)
     R = site_rotations(s_loc.pos, f)
     C = np.einsum("na,nb->nab", Gd, s_loc.dip)
     C += 2.0 * np.einsum("nab,nbc,ncd->nad", GT, R, _sym6_to_mat(s_loc.quad))
-    C += 2.0 * np.einsum("nab,nbc,ncd->nad", Ga, R, _sym6_to_mat(s_loc.alpha))
+    if Ga is not None:
+        C += 2.0 * np.einsum("nab,nbc,ncd->nad", Ga, R, _sym6_to_mat(s_loc.alpha))
     on = f[:, 0] >= 0
     per = np.zeros((s_loc.n, 3, 3))
     dR = frame_derivatives(s_loc.pos[f[on, 0]], s_loc.pos[f[on, 1]], s_loc.pos[f[on, 2]])
@@ -181,17 +182,34 @@ def _frame_terms(sys_local, frames, prm, mu_pol, ctx=None):
     return per
 
 
-def frame_forces(sys_local, frames, prm, mu_pol, ctx=None):
-    """The forces (n,3) from the rotation of the local multipoles and
-    polarizabilities: -sum_pq (dE/dR)_pq dR_pq/dr_k on each frame site k."""
+def _frame_terms(sys_local, frames, prm, mu_pol, ctx=None):
     f = np.asarray(frames, int)
-    per = _frame_terms(sys_local, f, prm, mu_pol, ctx)
-    F = np.zeros((sys_local.n, 3))
+    glob = to_global(sys_local, f)
+    Gd, GT, Ga = multipole_gradients(glob, prm, mu_pol, ctx)
+    return _terms_from_gradients(sys_local, f, Gd, GT, Ga)
+
+
+def _gather(per, frames, n):
+    f = np.asarray(frames, int)
+    F = np.zeros((n, 3))
     # each site's contribution, through its own frame sites
     on = f[:, 0] >= 0
     for k in range(3):
         np.add.at(F, f[on, k], per[on, k, :])
     return F
+
+
+def gradient_forces(sys_local, frames, Gd, GT, Ga=None):
+    """The forces (n,3) of the rotation for any energy of the global
+    multipoles, given its derivatives Gd (n,3), GT (n,3,3) and, optionally,
+    Ga (n,3,3): -sum_pq (dE/dR)_pq dR_pq/dr_k on each frame site k."""
+    return _gather(_terms_from_gradients(sys_local, frames, Gd, GT, Ga), frames, sys_local.n)
+
+
+def frame_forces(sys_local, frames, prm, mu_pol, ctx=None):
+    """The forces (n,3) from the rotation of the local multipoles and
+    polarizabilities: -sum_pq (dE/dR)_pq dR_pq/dr_k on each frame site k."""
+    return _gather(_frame_terms(sys_local, frames, prm, mu_pol, ctx), frames, sys_local.n)
 
 
 def _min_image(d, box):

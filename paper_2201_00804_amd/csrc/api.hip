@@ -1899,6 +1899,7 @@ sibfa_status sibfa_set_local_frames(sibfa_ctx c, const int32_t* frames, const do
   }
   c->ngroups = G;
   c->have_frames = true;
+  c->ct_on = false;   // the lone-pair checks were made against the old multipoles
   c->rot_alpha = alpha_local != nullptr;
   c->dirty_rot = true;
   if (c->rot_alpha) c->pol_ok = false;   // the rotated tensors are validated again
@@ -2169,6 +2170,17 @@ sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
   HIP_TRY(hipMemcpy(hd.data(), c->dip_c, 3 * nn * sizeof(double), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(ht.data(), c->quad_c, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(hal.data(), c->alpha_c, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> hdl, hql, hall;   // local frames: the local values too
+  if (c->have_frames) {
+    hdl.resize(3 * nn);
+    hql.resize(6 * nn);
+    HIP_TRY(hipMemcpy(hdl.data(), c->dloc, 3 * nn * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hql.data(), c->qloc, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
+    if (c->rot_alpha) {
+      hall.resize(6 * nn);
+      HIP_TRY(hipMemcpy(hall.data(), c->aloc, 6 * nn * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  }
   auto in = [&](int i) { return i >= 0 && i < n; };
   std::vector<int> lp_of(nn, -1);
   for (int p = 0; p < n_lp; ++p) {
@@ -2181,6 +2193,9 @@ sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
     bool zero = hq[L] == 0.0;
     for (int k = 0; k < 3; ++k) zero = zero && hd[3 * (size_t)L + k] == 0.0;
     for (int k = 0; k < 6; ++k) zero = zero && ht[6 * (size_t)L + k] == 0.0 && hal[6 * (size_t)L + k] == 0.0;
+    for (size_t k = 0; k < 3 && !hdl.empty(); ++k) zero = zero && hdl[3 * (size_t)L + k] == 0.0;
+    for (size_t k = 0; k < 6 && !hql.empty(); ++k) zero = zero && hql[6 * (size_t)L + k] == 0.0;
+    for (size_t k = 0; k < 6 && !hall.empty(); ++k) zero = zero && hall[6 * (size_t)L + k] == 0.0;
     if (!zero) return fail(c, SIBFA_E_ARG, at + ": a lone-pair site carries no multipoles or polarizability");
     if (!(hr[cr] > 0.0) || !std::isfinite(hr[cr]) || !std::isfinite(hlp[2 * p]) ||
         !std::isfinite(hlp[2 * p + 1]))
@@ -2233,6 +2248,7 @@ sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
       alloc_into(c, L, a.w, nl) && alloc_into(c, L, a.Fl, 3 * nl) && alloc_into(c, L, a.Fc, 3 * nl) &&
       alloc_into(c, L, a.Fa, 6 * na) && alloc_into(c, L, a.ua, 2 * na) &&
       alloc_into(c, L, a.W_s, nn) && alloc_into(c, L, a.U_s, nn) && alloc_into(c, L, a.F_s, nn) &&
+      alloc_into(c, L, a.flag_s, nn) &&
       alloc_into(c, L, c->ct_spw, nn) && alloc_into(c, L, c->ct_zero4, nn) &&
       alloc_into(c, L, c->ct_zero2, nn);
   if (!ok) {
@@ -2258,6 +2274,7 @@ sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
   launch_fill_double(reinterpret_cast<double*>(c->ct_zero4), 0.0, 4 * nn, c->stream);
   launch_fill_double(reinterpret_cast<double*>(c->ct_zero2), 0.0, 2 * nn, c->stream);
   launch_fill_double(a.Vint, 0.0, nn, c->stream);
+  launch_fill_double(a.Gr, 0.0, 3 * nl, c->stream);   // written only by the periodic gather
   a.n = n; a.n_lp = n_lp; a.n_acc = n_acc; a.n_vint = (int)vint.size();
   a.lp = dl; a.lp_par = dlp; a.acc = da; a.ah = dah; a.rvdw = dr;
   a.eta = prm->eta; a.cs = prm->cs; a.cp = prm->cp; a.t = prm->t; a.m = prm->m;
@@ -2287,7 +2304,13 @@ sibfa_status sibfa_ct_energy_forces(sibfa_ctx c, double* e_ct, double* forces) {
   }
   launch_ct_pairs(s, a, c->red, sm);
   if (forces) {
-    launch_ct_wforce(s, a, c->periodic ? c->ct_spw : nullptr, sm);
+    // local frames: the field and field gradient of the w and u charges at
+    // the sites give the derivatives with respect to the rotated
+    // multipoles, which the frame kernels turn into forces
+    const bool fr = c->have_frames;
+    double4* FS = fr ? c->FS : nullptr;
+    double* GS = fr ? c->GS : nullptr;
+    launch_ct_wforce(s, a, c->periodic ? c->ct_spw : nullptr, sm, FS, GS);
     if (c->periodic) {
       SysView sw = s;
       sw.sp = c->ct_spw;
@@ -2296,9 +2319,16 @@ sibfa_status sibfa_ct_energy_forces(sibfa_ctx c, double* e_ct, double* forces) {
       sw.sth2 = c->ct_zero2;
       launch_spread_mult(sw, c->pm, nullptr, false, sm);
       conv(c, false, sm, S_CTREC);
-      launch_gather_force(s, c->pm, c->red, c->ct_zero4, a.F_s, c->perm, forces, false, false, sm);
+      // no self terms: the w charges sit at sites without multipoles
+      launch_gather_force(s, c->pm, c->red, c->ct_zero4, a.F_s, c->perm, forces, false, false, sm,
+                          FS, GS, false);
     } else {
       launch_forces_out(c->n, c->perm, a.F_s, forces, sm);
+    }
+    if (fr) {
+      FrameArgs f = make_frames(c);
+      f.aloc = nullptr;   // E_ct does not depend on the polarizabilities
+      launch_frame_forces(f, c->red, forces, false, sm);
     }
   }
   double e = 0.0;

@@ -241,6 +241,21 @@ __device__ __forceinline__ int wave_atomic_inc(int* base, int key, bool active) 
   }
   return slot;
 }
+// base + the number of set bits of mask below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)base));
+}
+
+// Orders this wave's LDS accesses before the call against those after it
+// (the lanes of a wave issue together, so no hardware barrier is needed;
+// this keeps the compiler from moving LDS loads and stores across it).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

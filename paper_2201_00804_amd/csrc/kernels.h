@@ -50,11 +50,12 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
 // virial: also the site (amplitude) terms of the reciprocal virial (slots
 // S_VRG).
 // FS, GS (may be NULL): the reciprocal field and field gradient at every
-// site plus the Ewald self terms of d + mu and Theta are added to them.
+// site plus (self) the Ewald self terms of d + mu and Theta are added to
+// them.
 void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
                          bool virial, hipStream_t st, double4* FS = nullptr,
-                         double* GS = nullptr);
+                         double* GS = nullptr, bool self = true);
 
 // fft.hip: full convolution phi = IFFT(G * FFT(Q)) with E_rec partials in
 // the slot pm.erec_slot; virial: also the m-space sum of the reciprocal
@@ -209,6 +210,7 @@ struct CtArgs {
   const int* vint_sites;  // [n_vint] distinct acceptor atoms
   const int* perm;        // sorted -> caller
   const int* inv_perm;    // caller -> sorted
+  int* flag_s;            // [n] sorted: a1 / carrier / has-multipoles bits
   double* Vlp;            // [n_lp] V_l (e/A)
   double* Gr;             // [n_lp][3] reciprocal grad V_l
   double* Vint;           // [n] V_int at acceptor atoms (e/A)
@@ -226,7 +228,11 @@ void launch_ct_gather_pot(const SysView& s, const PmeView& pm, const CtArgs& a, 
 // energy partials into S_ECT
 void launch_ct_pairs(const SysView& s, const CtArgs& a, Reduce& red, hipStream_t st);
 // sp_w (may be NULL): records with the w charges for the reciprocal spread
-void launch_ct_wforce(const SysView& s, const CtArgs& a, double4* sp_w, hipStream_t st);
+// FS, GS (may be NULL): also the field and field gradient of the w and u
+// charges at every site (sorted, divided by the Coulomb constant), real
+// space, for the forces of local frames
+void launch_ct_wforce(const SysView& s, const CtArgs& a, double4* sp_w, hipStream_t st,
+                      double4* FS = nullptr, double* GS = nullptr);
 
 // global d, Theta (and alpha when aloc is set) from the local ones
 void launch_rotate(const FrameArgs& f, hipStream_t st);

@@ -625,12 +625,6 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
 //    64 at a time (a lane finds its run by binary search over the run
 //    offsets), so chunks are full;
 //  * polarizable-pair masks come from one ballot per chunk.
-// base + the number of set bits of mask below this lane
-__device__ __forceinline__ int lanes_below(unsigned long long mask, int base) {
-  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)base));
-}
-
 __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
   __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
   __shared__ int moli[kNlIB], poli[kNlIB];

@@ -275,7 +275,7 @@ template <typename R, int P, bool VIR>
 __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, Reduce red,
                                                          const double4* mu, const double4* Freal,
                                                          const int* perm, double* out,
-                                                         double4* FS, double* GS) {
+                                                         double4* FS, double* GS, bool self) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (i < s.n) {
@@ -341,7 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_force(SysView s, PmeView pm, 
       // (the latter 3x the quadrupole self derivative, as the field
       // gradient enters the quadrupole energy with 1/3)
       const double b = pm.beta, b3 = b * b * b;
-      const double sf = 4.0 * b3 / (3.0 * kSqrtPi), st = 16.0 * b3 * b * b / (15.0 * kSqrtPi);
+      const double sf = self ? 4.0 * b3 / (3.0 * kSqrtPi) : 0.0;
+      const double st = self ? 16.0 * b3 * b * b / (15.0 * kSqrtPi) : 0.0;
       double4 e = FS[i];
       e.x += sf * dd[0] - der(0, -1, -1);
       e.y += sf * dd[1] - der(1, -1, -1);
@@ -421,14 +422,14 @@ void launch_gather_field(const SysView& s, const PmeView& pm, double4* E0, bool 
 template <int P, bool VIR>
 static void gather_force_pv(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                             const double4* Freal, const int* perm, double* out, bool mixed,
-                            hipStream_t st, double4* FS, double* GS) {
+                            hipStream_t st, double4* FS, double* GS, bool self) {
   const dim3 g((s.n + kBlock - 1) / kBlock), b(kBlock);
   if (mixed)
     hipLaunchKernelGGL((k_gather_force<float, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
-                       out, FS, GS);
+                       out, FS, GS, self);
   else
     hipLaunchKernelGGL((k_gather_force<double, P, VIR>), g, b, 0, st, s, pm, red, mu, Freal, perm,
-                       out, FS, GS);
+                       out, FS, GS, self);
   if (VIR)
     for (int k = 0; k < 9; ++k) red.nparts[S_VRG + k] = (int)g.x;
 }
@@ -436,18 +437,18 @@ static void gather_force_pv(const SysView& s, const PmeView& pm, Reduce& red, co
 template <int P>
 static void gather_force_p(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                            const double4* Freal, const int* perm, double* out, bool mixed,
-                           bool vir, hipStream_t st, double4* FS, double* GS) {
-  if (vir) gather_force_pv<P, true>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS);
-  else gather_force_pv<P, false>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS);
+                           bool vir, hipStream_t st, double4* FS, double* GS, bool self) {
+  if (vir) gather_force_pv<P, true>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS, self);
+  else gather_force_pv<P, false>(s, pm, red, mu, Freal, perm, out, mixed, st, FS, GS, self);
 }
 
 void launch_gather_force(const SysView& s, const PmeView& pm, Reduce& red, const double4* mu,
                          const double4* Freal, const int* perm, double* out, bool mixed,
-                         bool virial, hipStream_t st, double4* FS, double* GS) {
+                         bool virial, hipStream_t st, double4* FS, double* GS, bool self) {
   switch (pm.order) {
-    case 4: gather_force_p<4>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
-    case 6: gather_force_p<6>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
-    default: gather_force_p<5>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS); break;
+    case 4: gather_force_p<4>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS, self); break;
+    case 6: gather_force_p<6>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS, self); break;
+    default: gather_force_p<5>(s, pm, red, mu, Freal, perm, out, mixed, virial, st, FS, GS, self); break;
   }
 }
 

@@ -157,9 +157,14 @@ def valu(args):
     out = ["# VALU issue of the kernels, 32,000-water box", "", "Commands:", "", "```"]
     out += args.command
     out += ["```", "",
-            "Instructions are wavefront instructions per working dispatch (counter run); "
-            "durations are working means from the kernel trace (a separate run, the same "
-            "workload).  Issue peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU "
+            "Instructions are wavefront instructions per working dispatch; durations are "
+            "working means from the kernel trace " + (
+                "of the same run (dispatches profiled for counters run one at a time, so a "
+                "kernel that normally overlaps another reads its own time alone).  "
+                if os.path.dirname(os.path.abspath(args.counters)) ==
+                os.path.dirname(os.path.abspath(args.trace)) else
+                "(a separate run, the same workload).  ") +
+            "Issue peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU "
             f"instruction = {VALU_PEAK / 1e9:.1f} G/s.  Transcendental and FP64 "
             "transcendental-helper instructions take longer than 4 cycles, so a kernel "
             "bound by them reads below 1.", "",

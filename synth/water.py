@@ -223,16 +223,20 @@ def config_system(name):
     return sysd, params
 
 
-def water_frames(sysd):
+def water_frames(sysd, sites_per_water=WATER_SITES):
     """Frame sites of every site for local-frame multipoles: each water's
     five sites (O, H1, H2, B1, B2, consecutive) use the frame of its O, H1
     and H2.  Returns int32 [n, 3] site indices (caller order).  The random
     dipoles, quadrupoles and polarizabilities of the system dicts serve as
     the local-frame values (their distributions do not depend on the
-    frame)."""
+    frame).  With sites_per_water = CT_SITES (the lone pairs appended by
+    water_lone_pairs) the two lone-pair rows are -1: no frame."""
     n = len(sysd["pos"])
-    first = (np.arange(n) // WATER_SITES) * WATER_SITES
-    return np.stack([first, first + 1, first + 2], axis=1).astype(np.int32)
+    first = (np.arange(n) // sites_per_water) * sites_per_water
+    f = np.stack([first, first + 1, first + 2], axis=1).astype(np.int32)
+    if sites_per_water == CT_SITES:
+        f[np.arange(n) % CT_SITES >= WATER_SITES] = -1
+    return f
 
 
 MASSES = {"O": 15.999, "H": 1.008}   # g/mol; the bond barycentres are massless

@@ -4,6 +4,10 @@ tests/test_oracle_ct.py): E_ct and its forces on a cluster, the 27-water
 box, the 120-water orthorhombic box and the 216-water box, each water with
 two lone-pair sites.
 
+With local frames (the dipoles and quadrupoles given in molecular frames,
+sibfa_set_local_frames): E_ct and the forces including the rotation against
+oracle/ct.py energy_forces_frames, itself pinned by central differences.
+
 Bars: E_ct within 1e-10 relative, forces within 1e-8 of the largest (both
 sides FP64, different summation order)."""
 import numpy as np
@@ -13,7 +17,7 @@ import torch
 from oracle import ct as oct_
 from oracle.model import System
 from synth import (water_box, water_cluster, water_box_ortho, water_lone_pairs, water_ct,
-                   config_system)
+                   config_system, water_frames, CT_SITES)
 from tests.gpu_util import say, oracle_params, gpu_params, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +73,31 @@ def test_ct_matches_oracle(case):
     assert E2 == E and none is None
 
 
+@pytest.mark.parametrize("case", ["cluster", "box27", "box216"])
+def test_ct_local_frames_match_oracle(case):
+    from paper_2201_00804_amd import SibfaError
+    d, kw = _case(case)
+    ct = water_ct(d)
+    fr = water_frames(d, CT_SITES)
+    E_o, F_o = oct_.energy_forces_frames(System.from_dict(d), fr, oracle_params(d, **kw), ct)
+    eng = _ct_engine(d, kw, ct)
+    eng.set_local_frames(_t(fr, torch.int32), _t(d["dip"]), _t(d["quad"]), _t(d["alpha"]))
+    with pytest.raises(SibfaError) as e:   # frames switched the term off
+        eng.ct_energy_forces()
+    assert e.value.status == -2
+    eng.set_charge_transfer(_t(ct["lp"], torch.int32), _t(ct["lp_par"]),
+                            _t(ct["acc"], torch.int32), _t(ct["ah"]), _t(ct["rvdw"]),
+                            ct["eta"], ct["cs"], ct["cp"], ct["t"], ct["m"])
+    E, F = eng.ct_energy_forces()
+    eng.close()
+    F = F.cpu().numpy()
+    err = rel_err(F, F_o)
+    say(f"[ct frames] {case}: E_ct {E:.10f} vs {E_o:.10f} (rel {abs(E - E_o) / abs(E_o):.1e}), "
+        f"forces {err:.2e}")
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert err <= 1e-8
+
+
 def test_ct_leaves_the_polarization_path_alone_and_follows_positions():
     """Lone-pair sites are inert for E_pol and E_elec (equal to a context
     without them, up to the summation order); a CT call between two
@@ -122,6 +151,19 @@ def test_ct_errors():
                                 _t(ct["acc"], torch.int32), _t(ct["ah"]), _t(ct["rvdw"]),
                                 ct["eta"], ct["cs"], ct["cp"], ct["t"], ct["m"])
     assert e.value.status == -1
+    # a lone pair given a local dipole through the frames
+    fr = water_frames(d, CT_SITES)
+    fr[ct["lp"][0, 0]] = fr[ct["lp"][0, 1]]
+    dl = d["dip"].copy()
+    dl[ct["lp"][0, 0]] = 0.2
+    eng.set_multipoles(_t(d["q"]), _t(d["dip"]), _t(d["quad"]))
+    eng.set_local_frames(_t(fr, torch.int32), _t(dl), _t(d["quad"]))
+    with pytest.raises(SibfaError) as e:
+        eng.set_charge_transfer(_t(ct["lp"], torch.int32), _t(ct["lp_par"]),
+                                _t(ct["acc"], torch.int32), _t(ct["ah"]), _t(ct["rvdw"]),
+                                ct["eta"], ct["cs"], ct["cp"], ct["t"], ct["m"])
+    assert e.value.status == -1
+    eng.set_local_frames(None)
     # an acceptor spread over two molecules
     eng.set_multipoles(_t(d["q"]), _t(d["dip"]), _t(d["quad"]))
     acc = ct["acc"].copy()

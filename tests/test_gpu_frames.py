@@ -196,4 +196,9 @@ def test_frames_box4096_against_global_multipoles(precision):
     assert abs(ep - ep2) <= tol * abs(ep2)
     assert abs(ee - ee2) <= tol * abs(ee2)
     assert np.abs(dF).max() > 1e-2 * np.abs(F2).max()
-    assert net <= 1e-10
+    # the two contexts' multipoles differ by rounding (device rotation vs
+    # numpy); FP64 keeps that at 1e-16, the FP32 stages of the mixed path
+    # round it to FP32 unit roundoff of the forces
+    net_tol = 1e-10 if precision == "fp64" else \
+        16 * 2.0 ** -24 * np.abs(F2).max() / np.abs(dF).max()
+    assert net <= net_tol

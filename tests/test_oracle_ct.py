@@ -15,6 +15,11 @@ C3  Forces equal central differences of E_ct (cluster, brute-force Ewald,
     (w) forces or their reciprocal part (planted) fails.  The paper prints
     no charge-transfer value for a system these inputs can reproduce: the
     values themselves are parity unpinned.
+C4  Local frames: with the dipoles and quadrupoles given in molecular
+    frames, the forces (fixed-multipole part plus the rotation through the
+    derivatives of E_ct with respect to the global multipoles) equal central
+    differences of E_ct at the rotated multipoles (cluster, SPME); dropping
+    the rotation part (planted) fails.
 """
 import numpy as np
 import pytest
@@ -22,7 +27,8 @@ import pytest
 from oracle import ct as oct_
 from oracle.model import System, Params, Context
 from oracle import realspace as rs
-from synth import water_cluster, water_box, water_lone_pairs, water_ct
+from oracle import frames as ofr
+from synth import water_cluster, water_box, water_lone_pairs, water_ct, water_frames, CT_SITES
 
 
 def _cluster(nw=3, seed=2):
@@ -182,3 +188,41 @@ def test_c3_planted_mistakes_fail(plant, monkeypatch):
         prm = Params(method="spme", beta=0.5, cutoff=3.7, grid=(12, 12, 12), order=5)
     with pytest.raises(AssertionError):
         _fd_forces(s, prm, c, SITES)
+
+
+def _fd_forces_frames(s, frames, prm, c, sites, h=1e-5, rtol=1e-6):
+    E, F = oct_.energy_forces_frames(s, frames, prm, c)
+    scale = np.abs(F).max()
+    for i, a in sites:
+        p = s.pos.copy()
+        p[i, a] += h
+        ep = oct_.energy_forces_frames(System(**{**s.__dict__, "pos": p}), frames, prm, c)[0]
+        p[i, a] -= 2 * h
+        em = oct_.energy_forces_frames(System(**{**s.__dict__, "pos": p}), frames, prm, c)[0]
+        assert abs(-(ep - em) / (2 * h) - F[i, a]) <= rtol * scale, (i, a, -(ep - em) / (2 * h),
+                                                                     F[i, a])
+    return F
+
+
+def test_c4_forces_frames_cluster():
+    s, c, d = _cluster()
+    fr = water_frames(d, CT_SITES)
+    F = _fd_forces_frames(s, fr, Params(method="direct"), c, SITES)
+    assert np.abs(F.sum(0)).max() < 1e-10 * np.abs(F).max()
+    # the rotation part is not small here
+    F0 = oct_.energy_forces(ofr.to_global(s, fr), Params(method="direct"), c)[1]
+    assert np.abs(F - F0).max() > 1e-2 * np.abs(F).max()
+
+
+def test_c4_forces_frames_spme():
+    d = water_lone_pairs(water_box(8, 8.0, 12))
+    _fd_forces_frames(System.from_dict(d), water_frames(d, CT_SITES),
+                      Params(method="spme", beta=0.5, cutoff=3.7, grid=(12, 12, 12), order=5),
+                      water_ct(d), SITES)
+
+
+def test_c4_planted_no_rotation_fails(monkeypatch):
+    monkeypatch.setattr(ofr, "gradient_forces", lambda s, f, Gd, GT, Ga=None: np.zeros((s.n, 3)))
+    s, c, d = _cluster()
+    with pytest.raises(AssertionError):
+        _fd_forces_frames(s, water_frames(d, CT_SITES), Params(method="direct"), c, SITES)
