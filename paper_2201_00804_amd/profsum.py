@@ -61,8 +61,10 @@ def stats(args):
         per[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     rows = list(csv.DictReader(open(args.stats)))
     total = sum(float(r["TotalDurationNs"]) for r in rows) / 1e3
-    out = [f"# {args.title}", "", "Command:", "", "```", args.command, "```", "",
-           f"Total kernel time {total / 1e3:.3f} ms over {len(rows)} kernels.", "",
+    out = [f"# {args.title}", "", "Command:", "", "```", args.command, "```", ""]
+    if args.note:
+        out += [args.note, ""]
+    out += [f"Total kernel time {total / 1e3:.3f} ms over {len(rows)} kernels.", "",
            "| kernel | calls | total us | avg us (rocprof) | % | working calls | "
            "working avg us | idle calls |",
            "|---|---|---|---|---|---|---|---|"]
@@ -187,6 +189,7 @@ def main(argv=None):
     a.add_argument("--command", required=True)
     a.add_argument("--title", default="Kernel time")
     a.add_argument("--top", type=int, default=30)
+    a.add_argument("--note", default="")
     b = sub.add_parser("traffic")
     b.add_argument("--kernel", required=True, choices=sorted(TRAFFIC_SOURCES))
     b.add_argument("--workload", default="")
