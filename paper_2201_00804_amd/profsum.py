@@ -5,7 +5,7 @@
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
         --copy-bytes N --command CMD
 
-    python -m paper_2201_00804_amd.profsum valu --counters C.csv --trace TRACE_CSV \
+    python -m paper_2201_00804_amd.profsum valu|issue --counters C.csv --trace TRACE_CSV \
         --command CMD [--command CMD2]
 
 `stats` lists the per-kernel totals of `--kernel-trace --stats` and, for
@@ -180,6 +180,59 @@ def valu(args):
     print("\n".join(out))
 
 
+def issue(args):
+    """VALU instructions per SIMD per 4 cycles on each kernel's own clock:
+    GRBM_GUI_ACTIVE (summed over the 8 XCDs) over the dispatch's duration
+    in the same run gives the clock the kernel ran at."""
+    inst = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(args.counters)):
+        inst[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = collections.defaultdict(list)
+    for r in csv.DictReader(open(args.trace)):
+        dur[short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) -
+                                             int(r["Start_Timestamp"])) / 1e3)
+
+    def working_mean(v):
+        med = sorted(v)[len(v) // 2]
+        w = [x for x in v if x >= IDLE_FRACTION * med]
+        return sum(w) / len(w)
+
+    rows = []
+    for k, d in dur.items():
+        c = inst.get(k, {})
+        if "SQ_INSTS_VALU" not in c or "GRBM_GUI_ACTIVE" not in c:
+            continue
+        t = working_mean(d)
+        nv = working_mean(c["SQ_INSTS_VALU"])
+        g = working_mean(c["GRBM_GUI_ACTIVE"]) / XCDS
+        na = working_mean(c["SQ_ACTIVE_INST_VALU"]) if "SQ_ACTIVE_INST_VALU" in c else float("nan")
+        rows.append((t * len(d), k, t, nv, g, na))
+    rows.sort(reverse=True)
+    out = ["# VALU issue on each kernel's own clock, 32,000-water box", "", "Command:", "",
+           "```"] + args.command + ["```", "",
+           "GRBM_GUI_ACTIVE counts GPU-busy cycles summed over the 8 XCDs, so per dispatch "
+           "GRBM_GUI_ACTIVE / 8 over the dispatch's duration (kernel trace of the same run) is "
+           "the clock the kernel ran at.  Issue is SQ_INSTS_VALU x 4 cycles / (1,024 SIMDs x "
+           "GRBM_GUI_ACTIVE / 8): 1.0 means every SIMD issued one wave64 VALU instruction every "
+           "4 cycles, the most a single VALU pipeline takes.  A value above 1 means some "
+           "instructions issued beside others (the kernel's transcendentals are the "
+           "candidates); SQ_ACTIVE_INST_VALU / SQ_INSTS_VALU near 1 shows that counter counts "
+           "instructions here, not cycles.  The busy count also covers the dispatch's own "
+           "start and drain, so for launches of tens of microseconds the clock reads above the "
+           "part's 2.4 GHz and the issue figure low: the columns mean what they say for the "
+           "long kernels (hundreds of microseconds).", "",
+           "| kernel | working avg us | clock GHz | VALU instr (M) | issue per SIMD per 4 cycles | "
+           "ACTIVE_INST / INSTS |", "|---|---|---|---|---|---|"]
+    for _, k, t, nv, g, na in rows[:args.top]:
+        out.append(f"| `{k}` | {t:.2f} | {g / (t * 1e3):.2f} | {nv / 1e6:.2f} | "
+                   f"{nv * 4.0 / (SIMDS * g):.3f} | {na / nv:.3f} |")
+    print("\n".join(out))
+
+
+XCDS = 8
+SIMDS = 256 * 4
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -199,13 +252,18 @@ def main(argv=None):
     b.add_argument("--copy-write", required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--command", action="append", required=True)
+    e = sub.add_parser("issue")
+    e.add_argument("--counters", required=True)
+    e.add_argument("--trace", required=True)
+    e.add_argument("--command", action="append", required=True)
+    e.add_argument("--top", type=int, default=24)
     c = sub.add_parser("valu")
     c.add_argument("--counters", required=True)
     c.add_argument("--trace", required=True)
     c.add_argument("--command", action="append", required=True)
     c.add_argument("--top", type=int, default=24)
     args = ap.parse_args(argv)
-    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "valu": valu, "issue": issue}[args.cmd](args)
 
 
 if __name__ == "__main__":
