@@ -2248,7 +2248,8 @@ sibfa_status sibfa_set_charge_transfer(sibfa_ctx c, int n_lp, const int32_t* lp,
       alloc_into(c, L, a.w, nl) && alloc_into(c, L, a.Fl, 3 * nl) && alloc_into(c, L, a.Fc, 3 * nl) &&
       alloc_into(c, L, a.Fa, 6 * na) && alloc_into(c, L, a.ua, 2 * na) &&
       alloc_into(c, L, a.W_s, nn) && alloc_into(c, L, a.U_s, nn) && alloc_into(c, L, a.F_s, nn) &&
-      alloc_into(c, L, a.flag_s, nn) &&
+      alloc_into(c, L, a.flag_s, nn) && alloc_into(c, L, a.rng_s, nn) &&
+      alloc_into(c, L, a.lp_rec, 8 * nl) && alloc_into(c, L, a.acc_rec, 8 * na) &&
       alloc_into(c, L, c->ct_spw, nn) && alloc_into(c, L, c->ct_zero4, nn) &&
       alloc_into(c, L, c->ct_zero2, nn);
   if (!ok) {

@@ -14,7 +14,10 @@
 // unit charge.  Everything runs in FP64.
 //
 //  k_ct_flags     : per sorted site, what it is (an a1, a carrier, has
-//                   multipoles), so list scans test one word per entry.
+//                   multipoles) and its acceptor and lone-pair ranges, so
+//                   list scans test one word per entry.
+//  k_ct_records   : per lone pair and per acceptor, one 64-byte record of
+//                   what a pair needs from that side.
 //  k_ct_vlp       : real-space part of V_l.
 //  k_ct_vint      : V_int at the acceptor atoms.
 //  k_ct_gather_pot: reciprocal V_l and its gradient from the PME grid.
@@ -56,13 +59,13 @@ constexpr int kIsCarrier = 2;   // carries at least one lone pair
 constexpr int kHasMult = 4;     // nonzero permanent multipoles
 
 // One wave walks entries [0, nt) of a list, kScanU chunks of 64 per step
-// (the loads of a step issue together).  hit(k, v) tells whether entry k
+// (the loads of a step issue together; more chunks hide more latency and
+// hold more registers).  hit(k, v) tells whether entry k
 // takes part and sets the value v to queue; queued values keep list order
 // in a ring of kRing slots, and whenever 64 are queued every lane takes one
 // and runs eval(v).  What is left runs at the end on the first lanes.  The
 // whole wave calls it with the same nt.
-constexpr int kScanU = 4;
-template <class Hit, class Eval>
+template <int kScanU, class Hit, class Eval>
 __device__ __forceinline__ void wave_compact(int nt, int* ring, Hit hit, Eval eval) {
   const int lane = threadIdx.x & 63;
   int head = 0, tail = 0;   // wave-uniform
@@ -151,51 +154,76 @@ struct CtPair {
   double gL[3], gC[3], gA1[3], gA2[3];   // dE/dr of l, c, a1, a2
 };
 
-// Everything of one (lone pair p, acceptor k) pair, given the positions of
-// the lone pair, its carrier and the acceptor's a1 and a2.
-__device__ __forceinline__ void ct_pair(const SysView& s, const CtArgs& a, int p, int k,
-                                        const double xL[3], const double xc[3],
-                                        const double x1[3], const double x2[3], CtPair& o) {
-  const int c = a.lp[2 * p + 1];
-  const int a1 = a.acc[2 * k], a2 = a.acc[2 * k + 1];
+// The lone-pair side of a pair (potentials already times the Coulomb
+// constant) and the acceptor side.
+struct LpSide {
+  double xL[3], xc[3], VL, nocc, ae, rvc;
+};
+struct AccSide {
+  double x1[3], x2[3], V1, V2, rv1, rv2, ah;
+};
+
+__device__ __forceinline__ void load_lp(const CtArgs& a, int p, LpSide& l) {
+  const double4* r = reinterpret_cast<const double4*>(a.lp_rec) + 2 * (size_t)p;
+  const double4 r0 = r[0], r1 = r[1];
+  l.xL[0] = r0.x; l.xL[1] = r0.y; l.xL[2] = r0.z; l.VL = r0.w;
+  l.nocc = r1.x; l.ae = r1.y; l.rvc = r1.z;
+}
+
+__device__ __forceinline__ void load_acc(const CtArgs& a, int k, AccSide& q) {
+  const double4* r = reinterpret_cast<const double4*>(a.acc_rec) + 2 * (size_t)k;
+  const double4 r0 = r[0], r1 = r[1];
+  q.x2[0] = r0.x; q.x2[1] = r0.y; q.x2[2] = r0.z; q.V1 = r0.w;
+  q.V2 = r1.x; q.rv1 = r1.y; q.rv2 = r1.z; q.ah = r1.w;
+}
+
+// Everything of one (lone pair, acceptor) pair.
+__device__ __forceinline__ void ct_pair(const SysView& s, const CtArgs& a, const LpSide& l,
+                                        const AccSide& q, CtPair& o) {
   double u[3], d1[3], d2[3];
-  sep(s, xL, xc, u);
-  sep(s, x1, xc, d1);
-  sep(s, x2, xc, d2);
-  const double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  const double r1 = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
-  const double r2 = sqrt(d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
-  const double s1 = 2.0 * sqrt(a.rvdw[c] * a.rvdw[a1]), s2 = 2.0 * sqrt(a.rvdw[c] * a.rvdw[a2]);
+  sep(s, l.xL, l.xc, u);
+  sep(s, q.x1, l.xc, d1);
+  sep(s, q.x2, l.xc, d2);
+  // reciprocal lengths (one rsqrt each) in place of the divisions
+  const double inu = rsqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const double ir1 = rsqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+  const double ir2 = rsqrt(d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
+  const double r1 = (d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]) * ir1;
+  const double r2 = (d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]) * ir2;
+  // eta / s = eta / (2 sqrt(rvdw_c rvdw_a))
+  const double es1 = 0.5 * a.eta * rsqrt(l.rvc * q.rv1), es2 = 0.5 * a.eta * rsqrt(l.rvc * q.rv2);
   const double ud1 = u[0] * d1[0] + u[1] * d1[1] + u[2] * d1[2];
   const double ud2 = u[0] * d2[0] + u[1] * d2[1] + u[2] * d2[2];
-  const double ca = ud1 / (nu * r1), cb = ud2 / (nu * r2);
-  const double ex1 = exp(-a.eta * r1 / s1), ex2 = exp(-a.eta * r2 / s2);
-  const double VL = kCoulomb * a.Vlp[p];
-  const double X1 = kCoulomb * a.Vint[a1] - VL, X2 = kCoulomb * a.Vint[a2] - VL;
+  const double ca = ud1 * inu * ir1, cb = ud2 * inu * ir2;
+  const double ex1 = exp(-es1 * r1), ex2 = exp(-es2 * r2);
+  const double VL = l.VL;
+  const double X1 = q.V1 - VL, X2 = q.V2 - VL;
   const double g1 = a.cs * a.t + a.cp * a.m * ca, g2 = a.cs * a.t + a.cp * a.m * cb;
   const double e1 = ex1 * X1 * g1, e2 = ex2 * X2 * g2;
-  const double nocc = a.lp_par[2 * p], dE = a.lp_par[2 * p + 1] + VL - a.ah[k];
+  const double nocc = l.nocc, idE = 1.0 / (l.ae + VL - q.ah);
   const double diff = e1 - e2;
-  o.E = -nocc * diff * diff / dE;
-  const double G = -2.0 * nocc * diff / dE;   // dE/de1; dE/de2 = -G
-  const double GD = nocc * diff * diff / (dE * dE);
+  const double G = -2.0 * nocc * diff * idE;   // dE/de1; dE/de2 = -G
+  o.E = 0.5 * G * diff;                        // -n (e1 - e2)^2 / dE
+  const double GD = -o.E * idE;                // dE/d(dE) = n (e1 - e2)^2 / dE^2
   o.dV = kCoulomb * (-G * ex1 * g1 + G * ex2 * g2 + GD);
   o.dVi1 = kCoulomb * G * ex1 * g1;
   o.dVi2 = -kCoulomb * G * ex2 * g2;
   const double k1 = G * ex1 * X1 * a.cp * a.m;    // dE/dcos(alpha)
   const double k2 = -G * ex2 * X2 * a.cp * a.m;   // dE/dcos(beta)
-  const double r1e = G * (-a.eta / s1) * e1;      // dE/dr1
-  const double r2e = -G * (-a.eta / s2) * e2;     // dE/dr2
+  const double r1e = -G * es1 * e1;               // dE/dr1
+  const double r2e = G * es2 * e2;                // dE/dr2
+  const double inu1 = inu * ir1, inu2 = inu * ir2, inu_sq = inu * inu;
+  const double ir1_sq = ir1 * ir1, ir2_sq = ir2 * ir2;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const double dca_du = d1[q] / (nu * r1) - ca * u[q] / (nu * nu);
-    const double dcb_du = d2[q] / (nu * r2) - cb * u[q] / (nu * nu);
-    const double dca_dd1 = u[q] / (nu * r1) - ca * d1[q] / (r1 * r1);
-    const double dcb_dd2 = u[q] / (nu * r2) - cb * d2[q] / (r2 * r2);
-    o.gL[q] = k1 * dca_du + k2 * dcb_du;
-    o.gA1[q] = r1e * d1[q] / r1 + k1 * dca_dd1;
-    o.gA2[q] = r2e * d2[q] / r2 + k2 * dcb_dd2;
-    o.gC[q] = -(o.gL[q] + o.gA1[q] + o.gA2[q]);
+  for (int c = 0; c < 3; ++c) {
+    const double dca_du = d1[c] * inu1 - ca * u[c] * inu_sq;
+    const double dcb_du = d2[c] * inu2 - cb * u[c] * inu_sq;
+    const double dca_dd1 = u[c] * inu1 - ca * d1[c] * ir1_sq;
+    const double dcb_dd2 = u[c] * inu2 - cb * d2[c] * ir2_sq;
+    o.gL[c] = k1 * dca_du + k2 * dcb_du;
+    o.gA1[c] = r1e * d1[c] * ir1 + k1 * dca_dd1;
+    o.gA2[c] = r2e * d2[c] * ir2 + k2 * dcb_dd2;
+    o.gC[c] = -(o.gL[c] + o.gA1[c] + o.gA2[c]);
   }
 }
 
@@ -210,8 +238,30 @@ __global__ __launch_bounds__(kBlock) void k_ct_flags(SysView s, CtArgs a) {
   const double2 t2 = s.sth2[i];
   const bool mult = p.w != 0.0 || d.x != 0.0 || d.y != 0.0 || d.z != 0.0 || t.x != 0.0 ||
                     t.y != 0.0 || t.z != 0.0 || t.w != 0.0 || t2.x != 0.0 || t2.y != 0.0;
-  a.flag_s[i] = (a.a1_start[c + 1] > a.a1_start[c] ? kIsA1 : 0) |
-                (a.car_start[c + 1] > a.car_start[c] ? kIsCarrier : 0) | (mult ? kHasMult : 0);
+  const int a0 = a.a1_start[c], a1 = a.a1_start[c + 1];
+  const int c0 = a.car_start[c], c1 = a.car_start[c + 1];
+  a.flag_s[i] = (a1 > a0 ? kIsA1 : 0) | (c1 > c0 ? kIsCarrier : 0) | (mult ? kHasMult : 0);
+  a.rng_s[i] = make_int4(a0, a1, c0, c1);
+}
+
+// The side records of the lone pairs (after V_l is complete) and of the
+// acceptors (after V_int).
+__global__ __launch_bounds__(kBlock) void k_ct_records(SysView s, CtArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < a.n_lp) {
+    const int c = a.lp[2 * t + 1];
+    const double4 x = s.sp[a.inv_perm[a.lp[2 * t]]];
+    double4* r = reinterpret_cast<double4*>(a.lp_rec) + 2 * (size_t)t;
+    r[0] = make_double4(x.x, x.y, x.z, kCoulomb * a.Vlp[t]);
+    r[1] = make_double4(a.lp_par[2 * t], a.lp_par[2 * t + 1], a.rvdw[c], 0.0);
+  }
+  if (t < a.n_acc) {
+    const int a1 = a.acc[2 * t], a2 = a.acc[2 * t + 1];
+    const double4 x = s.sp[a.inv_perm[a2]];
+    double4* r = reinterpret_cast<double4*>(a.acc_rec) + 2 * (size_t)t;
+    r[0] = make_double4(x.x, x.y, x.z, kCoulomb * a.Vint[a1]);
+    r[1] = make_double4(kCoulomb * a.Vint[a2], a.rvdw[a1], a.rvdw[a2], a.ah[t]);
+  }
 }
 
 // Real-space part of V_l: the other molecules within the cutoff (Ewald or
@@ -227,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_ct_vlp(SysView s, CtArgs a) {
   site_pos(s, i, xi);
   double V = 0.0;
   const int nn = s.nc_near[i];
-  wave_compact(
+  wave_compact<4>(
       s.nc_all[i], ring[wv],
       [&](int k, int& v) {
         v = all_entry(s, i, k, nn);
@@ -334,32 +384,32 @@ __global__ __launch_bounds__(kBlock) void k_ct_pairs_lp(SysView s, CtArgs a, Red
   double E = 0.0, w = 0.0, FL[3] = {0.0, 0.0, 0.0}, FC[3] = {0.0, 0.0, 0.0};
   if (p < a.n_lp) {   // wave-uniform
     const int i = a.inv_perm[a.lp[2 * p + 1]];
-    double xL[3], xc[3];
-    site_pos(s, a.inv_perm[a.lp[2 * p]], xL);
-    site_pos(s, i, xc);
+    LpSide l;
+    load_lp(a, p, l);
+    site_pos(s, i, l.xc);
     const int nn = s.nc_near[i];
-    wave_compact(
+    const int2* rng = reinterpret_cast<const int2*>(a.rng_s);   // [2 j]: a1 range
+    wave_compact<4>(
         s.nc_all[i], ring[wv],
         [&](int e, int& v) {
           v = all_entry(s, i, e, nn);
-          return (a.flag_s[v] & kIsA1) != 0;
+          const int2 r = rng[2 * (size_t)v];
+          return r.y > r.x;
         },
         [&](int j) {
-          double x1[3];
-          site_pos(s, j, x1);
-          const int cj = a.perm[j];
-          for (int r = a.a1_start[cj]; r < a.a1_start[cj + 1]; ++r) {
-            const int k = a.a1_ref[r];
-            double x2[3];
-            site_pos(s, a.inv_perm[a.acc[2 * k + 1]], x2);
+          AccSide q;
+          site_pos(s, j, q.x1);
+          const int2 rg = rng[2 * (size_t)j];
+          for (int r = rg.x; r < rg.y; ++r) {
+            load_acc(a, a.a1_ref[r], q);
             CtPair o;
-            ct_pair(s, a, p, k, xL, xc, x1, x2, o);
+            ct_pair(s, a, l, q, o);
             E += o.E;
             w += o.dV;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              FL[q] -= o.gL[q];
-              FC[q] -= o.gC[q];
+            for (int c = 0; c < 3; ++c) {
+              FL[c] -= o.gL[c];
+              FC[c] -= o.gC[c];
             }
           }
         });
@@ -392,49 +442,49 @@ __global__ __launch_bounds__(kBlock) void k_ct_pairs_acc(SysView s, CtArgs a) {
   if (k >= a.n_acc) return;   // wave-uniform; no block-wide barrier follows
   double F1[3] = {0.0, 0.0, 0.0}, F2[3] = {0.0, 0.0, 0.0}, u1 = 0.0, u2 = 0.0;
   const int i = a.inv_perm[a.acc[2 * k]];
-  double x1[3], x2[3];
-  site_pos(s, i, x1);
-  site_pos(s, a.inv_perm[a.acc[2 * k + 1]], x2);
+  AccSide q;
+  load_acc(a, k, q);
+  site_pos(s, i, q.x1);
   const int nn = s.nc_near[i];
-  wave_compact(
+  const int2* rng = reinterpret_cast<const int2*>(a.rng_s);   // [2 j + 1]: carrier range
+  wave_compact<4>(
       s.nc_all[i], ring[wv],
       [&](int e, int& v) {
         v = all_entry(s, i, e, nn);
-        return (a.flag_s[v] & kIsCarrier) != 0;
+        const int2 r = rng[2 * (size_t)v + 1];
+        return r.y > r.x;
       },
       [&](int j) {
-        double xc[3];
-        site_pos(s, j, xc);
-        const int cj = a.perm[j];
-        for (int r = a.car_start[cj]; r < a.car_start[cj + 1]; ++r) {
-          const int p = a.car_ref[r];
-          double xL[3];
-          site_pos(s, a.inv_perm[a.lp[2 * p]], xL);
+        LpSide l;
+        site_pos(s, j, l.xc);
+        const int2 rg = rng[2 * (size_t)j + 1];
+        for (int r = rg.x; r < rg.y; ++r) {
+          load_lp(a, a.car_ref[r], l);
           CtPair o;
-          ct_pair(s, a, p, k, xL, xc, x1, x2, o);
+          ct_pair(s, a, l, q, o);
           u1 += o.dVi1;
           u2 += o.dVi2;
 #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            F1[q] -= o.gA1[q];
-            F2[q] -= o.gA2[q];
+          for (int c = 0; c < 3; ++c) {
+            F1[c] -= o.gA1[c];
+            F2[c] -= o.gA2[c];
           }
         }
       });
   u1 = wave_sum(u1);
   u2 = wave_sum(u2);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    F1[q] = wave_sum(F1[q]);
-    F2[q] = wave_sum(F2[q]);
+  for (int c = 0; c < 3; ++c) {
+    F1[c] = wave_sum(F1[c]);
+    F2[c] = wave_sum(F2[c]);
   }
   if (lane == 0) {
     a.ua[2 * (size_t)k] = u1;
     a.ua[2 * (size_t)k + 1] = u2;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      a.Fa[6 * (size_t)k + q] = F1[q];
-      a.Fa[6 * (size_t)k + 3 + q] = F2[q];
+    for (int c = 0; c < 3; ++c) {
+      a.Fa[6 * (size_t)k + c] = F1[c];
+      a.Fa[6 * (size_t)k + 3 + c] = F2[c];
     }
   }
 }
@@ -487,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_ct_wforce_lp(SysView s, CtArgs a) {
   site_pos(s, i, xi);
   double F[3] = {0.0, 0.0, 0.0};
   const int nn = s.nc_near[i];
-  wave_compact(
+  wave_compact<4>(
       s.nc_all[i], ring[wv],
       [&](int k, int& v) {
         v = all_entry(s, i, k, nn);
@@ -536,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_ct_wforce_mp(SysView s, CtArgs a, do
   rec_mp(s, i, Mi, xi);
   double F[3] = {0.0, 0.0, 0.0}, E[3] = {0.0, 0.0, 0.0}, G[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nn = s.nc_near[i];
-  wave_compact(
+  wave_compact<4>(
       s.nc_all[i], ring[wv],
       [&](int k, int& v) {
         v = all_entry(s, i, k, nn);
@@ -706,6 +756,8 @@ void launch_ct_gather_pot(const SysView& s, const PmeView& pm, const CtArgs& a, 
 
 void launch_ct_pairs(const SysView& s, const CtArgs& a, Reduce& red, hipStream_t st) {
   const dim3 b(kBlock);
+  const int nr = std::max(std::max(a.n_lp, a.n_acc), 1);
+  hipLaunchKernelGGL(k_ct_records, dim3((nr + kBlock - 1) / kBlock), b, 0, st, s, a);
   const dim3 gl((std::max(a.n_lp, 1) + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(k_ct_pairs_lp, gl, b, 0, st, s, a, red);
   red.nparts[S_ECT] = (int)gl.x;

@@ -211,6 +211,9 @@ struct CtArgs {
   const int* perm;        // sorted -> caller
   const int* inv_perm;    // caller -> sorted
   int* flag_s;            // [n] sorted: a1 / carrier / has-multipoles bits
+  int4* rng_s;            // [n] sorted: a1_start range, car_start range
+  double* lp_rec;         // [n_lp][8] x_l, kC V_l, n, ae, rvdw of the carrier, 0
+  double* acc_rec;        // [n_acc][8] x_a2, kC V_int(a1), kC V_int(a2), rvdw a1, a2, ah
   double* Vlp;            // [n_lp] V_l (e/A)
   double* Gr;             // [n_lp][3] reciprocal grad V_l
   double* Vint;           // [n] V_int at acceptor atoms (e/A)
