@@ -103,6 +103,7 @@ class Params:
     tol: float = 1e-8               # Debye, RMS of alpha r
     max_iter: int = 200
     mumu_intramolecular: bool = True  # False: the variant excluding them
+    precond: str = "diag"           # 'diag' (alpha per site) | 'molblock'
 
     @property
     def periodic(self):
@@ -198,6 +199,66 @@ def apply_T(sysm, prm, p_pol, ctx=None, sites=None):
 def precond(sysm, r_pol):
     a3 = sysm.alpha3[sysm.pol]
     return np.einsum("nab,nb->na", a3, r_pol)
+
+
+MAX_BLOCK_SITES = 4   # molecules with more polarizable sites keep alpha per site
+
+
+def molblock_inverses(sysm, prm, ctx=None):
+    """The molecular block preconditioner: for every molecule with at most
+    MAX_BLOCK_SITES polarizable sites, the inverse of its block of T in the
+    bare (unscreened) form -- alpha_i^-1 on the diagonal, minus the
+    Thole-damped field tensor of a unit dipole between two sites of the
+    molecule off it (the mumu class, bare kernel).  For a cluster that is
+    exactly the molecule's block of T; in a box the molecule's periodic
+    images and the Ewald self terms are left out, which only changes how
+    well it preconditions.  A block that is not positive definite, and every
+    larger molecule, falls back to alpha per site.  Returns a list of
+    (polarizable indices, inverse (3k, 3k))."""
+    from .tensors import deriv_tensor
+    c = _ctx(sysm, prm, ctx)
+    s = c.s
+    pol = c.pol
+    mol = s.mol[pol]
+    a3 = s.alpha3[pol]
+    abar, at = c.thole
+    out = []
+    for m in np.unique(mol):
+        idx = np.flatnonzero(mol == m)
+        k = len(idx)
+        if k > MAX_BLOCK_SITES:
+            out += [(np.array([t]), a3[t]) for t in idx]
+            continue
+        M = np.zeros((k, 3, k, 3))
+        for u in range(k):
+            M[u, :, u, :] = np.linalg.inv(a3[idx[u]])
+        if k > 1:
+            uu, vv = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+            off = uu != vv
+            uu, vv = uu[off], vv[off]
+            i, j = pol[idx[uu]], pol[idx[vv]]
+            R = s.pos[i] - s.pos[j]
+            r = np.linalg.norm(R, axis=1)
+            coef = rs.class_coefficients(c.mumu_cls, r, np.ones(len(r), bool), "bare", prm.beta,
+                                         abar[i], abar[j], np.minimum(at[i], at[j]), 2)
+            D2 = deriv_tensor(2, R, coef)     # field of a unit dipole at j seen at i
+            for n_, (u, v) in enumerate(zip(uu, vv)):
+                M[u, :, v, :] = -D2[n_]
+        M = M.reshape(3 * k, 3 * k)
+        try:
+            np.linalg.cholesky(M)
+        except np.linalg.LinAlgError:
+            out += [(np.array([t]), a3[t]) for t in idx]
+            continue
+        out.append((idx, np.linalg.inv(M)))
+    return out
+
+
+def precond_blocks(blocks, r_pol):
+    z = np.zeros_like(r_pol)
+    for idx, Minv in blocks:
+        z[idx] = (Minv @ r_pol[idx].ravel()).reshape(-1, 3)
+    return z
 
 
 def dense_T_columns(sysm, prm, ctx=None):
@@ -348,12 +409,19 @@ def virial(sysm, prm, mu_pol, ctx=None):
 
 
 def solve(sysm, prm, E0, ctx=None, x0=None):
+    """PCG for T mu = E0.  The tolerance always measures alpha r (Debye RMS),
+    whichever preconditioner runs."""
     c = _ctx(sysm, prm, ctx)
     mv = lambda v: apply_T(sysm, prm, v, ctx=c)
-    pc = lambda r: precond(sysm, r)
+    measure = lambda r: precond(sysm, r)
+    if prm.precond == "molblock":
+        blocks = molblock_inverses(sysm, prm, c)
+        pc = lambda r: precond_blocks(blocks, r)
+    else:
+        pc = measure
     if x0 is None:
         x0 = pc(E0)
-    return pcg(mv, pc, E0, x0, prm.tol, prm.max_iter)
+    return pcg(mv, pc, E0, x0, prm.tol, prm.max_iter, measure=measure)
 
 
 def tcg(sysm, prm, E0, order, omega=0.0, ctx=None, x0=None):

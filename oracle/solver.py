@@ -31,15 +31,18 @@ def rms_debye(z):
     return DEBYE * float(np.sqrt(np.sum(z * z) / len(z)))
 
 
-def pcg(matvec, precond, rhs, x0, tol, max_iter=200, max_restarts=5):
-    """Returns (x, iterations, true rho)."""
+def pcg(matvec, precond, rhs, x0, tol, max_iter=200, max_restarts=5, measure=None):
+    """Returns (x, iterations, true rho).  The stop tests take the RMS of
+    measure(r) (default: the preconditioned residual itself)."""
+    if measure is None:
+        measure = precond
     x = x0.copy()
     iters = 0
     for _ in range(max_restarts + 1):
         r = rhs - matvec(x)
         z = precond(r)
-        if rms_debye(z) <= tol:
-            return x, iters, rms_debye(z)
+        if rms_debye(measure(r)) <= tol:
+            return x, iters, rms_debye(measure(r))
         p = z.copy()
         rz = float(np.sum(r * z))
         while iters < max_iter:
@@ -52,13 +55,12 @@ def pcg(matvec, precond, rhs, x0, tol, max_iter=200, max_restarts=5):
             r = r - gamma * q
             z = precond(r)
             iters += 1
-            if rms_debye(z) <= tol:
+            if rms_debye(measure(r)) <= tol:
                 break
             rz_new = float(np.sum(r * z))
             p = z + (rz_new / rz) * p
             rz = rz_new
-        true_z = precond(rhs - matvec(x))
-        rho = rms_debye(true_z)
+        rho = rms_debye(measure(rhs - matvec(x)))
         if rho <= tol or iters >= max_iter:
             return x, iters, rho
     return x, iters, rho
