@@ -5,7 +5,10 @@ One step = one full pol+elec energy/force evaluation of the 32,000-water
 periodic box (98.55 A, cutoff 9 A, beta 0.40/A, SPME 96^3 order 5, PCG to a
 true-residual RMS of 1e-8 D, cold start): cell sort and neighbour lists,
 permanent field (real space + SPME), PCG solve, E_pol, E_elec and all site
-forces.  Inputs are resident in HBM before timing starts.
+forces.  Inputs are resident in HBM before timing starts.  The solve runs
+with the molecular block preconditioner (--precond; the tolerance measures
+alpha r either way) and the same steps are timed with the diagonal one
+beside it.
 
 Prints ONE JSON line.  `value` is evaluations per second of the precision
 named in `dtype`; both precisions are reported under "fp64" and "mixed".
@@ -27,6 +30,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pol+elec energy/force evals/s @32k waters, FP32-mixed vs FP64; p50/p99 latency"
+PRECOND_NAMES = {"molblock": "molecular block-Jacobi (each water's 9x9 block of T, bare form)",
+                 "diag": "diagonal (alpha per site)"}
 WORKLOAD = "box32000"
 
 # MI355X published peaks: vector FP64 78.6 TFLOP/s, vector FP32 157.3
@@ -99,13 +104,13 @@ def _percentile(xs, q):
     return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def run_gpu(sysd, prm, precision, steps, warmup):
+def run_gpu(sysd, prm, precision, steps, warmup, precond="molblock", profile=True):
     import torch
     from paper_2201_00804_amd import Engine, default_params
 
     params = default_params(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"],
                             order=prm["order"], tol=prm["tol"], precision=precision,
-                            max_iter=400)
+                            max_iter=400, precond=precond)
     eng = Engine(0)
     eng.load(sysd, params)
     dev = eng.device
@@ -132,6 +137,12 @@ def run_gpu(sysd, prm, precision, steps, warmup):
         times.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    if not profile:
+        st = eng.stats()
+        out = dict(total_s=total, step_s=times, iters=info[0], true_rms_debye=info[1],
+                   e_pol=info[2], e_elec=info[3], stats=st)
+        eng.close()
+        return out
     # the same steps again with HIP events around the matvec kernel only
     # (roofline), then around every phase (breakdown)
     eng.set_profiling(True, phases=["matvec"])
@@ -151,7 +162,7 @@ def run_gpu(sysd, prm, precision, steps, warmup):
     return out
 
 
-def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
+def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0, precond="molblock"):
     """Fixed-cost truncated CG (with the peek step) against the converged
     solve, both without forces: ms per evaluation (positions update, lists,
     field, solve, E_pol) and E_pol; in FP64 also TCG energies with their
@@ -161,7 +172,7 @@ def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
 
     params = default_params(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"],
                             order=prm["order"], tol=prm["tol"], precision=precision,
-                            max_iter=400)
+                            max_iter=400, precond=precond)
     eng = Engine(0)
     eng.load(sysd, params)
     pos = torch.as_tensor(sysd["pos"], dtype=torch.float64, device=eng.device).contiguous()
@@ -202,7 +213,7 @@ def run_tcg(sysd, prm, precision, steps, warmup, orders=(1, 2), omega=1.0):
     return out
 
 
-def run_md(name, precision, relax_steps, steps, dt=1.0, predictor=3):
+def run_md(name, precision, relax_steps, steps, dt=1.0, predictor=3, precond="molblock"):
     """Beeman dynamics demo: the synthetic start relaxed with damped steps
     (0.2 fs, friction 0.3), then `steps` plain Beeman steps of dt fs with
     thermal velocities, warm-started solves with the extrapolating
@@ -220,7 +231,7 @@ def run_md(name, precision, relax_steps, steps, dt=1.0, predictor=3):
     eng = Engine(0)
     eng.load(d, default_params(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"],
                                order=cfg["order"], tol=cfg["tol"], precision=precision,
-                               max_iter=400))
+                               max_iter=400, precond=precond))
     eng.set_predictor(predictor)
     args = (t(m["masses"]), t(m["vsites"], torch.int32), t(m["bonds"], torch.int32),
             t(m["bond_k"]), t(m["bond_r0"]), t(m["rep_radius"]), m["rep_eps"])
@@ -594,6 +605,9 @@ def main():
     ap.add_argument("--no-tcg", action="store_true")
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-ct", action="store_true")
+    ap.add_argument("--precond", choices=["molblock", "diag"], default="molblock",
+                    help="preconditioner of the PCG solve (the other one is timed beside it)")
+    ap.add_argument("--no-alt-precond", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -615,7 +629,7 @@ def main():
     for prec in precisions:
         print(f"[bench] {prec}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
               flush=True)
-        results[prec] = run_gpu(sysd, prm, prec, args.steps, args.warmup)
+        results[prec] = run_gpu(sysd, prm, prec, args.steps, args.warmup, args.precond)
         r = results[prec]
         print(f"[bench] {prec}: {1e3 * r['total_s'] / args.steps:.2f} ms/step, iters "
               f"{r['iters']}, rms {r['true_rms_debye']:.2e} D", file=sys.stderr, flush=True)
@@ -647,7 +661,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "32,000 rigid waters, 98.55 A periodic box, cutoff 9 A, "
                                "beta 0.40/A, SPME 96^3 order 5, PCG to 1e-8 D RMS (cold start)",
-                   "n_waters": 32000, "n_sites": len(sysd["pos"]), "precision": head},
+                   "n_waters": 32000, "n_sites": len(sysd["pos"]), "precision": head,
+                   "precond": PRECOND_NAMES[args.precond]},
         "latency_ms": {"p50": round(1e3 * _percentile(main_r["step_s"], 0.5), 3),
                        "p99": round(1e3 * _percentile(main_r["step_s"], 0.99), 3)},
         "roofline": roofline(main_r, head),
@@ -672,12 +687,24 @@ def main():
                                            np.mean(a["forces"] ** 2))),
             "mu_rms_debye": float(4.803204 * np.sqrt(np.mean(np.sum((b["mu"] - a["mu"]) ** 2, 1)))),
         }
+    if not args.no_alt_precond:
+        alt = "diag" if args.precond == "molblock" else "molblock"
+        out["precond_" + alt] = {"precond": PRECOND_NAMES[alt]}
+        for prec in precisions:
+            print(f"[bench] {prec} with the {alt} preconditioner", file=sys.stderr, flush=True)
+            r = run_gpu(sysd, prm, prec, args.steps, args.warmup, alt, profile=False)
+            out["precond_" + alt][prec] = dict(
+                value=round(args.steps / r["total_s"], 3),
+                ms_per_step=round(1e3 * r["total_s"] / args.steps, 3),
+                iterations=r["iters"], true_rms_debye=r["true_rms_debye"], e_pol=r["e_pol"])
+            print(f"[bench] {prec} {alt}: {1e3 * r['total_s'] / args.steps:.2f} ms/step, iters "
+                  f"{r['iters']}", file=sys.stderr, flush=True)
     if not args.no_tcg:
         out["tcg"] = {}
         for prec in precisions:
             print(f"[bench] tcg {prec}: converged solve vs TCG-1/TCG-2 with peek, no forces",
                   file=sys.stderr, flush=True)
-            t = run_tcg(sysd, prm, prec, args.steps, args.warmup)
+            t = run_tcg(sysd, prm, prec, args.steps, args.warmup, precond=args.precond)
             out["tcg"][prec] = t
             print("[bench] tcg " + prec + ": " + ", ".join(
                 f"{k} {v['ms']} ms (E_pol rel err {v['e_pol_rel_err']:.2e})"
@@ -688,7 +715,7 @@ def main():
             for prec in precisions:
                 print(f"[bench] md {name} {prec}: {relax} relaxation + {nsteps} Beeman steps",
                       file=sys.stderr, flush=True)
-                r = run_md(name, prec, relax, nsteps)
+                r = run_md(name, prec, relax, nsteps, precond=args.precond)
                 r["precision"] = prec
                 out["md"].append(r)
                 print(f"[bench] md {name} {prec}: {r['steps_per_s']} steps/s, "

@@ -71,6 +71,16 @@ typedef enum {
 
 typedef enum { SIBFA_FP64 = 0, SIBFA_MIXED = 1 } sibfa_precision;
 
+/* Preconditioner of the PCG solve (Eq. 18; the paper names a preconditioned
+ * conjugate gradient and leaves the preconditioner open).  DIAG: z = alpha r
+ * per site.  MOLBLOCK: z = M^-1 r with M, per molecule of at most 4
+ * polarizable sites, the molecule's block of T in bare form (alpha^-1 on
+ * the diagonal, the Thole-damped dipole-dipole tensors between its sites);
+ * larger molecules keep alpha per site.  Either way the solve stops on the
+ * RMS of alpha (E - T mu), so both reach the same tolerance; the truncated
+ * solver (sibfa_solve_tcg) always uses DIAG. */
+typedef enum { SIBFA_PRECOND_DIAG = 0, SIBFA_PRECOND_MOLBLOCK = 1 } sibfa_precond;
+
 typedef struct {
   double ewald_beta;    /* A^-1, Ewald splitting parameter (periodic only)   */
   double cutoff;        /* A, real-space cutoff; must be < min(box)/2        */
@@ -81,6 +91,7 @@ typedef struct {
   int max_iter;         /* PCG iteration limit, all sequences together       */
   sibfa_precision precision; /* FP64, or FP32 pair/PME math with FP64
                                 accumulation, reductions and residuals      */
+  sibfa_precond precond;     /* preconditioner of sibfa_solve_induced       */
 } sibfa_params;
 
 typedef struct {

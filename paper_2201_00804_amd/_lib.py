@@ -13,13 +13,15 @@ SIBFA_OK = 0
 STATUS_NAMES = {0: "SIBFA_OK", -1: "SIBFA_E_ARG", -2: "SIBFA_E_STATE", -3: "SIBFA_E_NOMEM",
                 -4: "SIBFA_E_NOT_SPD", -5: "SIBFA_E_NOT_CONVERGED", -6: "SIBFA_E_DEVICE"}
 FP64, MIXED = 0, 1
+PRECOND_DIAG, PRECOND_MOLBLOCK = 0, 1
 
 
 class Params(ctypes.Structure):
     _fields_ = [("ewald_beta", ctypes.c_double), ("cutoff", ctypes.c_double),
                 ("grid", ctypes.c_int * 3), ("order", ctypes.c_int),
                 ("thole_a", ctypes.c_double), ("tol_debye", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -128,6 +128,8 @@ struct sibfa_ctx_s {
   bool phi_e0 = false;
   // second direction buffer (the spread kernel reads one and writes the other)
   double4* p2 = nullptr;
+  // molecular block preconditioner (sized n when params.precond asks for it)
+  PcView pcv{};
   float4* p2_32 = nullptr;
   // reductions
   Reduce red{};
@@ -353,6 +355,8 @@ sibfa_status check_params(sibfa_ctx c, const sibfa_params* p, const double* box)
     return fail(c, SIBFA_E_ARG, "tol_debye must be > 0 and max_iter >= 1");
   if (!(p->thole_a > 0) || !std::isfinite(p->thole_a))
     return fail(c, SIBFA_E_ARG, "thole_a must be positive");
+  if (p->precond != SIBFA_PRECOND_DIAG && p->precond != SIBFA_PRECOND_MOLBLOCK)
+    return fail(c, SIBFA_E_ARG, "precond must be SIBFA_PRECOND_DIAG or SIBFA_PRECOND_MOLBLOCK");
   if (p->precision != SIBFA_FP64 && p->precision != SIBFA_MIXED)
     return fail(c, SIBFA_E_ARG, "unknown precision");
   if (box) {
@@ -783,6 +787,7 @@ void enqueue_coef(sibfa_ctx c, hipStream_t st) {
   launch_pol_coef(s, static_cast<double2*>(c->coefbuf.p),
                   mixed(c) ? static_cast<float2*>(c->coef32buf.p) : nullptr,
                   static_cast<double2*>(c->icoefbuf.p), st);
+  if (c->prm.precond == SIBFA_PRECOND_MOLBLOCK) launch_pc_build(s, c->pcv, st);
   c->coef_valid = true;
 }
 
@@ -911,7 +916,9 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     return SIBFA_OK;
   }
   ensure_coef(c);
+  const bool blk = c->prm.precond == SIBFA_PRECOND_MOLBLOCK;
   if (warm && c->mu_have) warm_guess(c, s, st);
+  else if (blk) launch_pc_apply(s, c->pcv, c->E0, c->x, st);
   else launch_precond(s, c->E0, c->x, st);
   launch_copy4(c->x, c->x, c->x32, c->npol, st);
   const double tol = c->prm.tol_debye;
@@ -955,7 +962,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
     // below removes its rounding)
     const bool fp32_res = fresh && mix && !(warm && c->mu_have);
     matvec(c, c->x, c->x32, c->t, -1, fp32_res);
-    if (fresh)
+    if (blk)
+      launch_pc_init_residual(s, c->pcv, c->red, c->E0, c->t, c->r, c->z,
+                              fresh ? c->p : nullptr, fresh ? c->p32 : nullptr,
+                              fresh ? S_RZ0 : S_RZ0 + (kk & 1), st);
+    else if (fresh)
       launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, c->p, c->p32, S_RZ0, st);
     else
       launch_init_residual(s, c->red, c->E0, c->t, c->r, c->z, nullptr, nullptr,
@@ -1055,8 +1066,12 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
         }
         {
           Phase ph(c, SIBFA_PH_UPDATE);
-          launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z, c->p,
-                        c->q, st);
+          if (blk)
+            launch_pc_update(s, c->pcv, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x,
+                             c->r, c->z, c->p, c->q, st);
+          else
+            launch_update(s, c->red, S_RZ0 + (k & 1), S_RZ0 + ((k + 1) & 1), c->x, c->r, c->z,
+                          c->p, c->q, st);
           // the last iteration of a batch is tested here, the others by
           // the next direction update
           if (b == nb - 1 || it + j + 1 >= c->prm.max_iter)
@@ -1542,6 +1557,7 @@ void sibfa_default_params(sibfa_params* p) {
   p->tol_debye = 1e-8;
   p->max_iter = 200;
   p->precision = SIBFA_FP64;
+  p->precond = SIBFA_PRECOND_DIAG;
 }
 
 sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream, sibfa_alloc_fn alloc_fn,
@@ -1635,6 +1651,8 @@ size_t sibfa_footprint_bytes(int n_sites, int n_polarizable, const double* box,
   // lists, plus an FP32 copy of the former in mixed precision
   bytes += np * (cap_pol + 8) * 2 * sizeof(double);
   if (p->precision == SIBFA_MIXED) bytes += np * cap_pol * 2 * sizeof(float);
+  if (p->precond == SIBFA_PRECOND_MOLBLOCK)   // group sizes, members, packed inverses
+    bytes += n * ((1 + kPcMax) * sizeof(int) + kPcPacked * sizeof(double));
   return bytes + (1 << 20);
 }
 
@@ -1664,6 +1682,7 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
   c->ncell = c->nc[0] * c->nc[1] * c->nc[2];
   const size_t n = n_sites;
   auto& L = c->bufs;
+  c->pcv = PcView{};
   bool ok = alloc_into(c, L, c->xyz_c, 3 * n) && alloc_into(c, L, c->q_c, n) &&
             alloc_into(c, L, c->dip_c, 3 * n) && alloc_into(c, L, c->quad_c, 6 * n) &&
             alloc_into(c, L, c->alpha_c, 6 * n) && alloc_into(c, L, c->thole_c, n) &&
@@ -1686,6 +1705,9 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->q, n) && alloc_into(c, L, c->t, n) && alloc_into(c, L, c->p32, n) &&
             alloc_into(c, L, c->x32, n) && alloc_into(c, L, c->p2, n) && alloc_into(c, L, c->p2_32, n) && alloc_into(c, L, c->mu_s, n) &&
             alloc_into(c, L, c->mu_s32, n) && alloc_into(c, L, c->Freal, n);
+  if (ok && c->prm.precond == SIBFA_PRECOND_MOLBLOCK)
+    ok = alloc_into(c, L, c->pcv.n, n) && alloc_into(c, L, c->pcv.mem, (size_t)kPcMax * n) &&
+         alloc_into(c, L, c->pcv.inv, (size_t)kPcPacked * n);
   for (int k = 0; k < 4 && ok; ++k) ok = alloc_into(c, L, c->ncnt[k], n);
   ok = ok && alloc_into(c, L, c->ncnear, n);
   // partial sums: one per block of the largest reducing launch (site

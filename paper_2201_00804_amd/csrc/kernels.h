@@ -93,6 +93,29 @@ void launch_slot_totals(const Reduce& red, const SlotList& sl, double* out, hipS
 void launch_check(const Reduce& red, int* flag, double* zz_out, int iter, double zz_stop,
                   double zz_replace, const double* zz_ref, hipStream_t st);
 void launch_precond(const SysView& s, const double4* in, double4* out, hipStream_t st);
+
+// precond.hip: molecular block preconditioner (polarizable order).
+constexpr int kPcMax = 4;                               // sites per block
+constexpr int kPcPacked = 3 * kPcMax * (3 * kPcMax + 1) / 2;   // packed M^-1
+struct PcView {
+  int* n;         // [npol] group size at the group's leader, 0 elsewhere
+  int* mem;       // [npol][kPcMax] members of the leader's group (increasing)
+  double* inv;    // [npol][kPcPacked] M^-1 of the leader's group, lower packed
+};
+// M and M^-1 for the current positions and polarizabilities (after the
+// same-molecule polarizable lists)
+void launch_pc_build(const SysView& s, const PcView& pc, hipStream_t st);
+// out = M^-1 in
+void launch_pc_apply(const SysView& s, const PcView& pc, const double4* in, double4* out,
+                     hipStream_t st);
+// as launch_init_residual / launch_update with z = M^-1 r; S_ZZ still
+// receives |alpha r|^2, the quantity the tolerance measures
+void launch_pc_init_residual(const SysView& s, const PcView& pc, Reduce& red, const double4* E0,
+                             const double4* t, double4* r, double4* z, double4* p, float4* p32,
+                             int rz_slot, hipStream_t st);
+void launch_pc_update(const SysView& s, const PcView& pc, Reduce& red, int rz_slot,
+                      int rz_next_slot, double4* x, double4* r, double4* z, const double4* p,
+                      const double4* q, hipStream_t st);
 // x += w z over the polarizable sites
 void launch_axpy4(const SysView& s, double4* x, const double4* z, double w, hipStream_t st);
 // a.b into slot (and a.b2 into slot2 when b2 is given)

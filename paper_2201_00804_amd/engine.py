@@ -25,6 +25,8 @@ def default_params(**kw):
             p.grid[0], p.grid[1], p.grid[2] = g
         elif k == "precision":
             p.precision = {"fp64": _lib.FP64, "mixed": _lib.MIXED}.get(v, v)
+        elif k == "precond":
+            p.precond = {"diag": _lib.PRECOND_DIAG, "molblock": _lib.PRECOND_MOLBLOCK}.get(v, v)
         elif k == "beta":
             p.ewald_beta = v
         elif k == "tol":

@@ -55,10 +55,36 @@ def test_default_params_and_footprint():
     assert lib.sibfa_footprint_bytes(320, 192, None, ctypes.byref(p)) > 320 * 319 * 4
 
 
-def test_struct_layout_matches_header():
+def test_struct_layout_matches_header(tmp_path):
+    """The binding's structures against the header, as a C compiler lays
+    them out (size and the offset of every field)."""
+    import shutil
+    import subprocess
     mod, _ = _lib()
-    assert ctypes.sizeof(mod.Params) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(mod.Stats) == 4 + 4 + 7 * 8 + 3 * 4 + 4   # tail padding to 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"sibfa_params": mod.Params, "sibfa_stats": mod.Stats,
+               "sibfa_md_stats": mod.MdStats, "sibfa_ct_params": mod.CtParams,
+               "sibfa_profile": mod.Profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sibfa_pol.h"',
+             'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def _prototypes():

@@ -1,0 +1,108 @@
+"""Molecular block preconditioner through the C-ABI (params.precond =
+SIBFA_PRECOND_MOLBLOCK) against the oracle's PCG with precond='molblock'
+(oracle/model.py, pinned in tests/test_oracle_precond.py).
+
+Bars: mu elementwise within 1e-7 of its largest entry, iterations within one
+of the oracle's, E_pol within 1e-6 relative (FP64 both sides); the true
+residual within the tolerance; fewer iterations than alpha per site on the
+same system.  At 4,096 waters, where the oracle's solve is out of reach,
+the block-preconditioned solve equals the alpha-per-site one to the
+tolerance (FP64 and mixed).  The truncated solver ignores the setting."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.model import System
+from synth import water_box, water_cluster, config_system
+from tests.gpu_util import say, oracle_params, gpu_params, engine_for, rel_err, pol_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _case(name):
+    if name == "cluster":
+        return water_cluster(9, 2), dict(tol=1e-9)
+    if name == "box27":
+        return water_box(27, 9.5, 3), dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-9)
+    d, cfg = config_system("box216")
+    return d, dict(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"], tol=1e-9)
+
+
+@pytest.mark.parametrize("name", ["cluster", "box27", "box216"])
+def test_molblock_matches_oracle(name):
+    d, kw = _case(name)
+    s = System.from_dict(d)
+    op = dataclasses.replace(oracle_params(d, **kw), precond="molblock")
+    ref = oracle.evaluate(s, op, forces=False)
+    rows = pol_rows(d)
+    eng = engine_for(d, gpu_params(d, precond="molblock", **kw))
+    mu, it, rms = eng.solve()
+    e_pol, _, _ = eng.energy_forces(forces=False)
+    eng.close()
+    mu = mu.cpu().numpy()
+    diag = engine_for(d, gpu_params(d, **kw))
+    _, it_d, _ = diag.solve()
+    diag.close()
+    err = rel_err(mu[rows], ref["mu"])
+    say(f"[precond] {name}: iterations {it} (oracle {ref['iters']}, alpha per site {it_d}), "
+        f"mu {err:.2e}, E_pol {e_pol:.10f} vs {ref['E_pol']:.10f}")
+    assert rms <= kw["tol"]
+    assert err < 1e-7
+    assert abs(it - ref["iters"]) <= 1
+    assert abs(e_pol - ref["E_pol"]) <= 1e-6 * abs(ref["E_pol"])
+    assert it < it_d
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_molblock_box4096_equals_alpha_per_site(precision):
+    d, cfg = config_system("box4096")
+    kw = dict(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"], tol=cfg["tol"],
+              max_iter=400)
+    out = {}
+    for pc in ["diag", "molblock"]:
+        eng = engine_for(d, gpu_params(d, precision=precision, precond=pc, **kw))
+        mu, it, rms = eng.solve()
+        ep, ee, F = eng.energy_forces()
+        out[pc] = (mu.cpu().numpy(), it, rms, ep, ee, F.cpu().numpy())
+        eng.close()
+    mu_d, it_d, rms_d, ep_d, ee_d, F_d = out["diag"]
+    mu_b, it_b, rms_b, ep_b, ee_b, F_b = out["molblock"]
+    say(f"[precond] box4096 {precision}: iterations {it_b} vs {it_d}, E_pol {ep_b:.8f} vs "
+        f"{ep_d:.8f}, mu {rel_err(mu_b, mu_d):.2e}, forces {rel_err(F_b, F_d):.2e}")
+    assert rms_b <= cfg["tol"] and rms_d <= cfg["tol"]
+    assert it_b < it_d
+    # two solutions within the tolerance of the same system
+    assert rel_err(mu_b, mu_d) < 1e-6
+    assert abs(ep_b - ep_d) <= 1e-7 * abs(ep_d)
+    assert ee_b == ee_d
+    assert rel_err(F_b, F_d) < 1e-6
+
+
+def test_truncated_solver_ignores_the_setting():
+    d, kw = _case("box27")
+    res = []
+    for pc in ["diag", "molblock"]:
+        eng = engine_for(d, gpu_params(d, precond=pc, **kw))
+        mu, e = eng.solve_tcg(2)
+        res.append((mu.cpu().numpy(), e))
+        eng.close()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
+
+
+def test_bad_precond_rejected():
+    from paper_2201_00804_amd import Engine, SibfaError
+    d, kw = _case("cluster")
+    eng = Engine(0)
+    with pytest.raises(SibfaError) as e:
+        eng.load(d, gpu_params(d, precond=7, **kw))
+    assert e.value.status == -1
+    eng.close()
