@@ -13,8 +13,11 @@
 // Layout: the group of a molecule is kept by its leader, the member with
 // the smallest polarizable index (n[leader] = group size, 0 for the other
 // members); mem[4 i + k] lists the members in increasing order and
-// inv[kPcPacked i + ...] holds M^-1 of the leader's group, lower triangle
-// packed row by row.  A site of a larger molecule is a group of its own.
+// inv[kPcPacked i + ...] holds the Cholesky factor L of M (M = L L^T),
+// lower triangle packed row by row with 1 / L_jj on the diagonal, so that
+// z = M^-1 r is a forward and a backward substitution.  A site of a larger
+// molecule is a group of its own.  Every size has its own instantiation,
+// so the factor stays in registers.
 // The vector kernels run one thread per polarizable index; leaders work on
 // their whole group (no other thread touches those sites), the rest only
 // join the block reductions.
@@ -54,16 +57,25 @@ __device__ __forceinline__ int group_of(const SysView& s, int pi, int mem[kPcMax
   return cin + 1;
 }
 
-// y = M^-1 v for a group of NG sites (3 NG unknowns).
+// y = M^-1 v = L^-T L^-1 v for a group of NG sites (3 NG unknowns).
 template <int NG>
-__device__ __forceinline__ void apply_inv(const double* Mi, const double v[3 * NG],
+__device__ __forceinline__ void apply_inv(const double* L, const double v[3 * NG],
                                           double y[3 * NG]) {
+  constexpr int N = 3 * NG;
+  double w[N];
 #pragma unroll
-  for (int i = 0; i < 3 * NG; ++i) {
-    double acc = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double a = v[i];
 #pragma unroll
-    for (int j = 0; j < 3 * NG; ++j) acc += Mi[i >= j ? tri(i, j) : tri(j, i)] * v[j];
-    y[i] = acc;
+    for (int k = 0; k < i; ++k) a -= L[tri(i, k)] * w[k];
+    w[i] = a * L[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double a = w[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) a -= L[tri(k, i)] * y[k];
+    y[i] = a * L[tri(i, i)];
   }
 }
 
@@ -77,7 +89,88 @@ __device__ __forceinline__ double alpha_norm2(const SysView& s, int m, const dou
 
 }  // namespace
 
-// M of each leader's group, its Cholesky factorisation and M^-1.
+namespace {
+
+// M of a group of NG sites (lower packed), then its Cholesky factor with
+// 1 / L_jj on the diagonal; a block that is not positive definite is
+// replaced by blockdiag(alpha^-1), which is.
+template <int NG>
+__device__ __forceinline__ void build_group(const SysView& s, const int mem[kPcMax], double* out) {
+  constexpr int N = 3 * NG, P = N * (N + 1) / 2;
+  double M[P];
+  const int ia[6] = {0, 1, 1, 2, 2, 2}, ib[6] = {0, 0, 1, 0, 1, 2};
+  const int ka[6] = {0, 1, 3, 2, 4, 5};   // packed (xx,xy,xz,yy,yz,zz) index of (ia, ib)
+#pragma unroll
+  for (int t = 0; t < P; ++t) M[t] = 0.0;
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    const double* ai = s.ainv + 6 * (size_t)mem[u];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) M[tri(3 * u + ia[e], 3 * u + ib[e])] = ai[ka[e]];
+  }
+#pragma unroll
+  for (int u = 1; u < NG; ++u) {
+    const double4 pu = s.pp[mem[u]];
+#pragma unroll
+    for (int v = 0; v < u; ++v) {
+      const double4 pv = s.pp[mem[v]];
+      double R[3] = {pu.x - pv.x, pu.y - pv.y, pu.z - pv.z};
+      if (s.periodic)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) R[a] = min_image<double>(R[a], s.box[a], s.ibox[a]);
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
+      double c0[3], tp[5];
+      bare_coeffs<double, 2>(rinv, rinv2, c0);
+      thole_tp<double>(thole_pair(s, mem[u], mem[v]) * r2 * r * pu.w * pv.w, tp);
+      const double c1 = (1.0 - tp[1]) * c0[1], c2 = (1.0 - tp[2]) * c0[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          M[tri(3 * u + a, 3 * v + b)] = (a == b ? c1 : 0.0) - c2 * R[a] * R[b];
+    }
+  }
+  bool ok = true;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      if (ok) break;
+      // fallback: alpha per site
+#pragma unroll
+      for (int t = 0; t < P; ++t) M[t] = 0.0;
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        const double* ai = s.ainv + 6 * (size_t)mem[u];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) M[tri(3 * u + ia[e], 3 * u + ib[e])] = ai[ka[e]];
+      }
+      ok = true;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double d = M[tri(j, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= M[tri(j, k)] * M[tri(j, k)];
+      ok = ok && d > 0.0;
+      const double il = rsqrt(d > 0.0 ? d : 1.0);
+      M[tri(j, j)] = il;   // 1 / L_jj
+#pragma unroll
+      for (int i = j + 1; i < N; ++i) {
+        double v = M[tri(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= M[tri(i, k)] * M[tri(j, k)];
+        M[tri(i, j)] = v * il;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) out[t] = M[t];
+}
+
+}  // namespace
+
+// The group of each leader and the Cholesky factor of its M.
 __global__ __launch_bounds__(kBlock) void k_pc_build(SysView s, PcView pc) {
   const int pi = blockIdx.x * blockDim.x + threadIdx.x;
   if (pi >= s.npol) return;
@@ -86,77 +179,13 @@ __global__ __launch_bounds__(kBlock) void k_pc_build(SysView s, PcView pc) {
   pc.n[pi] = ng;
   if (ng == 0) return;
   for (int k = 0; k < kPcMax; ++k) pc.mem[kPcMax * (size_t)pi + k] = k < ng ? mem[k] : -1;
-  const int n3 = 3 * ng;
-  double M[kPcPacked], W[kPcPacked];
-  for (int t = 0; t < kPcPacked; ++t) M[t] = 0.0;
-  const int ia[6] = {0, 1, 1, 2, 2, 2}, ib[6] = {0, 0, 1, 0, 1, 2};
-  const int ka[6] = {0, 1, 3, 2, 4, 5};   // packed (xx,xy,xz,yy,yz,zz) index of (ia, ib)
-  for (int u = 0; u < ng; ++u) {
-    const double* ai = s.ainv + 6 * (size_t)mem[u];
-    for (int e = 0; e < 6; ++e) M[tri(3 * u + ia[e], 3 * u + ib[e])] = ai[ka[e]];
-  }
-  for (int u = 1; u < ng; ++u) {
-    const double4 pu = s.pp[mem[u]];
-    for (int v = 0; v < u; ++v) {
-      const double4 pv = s.pp[mem[v]];
-      double R[3] = {pu.x - pv.x, pu.y - pv.y, pu.z - pv.z};
-      if (s.periodic)
-        for (int a = 0; a < 3; ++a) R[a] = min_image<double>(R[a], s.box[a], s.ibox[a]);
-      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-      const double rinv = rsqrt(r2), r = r2 * rinv, rinv2 = rinv * rinv;
-      double c0[3], tp[5];
-      bare_coeffs<double, 2>(rinv, rinv2, c0);
-      thole_tp<double>(thole_pair(s, mem[u], mem[v]) * r2 * r * pu.w * pv.w, tp);
-      const double c1 = (1.0 - tp[1]) * c0[1], c2 = (1.0 - tp[2]) * c0[2];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          M[tri(3 * u + a, 3 * v + b)] = (a == b ? c1 : 0.0) - c2 * R[a] * R[b];
-    }
-  }
-  // Cholesky factor L (lower, in place)
-  bool ok = true;
-  for (int j = 0; j < n3 && ok; ++j) {
-    double d = M[tri(j, j)];
-    for (int k = 0; k < j; ++k) d -= M[tri(j, k)] * M[tri(j, k)];
-    if (!(d > 0.0)) {
-      ok = false;
-      break;
-    }
-    const double l = sqrt(d);
-    M[tri(j, j)] = l;
-    for (int i = j + 1; i < n3; ++i) {
-      double v = M[tri(i, j)];
-      for (int k = 0; k < j; ++k) v -= M[tri(i, k)] * M[tri(j, k)];
-      M[tri(i, j)] = v / l;
-    }
-  }
   double* out = pc.inv + kPcPacked * (size_t)pi;
-  if (!ok) {
-    // alpha per site: M^-1 = blockdiag(alpha)
-    for (int t = 0; t < kPcPacked; ++t) out[t] = 0.0;
-    for (int u = 0; u < ng; ++u) {
-      const double* al = s.alpha + 6 * (size_t)mem[u];
-      for (int e = 0; e < 6; ++e) out[tri(3 * u + ia[e], 3 * u + ib[e])] = al[ka[e]];
-    }
-    return;
+  switch (ng) {
+    case 1: build_group<1>(s, mem, out); break;
+    case 2: build_group<2>(s, mem, out); break;
+    case 3: build_group<3>(s, mem, out); break;
+    default: build_group<4>(s, mem, out); break;
   }
-  // W = L^-1 (lower)
-  for (int j = 0; j < n3; ++j) {
-    W[tri(j, j)] = 1.0 / M[tri(j, j)];
-    for (int i = j + 1; i < n3; ++i) {
-      double v = 0.0;
-      for (int k = j; k < i; ++k) v += M[tri(i, k)] * W[tri(k, j)];
-      W[tri(i, j)] = -v / M[tri(i, i)];
-    }
-  }
-  // M^-1 = W^T W: (i, j) = sum_{k >= i} W[k][i] W[k][j], i >= j
-  for (int i = 0; i < n3; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double v = 0.0;
-      for (int k = i; k < n3; ++k) v += W[tri(k, i)] * W[tri(k, j)];
-      out[tri(i, j)] = v;
-    }
-  for (int t = tri(n3 - 1, n3 - 1) + 1; t < kPcPacked; ++t) out[t] = 0.0;
 }
 
 namespace {
