@@ -557,7 +557,7 @@ def cpu_baseline(sysd, prm, iters, sample=360):
                                    parts_s={k: round(v, 2) for k, v in t.items()}))
 
 
-def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0):
+def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0, precond="molblock"):
     """Open-loop serving stream on the synthetic pool (48 clusters of
     U{2..64} waters, boxes of 216, 1,024 and 4,096 waters, two of each;
     70% cluster requests; repeats are MD steps of 0.01 A), mixed precision
@@ -567,7 +567,7 @@ def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0):
     (rate = utilisation / (0.3 S))."""
     from paper_2201_00804_amd.serve import Server, serving_pool, request_stream, summarize
     systems = serving_pool(seed)
-    srv = Server(systems, precision="mixed", tol=1e-8)
+    srv = Server(systems, precision="mixed", tol=1e-8, precond=precond)
     stream = request_stream(systems, n_warmup + n_requests, rate=1.0, seed=seed + 1)
     warm, timed = stream[:n_warmup], stream[n_warmup:]
     for q in warm:
@@ -587,6 +587,7 @@ def run_serving(n_requests, n_warmup, utilisation=0.65, seed=0):
                warmup_box_service_ms=round(1e3 * s_box, 3),
                pool="48 clusters U{2..64} waters + boxes 216, 1024, 4096 (x2); 70% clusters; "
                     "MD steps of 0.01 A; mixed precision, 1e-8 D",
+               box_precond=PRECOND_NAMES[precond],
                resident_mb=round(srv.resident_bytes / 2 ** 20, 1))
     srv.close()
     return out
@@ -732,7 +733,8 @@ def main():
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_warmup} warm-up + {args.serve_requests} requests",
               file=sys.stderr, flush=True)
-        out["serving"] = run_serving(args.serve_requests, args.serve_warmup)
+        out["serving"] = run_serving(args.serve_requests, args.serve_warmup,
+                                     precond=args.precond)
         sv = out["serving"]
         print(f"[bench] serving: {sv['throughput_per_s']} req/s at {sv['rate_per_s']}/s, p50 "
               f"{sv['p50_ms']} ms, p99 {sv['p99_ms']} ms", file=sys.stderr, flush=True)

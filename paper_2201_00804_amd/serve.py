@@ -66,10 +66,11 @@ class Server:
     alpha, box or None) plus, for boxes, 'params' (beta, cutoff, grid)."""
 
     def __init__(self, systems, device=0, precision="mixed", tol=1e-8, hbm_budget=None,
-                 max_batch_sites=1 << 18, max_iter=400, box_slots=3):
+                 max_batch_sites=1 << 18, max_iter=400, box_slots=3, precond="diag"):
         self.systems = systems
         self.dev = torch.device("cuda", device)
         self.precision = precision
+        self.precond = precond        # box contexts' PCG preconditioner
         self.tol = tol
         self.max_iter = max_iter
         if hbm_budget is None:
@@ -103,7 +104,8 @@ class Server:
         p = sysd["params"]
         return _engine.default_params(beta=p["beta"], cutoff=p["cutoff"], grid=p["grid"],
                                       order=p.get("order", 5), tol=self.tol,
-                                      precision=self.precision, max_iter=self.max_iter)
+                                      precision=self.precision, max_iter=self.max_iter,
+                                      precond=self.precond)
 
     def _admit(self, name):
         """Resident context of a box system, creating it (and evicting

@@ -62,12 +62,15 @@ def test_stream_results_match_standalone():
     srv.close()
 
 
-def test_stream_results_match_standalone_mixed():
+@pytest.mark.parametrize("precond", ["diag", "molblock"])
+def test_stream_results_match_standalone_mixed(precond):
     """The served precision (FP32-mixed), under a burst that keeps several
     box requests in flight at once: every sampled result equals a cold
     standalone mixed evaluation at the same positions within the mixed
     path's bounds (E_pol 1e-5 relative, E_elec 1e-5 relative, forces 1e-4
-    relative RMS), whether it ran alone or beside other boxes and clusters."""
+    relative RMS), whether it ran alone or beside other boxes and clusters,
+    with either preconditioner in the box contexts (the standalone
+    evaluations use the diagonal one: both converge to the tolerance)."""
     from paper_2201_00804_amd.serve import Server, request_stream, summarize
     systems = _small_pool()
     c = CONFIGS["box216"]
@@ -76,7 +79,7 @@ def test_stream_results_match_standalone_mixed():
         d["params"] = dict(beta=c["beta"], cutoff=c["cutoff"], grid=c["grid"], order=5)
         systems[f"box216_{k}"] = d
     tol = 1e-8
-    srv = Server(systems, precision="mixed", tol=tol, box_slots=3)
+    srv = Server(systems, precision="mixed", tol=tol, box_slots=3, precond=precond)
     reqs = request_stream(systems, 200, rate=20000.0, seed=5)
     wall = srv.run(reqs)
     summ = summarize(reqs, wall, srv)
