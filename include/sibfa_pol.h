@@ -420,7 +420,8 @@ sibfa_status sibfa_get_profile(sibfa_ctx ctx, sibfa_profile* out);
  * E_elec and forces), for many clusters in one call: one workgroup owns one
  * cluster and keeps its whole solve on the device, so a batch costs three
  * kernel launches and no host synchronisation.  A cluster's results are
- * bitwise independent of the other clusters in the batch.
+ * bitwise independent of the other clusters in the batch.  The batched
+ * solve uses the diagonal preconditioner (params.precond is not read).
  *
  * Limits per cluster: at most SIBFA_BATCH_MAX_SITES sites and
  * SIBFA_BATCH_MAX_POLARIZABLE polarizable sites (larger systems use a
