@@ -7,7 +7,10 @@ of the oracle's, E_pol within 1e-6 relative (FP64 both sides); the true
 residual within the tolerance; fewer iterations than alpha per site on the
 same system.  At 4,096 waters, where the oracle's solve is out of reach,
 the block-preconditioned solve equals the alpha-per-site one to the
-tolerance (FP64 and mixed).  The truncated solver ignores the setting."""
+tolerance (FP64 and mixed).  The truncated solver ignores the setting.
+The "mixed sizes" cases regroup the water sites into molecules of 1, 2, 3,
+4 and 6 polarizable sites: every block size, and the fallback to alpha per
+site above four."""
 import dataclasses
 
 import numpy as np
@@ -29,15 +32,22 @@ def _need_gpu():
 
 
 def _case(name):
+    from tests.test_oracle_precond import mixed_molecules
     if name == "cluster":
         return water_cluster(9, 2), dict(tol=1e-9)
+    if name == "cluster_mixed_sizes":
+        return mixed_molecules(water_cluster(12, 5)), dict(tol=1e-9)
+    if name == "box27_mixed_sizes":
+        return mixed_molecules(water_box(27, 9.5, 3)), dict(beta=0.45, cutoff=4.5, grid=24,
+                                                             tol=1e-9)
     if name == "box27":
         return water_box(27, 9.5, 3), dict(beta=0.45, cutoff=4.5, grid=24, tol=1e-9)
     d, cfg = config_system("box216")
     return d, dict(beta=cfg["beta"], cutoff=cfg["cutoff"], grid=cfg["grid"], tol=1e-9)
 
 
-@pytest.mark.parametrize("name", ["cluster", "box27", "box216"])
+@pytest.mark.parametrize("name", ["cluster", "box27", "box216", "cluster_mixed_sizes",
+                                  "box27_mixed_sizes"])
 def test_molblock_matches_oracle(name):
     d, kw = _case(name)
     s = System.from_dict(d)
