@@ -64,6 +64,42 @@ __device__ __forceinline__ void displacement(const SysView& s, const R xi[3], co
   }
 }
 
+// r_i - r_j from the FP64 positions, rounded to R.  In FP32 this carries
+// only the rounding of the separation itself, not that of two coordinates
+// as large as the box (about 1e-5 A at 100 A, which would dominate the
+// error of the FP32 pair energies and forces); in FP64 it is displacement().
+template <typename R>
+__device__ __forceinline__ void sep64(const SysView& s, const double xi[3], const double xj[3],
+                                      R Rv[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double d = xi[a] - xj[a];
+    if (s.periodic) d = min_image<double>(d, s.box[a], s.ibox[a]);
+    Rv[a] = R(d);
+  }
+}
+
+// The multipoles of site j in precision R and its FP64 position (the
+// charge comes from the FP64 record too, which holds both).
+template <typename R>
+__device__ __forceinline__ void load_mp_x64(const SysView& s, int j, MP<R>& M, double x[3]) {
+  const double4 p = s.sp[j];
+  x[0] = p.x; x[1] = p.y; x[2] = p.z;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    const double4 d = s.sd[j], t = s.sth[j];
+    const double2 t2 = s.sth2[j];
+    M.q = p.w;
+    M.d[0] = d.x; M.d[1] = d.y; M.d[2] = d.z;
+    M.t[0] = t.x; M.t[1] = t.y; M.t[2] = t.z; M.t[3] = t.w; M.t[4] = t2.x; M.t[5] = t2.y;
+  } else {
+    const float4 d = s.sd32[j], t = s.sth32[j];
+    const float2 t2 = s.sth232[j];
+    M.q = R(p.w);
+    M.d[0] = d.x; M.d[1] = d.y; M.d[2] = d.z;
+    M.t[0] = t.x; M.t[1] = t.y; M.t[2] = t.z; M.t[3] = t.w; M.t[4] = t2.x; M.t[5] = t2.y;
+  }
+}
+
 // base kernel E_0..E_N: Ewald B_n when periodic, bare c0_n for clusters
 template <typename R, int N>
 __device__ __forceinline__ void base_coeffs(const SysView& s, R r, R rinv, R rinv2, R E[N + 1]) {
@@ -143,11 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_perm_intra(SysView s, Reduce red, do
 // dropped, as it is for near pairs with x >= 50.
 template <typename R, bool NEAR>
 __device__ __forceinline__ void perm_pair(const SysView& s, int i, int j, int pi, const MP<R>& Mi,
-                                          const R xi[3], R si, double& U, double acc[3]) {
+                                          const double xi[3], R si, double& U, double acc[3]) {
   MP<R> Mj;
-  R xj[3], Rv[3];
-  load_mp<R>(s, j, Mj, xj);
-  displacement<R>(s, xi, xj, Rv);
+  R Rv[3];
+  double xj[3];
+  load_mp_x64<R>(s, j, Mj, xj);
+  sep64<R>(s, xi, xj, Rv);
   const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
   const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
   R c[6];
@@ -187,8 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_perm(SysView s, Reduce red, double4*
   if (i < s.n) {
     pi = s.polidx[i];
     MP<R> Mi;
-    R xi[3];
-    load_mp<R>(s, i, Mi, xi);
+    R xr[3];
+    load_mp<R>(s, i, Mi, xr);
+    const double4 p4 = s.sp[i];
+    const double xi[3] = {p4.x, p4.y, p4.z};
     const R si = site_s<R>(s, i);
     const int* row = s.nb_all + (size_t)i * s.cap_all;
     const int nn = s.nc_near[i], nf = s.nc_all[i] - nn;
@@ -612,14 +651,15 @@ __device__ __forceinline__ void mp_field_grad(const R c[6], const MP<R>& B, cons
 // pair may be damped (x < 50); far pairs never are.
 template <typename R, bool NEAR, bool VIR, bool FG>
 __device__ __forceinline__ void force_pair(const SysView& s, int i, int j, const MP<R>& Mi,
-                                           const MP<R>& Pi, const R xi[3], R si,
+                                           const MP<R>& Pi, const double xi[3], R si,
                                            const double4* mu, const float4* mu32, double F[3],
                                            double W[9], double E[3], double Gg[6]) {
   MP<R> Mj;
-  R xj[3], Rv[3], muj[3];
-  load_mp<R>(s, j, Mj, xj);
+  R Rv[3], muj[3];
+  double xj[3];
+  load_mp_x64<R>(s, j, Mj, xj);
   load_mu<R>(mu, mu32, j, muj);
-  displacement<R>(s, xi, xj, Rv);
+  sep64<R>(s, xi, xj, Rv);
   const R r2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
   const R rinv = dev_rsqrt<R>(r2), r = r2 * rinv, rinv2 = rinv * rinv;
   R c[6];
@@ -678,8 +718,10 @@ __global__ __launch_bounds__(kBlock) void k_force(SysView s, Reduce red, const d
   double E[3] = {0.0, 0.0, 0.0}, Gg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (i < s.n) {
     MP<R> Mi;
-    R xi[3], mui[3];
-    load_mp<R>(s, i, Mi, xi);
+    R xr[3], mui[3];
+    load_mp<R>(s, i, Mi, xr);
+    const double4 p4 = s.sp[i];
+    const double xi[3] = {p4.x, p4.y, p4.z};
     load_mu<R>(mu, mu32, i, mui);
     MP<R> Pi = Mi;
     Pi.d[0] += mui[0]; Pi.d[1] += mui[1]; Pi.d[2] += mui[2];
