@@ -395,6 +395,9 @@ typedef enum {
   SIBFA_PH_FORCE_RECIP,   /* combined-density PME forces                    */
   SIBFA_PH_PAIRCOEF,      /* solver: damped pair coefficients, once a solve  */
   SIBFA_PH_MATVEC_RECIP,  /* solver: PME field gather of T p and p.Tp        */
+  SIBFA_PH_MATVEC_FP64,   /* mixed precision: each whole FP64 T x (residual
+                             replacements, TCG adjoint products); the
+                             phases above then hold FP32 launches only      */
   SIBFA_PH_COUNT
 } sibfa_phase;
 

@@ -39,7 +39,7 @@ class Profile(ctypes.Structure):
 
 
 PHASES = ["lists", "field_real", "field_recip", "spread", "fft", "matvec", "update",
-          "force_real", "force_recip", "paircoef", "matvec_recip"]
+          "force_real", "force_recip", "paircoef", "matvec_recip", "matvec_fp64"]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)

@@ -189,6 +189,7 @@ struct sibfa_ctx_s {
   struct Mark { int phase; hipEvent_t a, b; int tag; bool work; };
   std::vector<Mark> marks;
   int cur_tag = -1;
+  static_assert(SIBFA_PH_COUNT <= 16, "phases fit the profile record");
   double prof_ms[16] = {0};
   int prof_calls[16] = {0};
 };
@@ -468,25 +469,38 @@ void fold_marks(sibfa_ctx c) {
 }
 
 // Brackets the launches of one phase with events when profiling is on.
+// attach: the phase is a single kernel launched with start() and stop() as
+// its own dispatch events (hipExtLaunchKernelGGL), which time the kernel
+// itself rather than marker packets around it; the launcher must record
+// both.
 struct Phase {
   sibfa_ctx c;
   int ph;
   hipStream_t st;
-  hipEvent_t a = nullptr;
-  Phase(sibfa_ctx cc, int p, hipStream_t s = nullptr) : c(cc), ph(p), st(s ? s : cc->stream) {
-    if (c->prof && ((c->prof_mask >> p) & 1u)) {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool attach;
+  Phase(sibfa_ctx cc, int p, hipStream_t s = nullptr, bool att = false)
+      : c(cc), ph(p), st(s ? s : cc->stream), attach(att) {
+    if (p >= 0 && c->prof && ((c->prof_mask >> p) & 1u)) {
       if (c->marks.size() > 4096 && c->cur_tag < 0) fold_marks(c);
       a = next_event(c);
-      if (a) (void)hipEventRecord(a, st);
+      if (a && attach) {
+        b = next_event(c);
+        if (!b) a = nullptr;
+      } else if (a) {
+        (void)hipEventRecord(a, st);
+      }
     }
   }
+  hipEvent_t start() const { return attach ? a : nullptr; }
+  hipEvent_t stop() const { return attach ? b : nullptr; }
   ~Phase() {
     if (c->prof && a) {
-      hipEvent_t b = next_event(c);
-      if (b) {
-        (void)hipEventRecord(b, st);
-        c->marks.push_back({ph, a, b, c->cur_tag, true});
+      if (!attach) {
+        b = next_event(c);
+        if (b) (void)hipEventRecord(b, st);
       }
+      if (b) c->marks.push_back({ph, a, b, c->cur_tag, true});
     }
   }
 };
@@ -797,35 +811,50 @@ sibfa_status ensure_coef(sibfa_ctx c) {
   return SIBFA_OK;
 }
 
-// t = T v.  mix: FP32 pair/PME arithmetic (cached FP32 coefficients);
-// otherwise FP64 (cached FP64 coefficients, kept in both modes).  Callers
-// run ensure_coef first.
-void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
+// t = T v, each part timed as its own phase when timed (else untimed).
+void matvec_parts(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix,
+                  bool timed) {
   SysView s = make_view(c);
+  auto P = [timed](int ph) { return timed ? ph : -1; };
   if (c->periodic) {
     // as in the solver loop: reciprocal chain on the main stream, the
     // real-space part beside it
     fork(c);
     {
-      Phase ph2(c, SIBFA_PH_MATVEC, c->aux);
+      Phase ph2(c, P(SIBFA_PH_MATVEC), c->aux, true);
       launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->aux,
-                         c->aux != c->stream ? c->ev_join : nullptr);
+                         c->aux != c->stream ? c->ev_join : nullptr, ph2.start(), ph2.stop());
     }
     {
-      Phase ph(c, SIBFA_PH_SPREAD);
+      Phase ph(c, P(SIBFA_PH_SPREAD));
       launch_spread_dip(s, c->pm, v, mix, c->stream);
     }
     {
-      Phase ph(c, SIBFA_PH_FFT);
+      Phase ph(c, P(SIBFA_PH_FFT));
       conv(c, mix, c->stream);
     }
     if (c->aux != c->stream) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
   } else {
-    Phase ph2(c, SIBFA_PH_MATVEC);
-    launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->stream);
+    Phase ph2(c, P(SIBFA_PH_MATVEC), c->stream, true);
+    launch_matvec_real(s, c->red, v, v32, out, dot_slot, mix, c->stream, nullptr, ph2.start(),
+                       ph2.stop());
   }
-  Phase ph3(c, SIBFA_PH_MATVEC_RECIP);
+  Phase ph3(c, P(SIBFA_PH_MATVEC_RECIP));
   launch_matvec_recip(s, c->pm, c->red, v, out, dot_slot, mix, c->stream);
+}
+
+// t = T v.  mix: FP32 pair/PME arithmetic (cached FP32 coefficients);
+// otherwise FP64 (cached FP64 coefficients, kept in both modes).  Callers
+// run ensure_coef first.  An FP64 product in a mixed-precision context is
+// timed whole, as a phase of its own, so that the per-kernel phases hold
+// the launches of the context's own precision only.
+void matvec(sibfa_ctx c, double4* v, float4* v32, double4* out, int dot_slot, bool mix) {
+  if (!mix && mixed(c)) {
+    Phase ph(c, SIBFA_PH_MATVEC_FP64);
+    matvec_parts(c, v, v32, out, dot_slot, false, false);
+    return;
+  }
+  matvec_parts(c, v, v32, out, dot_slot, mix, true);
 }
 
 sibfa_status compute_E0(sibfa_ctx c) {
@@ -1042,10 +1071,11 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           if (fork_by_dir) (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
           else fork(c);
           {
-            Phase ph(c, SIBFA_PH_MATVEC, c->aux);
+            Phase ph(c, SIBFA_PH_MATVEC, c->aux, true);
             // the matvec's completion records the join event itself
             launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, c->aux,
-                               c->aux != c->stream ? c->ev_join : nullptr);
+                               c->aux != c->stream ? c->ev_join : nullptr, ph.start(),
+                               ph.stop());
           }
           {
             Phase ph(c, SIBFA_PH_SPREAD);
@@ -1057,8 +1087,9 @@ sibfa_status solve(sibfa_ctx c, bool warm) {
           }
           if (c->aux != c->stream) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
         } else {
-          Phase ph(c, SIBFA_PH_MATVEC);
-          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st);
+          Phase ph(c, SIBFA_PH_MATVEC, st, true);
+          launch_matvec_real(s, c->red, c->p, c->p32, c->q, S_PQ, mix, st, nullptr, ph.start(),
+                             ph.stop());
         }
         {
           Phase ph(c, SIBFA_PH_MATVEC_RECIP);

@@ -9,9 +9,12 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
 // T p in two kernels: real space (reads the cached pair coefficients, which
 // must be current) and, for periodic systems, the PME field gather with
 // p.Tp.  The dot product's partials come from the last of the two.
+// done: recorded when the kernel completes; t0, t1 (both or neither): the
+// kernel's own dispatch events, for timing
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
                         double4* out, int dot_slot, bool mixed, hipStream_t st,
-                        hipEvent_t done = nullptr);
+                        hipEvent_t done = nullptr, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 void launch_matvec_recip(const SysView& s, const PmeView& pm, Reduce& red, const double4* p,
                          double4* out, int dot_slot, bool mixed, hipStream_t st);
 // cache the pol-list pair coefficients: FP64 into out, or FP32 into out32

@@ -818,19 +818,25 @@ void launch_perm(const SysView& s, Reduce& red, double4* E0, bool mixed, hipStre
 }
 
 void launch_matvec_real(const SysView& s, Reduce& red, const double4* p, const float4* p32,
-                        double4* out, int dot_slot, bool mixed, hipStream_t st, hipEvent_t done) {
+                        double4* out, int dot_slot, bool mixed, hipStream_t st, hipEvent_t done,
+                        hipEvent_t t0, hipEvent_t t1) {
   if (s.npol <= 0) {
+    if (t0) (void)hipEventRecord(t0, st);
+    if (t1) (void)hipEventRecord(t1, st);
     if (done) (void)hipEventRecord(done, st);
     return;
   }
   const dim3 g(blocks_for(s.npol, kG)), b(kBlock);
-  // done: recorded by the kernel's own completion (no marker packet)
+  // done: recorded by the kernel's own completion (no marker packet),
+  // unless the completion event is taken by the timing pair
+  hipEvent_t end = t1 ? t1 : done;
   if (mixed)
-    hipExtLaunchKernelGGL((k_matvec<float, kG>), g, b, 0, st, nullptr, done, 0, s, red, p, p32, out,
+    hipExtLaunchKernelGGL((k_matvec<float, kG>), g, b, 0, st, t0, end, 0, s, red, p, p32, out,
                           dot_slot);
   else
-    hipExtLaunchKernelGGL((k_matvec<double, kG>), g, b, 0, st, nullptr, done, 0, s, red, p, p32, out,
+    hipExtLaunchKernelGGL((k_matvec<double, kG>), g, b, 0, st, t0, end, 0, s, red, p, p32, out,
                           dot_slot);
+  if (t1 && done) (void)hipEventRecord(done, st);
   if (!s.periodic && dot_slot >= 0) red.nparts[dot_slot] = (int)g.x;
 }
 
