@@ -76,6 +76,7 @@ struct sibfa_ctx_s {
   // cells
   int nc[3] = {1, 1, 1}, ncell = 1;
   int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cursor = nullptr;
+  int4* cellmax = nullptr;   // per-cell list count maxima
   int *perm = nullptr, *inv_perm = nullptr, *mol_count = nullptr, *mol_s = nullptr;
   int* scan_tmp = nullptr;
   // records
@@ -599,7 +600,7 @@ sibfa_status build_lists(sibfa_ctx c) {
     for (int k = 0; k < 4; ++k) want[k] = std::max(want[k], c->cap[k]);
     sibfa_status st = alloc_lists(c, want);
     if (st != SIBFA_OK) return st;
-    launch_fill_ints({{c->dints, 4}, {c->dints + 5, 1}}, 0, c->stream);
+    launch_fill_ints({{c->dints + 5, 1}}, 0, c->stream);
     NlistArgs a{};
     a.periodic = c->periodic;
     for (int d = 0; d < 3; ++d) {
@@ -619,11 +620,12 @@ sibfa_status build_lists(sibfa_ctx c) {
     a.nb_in = c->nb[1]; a.nc_in = c->ncnt[1]; a.cap_in = c->cap[1];
     a.nb_pol = c->nb[2]; a.nc_pol = c->ncnt[2]; a.cap_pol = c->cap[2];
     a.nb_ipol = c->nb[3]; a.nc_ipol = c->ncnt[3]; a.cap_ipol = c->cap[3];
-    a.maxcnt = c->dints;
+    a.cellmax = c->cellmax;
     a.err = c->dints + 5;
     {
       Phase ph(c, SIBFA_PH_LISTS);
       launch_nlist(a, c->ncell, c->stream);
+      launch_cellmax_reduce(c->cellmax, c->ncell, c->dints, c->stream);
     }
     HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     sibfa_status s2 = sync_read(c);
@@ -1672,6 +1674,10 @@ size_t sibfa_footprint_bytes(int n_sites, int n_polarizable, const double* box,
       tiles *= (size_t)((p->grid[a] + e - 1) / e) * (e + p->order - 1);
     }
     bytes += tiles * (8 + 4);
+    size_t cells = 1;   // cell grid as in sibfa_set_system: count, start, cursor, maxima
+    for (int a = 0; a < 3; ++a)
+      cells *= (size_t)std::max(1, std::min(1024, (int)std::floor(box[a] / (0.5 * p->cutoff))));
+    bytes += cells * (3 * sizeof(int) + sizeof(int4));
   } else {
     cap_all = n;
     cap_pol = np;
@@ -1720,6 +1726,7 @@ sibfa_status sibfa_set_system(sibfa_ctx c, int n_sites, const double* xyz, const
             alloc_into(c, L, c->mu_c, 3 * n) && alloc_into(c, L, c->mol_c, n) &&
             alloc_into(c, L, c->cell_of, n) && alloc_into(c, L, c->cell_count, c->ncell + 1) &&
             alloc_into(c, L, c->cell_start, c->ncell + 1) && alloc_into(c, L, c->cursor, c->ncell) &&
+            alloc_into(c, L, c->cellmax, c->ncell) &&
             alloc_into(c, L, c->perm, n) && alloc_into(c, L, c->inv_perm, n) &&
             alloc_into(c, L, c->mol_count, n) && alloc_into(c, L, c->mol_s, n) &&
             alloc_into(c, L, c->scan_tmp, scan_temp_ints((int)std::max<size_t>(n + 1, c->ncell + 1)) + 16) &&

@@ -261,6 +261,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_max(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // Sum over groups of G consecutive lanes (G a power of two <= 64).
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {

@@ -59,11 +59,16 @@ struct NlistArgs {
   int* nb_in; int* nc_in; int cap_in;
   int* nb_pol; int* nc_pol; int cap_pol;
   int* nb_ipol; int* nc_ipol; int cap_ipol;
-  int* maxcnt;           // [4] running maxima of the four counts
+  // [cell] maxima of the four counts over the cell's sites, written by the
+  // cell's wavefront (no atomics: one same-address atomic per wavefront
+  // costs the launch more than the list build itself)
+  int4* cellmax;
   int* err;              // bit 1: a molecule's sites not all within reach
 };
 
 void launch_bin(const BinArgs& a, hipStream_t s);
+// out[0..3] = the maxima of cellmax over ncell cells
+void launch_cellmax_reduce(const int4* cellmax, int ncell, int* out, hipStream_t s);
 void launch_scatter(const int* cell_of, const int* cell_start, int* cursor, int* perm,
                     int n, hipStream_t s);
 void launch_sort_cells(const int* cell_start, int ncell, int* perm, hipStream_t s);

@@ -493,6 +493,7 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
     if (a.nc[d] < 5) { span[d] = a.nc[d]; lo[d] = 0; }
     else { span[d] = 5; lo[d] = c3[d] - 2; }
   }
+  int4 mx = make_int4(0, 0, 0, 0);   // the cell's count maxima
   for (int ib = i0; ib < i1; ib += kNlIB) {
     const int ni = min(kNlIB, i1 - ib);
     if (lane < ni) {
@@ -600,34 +601,49 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
       a.nc_all[i] = cnt0 + cntf;
       a.nc_near[i] = cnt0;
       a.nc_in[i] = cnt1;
-      atomicMax(&a.maxcnt[0], cnt0 + cntf);
-      atomicMax(&a.maxcnt[1], cnt1);
       if (poli[lane] >= 0) {
         a.nc_pol[poli[lane]] = cnt2;
         a.nc_ipol[poli[lane]] = cnt3;
-        atomicMax(&a.maxcnt[2], cnt2);
-        atomicMax(&a.maxcnt[3], cnt3);
       }
       if (cnt1 != a.mol_count[moli[lane]] - 1) atomicOr(a.err, 1);
     }
+    mx.x = max(mx.x, wave_max(lane < ni ? cnt0 + cntf : 0));
+    mx.y = max(mx.y, wave_max(lane < ni ? cnt1 : 0));
+    mx.z = max(mx.z, wave_max(lane < ni && poli[lane] >= 0 ? cnt2 : 0));
+    mx.w = max(mx.w, wave_max(lane < ni && poli[lane] >= 0 ? cnt3 : 0));
     __syncthreads();
   }
+  if (lane == 0) a.cellmax[cell] = mx;
 }
 
 // Periodic boxes with at least five cells along every axis.  Same lists, in
-// the same order, as k_nlist, with two changes that cut the work per
-// candidate pair:
+// the same order, as k_nlist, with changes that cut the work per candidate
+// pair:
 //  * the 5 x 5 rows of the stencil give at most 50 runs of consecutive
 //    cells, each with a fixed periodic image shift (the stencil reaches a
 //    wrapped cell through exactly one image), so a candidate's displacement
 //    is x_i - (x_j + shift) without a per-pair rint;
-//  * the runs are concatenated into one virtual candidate range processed
-//    64 at a time (a lane finds its run by binary search over the run
-//    offsets), so chunks are full;
-//  * polarizable-pair masks come from one ballot per chunk.
+//  * the runs are concatenated into one virtual candidate range, taken
+//    kNlG chunks of 64 at a time into registers (a lane finds its run by
+//    binary search over the run offsets), so chunks are full;
+//  * each i-site's five running counts are read once per pass over those
+//    chunks into wave-uniform (scalar) registers, so a candidate chunk costs
+//    the distance test, the ballots and the slot arithmetic of its hits;
+constexpr int kNlG = 4;   // candidate chunks per pass over the i-sites
+
+__device__ __forceinline__ int rl(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+// lane masks straight from one vector compare (predicate codes of the
+// compiler's compare intrinsics: ordered less-than; signed equal, >=)
+constexpr int kCmpOLT = 4, kCmpEQ = 32, kCmpSGE = 39;
+__device__ __forceinline__ unsigned long long mask_lt(double a, double b) {
+  return __builtin_amdgcn_fcmp(a, b, kCmpOLT);
+}
+__device__ __forceinline__ unsigned long long mask_eq(int a, int b) {
+  return __builtin_amdgcn_sicmp(a, b, kCmpEQ);
+}
+
 __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
   __shared__ double xi[kNlIB], yi[kNlIB], zi[kNlIB];
-  __shared__ int moli[kNlIB], poli[kNlIB];
   __shared__ int run_s[50], run_off[51], run_code[50];
   const int lane = threadIdx.x;
   const int cell = blockIdx.x;
@@ -635,7 +651,6 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
   const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
   const int i0 = a.cell_start[cell], i1 = a.cell_start[cell + 1];
   const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if (lane < 25) {
     const int dz = lane / 5 - 2, dy = lane % 5 - 2;
     int zz = cz + dz, zc = 1;
@@ -668,91 +683,123 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
   }
   __syncthreads();
   const int ncand = run_off[50];
+  const int cap_all = a.cap_all, cap_in = a.cap_in, cap_pol = a.cap_pol, cap_ipol = a.cap_ipol;
+  const double cut2 = a.cutoff2, split2 = a.rsplit2;
+  int4 mx = make_int4(0, 0, 0, 0);   // the cell's count maxima
   for (int ib = i0; ib < i1; ib += kNlIB) {
     const int ni = min(kNlIB, i1 - ib);
+    // i-site `lane`: position in LDS (read back as a broadcast), molecule
+    // and polarizable index in registers
+    int mol_v = -1, pol_v = -1;
     if (lane < ni) {
       const double4 p = a.sp[ib + lane];
       xi[lane] = p.x; yi[lane] = p.y; zi[lane] = p.z;
-      moli[lane] = a.mol_s[ib + lane];
-      poli[lane] = a.polidx[ib + lane];
+      mol_v = a.mol_s[ib + lane];
+      pol_v = a.polidx[ib + lane];
     }
     __syncthreads();
     // counts of i-site `lane`: all near (cnt0) and far (cntf), in, pol, ipol
     int cnt0 = 0, cntf = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
-    for (int c = 0; c < ncand; c += 64) {
-      const int cidx = c + lane;
-      const bool valid = cidx < ncand;
-      double xj = 0, yj = 0, zj = 0;
-      int j = -1, molj = -1, polj = -1;
-      if (valid) {
-        int lo = 0, hi = 50;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (run_off[mid] <= cidx) lo = mid; else hi = mid;
+    for (int c = 0; c < ncand; c += 64 * kNlG) {
+      // a lane past the candidates sits far away in no molecule: it never
+      // tests as a neighbour
+      double xj[kNlG], yj[kNlG], zj[kNlG];
+      int jj[kNlG], molj[kNlG], polj[kNlG];
+      unsigned long long pjm[kNlG];
+#pragma unroll
+      for (int g = 0; g < kNlG; ++g) {
+        const int cidx = c + g * 64 + lane;
+        xj[g] = yj[g] = zj[g] = 1e30;
+        jj[g] = -1; molj[g] = -1; polj[g] = -1;
+        if (cidx < ncand) {
+          int lo = 0, hi = 50;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (run_off[mid] <= cidx) lo = mid; else hi = mid;
+          }
+          const int j = run_s[lo] + (cidx - run_off[lo]);
+          const int code = run_code[lo];
+          const double4 p = a.sp[j];
+          xj[g] = p.x + L0 * (double)(code % 3 - 1);
+          yj[g] = p.y + L1 * (double)((code / 3) % 3 - 1);
+          zj[g] = p.z + L2 * (double)(code / 9 - 1);
+          jj[g] = j;
+          molj[g] = a.mol_s[j];
+          polj[g] = a.polidx[j];
         }
-        j = run_s[lo] + (cidx - run_off[lo]);
-        const int code = run_code[lo];
-        const double4 p = a.sp[j];
-        xj = p.x + L0 * (double)(code % 3 - 1);
-        yj = p.y + L1 * (double)((code / 3) % 3 - 1);
-        zj = p.z + L2 * (double)(code / 9 - 1);
-        molj = a.mol_s[j];
-        polj = a.polidx[j];
+        pjm[g] = __builtin_amdgcn_sicmp(polj[g], 0, kCmpSGE);
       }
-      const bool pj = valid && polj >= 0;
-      const unsigned long long pjmask = __builtin_amdgcn_ballot_w64(pj);
-      // Site t's counts live in lane t: read with readlane (a wave-uniform
-      // base) and updated by lane t; a lane's slot is the base plus
-      // the lower lanes of the ballot (mbcnt).
       for (int t = 0; t < ni; ++t) {
-        const double dx = xi[t] - xj, dy = yi[t] - yj, dz = zi[t] - zj;
-        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double x = xi[t], y = yi[t], z = zi[t];
         const int i = ib + t;
-        const int mi = moli[t], pi_ = poli[t];
-        const bool same = valid && (molj == mi) && (j != i);
-        const bool inter = valid && (molj != mi) && (r2 < a.cutoff2);
-        const unsigned long long b0 = __builtin_amdgcn_ballot_w64(inter);
-        const unsigned long long b1 = __builtin_amdgcn_ballot_w64(same);
-        if ((b0 | b1) == 0ull) continue;   // no neighbour of site t in this chunk
-        if (b0) {
-          const bool near = r2 < a.rsplit2;
-          const unsigned long long bn = __builtin_amdgcn_ballot_w64(inter && near), bf = b0 & ~bn;
-          const int basen = __builtin_amdgcn_readlane(cnt0, t);
-          const int basef = __builtin_amdgcn_readlane(cntf, t);
-          if (inter) {
-            const int k = near ? lanes_below(bn, basen) : lanes_below(bf, basef);
-            const int e = near ? k : a.cap_all - 1 - k;
-            if (k < a.cap_all) a.nb_all[(size_t)i * a.cap_all + e] = j;
-          }
-          if (lane == t) cnt0 = basen + __popcll(bn);
-          if (lane == t) cntf = basef + __popcll(bf);
-        }
-        if (b1) {
-          const int base1 = __builtin_amdgcn_readlane(cnt1, t);
-          if (same) {
-            const int k = lanes_below(b1, base1);
-            if (k < a.cap_in) a.nb_in[(size_t)i * a.cap_in + k] = j;
-          }
-          if (lane == t) cnt1 = base1 + __popcll(b1);
-        }
-        if (pi_ >= 0) {
-          const unsigned long long b2 = b0 & pjmask, b3 = b1 & pjmask;
-          if (b2) {
-            const int base2 = __builtin_amdgcn_readlane(cnt2, t);
-            if (inter && pj) {
-              const int k = lanes_below(b2, base2);
-              if (k < a.cap_pol) a.nb_pol[(size_t)pi_ * a.cap_pol + k] = polj;
+        const int mi = rl(mol_v, t), pi_ = rl(pol_v, t);
+        // site t's counts, wave-uniform for the chunks of this pass; a
+        // lane's slot is the count plus the lower lanes of its mask
+        int k0 = rl(cnt0, t), kf = rl(cntf, t), k1 = rl(cnt1, t), k2 = rl(cnt2, t),
+            k3 = rl(cnt3, t);
+        int* row_all = a.nb_all + (size_t)i * cap_all;
+        int* row_in = a.nb_in + (size_t)i * cap_in;
+        int* row_pol = a.nb_pol + (size_t)(pi_ >= 0 ? pi_ : 0) * cap_pol;
+        int* row_ipol = a.nb_ipol + (size_t)(pi_ >= 0 ? pi_ : 0) * cap_ipol;
+#pragma unroll
+        for (int g = 0; g < kNlG; ++g) {
+          const double dx = x - xj[g], dy = y - yj[g], dz = z - zj[g];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          // the same compares give the wave's masks and each lane's own
+          // bit (the compiler folds them into one instruction each)
+          const bool in_cut = r2 < cut2, in_mol = molj[g] == mi, in_near = r2 < split2;
+          const unsigned long long bmol = mask_eq(molj[g], mi);
+          const unsigned long long b0 = mask_lt(r2, cut2) & ~bmol;   // intermolecular
+          if ((b0 | bmol) == 0ull) continue;   // no neighbour of site t in this chunk
+          const bool inter = in_cut && !in_mol;
+          const bool same = in_mol && jj[g] != i;
+          unsigned long long b1 = 0ull;        // same molecule, not site t itself
+          if (bmol) b1 = bmol & ~mask_eq(jj[g], i);
+          if (b0) {
+            const unsigned long long bnear = mask_lt(r2, split2);
+            const unsigned long long bn = b0 & bnear, bf = b0 & ~bnear;
+            if (bn) {
+              if (inter && in_near) {
+                const int k = lanes_below(bn, k0);
+                if (k < cap_all) row_all[(unsigned)k] = jj[g];
+              }
+              k0 += __popcll(bn);
             }
-            if (lane == t) cnt2 = base2 + __popcll(b2);
-          }
-          if (b3) {
-            const int base3 = __builtin_amdgcn_readlane(cnt3, t);
-            if (same && pj) {
-              const int k = lanes_below(b3, base3);
-              if (k < a.cap_ipol) a.nb_ipol[(size_t)pi_ * a.cap_ipol + k] = polj;
+            if (bf) {
+              if (inter && !in_near) {
+                const int k = lanes_below(bf, kf);
+                if (k < cap_all) row_all[(unsigned)(cap_all - 1 - k)] = jj[g];
+              }
+              kf += __popcll(bf);
             }
-            if (lane == t) cnt3 = base3 + __popcll(b3);
           }
+          if (b1) {
+            if (same) {
+              const int k = lanes_below(b1, k1);
+              if (k < cap_in) row_in[(unsigned)k] = jj[g];
+            }
+            k1 += __popcll(b1);
+          }
+          if (pi_ >= 0) {
+            const unsigned long long b2 = b0 & pjm[g], b3 = b1 & pjm[g];
+            if (b2) {
+              if (inter && polj[g] >= 0) {
+                const int k = lanes_below(b2, k2);
+                if (k < cap_pol) row_pol[(unsigned)k] = polj[g];
+              }
+              k2 += __popcll(b2);
+            }
+            if (b3) {
+              if (same && polj[g] >= 0) {
+                const int k = lanes_below(b3, k3);
+                if (k < cap_ipol) row_ipol[(unsigned)k] = polj[g];
+              }
+              k3 += __popcll(b3);
+            }
+          }
+        }
+        if (lane == t) {
+          cnt0 = k0; cntf = kf; cnt1 = k1; cnt2 = k2; cnt3 = k3;
         }
       }
     }
@@ -761,18 +808,44 @@ __global__ __launch_bounds__(64) void k_nlist_shift(NlistArgs a) {
       a.nc_all[i] = cnt0 + cntf;
       a.nc_near[i] = cnt0;
       a.nc_in[i] = cnt1;
-      atomicMax(&a.maxcnt[0], cnt0 + cntf);
-      atomicMax(&a.maxcnt[1], cnt1);
-      if (poli[lane] >= 0) {
-        a.nc_pol[poli[lane]] = cnt2;
-        a.nc_ipol[poli[lane]] = cnt3;
-        atomicMax(&a.maxcnt[2], cnt2);
-        atomicMax(&a.maxcnt[3], cnt3);
+      if (pol_v >= 0) {
+        a.nc_pol[pol_v] = cnt2;
+        a.nc_ipol[pol_v] = cnt3;
       }
-      if (cnt1 != a.mol_count[moli[lane]] - 1) atomicOr(a.err, 1);
+      if (cnt1 != a.mol_count[mol_v] - 1) atomicOr(a.err, 1);
     }
+    mx.x = max(mx.x, wave_max(lane < ni ? cnt0 + cntf : 0));
+    mx.y = max(mx.y, wave_max(lane < ni ? cnt1 : 0));
+    mx.z = max(mx.z, wave_max(pol_v >= 0 ? cnt2 : 0));
+    mx.w = max(mx.w, wave_max(pol_v >= 0 ? cnt3 : 0));
     __syncthreads();
   }
+  if (lane == 0) a.cellmax[cell] = mx;
+}
+
+__global__ __launch_bounds__(1024) void k_cellmax_reduce(const int4* cellmax, int ncell, int* out) {
+  __shared__ int4 part[16];
+  int4 m = make_int4(0, 0, 0, 0);
+  for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+    const int4 v = cellmax[k];
+    m.x = max(m.x, v.x); m.y = max(m.y, v.y); m.z = max(m.z, v.z); m.w = max(m.w, v.w);
+  }
+  m.x = wave_max(m.x); m.y = wave_max(m.y); m.z = wave_max(m.z); m.w = wave_max(m.w);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) part[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int4 r = part[0];
+    for (int k = 1; k < nw; ++k) {
+      r.x = max(r.x, part[k].x); r.y = max(r.y, part[k].y);
+      r.z = max(r.z, part[k].z); r.w = max(r.w, part[k].w);
+    }
+    out[0] = r.x; out[1] = r.y; out[2] = r.z; out[3] = r.w;
+  }
+}
+
+void launch_cellmax_reduce(const int4* cellmax, int ncell, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cellmax_reduce, dim3(1), dim3(1024), 0, s, cellmax, ncell, out);
 }
 
 void launch_nlist(const NlistArgs& a, int ncell, hipStream_t s) {

@@ -184,6 +184,37 @@ def test_neighbor_counts_exact(name):
     eng.close()
 
 
+def test_neighbor_lists_grow_on_overflow():
+    """A dense pocket (the waters within 12 A of the box centre pulled in by
+    half) gives its sites about twice the neighbours the density estimate
+    sizes the lists for, and more sites per cell than one pass of the
+    builder holds: the builder must see the overflow in its count maxima,
+    grow the lists and rebuild.  Counts stay exact and max_neighbors is
+    their maximum."""
+    say("[nlist] dense pocket, box4096")
+    d, prm = config_system("box4096")
+    d = dict(d)
+    pos = np.array(d["pos"], float)
+    box = np.asarray(d["box"], float)
+    mol = np.asarray(d["mol"])
+    c = 0.5 * box
+    first = np.flatnonzero(np.r_[True, mol[1:] != mol[:-1]])
+    near = np.zeros(len(pos), bool)
+    for m0, m1 in zip(first, np.r_[first[1:], len(pos)]):
+        if np.linalg.norm(pos[m0] - c) < 12.0:
+            near[m0:m1] = True
+    pos[near] = c + 0.5 * (pos[near] - c)
+    d["pos"] = pos
+    eng = engine_for(d, gpu_params(d, beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"]))
+    got = eng.neighbor_counts().cpu().numpy()
+    ref = _kdtree_counts(d, prm["cutoff"])
+    estimate = 1.3 * len(pos) / np.prod(box) * 4.0 / 3.0 * np.pi * prm["cutoff"] ** 3 + 64
+    assert ref.max() > estimate            # the pocket overflows the first lists
+    assert np.array_equal(got, ref)
+    assert eng.stats()["max_neighbors"] == ref.max()
+    eng.close()
+
+
 def test_polarizable_count_changes_on_a_live_context():
     """set_polarizabilities may change which sites are polarizable: the
     polarizable-pair lists (whose row counts follow that number) are
