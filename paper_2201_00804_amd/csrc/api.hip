@@ -582,7 +582,10 @@ sibfa_status alloc_lists(sibfa_ctx c, const int want[4]) {
   return SIBFA_OK;
 }
 
-sibfa_status build_lists(sibfa_ctx c) {
+// beside: enqueued once, right after the first list launch (work for the
+// auxiliary stream that the host should not make the list build wait for).
+template <class Beside>
+sibfa_status build_lists(sibfa_ctx c, Beside beside) {
   int want[4];
   if (c->periodic) {
     const double V = c->box[0] * c->box[1] * c->box[2];
@@ -627,6 +630,7 @@ sibfa_status build_lists(sibfa_ctx c) {
       launch_nlist(a, c->ncell, c->stream);
       launch_cellmax_reduce(c->cellmax, c->ncell, c->dints, c->stream);
     }
+    if (attempt == 0) beside();
     HIP_TRY(hipMemcpyAsync(c->h_ints, c->dints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     sibfa_status s2 = sync_read(c);
     if (s2 != SIBFA_OK) return s2;
@@ -774,17 +778,23 @@ sibfa_status prepare(sibfa_ctx c) {
         }
       }
       // the reciprocal potential of the permanent multipoles needs the
-      // brick lists but not the neighbour lists: start it on the auxiliary
-      // stream while the lists are built
+      // brick lists but not the neighbour lists: it runs on the auxiliary
+      // stream while the lists are built, forked here but enqueued after
+      // the list launch, so that the GPU starts the lists while the host
+      // is still enqueueing the reciprocal chain
       // (FP64 in both modes: it runs beside the list build, and the
       // reciprocal energy is a large term of E_elec, which is a small sum)
-      fork(c);
+      if (c->aux != c->stream) (void)hipEventRecord(c->ev_fork, c->stream);
+    }
+    auto recip = [c]() {
+      if (!c->periodic) return;
+      if (c->aux != c->stream) (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
       Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
       launch_spread_mult(make_view(c), c->pm, nullptr, false, c->aux);
       conv(c, false, c->aux, S_EREC0);
       c->phi_e0 = true;
-    }
-    sibfa_status st = build_lists(c);
+    };
+    sibfa_status st = build_lists(c, recip);
     if (st != SIBFA_OK) return st;
     c->dirty_lists = false;
     c->e0_valid = false;
