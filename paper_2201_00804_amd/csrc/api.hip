@@ -49,6 +49,7 @@ struct sibfa_ctx_s {
   // real-space kernel on `stream`; ev_fork / ev_join order the two
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_bricks = nullptr;   // the PME brick lists are built (auxiliary stream)
   sibfa_alloc_fn af = nullptr;
   sibfa_free_fn ff = nullptr;
   void* user = nullptr;
@@ -758,40 +759,46 @@ sibfa_status prepare(sibfa_ctx c) {
     c->e0_valid = false;
   }
   if (c->dirty_lists) {
-    if (c->periodic) {
+    // PME brick lists and the reciprocal potential of the permanent
+    // multipoles need the sorted records but not the neighbour lists: they
+    // run on the auxiliary stream beside the list build, forked here but
+    // enqueued after the list launch, so that the GPU starts the lists
+    // while the host is still enqueueing them.  The main stream waits for
+    // the brick lists after the list kernels (its dipole spreading and
+    // force PME read them); the potential is joined by its consumer.
+    // (FP64 in both modes: it runs beside the list build, and the
+    // reciprocal energy is a large term of E_elec, which is a small sum)
+    const bool two = c->aux != c->stream;
+    if (c->periodic && two) (void)hipEventRecord(c->ev_fork, c->stream);
+    auto recip = [c, two]() {
+      if (!c->periodic) return;
+      hipStream_t a = c->aux;
+      if (two) (void)hipStreamWaitEvent(a, c->ev_fork, 0);
       {
-        Phase ph(c, SIBFA_PH_LISTS);
+        Phase ph(c, SIBFA_PH_LISTS, a);
         SysView sv = make_view(c);
         for (int pol = 0; pol < 2; ++pol) {
           int* start = pol ? c->bstart_pol : c->bstart_all;
           int* order = pol ? c->border_pol : c->border_all;
           const int cnt = pol ? c->npol : c->n;
           launch_fill_ints({{c->bcount, (size_t)c->nbricks + 1}, {c->bcursor, (size_t)c->nbricks}},
-                           0, s);
-          launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, s);
-          launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, s);
+                           0, a);
+          launch_brick_bin(sv, c->pm, pol, c->brick_of, c->bcount, a);
+          launch_exclusive_scan(c->bcount, start, c->nbricks + 1, c->bscan_tmp, a);
           if (cnt > 0) {
-            launch_scatter(c->brick_of, start, c->bcursor, order, cnt, s);
+            launch_scatter(c->brick_of, start, c->bcursor, order, cnt, a);
             // increasing site index within each brick: reproducible sums
-            launch_sort_cells(start, c->nbricks, order, s);
+            launch_sort_cells(start, c->nbricks, order, a);
           }
         }
       }
-      // the reciprocal potential of the permanent multipoles needs the
-      // brick lists but not the neighbour lists: it runs on the auxiliary
-      // stream while the lists are built, forked here but enqueued after
-      // the list launch, so that the GPU starts the lists while the host
-      // is still enqueueing the reciprocal chain
-      // (FP64 in both modes: it runs beside the list build, and the
-      // reciprocal energy is a large term of E_elec, which is a small sum)
-      if (c->aux != c->stream) (void)hipEventRecord(c->ev_fork, c->stream);
-    }
-    auto recip = [c]() {
-      if (!c->periodic) return;
-      if (c->aux != c->stream) (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
-      Phase ph(c, SIBFA_PH_FIELD_RECIP, c->aux);
-      launch_spread_mult(make_view(c), c->pm, nullptr, false, c->aux);
-      conv(c, false, c->aux, S_EREC0);
+      if (two) {
+        (void)hipEventRecord(c->ev_bricks, a);
+        (void)hipStreamWaitEvent(c->stream, c->ev_bricks, 0);
+      }
+      Phase ph(c, SIBFA_PH_FIELD_RECIP, a);
+      launch_spread_mult(make_view(c), c->pm, nullptr, false, a);
+      conv(c, false, a, S_EREC0);
       c->phi_e0 = true;
     };
     sibfa_status st = build_lists(c, recip);
@@ -1633,6 +1640,8 @@ sibfa_status sibfa_create(sibfa_ctx* out, int device, void* hip_stream, sibfa_al
              hipEventCreateWithFlags(&c->ev_fork,
                                      hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
              hipEventCreateWithFlags(&c->ev_join,
+                                     hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_bricks,
                                      hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
     sibfa_destroy(c);
     return SIBFA_E_DEVICE;
@@ -1650,6 +1659,7 @@ void sibfa_destroy(sibfa_ctx c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_bricks) (void)hipEventDestroy(c->ev_bricks);
   if (c->aux && c->aux != c->stream) (void)hipStreamDestroy(c->aux);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
