@@ -628,7 +628,10 @@ __global__ __launch_bounds__(64) void k_nlist(NlistArgs a) {
 //    binary search over the run offsets), so chunks are full;
 //  * each i-site's five running counts are read once per pass over those
 //    chunks into wave-uniform (scalar) registers, so a candidate chunk costs
-//    the distance test, the ballots and the slot arithmetic of its hits;
+//    the distance test, the lane masks and the slot arithmetic of its hits;
+//  * the cell's count maxima go to its own slot of cellmax (plain stores;
+//    launch_cellmax_reduce folds them), not to one atomic per wavefront on
+//    four shared addresses.
 constexpr int kNlG = 4;   // candidate chunks per pass over the i-sites
 
 __device__ __forceinline__ int rl(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
