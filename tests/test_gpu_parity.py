@@ -116,6 +116,30 @@ def test_multipass_fft_matches_plane_fft(monkeypatch):
     _compare_full(d, kw, "box27-multipass")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_stream_matches_two(monkeypatch, precision):
+    """With the second stream switched off (SIBFA_PME_OVERLAP=0) every step
+    runs in order on one stream: the PME brick lists and the permanent
+    reciprocal potential after the neighbour lists instead of beside them,
+    the real-space matvec after the reciprocal chain.  The kernels and their
+    summation orders are the same, so the results are bit-identical."""
+    say(f"[streams] box1024 {precision}")
+    d, prm = config_system("box1024")
+    kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"], tol=prm["tol"],
+              precision=precision, precond="molblock")
+    res = {}
+    for overlap in ("1", "0"):
+        monkeypatch.setenv("SIBFA_PME_OVERLAP", overlap)
+        eng = engine_for(d, gpu_params(d, **kw))
+        mu, it, rms = eng.solve()
+        ep, ee, F = eng.energy_forces()
+        res[overlap] = (mu.cpu().numpy(), it, rms, ep, ee, F.cpu().numpy())
+        eng.close()
+    a, b = res["1"], res["0"]
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
+    assert a[3] == b[3] and a[4] == b[4] and np.array_equal(a[5], b[5])
+
+
 @pytest.mark.parametrize("scale", [0.05, 3.0])
 def test_damping_split_extremes(scale):
     """The all-pairs rows are split at the radius beyond which no
