@@ -770,7 +770,7 @@ sibfa_status prepare(sibfa_ctx c) {
     // reciprocal energy is a large term of E_elec, which is a small sum)
     const bool two = c->aux != c->stream;
     if (c->periodic && two) (void)hipEventRecord(c->ev_fork, c->stream);
-    auto recip = [c, two]() {
+    auto beside_lists = [c, two]() {
       if (!c->periodic) return;
       hipStream_t a = c->aux;
       if (two) (void)hipStreamWaitEvent(a, c->ev_fork, 0);
@@ -801,7 +801,7 @@ sibfa_status prepare(sibfa_ctx c) {
       conv(c, false, a, S_EREC0);
       c->phi_e0 = true;
     };
-    sibfa_status st = build_lists(c, recip);
+    sibfa_status st = build_lists(c, beside_lists);
     if (st != SIBFA_OK) return st;
     c->dirty_lists = false;
     c->e0_valid = false;
