@@ -213,8 +213,9 @@ def test_neighbor_lists_grow_on_overflow():
     half) gives its sites about twice the neighbours the density estimate
     sizes the lists for, and more sites per cell than one pass of the
     builder holds: the builder must see the overflow in its count maxima,
-    grow the lists and rebuild.  Counts stay exact and max_neighbors is
-    their maximum."""
+    grow the lists and rebuild.  Counts stay exact, max_neighbors is their
+    maximum, and the lists' contents give the oracle's permanent-field and
+    T rows at sites of the pocket."""
     say("[nlist] dense pocket, box4096")
     d, prm = config_system("box4096")
     d = dict(d)
@@ -236,7 +237,21 @@ def test_neighbor_lists_grow_on_overflow():
     assert ref.max() > estimate            # the pocket overflows the first lists
     assert np.array_equal(got, ref)
     assert eng.stats()["max_neighbors"] == ref.max()
+    # list contents: permanent-field rows and rows of T at polarizable sites
+    # of the pocket against the oracle's sampled rows (FP64 both sides)
+    E0_g = eng.permanent_field().cpu().numpy()
+    rng = np.random.default_rng(5)
+    mu = np.zeros_like(pos)
+    s = System.from_dict(d)
+    mu[s.pol] = rng.normal(scale=0.05, size=(len(s.pol), 3))
+    Tmu_g = eng.apply_T(torch.as_tensor(mu, device="cuda")).cpu().numpy()
     eng.close()
+    kw = dict(beta=prm["beta"], cutoff=prm["cutoff"], grid=prm["grid"])
+    op = oracle_params(d, **kw)
+    samp = np.sort(rng.choice(s.pol[near[s.pol]], 16, replace=False))
+    ctx = Context(s, op, subset=samp)
+    assert rel_err(E0_g[samp], permanent_field(s, op, ctx=ctx, sites=samp)) < 1e-8
+    assert rel_err(Tmu_g[samp], apply_T(s, op, mu[s.pol], ctx=ctx, sites=samp)) < 1e-8
 
 
 def test_polarizable_count_changes_on_a_live_context():
