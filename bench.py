@@ -443,6 +443,27 @@ def _rs_rows_worker(rows):
     return t
 
 
+def cpu_full_eval(name):
+    """One whole FP64 oracle evaluation of a small box, on one thread: the
+    permanent field, the PCG solve to the tolerance, E_pol, E_elec and all
+    forces (the oracle's own evaluate, unsampled)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.model import System, Params, evaluate
+    from synth import config_system
+
+    d, cfg = config_system(name)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s = System.from_dict(d)
+        p = Params(method="spme", beta=cfg["beta"], cutoff=cfg["cutoff"],
+                   grid=(cfg["grid"],) * 3, order=cfg["order"], tol=cfg["tol"])
+        r = evaluate(s, p)
+        sec = time.perf_counter() - t0
+    return dict(workload=name, n_sites=len(d["pos"]), seconds=round(sec, 2), cores=1,
+                kind="oracle", iterations=int(r["iters"]), e_pol=float(r["E_pol"]))
+
+
 def cpu_baseline(sysd, prm, iters, sample=360):
     """The FP64 oracle on a bounded sample of the same box, scaled to one
     evaluation: the oracle's real-space pair sums for `sample` sites
@@ -742,6 +763,9 @@ def main():
         iters = results.get("fp64", main_r)["iters"]
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sysd, prm, iters)
+        print("[bench] cpu baseline: one whole oracle evaluation of the 216-water box",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"]["full_eval"] = cpu_full_eval("box216")
     print(json.dumps(out), flush=True)
 
 
