@@ -563,8 +563,9 @@ def cpu_baseline(sysd, prm, iters, sample=360):
     t_eval_mc = per_eval(tm)
     return dict(value=1.0 / t_eval_mc, unit="evals/s", cores=cores, kind="oracle",
                 cpu_model=_cpu_model(),
-                sample=(f"{sample} polarizable + {sample} arbitrary sites of the 32,000-water "
-                        f"box (real-space rows and neighbour search scaled by N/sample; rows "
+                sample=(f"{sample} polarizable + {sample} arbitrary sites of the "
+                        f"{len(np.unique(sysd['mol'])):,}-molecule box (real-space rows and "
+                        f"neighbour search scaled by N/sample; rows "
                         f"split over {cores} worker processes, one thread each) plus "
                         f"full-size SPME passes on one thread (permanent; dipole, once per "
                         f"matvec; combined for forces); {iters + 1} matvecs per solve; "
@@ -766,6 +767,15 @@ def main():
         print("[bench] cpu baseline: one whole oracle evaluation of the 216-water box",
               file=sys.stderr, flush=True)
         out["cpu_baseline"]["full_eval"] = cpu_full_eval("box216")
+        print("[bench] cpu baseline: the 4,096-water box, same bounded sample",
+              file=sys.stderr, flush=True)
+        from synth import config_system
+        d2, cfg2 = config_system("box4096")
+        c2 = cpu_baseline(d2, cfg2, iters)
+        out["cpu_baseline"]["box4096"] = dict(
+            n_sites=len(d2["pos"]), seconds_per_eval=c2["seconds_per_eval"], cores=c2["cores"],
+            single_thread_seconds_per_eval=c2["single_thread"]["seconds_per_eval"],
+            sample=c2["sample"])
     print(json.dumps(out), flush=True)
 
 
