@@ -226,8 +226,10 @@ sibfa_status sibfa_solve_induced(sibfa_ctx ctx, int warm_start, double* mu_out,
  * kcal/mol) = -1/2 mu.E (the form of Eq. 19) or NULL.  Runs in the
  * context's precision and returns after a stream synchronisation.  The
  * dipoles of the last solve_induced stay the warm start; the next
- * energy_forces solves again.  Forces at TCG dipoles are not provided:
- * the fixed-dipole force identity holds only at the converged solution.
+ * energy_forces solves again.  This call returns no forces:
+ * sibfa_tcg_energy_forces below gives the forces at TCG dipoles (the
+ * fixed-dipole identity of sibfa_energy_forces holds only at the converged
+ * solution).
  * Returns SIBFA_E_ARG for a bad order or a non-finite omega, SIBFA_E_NOT_SPD
  * if p.Tp <= 0 in a step. */
 #define SIBFA_TCG_MAX_ORDER 64
