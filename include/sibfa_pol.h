@@ -205,7 +205,8 @@ sibfa_status sibfa_permanent_field(sibfa_ctx ctx, double* field_out);
  * non-polarizable sites are ignored, their output rows are zero). */
 sibfa_status sibfa_apply_T(sibfa_ctx ctx, const double* p, double* tp_out);
 
-/* Solve T mu = E by PCG (block-diagonal preconditioner alpha).
+/* Solve T mu = E by PCG (preconditioner per params.precond: alpha per site,
+ * or the molecular blocks of T).
  * warm_start: start from the dipoles kept from the previous solve (or set
  * by sibfa_set_dipoles), or the predictor's extrapolation of them (see
  * sibfa_set_predictor), instead of alpha E.  mu_out [n][3] (device) or
