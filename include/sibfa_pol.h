@@ -335,9 +335,9 @@ sibfa_status sibfa_ct_energy_forces(sibfa_ctx ctx, double* e_ct, double* forces)
 
 /* Molecular dynamics (Computational Details: Beeman integrator, 1 fs
  * steps, the polarization solved at every step).  The paper's other terms
- * (repulsion, dispersion, charge transfer, bonded terms) are outside this
- * library, so the driver takes harmonic bonds as a stand-in that holds the
- * molecules together; a trajectory exercises and times the polarization
+ * (repulsion, dispersion, bonded terms) are outside this library, and the
+ * charge transfer above is not added to the MD forces, so the driver takes
+ * harmonic bonds as a stand-in that holds the molecules together; a trajectory exercises and times the polarization
  * path, it is not the paper's model.
  * sibfa_md_init: masses [n] (device, g/mol; 0 marks a virtual site),
  * vsites [n][2] (device int32 or NULL: none): the two atoms whose midpoint
